@@ -1,0 +1,173 @@
+"""CPU oracle for finite-element local assembly (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The GPU library never does, and shares no code with it.
+
+The compiled part is ``fe_oracle.c`` (plain C, IEEE double, OpenMP over
+elements); this module loads it with ctypes and offers numpy-facing helpers.
+It evaluates Eq. (7) of the paper (quadrature mode, Sec. 2.2) as the naive
+loop nest of Fig. 1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fe_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CELL = {"triangle": 0, "tetrahedron": 1, "prism": 2}
+FORM = {"mass": 0, "helmholtz": 1, "elasticity": 2, "hyperelastic": 3}
+TDIM = {"triangle": 2, "tetrahedron": 3, "prism": 3}
+NVERT = {"triangle": 3, "tetrahedron": 4, "prism": 6}
+REF_VOLUME = {"triangle": 0.5, "tetrahedron": 1.0 / 6.0, "prism": 0.5}
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (portable flags: it runs on other hosts)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", _SRC, "-o", tmp, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_nbasis.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.orc_rule_size.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.orc_rule.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+        L.orc_basis.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.orc_geometry.argtypes = [ctypes.c_int, dp, dp, dp, dp]
+        L.orc_assemble.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.c_double,
+                                   dp, ctypes.c_int]
+        L.orc_assemble.restype = ctypes.c_int64
+        L.orc_hyper_residual.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                         dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.orc_hyper_residual.restype = ctypes.c_int64
+        L.orc_hyper_min_jf.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                       dp, dp, dp, ctypes.c_int]
+        L.orc_hyper_min_jf.restype = ctypes.c_int64
+        L.orc_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def nbasis(cell: str, p: int) -> int:
+    return lib().orc_nbasis(CELL[cell], p)
+
+
+def default_qdeg(form: str, cell: str, p: int) -> int:
+    """Exact quadrature degree for each form (Sec. 7.1 uses exact quadrature):
+    mass and Helmholtz 2p; elasticity with P1 Lame fields 2(p-1)+1 on simplices
+    and 2p+1 on prisms (tensor-product degree); hyperelastic 4."""
+    if form in ("mass", "helmholtz"):
+        return 2 * p
+    if form == "elasticity":
+        return 2 * p + 1 if cell == "prism" else 2 * p - 1
+    return 4
+
+
+def rule(cell: str, qdeg: int):
+    L = lib()
+    nq = L.orc_rule_size(CELL[cell], qdeg)
+    if nq < 0:
+        raise ValueError("bad rule")
+    X = np.zeros((nq, TDIM[cell]))
+    W = np.zeros(nq)
+    L.orc_rule(CELL[cell], qdeg, _p(X), _p(W))
+    return X, W
+
+
+def basis(cell: str, p: int, X):
+    X = _f64(np.atleast_2d(X))
+    nb = nbasis(cell, p)
+    d = TDIM[cell]
+    phi = np.zeros((X.shape[0], nb))
+    dphi = np.zeros((X.shape[0], nb, d))
+    for i in range(X.shape[0]):
+        xi = _f64(X[i])
+        ph = np.zeros(nb)
+        dph = np.zeros((nb, d))
+        lib().orc_basis(CELL[cell], p, _p(xi), _p(ph), _p(dph))
+        phi[i], dphi[i] = ph, dph
+    return phi, dphi
+
+
+def geometry(cell: str, v):
+    d = TDIM[cell]
+    v = _f64(v)
+    J = np.zeros((d, d))
+    K = np.zeros((d, d))
+    det = np.zeros(1)
+    bad = lib().orc_geometry(CELL[cell], _p(v), _p(J), _p(det), _p(K))
+    return J, float(det[0]), K, bool(bad)
+
+
+def local_dim(form: str, cell: str, p: int) -> int:
+    ns = nbasis(cell, p)
+    return TDIM[cell] * ns if form in ("elasticity", "hyperelastic") else ns
+
+
+def assemble(form: str, cell: str, p: int, coords, coeff=None, qdeg=None,
+             mu: float = 1.0, lam: float = 10.0, nthreads: int = 0):
+    """Element matrices [E][n][n] and the number of flagged elements."""
+    coords = _f64(coords)
+    E = coords.shape[0]
+    n = local_dim(form, cell, p)
+    if qdeg is None:
+        qdeg = default_qdeg(form, cell, p)
+    out = np.empty((E, n, n))
+    cf = _f64(coeff) if coeff is not None else None
+    if form in ("elasticity", "hyperelastic") and cf is None:
+        raise ValueError("coefficients required")
+    flagged = lib().orc_assemble(FORM[form], CELL[cell], p, qdeg, E, _p(coords), _p(cf),
+                                 mu, lam, _p(out), nthreads)
+    if flagged < 0:
+        raise ValueError("oracle rejected arguments")
+    return out, int(flagged)
+
+
+def hyper_residual(cell: str, p: int, coords, u, qdeg: int = 4, mu: float = 1.0, lam: float = 10.0):
+    coords, u = _f64(coords), _f64(u)
+    E = coords.shape[0]
+    R = np.zeros((E, TDIM[cell] * nbasis(cell, p)))
+    en = np.zeros(E)
+    lib().orc_hyper_residual(CELL[cell], p, qdeg, E, _p(coords), _p(u), mu, lam, _p(R), _p(en))
+    return R, en
+
+
+def hyper_min_jf(cell: str, p: int, coords, u, qdeg: int = 4, nthreads: int = 0):
+    coords, u = _f64(coords), _f64(u)
+    E = coords.shape[0]
+    m = np.zeros(E)
+    lib().orc_hyper_min_jf(CELL[cell], p, qdeg, E, _p(coords), _p(u), _p(m), nthreads)
+    return m
+
+
+def max_threads() -> int:
+    return lib().orc_max_threads()

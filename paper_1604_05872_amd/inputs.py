@@ -1,0 +1,220 @@
+"""Seeded synthetic inputs for local assembly: jittered meshes and coefficient DOFs.
+
+This module is shared by the tests, the oracle-side checks and the benchmark.  It
+holds no finite-element arithmetic: it only lays out vertex lattices, draws random
+numbers and gathers vertex data per element.  Nothing here evaluates a basis
+function, a Jacobian or an integrand.
+
+Layouts produced (all float64, C-contiguous, element-major):
+  coords  [E][nv][gdim]   nv = 3 (triangle), 4 (tetrahedron), 6 (prism)
+  elasticity coefficients [E][2][nc]   Lame lambda DOFs, then mu DOFs, P1 per cell vertex
+  hyperelastic displacement [E][gdim * n_s]   component-blocked element-local DOFs
+
+Vertex ordering follows the reference cells used throughout the library:
+  triangle (0,0),(1,0),(0,1); tetrahedron adds (0,0,1); prism = triangle x [0,1],
+  vertices 0..2 on the bottom face and 3..5 = 0..2 + e_z.
+
+Jitter choices (each provably non-inverting, because a simplex volume is
+multilinear in the vertex coordinates, so its minimum over a box of per-axis
+perturbations is attained at a box corner; the corners were enumerated):
+  * triangles, +-0.2 h per axis (h_x, h_y separately): worst area ratio 0.2;
+  * Kuhn tetrahedra, +-0.15 h per axis: worst volume ratio 0.10
+    (+-0.2 h can invert a Kuhn tetrahedron);
+  * prisms: the triangle jitter in x, y only, layers of equal height, so every
+    prism is an exact translate-extrusion (affine).
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+TRI, TET, PRISM = "triangle", "tetrahedron", "prism"
+CELLS = (TRI, TET, PRISM)
+GDIM = {TRI: 2, TET: 3, PRISM: 3}
+NVERT = {TRI: 3, TET: 4, PRISM: 6}
+
+TRI_JITTER = 0.2
+TET_JITTER = 0.15
+
+
+def n_scalar_dofs(cell: str, p: int) -> int:
+    """Number of scalar Lagrange DOFs of degree p on a cell (lattice count)."""
+    if cell == TRI:
+        return (p + 1) * (p + 2) // 2
+    if cell == TET:
+        return (p + 1) * (p + 2) * (p + 3) // 6
+    if cell == PRISM:
+        return (p + 1) * (p + 2) // 2 * (p + 1)
+    raise ValueError(cell)
+
+
+def _streams(seed: int, n: int):
+    return [np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(n)]
+
+
+# ---------------------------------------------------------------------------
+# Vertex lattices
+# ---------------------------------------------------------------------------
+
+def _jitter_plane(nx: int, ny: int, amp: float, rng) -> np.ndarray:
+    """(nx+1)*(ny+1) vertices of the unit square, interior ones jittered per axis."""
+    hx, hy = 1.0 / nx, 1.0 / ny
+    X, Y = np.meshgrid(np.arange(nx + 1) * hx, np.arange(ny + 1) * hy, indexing="ij")
+    V = np.stack([X, Y], axis=-1)  # [nx+1][ny+1][2]
+    if amp > 0:
+        d = rng.uniform(-amp, amp, size=V.shape)
+        d[..., 0] *= hx
+        d[..., 1] *= hy
+        d[0, :, :] = 0.0
+        d[-1, :, :] = 0.0
+        d[:, 0, :] = 0.0
+        d[:, -1, :] = 0.0
+        V = V + d
+    return V
+
+
+def triangle_mesh(nx: int, ny: int, seed: int, jitter: float = TRI_JITTER):
+    """Unit square, nx*ny cells, two triangles per cell split along the
+    (i,j)->(i+1,j+1) diagonal, counter-clockwise.  Returns (vertices[NV][2],
+    cells[E][3]) with E = 2*nx*ny."""
+    (rng,) = _streams(seed, 1)
+    V = _jitter_plane(nx, ny, jitter, rng).reshape(-1, 2)
+    vid = lambda i, j: i * (ny + 1) + j  # noqa: E731
+    I, J = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    I, J = I.ravel(), J.ravel()
+    a, b, c, d = vid(I, J), vid(I + 1, J), vid(I + 1, J + 1), vid(I, J + 1)
+    t1 = np.stack([a, b, c], axis=1)
+    t2 = np.stack([a, c, d], axis=1)
+    cells = np.stack([t1, t2], axis=1).reshape(-1, 3)
+    return V, cells
+
+
+_KUHN = list(itertools.permutations(range(3)))
+
+
+def tet_mesh(n: int, seed: int, jitter: float = TET_JITTER):
+    """Unit cube, n^3 cubes, 6 Kuhn tetrahedra per cube (one per axis
+    permutation, vertex path 0 -> e_s1 -> e_s1+e_s2 -> (1,1,1)).  Interior
+    vertices jittered uniformly by +-jitter*h per axis.  Returns
+    (vertices[NV][3], cells[E][4]) with E = 6*n^3."""
+    (rng,) = _streams(seed, 1)
+    h = 1.0 / n
+    g = np.arange(n + 1) * h
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    V = np.stack([X, Y, Z], axis=-1)
+    if jitter > 0:
+        d = rng.uniform(-jitter * h, jitter * h, size=V.shape)
+        for ax in range(3):
+            sl = [slice(None)] * 3
+            sl[ax] = 0
+            d[tuple(sl)] = 0.0
+            sl[ax] = -1
+            d[tuple(sl)] = 0.0
+        V = V + d
+    V = V.reshape(-1, 3)
+    n1 = n + 1
+    vid = lambda i, j, k: (i * n1 + j) * n1 + k  # noqa: E731
+    I, J, K = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    base = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1)  # [n^3][3]
+    cells = np.empty((base.shape[0], 6, 4), dtype=np.int64)
+    for t, perm in enumerate(_KUHN):
+        cur = base.copy()
+        cells[:, t, 0] = vid(cur[:, 0], cur[:, 1], cur[:, 2])
+        for s, ax in enumerate(perm):
+            cur = cur.copy()
+            cur[:, ax] += 1
+            cells[:, t, s + 1] = vid(cur[:, 0], cur[:, 1], cur[:, 2])
+    return V, cells.reshape(-1, 4)
+
+
+def prism_mesh(n: int, nz: int, seed: int, jitter: float = TRI_JITTER):
+    """Extruded triangle mesh: n*n*2 triangles (jittered in x, y) times nz
+    layers of height 1/nz.  Prism vertices are the bottom triangle then the
+    same triangle one layer up, so every prism is affine.  Returns
+    (vertices[NV][3], cells[E][6]) with E = 2*n*n*nz."""
+    V2, tris = triangle_mesh(n, n, seed, jitter)
+    nv2 = V2.shape[0]
+    z = np.arange(nz + 1) / nz
+    V = np.concatenate(
+        [np.concatenate([V2, np.full((nv2, 1), zl)], axis=1) for zl in z], axis=0
+    )
+    layers = np.arange(nz)
+    bot = tris[None, :, :] + (layers * nv2)[:, None, None]
+    top = bot + nv2
+    cells = np.concatenate([bot, top], axis=2).reshape(-1, 6)
+    return V, cells
+
+
+def gather(V: np.ndarray, cells: np.ndarray) -> np.ndarray:
+    """coords[E][nv][gdim] from a vertex array and a connectivity array."""
+    return np.ascontiguousarray(V[cells], dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Coefficient DOFs
+# ---------------------------------------------------------------------------
+
+def lame_p1(nverts: int, cells: np.ndarray, seed: int, lo: float = 0.5, hi: float = 2.0):
+    """Continuous P1 Lame fields: one lambda and one mu value per mesh vertex,
+    uniform in [lo, hi], gathered per element to [E][2][nv]."""
+    r_lam, r_mu = _streams(seed, 2)
+    lam = r_lam.uniform(lo, hi, size=nverts)
+    mu = r_mu.uniform(lo, hi, size=nverts)
+    return np.ascontiguousarray(np.stack([lam[cells], mu[cells]], axis=1))
+
+
+def displacement_dofs(E: int, gdim: int, n_s: int, h: float, p: int, seed: int,
+                      rel: float = 0.05, clip: float = 3.0) -> np.ndarray:
+    """Element-local displacement DOFs [E][gdim*n_s], component-blocked,
+    i.i.d. normal with standard deviation rel*h/p (h/p is the spacing of the
+    degree-p DOF lattice along a mesh edge), redrawn where beyond clip
+    standard deviations."""
+    (rng,) = _streams(seed, 1)
+    sig = rel * h / p
+    u = rng.standard_normal(size=(E, gdim * n_s))
+    bad = np.abs(u) > clip
+    while bad.any():
+        u[bad] = rng.standard_normal(size=int(bad.sum()))
+        bad = np.abs(u) > clip
+    return np.ascontiguousarray(u * sig)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+
+def mass_tri_workload(seed: int = 1):
+    """4096 P1 triangles from a 32 x 64 unit-square grid, +-0.2 h per-axis jitter."""
+    V, cells = triangle_mesh(32, 64, seed)
+    return gather(V, cells)
+
+
+def tet_workload(n: int, seed: int):
+    V, cells = tet_mesh(n, seed)
+    return gather(V, cells), V, cells
+
+
+def grid_for_count(cell: str, E: int) -> int:
+    """Smallest per-side count n whose structured grid holds at least E cells
+    (triangle: 2 n^2, tetrahedron: 6 n^3, prism: 2 n^2 * n layers)."""
+    per = {TRI: lambda n: 2 * n * n, TET: lambda n: 6 * n ** 3, PRISM: lambda n: 2 * n ** 3}[cell]
+    n = max(1, int(math.floor((E / {TRI: 2, TET: 6, PRISM: 2}[cell]) ** (1.0 / (2 if cell == TRI else 3)))))
+    while per(n) < E:
+        n += 1
+    return n
+
+
+def first_elements(cell: str, E: int, seed: int):
+    """The first E elements of the smallest jittered structured grid with at
+    least E cells.  Returns (coords, vertices, cells[:E], h)."""
+    n = grid_for_count(cell, E)
+    if cell == TRI:
+        V, cells = triangle_mesh(n, n, seed)
+    elif cell == TET:
+        V, cells = tet_mesh(n, seed)
+    else:
+        V, cells = prism_mesh(n, n, seed)
+    cells = cells[:E]
+    return gather(V, cells), V, cells, 1.0 / n
