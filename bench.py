@@ -1,0 +1,331 @@
+"""Benchmark of per-element local assembly on one MI355X.
+
+Headline workload (one step = one pass over it): the Helmholtz form
+(grad u . grad v + u v) on 750,000 jittered tetrahedra (50^3 cubes x 6 Kuhn
+tetrahedra), scalar Lagrange P1, P2, P3 and P4, float64 -- four launches per
+step.  value = element matrices per second over the timed steps.
+
+Also measured (fields "workloads"): P1 triangle mass on 4,096 elements,
+vector P2 elasticity on 1,971,054 tetrahedra (float64 and the split-precision
+MFMA variants), the neo-Hookean tangent on 998,250 tetrahedra (P1, P2; float64
+and split), and a 16-sub-batch mixed persistent launch replayed from a HIP
+graph.  Inputs are seeded synthetic meshes resident in HBM before timing.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Algorithmic work per element (flop-reduced formulation; compulsory bytes)
+# ---------------------------------------------------------------------------
+
+def n_scalar(cell, p):
+    return {"triangle": (p + 1) * (p + 2) // 2, "tetrahedron": (p + 1) * (p + 2) * (p + 3) // 6,
+            "prism": (p + 1) * (p + 2) // 2 * (p + 1)}[cell]
+
+
+GD = {"triangle": 2, "tetrahedron": 3, "prism": 3}
+NV = {"triangle": 3, "tetrahedron": 4, "prism": 6}
+
+
+def rule_size(cell, qdeg):
+    m = max(1, (qdeg + 2) // 2)
+    tri = 3 if qdeg <= 2 else m * m
+    return {"triangle": tri, "tetrahedron": m ** 3, "prism": tri * m}[cell]
+
+
+def default_qdeg(form, cell, p):
+    if form in ("mass", "helmholtz"):
+        return 2 * p
+    if form == "elasticity":
+        return 2 * p + 1 if cell == "prism" else 2 * p - 1
+    return 4
+
+
+def alg_bytes(form, cell, p):
+    d, ns = GD[cell], n_scalar(cell, p)
+    n = d * ns if form in ("elasticity", "hyperelastic") else ns
+    coeff = {"mass": 0, "helmholtz": 0, "elasticity": 2 * NV[cell], "hyperelastic": d * ns}[form]
+    return 8 * (NV[cell] * d + coeff + n * n)
+
+
+def alg_flops(form, cell, p, collapsed=True):
+    """Operation count of the flop-reduced evaluation (counting + and * once)."""
+    d, ns = GD[cell], n_scalar(cell, p)
+    geo = 24 if d == 2 else 87
+    if form == "mass":
+        return ns * ns + geo
+    if form == "helmholtz":
+        return (2 * (1 + d * (d + 1) // 2) - 1) * ns * ns + geo
+    nq = rule_size(cell, default_qdeg(form, cell, p))
+    nqi = 1 if (collapsed and p == 1 and cell != "prism") else nq   # q-invariant P1 gradients
+    inner = nqi * ns * ns * (4 * d * d + 3 * d)
+    if form == "elasticity":
+        return inner + nq * (ns * d * (2 * d - 1) + 4 * NV[cell] + 4) + geo
+    return inner + nq * (2 * ns * d * (2 * d - 1) + 2 * d * d * ns + 60) + geo
+
+
+# ---------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-headline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); local assembly shards by element "
+              f"ranges with no exchange, so run one process per GPU on its own range.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1604_05872_amd import felocal, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    felocal.lib()
+    stream = torch.cuda.current_stream()
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    # ------------------------------------------------------------------ headline
+    log("headline: helmholtz P1-P4 on 750k tets")
+    coords_np, V, cells = inputs.tet_workload(50, seed=2)
+    E = coords_np.shape[0]
+    coords = torch.from_numpy(coords_np).cuda()
+    outs = {p: torch.empty((E, n_scalar("tetrahedron", p), n_scalar("tetrahedron", p)), dtype=torch.float64,
+                           device="cuda") for p in (1, 2, 3, 4)}
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def step(times=None):
+        for p in (1, 2, 3, 4):
+            if times is not None:
+                a, b = ev(), ev()
+                a.record(stream)
+            felocal.fe_assemble_local("helmholtz", "tetrahedron", p, coords, None, outs[p], status=status)
+            if times is not None:
+                b.record(stream)
+                times[p].append((a, b))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    per = {p: [] for p in (1, 2, 3, 4)}
+    t0, t1 = ev(), ev()
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for _ in range(args.steps):
+        step(per)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t0.elapsed_time(t1)
+    ms_step = ms_total / args.steps
+    value = 4 * E / (ms_step * 1e-3)
+    kern_ms = {p: float(np.mean([a.elapsed_time(b) for a, b in per[p]])) for p in per}
+    assert int(status.item()) == 0
+    per_degree = {}
+    for p in (1, 2, 3, 4):
+        B = alg_bytes("helmholtz", "tetrahedron", p) * E
+        F = alg_flops("helmholtz", "tetrahedron", p) * E
+        per_degree[f"P{p}"] = {
+            "ms": round(kern_ms[p], 4), "elem_per_s": E / (kern_ms[p] * 1e-3),
+            "alg_GBs": B / (kern_ms[p] * 1e-3) / 1e9, "alg_GFLOPs": F / (kern_ms[p] * 1e-3) / 1e9,
+            "frac_hbm": B / (kern_ms[p] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        }
+    dom = max(kern_ms, key=kern_ms.get)
+    dom_bytes = alg_bytes("helmholtz", "tetrahedron", dom) * E
+    achieved = dom_bytes / (kern_ms[dom] * 1e-3) / 1e9
+    roofline = {"kernel": f"k_preeval<HELMHOLTZ,TET> P{dom}", "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "bytes_per_launch": dom_bytes, "ms_per_launch": round(kern_ms[dom], 4)}
+    step_bytes = sum(alg_bytes("helmholtz", "tetrahedron", p) for p in (1, 2, 3, 4)) * E
+    step_flops = sum(alg_flops("helmholtz", "tetrahedron", p) for p in (1, 2, 3, 4)) * E
+    del outs
+    torch.cuda.empty_cache()
+
+    result = {
+        "metric": "element matrices/s", "value": round(value, 1), "unit": "element matrices/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded jittered Kuhn-tetrahedron mesh)",
+        "config": {"workload": "helmholtz_tet_p1-p4", "elements": E, "mesh": "50^3 cubes x 6 tets, +-0.15h jitter",
+                   "degrees": [1, 2, 3, 4], "launches_per_step": 4, "quadrature": "exact to degree 2p"},
+        "alg_GBs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "alg_GFLOPs": round(step_flops / (ms_step * 1e-3) / 1e9, 1),
+        "wall_s_timed": round(wall, 3),
+        "per_degree": per_degree,
+        "roofline": roofline,
+    }
+
+    # ------------------------------------------------------------------ other workloads
+    if not args.only_headline:
+        result["workloads"] = other_workloads(torch, felocal, inputs, stream, ev, max(3, args.steps // 2))
+
+    # ------------------------------------------------------------------ CPU baseline (oracle)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(coords_np)
+    print(json.dumps(result), flush=True)
+
+
+def time_launch(torch, fn, stream, ev, reps):
+    fn()
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def other_workloads(torch, felocal, inputs, stream, ev, reps):
+    res = []
+
+    def record(name, form, cell, p, E, ms, prec="fp64", **extra):
+        B = alg_bytes(form, cell, p) * E
+        F = alg_flops(form, cell, p) * E
+        row = {"workload": name, "form": form, "cell": cell, "degree": p, "elements": E, "precision": prec,
+               "ms": round(ms, 4), "elem_per_s": round(E / (ms * 1e-3), 1),
+               "alg_GBs": round(B / (ms * 1e-3) / 1e9, 1), "alg_GFLOPs": round(F / (ms * 1e-3) / 1e9, 1),
+               "frac_hbm": round(B / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "frac_fp64": round(F / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+        row.update(extra)
+        res.append(row)
+        log(f"  {name} {prec}: {ms:.4f} ms, {row['elem_per_s']:.3e} elem/s, {row['alg_GBs']} GB/s")
+
+    # mass P1 triangles, 4096 elements (launch-latency bound)
+    log("mass P1 triangles 4096")
+    c1 = torch.from_numpy(inputs.mass_tri_workload(seed=1)).cuda()
+    o1 = torch.empty((4096, 3, 3), dtype=torch.float64, device="cuda")
+    ms = time_launch(torch, lambda: felocal.fe_assemble_local("mass", "triangle", 1, c1, None, o1, qdeg=2),
+                     stream, ev, 50)
+    record("mass_tri_p1_4096", "mass", "triangle", 1, 4096, ms, note="launch-latency bound (0.49 MB)")
+
+    # elasticity P2 tets, 1,971,054 elements
+    log("elasticity P2 on 1.97M tets")
+    cn, V, cells = inputs.tet_workload(69, seed=3)
+    E3 = cn.shape[0]
+    c3 = torch.from_numpy(cn).cuda()
+    cf3 = torch.from_numpy(inputs.lame_p1(V.shape[0], cells, seed=3)).cuda()
+    o3 = torch.empty((E3, 30, 30), dtype=torch.float64, device="cuda")
+    for prec in ("fp64", "fp32", "bf16x3"):
+        ms = time_launch(torch, lambda: felocal.fe_assemble_local("elasticity", "tetrahedron", 2, c3, cf3, o3,
+                                                                  precision=prec), stream, ev, reps)
+        record("elasticity_tet_p2_2m", "elasticity", "tetrahedron", 2, E3, ms, prec)
+    del o3, c3, cf3
+    torch.cuda.empty_cache()
+
+    # hyperelastic P1, P2 tets, 998,250 elements
+    cn, V, cells = inputs.tet_workload(55, seed=4)
+    E4 = cn.shape[0]
+    c4 = torch.from_numpy(cn).cuda()
+    for p in (1, 2):
+        log(f"hyperelastic P{p} on 998k tets")
+        ns = n_scalar("tetrahedron", p)
+        u = torch.from_numpy(inputs.displacement_dofs(E4, 3, ns, 1.0 / 55, p, seed=40 + p)).cuda()
+        o4 = torch.empty((E4, 3 * ns, 3 * ns), dtype=torch.float64, device="cuda")
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        for prec in ("fp64", "fp32", "bf16x3"):
+            st.zero_()
+            ms = time_launch(torch, lambda: felocal.fe_assemble_local("hyperelastic", "tetrahedron", p, c4, u, o4,
+                                                                      precision=prec, status=st), stream, ev, reps)
+            record(f"hyperelastic_tet_p{p}_1m", "hyperelastic", "tetrahedron", p, E4, ms, prec,
+                   flagged_per_launch=int(st.item()) // (reps + 1))
+        del o4, u
+        torch.cuda.empty_cache()
+    del c4
+
+    # mixed persistent batch, 16 sub-batches, one HIP graph
+    log("mixed batch: 16 sub-batches in one persistent graph launch")
+    rng = np.random.default_rng(5)
+    subs, tot_e, tot_b, tot_f = [], 0, 0, 0
+    desc = []
+    for i in range(16):
+        form = ["mass", "helmholtz", "elasticity"][rng.integers(3)]
+        cell = ["triangle", "tetrahedron", "prism"][rng.integers(3)]
+        p = int(rng.integers(1, 5))
+        E = int(round(math.exp(rng.uniform(math.log(1e4), math.log(5e5)))))
+        n = n_scalar(cell, p) * (GD[cell] if form == "elasticity" else 1)
+        E = min(E, (4 << 30) // (8 * n * n))
+        coords, Vb, cb, h = inputs.first_elements(cell, E, seed=500 + i)
+        cf = inputs.lame_p1(Vb.shape[0], cb, seed=600 + i) if form == "elasticity" else None
+        subs.append(dict(form=form, cell=cell, degree=p, coords=torch.from_numpy(coords).cuda(),
+                         coeff=torch.from_numpy(cf).cuda() if cf is not None else None,
+                         out=torch.empty((E, n, n), dtype=torch.float64, device="cuda")))
+        desc.append(f"{form}/{cell}/P{p}/{E}")
+        tot_e += E
+        tot_b += alg_bytes(form, cell, p) * E
+        tot_f += alg_flops(form, cell, p) * E
+    b = felocal.Batch(subs)
+    ntiles, grid = b.info()
+    ms = time_launch(torch, b.run, stream, ev, reps)
+    seq = time_launch(torch, lambda: [felocal.fe_assemble_local(s["form"], s["cell"], s["degree"], s["coords"],
+                                                                 s["coeff"], s["out"]) for s in subs],
+                      stream, ev, reps)
+    b.close()
+    res.append({"workload": "mixed_batch_16", "elements": tot_e, "ms": round(ms, 4),
+                "elem_per_s": round(tot_e / (ms * 1e-3), 1), "alg_GBs": round(tot_b / (ms * 1e-3) / 1e9, 1),
+                "alg_GFLOPs": round(tot_f / (ms * 1e-3) / 1e9, 1), "tiles": ntiles, "grid": grid,
+                "separate_launches_ms": round(seq, 4), "sub_batches": desc})
+    log(f"  mixed batch: {ms:.3f} ms graph vs {seq:.3f} ms separate launches, {tot_e} elements")
+    del subs
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(coords_np):
+    """The float64 oracle (naive Eq. (7) nest, OpenMP over elements) on a
+    bounded sample of the headline workload: for each degree, the first n
+    elements with n grown until that degree takes >= 2.5 s."""
+    import oracle
+
+    cores = oracle.max_threads()
+    t_per = {}
+    sample = {}
+    for p in (1, 2, 3, 4):
+        n = 256
+        while True:
+            t = time.perf_counter()
+            oracle.assemble("helmholtz", "tetrahedron", p, coords_np[:n], nthreads=cores)
+            dt = time.perf_counter() - t
+            if dt >= 2.5 or n >= coords_np.shape[0]:
+                break
+            n = min(coords_np.shape[0], n * 4 if dt < 0.5 else n * 2)
+        t_per[p] = dt / n
+        sample[p] = n
+        log(f"cpu oracle P{p}: {n} elements in {dt:.2f} s on {cores} threads")
+    per_step = sum(t_per.values())
+    return {"value": round(4.0 / per_step, 1), "unit": "element matrices/s", "cores": cores, "kind": "oracle",
+            "sample": "helmholtz tet P1-P4, first " + ", ".join(f"P{p}:{sample[p]}" for p in sample)
+                      + " elements of the 750k mesh; rate = 4 / sum_p(seconds per element)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,237 @@
+/*
+ * felocal.h -- finite-element local assembly on AMD Instinct MI355X (gfx950).
+ *
+ * Computes per-element matrices
+ *     A_e[i][j] = sum_q W_q |det J_e| * integrand(phi_i, phi_j, coefficients)(X_q)
+ * (Luporini, Ham, Kelly, "An algorithm for the optimization of finite element
+ * integration loops": quadrature mode Sec. 2.2 Eq. (7), tensor-contraction
+ * mode Sec. 2.3 Eqs. (8)-(9)) in the flop-reduced form selected by the
+ * transformation algorithm of Sec. 4.1 (Algorithm 3): pre-evaluated reference
+ * tensors (Sec. 3.3, Algorithm 2) or sharing-eliminated quadrature
+ * (Sec. 3.2, Algorithm 1), under the memory threshold T_H (Sec. 3.4,
+ * Constraint 2).
+ *
+ * Conventions
+ *   Reference cells: triangle (0,0),(1,0),(0,1); tetrahedron adds (0,0,1);
+ *   prism = triangle x [0,1], vertices 0..2 at Z=0 and 3..5 = 0..2 + e_Z.
+ *   Affine map x = v0 + J X, columns of J = v1-v0, v2-v0 (, v3-v0); prisms
+ *   must be affine (v4-v1 = v5-v2 = v3-v0).
+ *   Basis: Lagrange P_p on the equispaced lattice (i,j,k)/p, node loop order
+ *   k, j, i with i fastest; prism node (t,l) has index l*n_tri + t.  Vector
+ *   spaces are component-blocked: DOF (c, j) has index c*n_s + j.
+ *   Output rows are test functions, columns trial functions.
+ *
+ * Memory layouts (row-major, element-major, float64):
+ *   coords      [E][nv][gdim]     nv = 3 / 4 / 6, gdim = 2 / 3 / 3
+ *   coeff_dofs  elasticity   [E][2][nc]   P1 (prism: P1 x P1) Lame lambda
+ *                            DOFs then mu DOFs, nc = nv
+ *               hyperelastic [E][gdim*n_s] displacement DOFs, component-blocked
+ *               mass, Helmholtz: unused (may be NULL)
+ *   out_A       [E][n][n]         n = n_s (scalar forms) or gdim*n_s (vector
+ *                                 forms); fully overwritten
+ *
+ * Forms (integrands summed with weight W_q |det J|; g = J^{-T} grad_X phi):
+ *   FE_MASS          phi_i phi_j
+ *   FE_HELMHOLTZ     g_i . g_j + phi_i phi_j
+ *   FE_ELASTICITY    2 mu eps(v):eps(u) + lambda div v div u, lambda and mu
+ *                    interpolated from their P1 DOFs at each point
+ *   FE_HYPERELASTIC  tangent of the compressible neo-Hookean first Piola
+ *                    stress P = mu (F - F^{-T}) + lambda ln(det F) F^{-T},
+ *                    F = I + grad u, with constants mu, lambda from the options
+ *
+ * Errors: every entry point returns FE_OK (0) or a negative FE_E* code and
+ * never aborts.  fe_strerror() describes a code; after FE_EHIP it also holds
+ * the HIP runtime message of the failing call.
+ *
+ * Threading: entry points may be called from several host threads on
+ * different streams; library caches are guarded by a mutex.
+ */
+#ifndef FELOCAL_H
+#define FELOCAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { FE_TRIANGLE = 0, FE_TETRAHEDRON = 1, FE_PRISM = 2 } fe_cell_t;
+typedef enum { FE_MASS = 0, FE_HELMHOLTZ = 1, FE_ELASTICITY = 2, FE_HYPERELASTIC = 3 } fe_form_t;
+
+/* Arithmetic of the element contraction.  Geometry (J, det J, J^{-1}) and the
+ * per-point kinematics always run in float64.
+ *   FE_FP64          float64 everywhere (all forms)
+ *   FE_SPLIT_FP32    contraction on MFMA with float32 operands and float32
+ *                    accumulation, final combination in float64
+ *   FE_SPLIT_BF16X3  contraction on MFMA with each operand split into a
+ *                    bf16 high and low part (three products hi*hi + hi*lo +
+ *                    lo*hi), float32 accumulation, float64 combination
+ * The split precisions apply to FE_ELASTICITY and FE_HYPERELASTIC when the
+ * element matrix fits one 32x32 tile (gdim*n_s <= 32) and the rule has at most
+ * 32 points; otherwise FE_ENOTSUP.  Stated error bounds (normwise per element,
+ * max|A - A_exact| / max|A_exact|): FE_SPLIT_BF16X3 <= 1e-4,
+ * FE_SPLIT_FP32 <= 2e-6; FE_FP64 agrees with the float64 oracle to 1e-12. */
+typedef enum { FE_FP64 = 0, FE_SPLIT_FP32 = 1, FE_SPLIT_BF16X3 = 2 } fe_precision_t;
+
+/* Contraction mode (Sec. 4.1, Algorithm 3 chooses it when FE_MODE_AUTO). */
+typedef enum {
+    FE_MODE_AUTO = 0,      /* planner decides from theta and T_H           */
+    FE_MODE_PREEVAL = 1,   /* pre-evaluated reference tensors (Alg. 2)     */
+    FE_MODE_QUADRATURE = 2 /* sharing-eliminated quadrature (Alg. 1)       */
+} fe_mode_t;
+
+enum {
+    FE_OK = 0,
+    FE_EINVAL = -1,     /* invalid argument (NULL pointer, degree, size ...)  */
+    FE_ENOTSUP = -2,    /* valid but unsupported combination               */
+    FE_EHIP = -3,       /* HIP runtime error; see fe_strerror              */
+    FE_ENONAFFINE = -4, /* a prism is not affine (host-side validation)    */
+    FE_ENOMEM = -5      /* allocation failed, or a size limit exceeded     */
+};
+
+typedef struct {
+    int            qdeg;       /* -1: form default (mass, Helmholtz 2p;
+                                  elasticity 2p-1, prisms 2p+1; hyperelastic 4);
+                                  else the exact degree of the rule          */
+    fe_precision_t precision;  /* FE_FP64 by default                        */
+    fe_mode_t      mode;       /* FE_MODE_AUTO by default                   */
+    void*          stream;     /* hipStream_t; NULL = the null stream       */
+    double         mu, lambda; /* hyperelastic constants (default 1, 10)    */
+    int*           d_status;   /* optional device int32: atomically
+                                  incremented once per flagged element
+                                  (degenerate map, non-affine prism, or
+                                  det F <= 0 at a point); the element's block
+                                  is filled with NaN.  NULL = not counted.    */
+    size_t         th_bytes;   /* T_H (Constraint 2); 0 = LDS capacity of one
+                                  compute unit (160 KiB on gfx950)          */
+    int            validate;   /* nonzero: synchronously copy coords to the
+                                  host and reject non-affine prisms with
+                                  FE_ENONAFFINE before launching            */
+} fe_options_t;
+
+/* Fills *opt with the defaults listed above. */
+void fe_options_init(fe_options_t* opt);
+
+/* Reference tabulation (Sec. 2.2: the local basis Phi_i on the reference cell
+ * K_0 and the quadrature rule; Sec. 7.1: exact Gauss-Legendre-Jacobi rule).
+ * Rules are collapsed conical products (Gauss-Legendre x Gauss-Jacobi with
+ * weights (1-t), (1-u)^2) with m = ceil((qdeg+1)/2) points per direction,
+ * exact to total degree 2m-1; triangles with qdeg <= 2 use the three-point
+ * interior rule (1/6,1/6), (2/3,1/6), (1/6,2/3); prisms use the triangle
+ * rule times m-point Gauss-Legendre in Z.
+ * All arrays are HOST pointers owned by the caller.  With points == NULL the
+ * call only fills info = {nq, nb, tdim}.  Otherwise points [nq][tdim],
+ * weights [nq], phi [nq][nb] and dphi [nq][nb][tdim] must all be non-NULL.
+ * The basis values are computed by a HIP kernel; the call is synchronous.
+ * Errors: FE_EINVAL (degree not in 1..4, qdeg not in 0..20, info NULL),
+ * FE_EHIP. */
+int fe_tabulate(fe_cell_t cell, int degree, int qdeg,
+                double* points, double* weights, double* phi, double* dphi,
+                int* info);
+
+/* n (rows of the element matrix) and the number of coefficient DOFs per
+ * element for (form, cell, degree).  Host pointers; either may be NULL.
+ * Errors: FE_EINVAL. */
+int fe_local_dims(fe_form_t form, fe_cell_t cell, int degree, int* n_rows, int* n_coeff);
+
+/* Local assembly (Sec. 2: element tensor A^K of Eq. (7); evaluated in the
+ * mode chosen by Algorithm 3, Sec. 4.1).  coords, coeff_dofs and out_A are
+ * DEVICE pointers owned by the caller, in the layouts above; out_A must not
+ * alias the inputs.  The call is asynchronous on opt->stream (reference
+ * tables are built on first use of a (cell, degree, qdeg) and cached).
+ * n_elems = 0 returns FE_OK without work.  opt = NULL uses the defaults.
+ * Errors (returned synchronously, nothing launched): FE_EINVAL for NULL
+ * pointers with n_elems > 0, n_elems < 0, degree not in 1..4, bad enums or
+ * qdeg; FE_ENOTSUP for an unsupported precision/form/size combination;
+ * FE_ENONAFFINE (opt->validate only); FE_ENOMEM; FE_EHIP for launch
+ * failures.  Flagged elements are reported through opt->d_status. */
+int fe_assemble_local(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems,
+                      const double* coords, const double* coeff_dofs, double* out_A,
+                      const fe_options_t* opt);
+
+/* Geometry of the affine maps (Sec. 2.2, Eq. (7): dX/dx and det F_K').
+ * DEVICE pointers: coords [E][nv][gdim] in; out_detJ [E] (signed det J) and
+ * out_Kinv [E][gdim][gdim] (Kinv[a][b] = dX_a/dx_b) out.  Asynchronous on
+ * stream.  Errors: FE_EINVAL, FE_EHIP. */
+int fe_geometry(fe_cell_t cell, int64_t n_elems, const double* coords,
+                double* out_detJ, double* out_Kinv, void* stream);
+
+/* Plan of the transformation algorithm (Sec. 4.1, Algorithm 3) with the cost
+ * function theta = theta_pre - theta_se (Sec. 4.2; increase factor iota and
+ * term count rho) for one form.  Host-only; no GPU needed. */
+typedef struct {
+    int    n_monomials;        /* monomials of the form (Sec. 2.1)           */
+    int    preevaluated[4];    /* 1 if monomial m is pre-evaluated            */
+    double theta_se[4];        /* operation count of monomial m after sharing
+                                  elimination, per element                   */
+    double theta_pre[4];       /* operation count after pre-evaluation, per
+                                  element (infinite when illegal)            */
+    int    iota[4], rho[4];    /* increase factor and pre-evaluable terms    */
+    size_t table_bytes[4];     /* bytes of the tables of monomial m          */
+    size_t th_bytes;           /* the T_H used                               */
+    double cost;               /* D[b] of the chosen bipartition             */
+    fe_mode_t mode;            /* FE_MODE_PREEVAL if every monomial is
+                                  pre-evaluated, else FE_MODE_QUADRATURE     */
+} fe_plan_t;
+
+/* qdeg = -1 for the form default; th_bytes = 0 for the LDS capacity of one
+ * compute unit (160 KiB when no device is present).  A plan may pre-evaluate
+ * only some monomials (Fig. 5): mode is then FE_MODE_QUADRATURE and the
+ * quadrature kernel adds the pre-evaluated monomials' tables.
+ * Errors: FE_EINVAL. */
+int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int qdeg, size_t th_bytes,
+            fe_plan_t* plan);
+
+/* Mixed batches: several (form, cell, degree) sub-batches executed by one
+ * persistent kernel that takes element tiles from a device work queue, the
+ * whole launch captured once in a HIP graph and replayed by fe_batch_run.
+ * All sub-batch pointers are DEVICE pointers owned by the caller and must
+ * stay valid until fe_batch_destroy.  Every sub-batch uses FE_FP64 and the
+ * mode Algorithm 3 chooses for it; tile sizes come from the autotune cache
+ * (fe_autotune) when present, else from built-in defaults.
+ * Errors: FE_EINVAL, FE_ENOTSUP, FE_ENOMEM, FE_EHIP. */
+typedef struct fe_subbatch {
+    fe_form_t     form;
+    fe_cell_t     cell;
+    int           degree;
+    int           qdeg;        /* -1 = form default */
+    int64_t       n_elems;
+    const double* coords;
+    const double* coeff_dofs;
+    double*       out_A;
+} fe_subbatch_t;
+
+typedef struct fe_batch fe_batch_t;
+
+int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* opt,
+                    fe_batch_t** batch);
+int fe_batch_run(fe_batch_t* batch, void* stream);
+int fe_batch_destroy(fe_batch_t* batch);
+/* Number of work tiles and the persistent grid size of a batch. */
+int fe_batch_info(const fe_batch_t* batch, int64_t* n_tiles, int* grid);
+
+/* Autotuner: times the candidate tile shapes of the variant that serves
+ * (form, cell, degree) on the given DEVICE inputs (n_elems >= 1) and stores
+ * the fastest in the in-memory cache (and in the JSON file named by the
+ * environment variable FE_AUTOTUNE_CACHE, if set).  Synchronous.  *best_ms
+ * (may be NULL) receives the best time per launch.
+ * Errors: FE_EINVAL, FE_ENOTSUP, FE_EHIP. */
+int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems,
+                const double* coords, const double* coeff_dofs, double* out_A,
+                const fe_options_t* opt, double* best_ms);
+
+/* Human-readable text for an FE_* code. */
+const char* fe_strerror(int code);
+
+/* Frees the reference-table and autotune caches (device memory included). */
+void fe_release_caches(void);
+
+/* Library version string. */
+const char* fe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FELOCAL_H */

@@ -1,0 +1,199 @@
+// Tile-shape autotuner and configuration cache.
+//
+// A variant is (form, cell, degree, rule, mode, precision).  Its tunable
+// shape is, for the pre-evaluated kernel, the block size, the elements per
+// step and per tile; for the quadrature kernel, the elements per tile and the
+// points per LDS chunk; for every kernel, the resident blocks per CU of the
+// persistent grid.  fe_autotune times each candidate with HIP events on the
+// caller's inputs and keeps the fastest in memory (and, when the environment
+// variable FE_AUTOTUNE_CACHE names a file, appends it there as one JSON object
+// per line; the file is read back on first use, so tuning persists).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "felocal.h"
+#include "internal.hpp"
+
+namespace fe {
+
+namespace {
+
+using Key = std::tuple<int, int, int, int, int, int>;
+std::mutex g_tmu;
+std::map<Key, Config> g_tuned;
+bool g_loaded = false;
+
+Key key_of(const Call& c) { return Key(c.form, c.cell, c.degree, c.qdeg, c.mode, c.prec); }
+
+void load_file_locked()
+{
+    if (g_loaded) return;
+    g_loaded = true;
+    const char* path = std::getenv("FE_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        int v[6];
+        Config c;
+        if (std::sscanf(line,
+                        "{\"form\": %d, \"cell\": %d, \"degree\": %d, \"qdeg\": %d, \"mode\": %d, \"precision\": %d, "
+                        "\"block\": %d, \"epi\": %d, \"chunk\": %d, \"eb\": %d, \"qc\": %d, \"grid_per_cu\": %d",
+                        &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &c.block, &c.epi, &c.chunk, &c.eb, &c.qc,
+                        &c.grid_per_cu) == 12)
+            g_tuned[Key(v[0], v[1], v[2], v[3], v[4], v[5])] = c;
+    }
+    std::fclose(f);
+}
+
+Config default_for(const Call& c)
+{
+    if (c.prec != FE_FP64) return Config();
+    if (c.mode == FE_MODE_PREEVAL) return default_preeval_config(c.tables->nb * c.tables->nb, preeval_mm(c.form));
+    return default_quad_config(c.form, c.cell, c.degree, c.tables->nq);
+}
+
+std::vector<Config> candidates(const Call& c)
+{
+    std::vector<Config> out;
+    const Config base = default_for(c);
+    if (c.prec != FE_FP64) {
+        for (int g : {4, 8, 16}) {
+            Config x = base;
+            x.grid_per_cu = g;
+            out.push_back(x);
+        }
+        return out;
+    }
+    if (c.mode == FE_MODE_PREEVAL) {
+        const int nn = c.tables->nb * c.tables->nb, mm = preeval_mm(c.form);
+        for (int block : {256, 320, 384, 512}) {
+            for (int epi : {1, 2, 4, 8, 16, 32, 64}) {
+                const int m = (epi * nn + block - 1) / block;
+                if (m > 2 * mm || (epi > 1 && epi * nn > 8 * block * mm)) continue;
+                const double waste = 1.0 - (double)(epi * nn) / (m * block);
+                if (waste > 0.2) continue;
+                for (int per : {1, 2}) {
+                    Config x;
+                    x.block = block;
+                    x.epi = epi;
+                    x.chunk = epi * std::max(1, per * 256 / epi);
+                    for (int g : {4, 8}) {
+                        x.grid_per_cu = g;
+                        out.push_back(x);
+                    }
+                }
+            }
+        }
+        if (out.empty()) out.push_back(base);
+        return out;
+    }
+    for (int div : {1, 2, 4}) {
+        for (int g : {4, 8}) {
+            Config x = base;
+            x.eb = std::max(1, base.eb / div);
+            const int D = cell_dim(c.cell), ns = c.tables->nb;
+            const int ppt = ns * D + (c.form == HYPERELASTIC ? ns * D + 9 : 0) + 3;
+            const size_t per_q = ((size_t)ns + (size_t)x.eb * ppt) * 8;
+            x.qc = std::max(1, std::min(c.tables->nq, (int)((QUAD_LDS_BUDGET - x.eb * 96) / per_q)));
+            x.grid_per_cu = g;
+            out.push_back(x);
+        }
+    }
+    return out;
+}
+
+}  // namespace
+
+void lookup_config(const Call& c, Config* cfg)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        load_file_locked();
+        auto it = g_tuned.find(key_of(c));
+        if (it != g_tuned.end()) {
+            *cfg = it->second;
+            return;
+        }
+    }
+    *cfg = default_for(c);
+}
+
+int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
+                 const double* coeff_dofs, double* out_A, const fe_options_t* opt, Call* c);
+
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
+                           const double* coeff_dofs, double* out_A, const fe_options_t* opt, double* best_ms)
+{
+    if (n_elems < 1) return FE_EINVAL;
+    Call c;
+    int rc = resolve_call(form, cell, degree, n_elems, coords, coeff_dofs, out_A, opt, &c);
+    if (rc) return rc;
+    std::vector<Config> cands = candidates(c);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return set_hip_error(hipErrorUnknown, "autotune events");
+    double best = 1e30;
+    Config best_cfg = cands[0];
+    for (const Config& x : cands) {
+        rc = launch_call(c, x);   // warm-up
+        if (rc) break;
+        hipError_t e = hipEventRecord(e0, c.stream);
+        for (int r = 0; r < 3 && e == hipSuccess && rc == FE_OK; ++r) rc = launch_call(c, x);
+        if (e == hipSuccess) e = hipEventRecord(e1, c.stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = set_hip_error(e, "autotune timing");
+            break;
+        }
+        if (rc) break;
+        if (ms / 3.0 < best) {
+            best = ms / 3.0;
+            best_cfg = x;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        load_file_locked();
+        g_tuned[key_of(c)] = best_cfg;
+        const char* path = std::getenv("FE_AUTOTUNE_CACHE");
+        if (path) {
+            FILE* f = std::fopen(path, "a");
+            if (f) {
+                std::fprintf(f,
+                             "{\"form\": %d, \"cell\": %d, \"degree\": %d, \"qdeg\": %d, \"mode\": %d, "
+                             "\"precision\": %d, \"block\": %d, \"epi\": %d, \"chunk\": %d, \"eb\": %d, \"qc\": %d, "
+                             "\"grid_per_cu\": %d, \"ms\": %.6f}\n",
+                             c.form, c.cell, c.degree, c.qdeg, c.mode, c.prec, best_cfg.block, best_cfg.epi,
+                             best_cfg.chunk, best_cfg.eb, best_cfg.qc, best_cfg.grid_per_cu, best);
+                std::fclose(f);
+            }
+        }
+    }
+    if (best_ms) *best_ms = best;
+    return FE_OK;
+}
+
+extern "C" void fe_autotune_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_tuned.clear();
+}

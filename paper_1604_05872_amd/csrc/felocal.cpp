@@ -1,0 +1,462 @@
+// C ABI of the local-assembly library (include/felocal.h): argument
+// validation, reference-table cache, variant selection and launches.
+#include "felocal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.hpp"
+#include "preeval.hpp"
+#include "quad.hpp"
+#include "split.hpp"
+
+namespace fe {
+
+namespace {
+
+std::mutex g_mu;
+thread_local std::string g_hip_msg = "no HIP error recorded";
+std::map<std::tuple<int, int, int, int>, RefTables*> g_tables;   // (device, cell, p, qdeg)
+
+int current_device()
+{
+    int d = 0;
+    (void)hipGetDevice(&d);
+    return d;
+}
+
+}  // namespace
+
+int set_hip_error(hipError_t e, const char* where)
+{
+    g_hip_msg = std::string(where) + ": " + hipGetErrorString(e);
+    return FE_EHIP;
+}
+
+int device_cus()
+{
+    static int cus[64] = {0};
+    int d = current_device();
+    if (d < 0 || d >= 64) return 256;
+    if (cus[d] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess || v <= 0) v = 256;
+        cus[d] = v;
+    }
+    return cus[d];
+}
+
+// LDS capacity of one compute unit: the default memory threshold T_H
+// (160 KiB on gfx950 when the runtime does not report it).
+size_t device_lds_per_cu()
+{
+    static size_t lds[64] = {0};
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return 160 * 1024;
+    if (lds[d] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, d) != hipSuccess || v <= 0)
+            v = 160 * 1024;
+        lds[d] = (size_t)v;
+    }
+    return lds[d];
+}
+
+// Builds (once) the rule, the tabulated basis, the P1 coefficient basis and
+// the pre-evaluated tensors of (cell, p, qdeg) on the current device.
+int get_tables(int cell, int p, int qdeg, hipStream_t s, const RefTables** out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_tuple(current_device(), cell, p, qdeg);
+    auto it = g_tables.find(key);
+    if (it != g_tables.end()) {
+        *out = it->second;
+        return FE_OK;
+    }
+    RefTables* t = new RefTables();
+    t->cell = cell;
+    t->p = p;
+    t->qdeg = qdeg;
+    t->d = cell_dim(cell);
+    t->nv = cell_nv(cell);
+    t->nb = n_scalar(cell, p);
+    t->nq = build_rule(cell, qdeg, t->X, t->W);
+    if (t->nq <= 0) {
+        delete t;
+        return FE_EINVAL;
+    }
+    const int nq = t->nq, nb = t->nb, d = t->d;
+    const int nt = n_tables(HELMHOLTZ, cell);
+    hipError_t e = hipSuccess;
+    auto M = [&](double** p_, size_t n) {
+        if (e == hipSuccess) e = hipMalloc((void**)p_, n * sizeof(double));
+    };
+    M(&t->dX, (size_t)nq * d);
+    M(&t->dW, nq);
+    M(&t->dphi, (size_t)nq * nb);
+    M(&t->ddphi, (size_t)nq * nb * d);
+    M(&t->dpsi, (size_t)nq * t->nv);
+    M(&t->dR, (size_t)nt * nb * nb);
+    double* tmp = nullptr;
+    M(&tmp, (size_t)nq * t->nv * d);
+    if (e == hipSuccess) e = hipMemcpyAsync(t->dX, t->X.data(), sizeof(double) * nq * d, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(t->dW, t->W.data(), sizeof(double) * nq, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_tabulate(cell, p, nq, t->dX, t->dphi, t->ddphi, s);
+    if (e == hipSuccess) e = launch_tabulate(cell, 1, nq, t->dX, t->dpsi, tmp, s);
+    if (e == hipSuccess) e = launch_preeval_tables(nq, nb, d, t->dW, t->dphi, t->ddphi, t->dR, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) {
+        for (double* p_ : {t->dX, t->dW, t->dphi, t->ddphi, t->dpsi, t->dR})
+            if (p_) (void)hipFree(p_);
+        delete t;
+        return set_hip_error(e, "building reference tables");
+    }
+    g_tables[key] = t;
+    *out = t;
+    return FE_OK;
+}
+
+Config default_preeval_config(int nn, int mm)
+{
+    // choose (block, epi) with the least idle slots, one pass when possible
+    Config best;
+    double best_waste = 1e9;
+    for (int block : {256, 320, 384, 448, 512}) {
+        for (int epi = 1; epi <= 64; ++epi) {
+            const int slots = epi * nn;
+            const int m = (slots + block - 1) / block;
+            if (m > mm && epi > 1) break;
+            const int passes = (m + mm - 1) / mm;
+            const double waste = (double)(passes * mm * block - slots) / (passes * mm * block) * 0.25 +
+                                 (double)(m * block - slots) / (m * block) + (epi * nn < 512 ? 0.5 : 0.0) +
+                                 0.01 * passes;
+            if (waste < best_waste - 1e-9) {
+                best_waste = waste;
+                best.block = block;
+                best.epi = epi;
+            }
+        }
+    }
+    best.chunk = best.epi * std::max(1, 256 / best.epi);
+    return best;
+}
+
+Config default_quad_config(int form, int cell, int p, int nq)
+{
+    Config c;
+    c.block = QUAD_BLOCK;
+    const int ns = n_scalar(cell, p);
+    const int kb = quad_kb(cell, p);
+    const int units = ns * ((ns + kb - 1) / kb);
+    c.eb = std::max(1, QUAD_BLOCK / units);
+    const int D = cell_dim(cell);
+    const int ppt = ns * D + (form == HYPERELASTIC ? ns * D + 9 : 0) + 3;
+    const size_t fixed = (size_t)c.eb * 12 * 8;
+    const size_t per_q = ((size_t)ns + (size_t)c.eb * ppt) * 8;
+    int qc = (int)((QUAD_LDS_BUDGET - fixed) / per_q);
+    c.qc = std::max(1, std::min(nq, qc));
+    return c;
+}
+
+size_t quad_lds_bytes(int form, int cell, int ns, int eb, int qc)
+{
+    const int D = cell_dim(cell);
+    const int ppt = ns * D + (form == HYPERELASTIC ? ns * D + 9 : 0) + 3;
+    return ((size_t)eb * 12 + (size_t)qc * ns + (size_t)eb * qc * ppt) * 8;
+}
+
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" {
+
+void fe_options_init(fe_options_t* opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->qdeg = -1;
+    opt->precision = FE_FP64;
+    opt->mode = FE_MODE_AUTO;
+    opt->stream = nullptr;
+    opt->mu = 1.0;
+    opt->lambda = 10.0;
+    opt->d_status = nullptr;
+    opt->th_bytes = 0;
+    opt->validate = 0;
+}
+
+const char* fe_version(void) { return "felocal 0.1 (gfx950)"; }
+
+const char* fe_strerror(int code)
+{
+    switch (code) {
+    case FE_OK: return "success";
+    case FE_EINVAL: return "invalid argument";
+    case FE_ENOTSUP: return "unsupported combination of form, cell, degree, precision or size";
+    case FE_EHIP: return g_hip_msg.c_str();
+    case FE_ENONAFFINE: return "a prism element is not affine";
+    case FE_ENOMEM: return "out of memory or size limit exceeded";
+    default: return "unknown error code";
+    }
+}
+
+int fe_local_dims(fe_form_t form, fe_cell_t cell, int degree, int* n_rows_out, int* n_coeff)
+{
+    if ((int)form < 0 || (int)form > 3 || (int)cell < 0 || (int)cell > 2 || degree < 1 || degree > MAX_DEGREE)
+        return FE_EINVAL;
+    if (n_rows_out) *n_rows_out = n_rows(form, cell, degree);
+    if (n_coeff) {
+        const int nv = cell_nv(cell);
+        *n_coeff = form == ELASTICITY ? 2 * nv : form == HYPERELASTIC ? cell_dim(cell) * n_scalar(cell, degree) : 0;
+    }
+    return FE_OK;
+}
+
+int fe_tabulate(fe_cell_t cell, int degree, int qdeg, double* points, double* weights, double* phi, double* dphi,
+                int* info)
+{
+    if (!info || (int)cell < 0 || (int)cell > 2 || degree < 1 || degree > MAX_DEGREE || qdeg < 0 || qdeg > MAX_QDEG)
+        return FE_EINVAL;
+    std::vector<double> X, W;
+    const int nq = build_rule(cell, qdeg, X, W);
+    if (nq <= 0) return FE_EINVAL;
+    const int nb = n_scalar(cell, degree), d = cell_dim(cell);
+    info[0] = nq;
+    info[1] = nb;
+    info[2] = d;
+    if (!points) return FE_OK;
+    if (!weights) return FE_EINVAL;
+    std::memcpy(points, X.data(), sizeof(double) * nq * d);
+    std::memcpy(weights, W.data(), sizeof(double) * nq);
+    if (!phi && !dphi) return FE_OK;   // rule only: host-side, no device needed
+    if (!phi || !dphi) return FE_EINVAL;
+    const RefTables* t = nullptr;
+    int rc = get_tables(cell, degree, qdeg, nullptr, &t);
+    if (rc) return rc;
+    hipError_t e = hipMemcpy(phi, t->dphi, sizeof(double) * nq * nb, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(dphi, t->ddphi, sizeof(double) * nq * nb * d, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return set_hip_error(e, "fe_tabulate copy");
+    return FE_OK;
+}
+
+int fe_geometry(fe_cell_t cell, int64_t n_elems, const double* coords, double* out_detJ, double* out_Kinv,
+                void* stream)
+{
+    if ((int)cell < 0 || (int)cell > 2 || n_elems < 0) return FE_EINVAL;
+    if (n_elems == 0) return FE_OK;
+    if (!coords || !out_detJ || !out_Kinv) return FE_EINVAL;
+    hipError_t e = launch_geometry(cell, n_elems, coords, out_detJ, out_Kinv, (hipStream_t)stream);
+    if (e != hipSuccess) return set_hip_error(e, "fe_geometry launch");
+    return FE_OK;
+}
+
+}  // extern "C"
+
+// host-side affinity check of prisms (opt->validate)
+static int validate_prisms(int64_t E, const double* d_coords, hipStream_t s)
+{
+    std::vector<double> h((size_t)E * 18);
+    hipError_t e = hipMemcpyAsync(h.data(), d_coords, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_hip_error(e, "validate copy");
+    for (int64_t i = 0; i < E; ++i) {
+        const double* v = &h[(size_t)i * 18];
+        double vmax = 0.0;
+        for (int k = 0; k < 18; ++k) vmax = std::fmax(vmax, std::fabs(v[k]));
+        const double tol = 1e-12 * (vmax > 0 ? vmax : 1.0);
+        for (int t = 1; t < 3; ++t)
+            for (int r = 0; r < 3; ++r)
+                if (!(std::fabs((v[(t + 3) * 3 + r] - v[t * 3 + r]) - (v[9 + r] - v[r])) <= tol))
+                    return FE_ENONAFFINE;
+    }
+    return FE_OK;
+}
+
+extern "C" {
+
+// Resolves the variant of one call: mode (Algorithm 3) and kernel family.
+// *mass_pre is set for a Helmholtz plan that pre-evaluates only the mass
+// monomial (the quadrature kernel then adds |det J| Mhat).
+int fe_resolve_variant(int form, int cell, int degree, int qdeg, const fe_options_t* o, int* mode_out,
+                       int* mass_pre)
+{
+    *mass_pre = 0;   // bit 0: mass monomial pre-evaluated; bit 1: gradient monomial pre-evaluated
+    if (o->precision != FE_FP64) {
+        if (!is_vector_form(form)) return FE_ENOTSUP;
+        if (o->mode == FE_MODE_PREEVAL) return FE_ENOTSUP;
+        const int n = n_rows(form, cell, degree);
+        if (n > 32 || rule_size(cell, qdeg) > 32) return FE_ENOTSUP;
+        *mode_out = FE_MODE_QUADRATURE;
+        return FE_OK;
+    }
+    if (o->mode == FE_MODE_PREEVAL) {
+        if (is_vector_form(form)) return FE_ENOTSUP;
+        *mode_out = FE_MODE_PREEVAL;
+        return FE_OK;
+    }
+    if (o->mode == FE_MODE_QUADRATURE) {
+        *mode_out = FE_MODE_QUADRATURE;
+        return FE_OK;
+    }
+    fe_plan_t plan;
+    int rc = fe_plan((fe_form_t)form, (fe_cell_t)cell, degree, qdeg, o->th_bytes, &plan);
+    if (rc) return rc;
+    *mode_out = plan.mode;
+    if (form == HELMHOLTZ && plan.mode == FE_MODE_QUADRATURE)
+        *mass_pre = (plan.preevaluated[1] ? 1 : 0) | (plan.preevaluated[0] ? 2 : 0);
+    return FE_OK;
+}
+
+}  // extern "C"
+
+namespace fe {
+
+// Launches one resolved call with an explicit configuration.
+int launch_call(const Call& c, const Config& cfg)
+{
+    const RefTables* t = c.tables;
+    const int cus = device_cus();
+    hipError_t e;
+    if (c.prec != FE_FP64) {
+        SplitArgs a;
+        a.coords = c.coords;
+        a.coeff = c.coeff;
+        a.out = c.out;
+        a.status = c.status;
+        a.W = t->dW;
+        a.dphi = t->ddphi;
+        a.psi = t->dpsi;
+        a.E = c.E;
+        a.nq = t->nq;
+        a.ns = t->nb;
+        a.mu = c.mu;
+        a.lam = c.lam;
+        const int nkb = t->nq <= 8 ? 1 : t->nq <= 16 ? 2 : 4;
+        const int64_t steps = (c.E + SPLIT_WAVES - 1) / SPLIT_WAVES;
+        const int grid = (int)std::min<int64_t>(steps, (int64_t)cus * cfg.grid_per_cu);
+        const size_t lds = (c.cell == TRI ? split_lds_bytes<ELASTICITY, TRI>(t->nq, t->nb)
+                                          : split_lds_bytes<ELASTICITY, TET>(t->nq, t->nb));
+        e = launch_split(c.form, c.cell, c.prec == FE_SPLIT_FP32 ? SPLIT_FP32 : SPLIT_BF16X3, nkb, a, grid, lds,
+                         c.stream);
+        if (e != hipSuccess) return set_hip_error(e, "split-precision launch");
+        return FE_OK;
+    }
+    if (c.mode == FE_MODE_PREEVAL) {
+        PreevalArgs a;
+        a.coords = c.coords;
+        a.tables = t->dR;
+        a.out = c.out;
+        a.status = c.status;
+        a.E = c.E;
+        a.nn = t->nb * t->nb;
+        a.epi = cfg.epi;
+        a.chunk = cfg.chunk;
+        const int64_t tiles = (c.E + a.chunk - 1) / a.chunk;
+        const int grid = (int)std::min<int64_t>(tiles, (int64_t)cus * cfg.grid_per_cu);
+        e = launch_preeval(c.form, c.cell, a, cfg.block, grid, c.stream);
+        if (e != hipSuccess) return set_hip_error(e, "pre-evaluated launch");
+        return FE_OK;
+    }
+    QuadArgs a;
+    a.coords = c.coords;
+    a.coeff = c.coeff;
+    a.out = c.out;
+    a.status = c.status;
+    a.W = t->dW;
+    a.phi = t->dphi;
+    a.dphi = t->ddphi;
+    a.psi = t->dpsi;
+    a.mass_table = (c.mass_pre & 1) ? t->dR : nullptr;
+    a.stiff_tables = (c.mass_pre & 2) ? t->dR : nullptr;
+    a.E = c.E;
+    a.nq = t->nq;
+    a.ns = t->nb;
+    a.eb = cfg.eb;
+    a.qc = cfg.qc;
+    a.mu = c.mu;
+    a.lam = c.lam;
+    const int64_t tiles = (c.E + a.eb - 1) / a.eb;
+    const int grid = (int)std::min<int64_t>(tiles, (int64_t)cus * cfg.grid_per_cu);
+    const size_t lds = quad_lds_bytes(c.form, c.cell, t->nb, a.eb, a.qc);
+    e = launch_quad(c.form, c.cell, quad_kb(c.cell, c.degree), a, grid, lds, c.stream);
+    if (e != hipSuccess) return set_hip_error(e, "quadrature launch");
+    return FE_OK;
+}
+
+// Validates the arguments of fe_assemble_local and resolves them into a Call.
+int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
+                 const double* coeff_dofs, double* out_A, const fe_options_t* opt, Call* c)
+{
+    fe_options_t o;
+    if (opt) o = *opt;
+    else fe_options_init(&o);
+    if ((int)form < 0 || (int)form > 3 || (int)cell < 0 || (int)cell > 2 || degree < 1 || degree > MAX_DEGREE ||
+        n_elems < 0)
+        return FE_EINVAL;
+    if ((int)o.precision < 0 || (int)o.precision > 2 || (int)o.mode < 0 || (int)o.mode > 2) return FE_EINVAL;
+    const int qdeg = o.qdeg < 0 ? default_qdeg(form, cell, degree) : o.qdeg;
+    if (qdeg > MAX_QDEG) return FE_EINVAL;
+    c->form = form;
+    c->cell = cell;
+    c->degree = degree;
+    c->qdeg = qdeg;
+    c->E = n_elems;
+    c->prec = o.precision;
+    c->coords = coords;
+    c->coeff = coeff_dofs;
+    c->out = out_A;
+    c->status = o.d_status;
+    c->mu = o.mu;
+    c->lam = o.lambda;
+    c->stream = (hipStream_t)o.stream;
+    if (n_elems == 0) return FE_OK;
+    if (!coords || !out_A) return FE_EINVAL;
+    if (is_vector_form(form) && !coeff_dofs) return FE_EINVAL;
+    if (form == HYPERELASTIC && !(std::isfinite(o.mu) && std::isfinite(o.lambda))) return FE_EINVAL;
+    int rc = fe_resolve_variant(form, cell, degree, qdeg, &o, &c->mode, &c->mass_pre);
+    if (rc) return rc;
+    if (o.validate && cell == PRISM) {
+        rc = validate_prisms(n_elems, coords, c->stream);
+        if (rc) return rc;
+    }
+    return get_tables(cell, degree, qdeg, c->stream, &c->tables);
+}
+
+}  // namespace fe
+
+extern "C" {
+
+int fe_assemble_local(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
+                      const double* coeff_dofs, double* out_A, const fe_options_t* opt)
+{
+    Call c;
+    int rc = resolve_call(form, cell, degree, n_elems, coords, coeff_dofs, out_A, opt, &c);
+    if (rc || n_elems == 0) return rc;
+    Config cfg;
+    lookup_config(c, &cfg);
+    return launch_call(c, cfg);
+}
+
+void fe_release_caches(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto& kv : g_tables) {
+        RefTables* t = kv.second;
+        for (double* p_ : {t->dX, t->dW, t->dphi, t->ddphi, t->dpsi, t->dR})
+            if (p_) (void)hipFree(p_);
+        delete t;
+    }
+    g_tables.clear();
+}
+
+}  // extern "C"

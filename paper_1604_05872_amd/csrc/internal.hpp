@@ -1,0 +1,107 @@
+// Internal host-side interfaces of the local-assembly library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "fe_common.hpp"
+
+namespace fe {
+
+struct PreevalArgs;
+struct QuadArgs;
+struct SplitArgs;
+
+// quadrature.cpp
+int build_rule(int cell, int qdeg, std::vector<double>& X, std::vector<double>& W);
+
+// tabulate.hip
+hipError_t launch_tabulate(int cell, int p, int nq, const double* X, double* phi, double* dphi, hipStream_t s);
+hipError_t launch_preeval_tables(int nq, int nb, int d, const double* W, const double* phi, const double* dphi,
+                                 double* R, hipStream_t s);
+hipError_t launch_geometry(int cell, int64_t E, const double* coords, double* det, double* kinv, hipStream_t s);
+
+// assemble_*.hip
+hipError_t launch_preeval(int form, int cell, const PreevalArgs& a, int block, int grid, hipStream_t s);
+hipError_t launch_quad_mass(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t launch_quad_helmholtz(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t launch_quad_elasticity(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t launch_quad_hyperelastic(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
+inline hipError_t launch_quad(int form, int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s)
+{
+    switch (form) {
+    case MASS: return launch_quad_mass(cell, kb, a, grid, lds, s);
+    case HELMHOLTZ: return launch_quad_helmholtz(cell, kb, a, grid, lds, s);
+    case ELASTICITY: return launch_quad_elasticity(cell, kb, a, grid, lds, s);
+    default: return launch_quad_hyperelastic(cell, kb, a, grid, lds, s);
+    }
+}
+hipError_t launch_split(int form, int cell, int prec, int nkb, const SplitArgs& a, int grid, size_t lds,
+                        hipStream_t s);
+
+// slot tile of the pre-evaluated kernel (registers per pass) per form
+constexpr int preeval_mm(int form) { return form == MASS ? 16 : 8; }
+// k-block width of the quadrature kernel
+constexpr int quad_kb(int cell, int p)
+{
+    return cell == TET ? (p == 1 ? 4 : 5) : (p <= 2 ? 3 : 5);
+}
+constexpr int QUAD_BLOCK = 256;
+constexpr int SPLIT_BLOCK = 256;
+constexpr size_t QUAD_LDS_BUDGET = 48 * 1024;
+
+// Reference tables of one (cell, degree, rule), device resident.
+struct RefTables {
+    int cell = 0, p = 0, qdeg = 0, nq = 0, nb = 0, d = 0, nv = 0;
+    std::vector<double> X, W;          // host copy of the rule
+    double* dX = nullptr;              // [nq][d]
+    double* dW = nullptr;              // [nq]
+    double* dphi = nullptr;            // [nq][nb]
+    double* ddphi = nullptr;           // [nq][nb][d]
+    double* dpsi = nullptr;            // [nq][nv] P1 (prism P1 x P1) basis
+    double* dR = nullptr;              // [1 + d(d+1)/2][nb][nb] pre-evaluated tensors
+};
+
+// felocal.cpp
+int get_tables(int cell, int p, int qdeg, hipStream_t s, const RefTables** out);
+int device_cus();
+size_t device_lds_per_cu();
+int set_hip_error(hipError_t e, const char* where);
+
+// Launch configuration of one variant.
+struct Config {
+    int block = 256;
+    int epi = 1;      // pre-evaluated: elements per step
+    int chunk = 256;  // pre-evaluated: elements per tile
+    int eb = 1;       // quadrature: elements per tile
+    int qc = 1;       // quadrature: points per LDS chunk
+    int grid_per_cu = 8;
+};
+
+Config default_preeval_config(int nn, int mm);
+Config default_quad_config(int form, int cell, int p, int nq);
+size_t quad_lds_bytes(int form, int cell, int ns, int eb, int qc);
+
+// One resolved assembly call.
+struct Call {
+    int form = 0, cell = 0, degree = 1, qdeg = 2;
+    int mode = 0;       // FE_MODE_PREEVAL or FE_MODE_QUADRATURE
+    int mass_pre = 0;   // Helmholtz quadrature: bit 0 mass monomial pre-evaluated,
+                        // bit 1 gradient monomial pre-evaluated
+    int prec = 0;       // fe_precision_t
+    int64_t E = 0;
+    const double* coords = nullptr;
+    const double* coeff = nullptr;
+    double* out = nullptr;
+    int* status = nullptr;
+    double mu = 1.0, lam = 10.0;
+    hipStream_t stream = nullptr;
+    const RefTables* tables = nullptr;
+};
+
+int launch_call(const Call& c, const Config& cfg);
+// configuration from the autotune cache, else the built-in default
+void lookup_config(const Call& c, Config* cfg);
+
+}  // namespace fe

@@ -1,0 +1,137 @@
+// Pre-evaluated contraction for the scalar forms (mass, Helmholtz):
+//     A_e[j][k] = sum_r c_r(e) R_r[j][k]
+// with reference tensors R_r pre-evaluated once (Sec. 3.3, Algorithm 2; the
+// tensor-contraction mode of Sec. 2.3, Eqs. (8)-(9)) and the geometry tensor
+// c(e) = (|det J|, G'_00, G'_11, ..., G'_01, ...), G' = |det J| K K^T.
+//
+// The work is bound by the store of A (a few flops per 8-byte entry), so the
+// kernel is organised around the output stream:
+//   * a workgroup owns a tile of `chunk` consecutive elements, whose output
+//     blocks are one contiguous span of chunk*n^2 doubles;
+//   * the span is walked `epi` elements at a time; thread t owns the fixed
+//     slots f = t + B*m of the epi*n^2 entries of one step, so every step
+//     stores a contiguous range with consecutive lanes on consecutive words;
+//   * because a slot always maps to the same table entry (j,k), the thread
+//     keeps R_r[j][k] for its slots in registers (MM slots per pass, more
+//     passes when n^2 is large), and only the per-element geometry tensor is
+//     read from LDS.
+// Nothing proportional to the element count is stored besides A itself
+// (Constraint 1, Sec. 3.4).
+#pragma once
+#include "device_common.hpp"
+
+namespace fe {
+
+struct PreevalArgs {
+    const double* coords;
+    const double* tables;   // [NT][nn]
+    double* out;            // [E][nn]
+    int* status;
+    int64_t E;
+    int nn;                 // n^2
+    int epi;                // elements per step
+    int chunk;              // elements per tile (multiple of epi)
+};
+
+template <int FORM, int CELL>
+constexpr int preeval_nt() { return n_tables(FORM, CELL); }
+
+// Geometry tensor of one element; returns nonzero when the element is flagged.
+template <int FORM, int CELL>
+__device__ __forceinline__ int preeval_coeffs(const double* __restrict__ coords, int64_t e, double* c)
+{
+    constexpr int D = cell_dim(CELL), NV = cell_nv(CELL);
+    double v[NV * D];
+#pragma unroll
+    for (int k = 0; k < NV * D; ++k) v[k] = coords[e * (NV * D) + k];
+    double K[3][3], adet;
+    const int bad = affine_map<CELL>(v, K, adet);
+    c[0] = adet;
+    if (FORM == HELMHOLTZ) {
+        int r = 1;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < D; ++b) s += K[a][b] * K[a][b];
+            c[r++] = adet * s;
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int a2 = a + 1; a2 < D; ++a2) {
+                double s = 0.0;
+#pragma unroll
+                for (int b = 0; b < D; ++b) s += K[a][b] * K[a2][b];
+                c[r++] = adet * s;
+            }
+    }
+    return bad;
+}
+
+// One tile of elements [e_begin, min(e_begin + chunk, E)).  sG: LDS of
+// chunk * NT doubles.  Every thread of the block must call it.
+template <int FORM, int CELL, int MM>
+__device__ void preeval_tile(const PreevalArgs& a, int64_t e_begin, double* sG)
+{
+    constexpr int NT = preeval_nt<FORM, CELL>();
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int64_t rem = a.E - e_begin;
+    const int ne = rem < a.chunk ? (int)rem : a.chunk;
+
+    for (int i = tid; i < ne; i += B) {
+        double c[NT];
+        const int bad = preeval_coeffs<FORM, CELL>(a.coords, e_begin + i, c);
+        if (bad) {
+#pragma unroll
+            for (int r = 0; r < NT; ++r) c[r] = __builtin_nan("");
+            if (a.status) atomicAdd(a.status, 1);
+        }
+#pragma unroll
+        for (int r = 0; r < NT; ++r) sG[i * NT + r] = c[r];
+    }
+    __syncthreads();
+
+    const int nn = a.nn, epi = a.epi;
+    const int slots = epi * nn;
+    const int per_pass = B * MM;
+    const int npass = (slots + per_pass - 1) / per_pass;
+    const int steps = (ne + epi - 1) / epi;
+    for (int pass = 0; pass < npass; ++pass) {
+        double R[MM][NT];
+        int el[MM], fs[MM];
+#pragma unroll
+        for (int m = 0; m < MM; ++m) {
+            const int f = tid + B * (pass * MM + m);
+            fs[m] = f;
+            if (f < slots) {
+                el[m] = f / nn;
+                const int jk = f - el[m] * nn;
+#pragma unroll
+                for (int r = 0; r < NT; ++r) R[m][r] = a.tables[r * nn + jk];
+            } else {
+                el[m] = 1 << 30;
+#pragma unroll
+                for (int r = 0; r < NT; ++r) R[m][r] = 0.0;
+            }
+        }
+        for (int it = 0; it < steps; ++it) {
+            const int lim = ne - it * epi;
+            double* o = a.out + (e_begin + (int64_t)it * epi) * nn;
+            const double* g0 = sG + it * epi * NT;
+#pragma unroll
+            for (int m = 0; m < MM; ++m) {
+                if (el[m] < lim) {
+                    const double* g = g0 + el[m] * NT;
+                    double v = g[0] * R[m][0];
+#pragma unroll
+                    for (int r = 1; r < NT; ++r) v = fma(g[r], R[m][r], v);
+                    store_out(o + fs[m], v);
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace fe

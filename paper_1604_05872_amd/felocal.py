@@ -1,0 +1,303 @@
+"""ctypes binding of libfelocal.so (include/felocal.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Device
+arrays are torch tensors on a ROCm device (float64, contiguous); the stream
+defaults to torch's current stream.  When the shared library has not been
+built the binding raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfelocal.so")
+
+FE_OK, FE_EINVAL, FE_ENOTSUP, FE_EHIP, FE_ENONAFFINE, FE_ENOMEM = 0, -1, -2, -3, -4, -5
+CELLS = {"triangle": 0, "tetrahedron": 1, "prism": 2}
+FORMS = {"mass": 0, "helmholtz": 1, "elasticity": 2, "hyperelastic": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+MODES = {"auto": 0, "preeval": 1, "quadrature": 2}
+GDIM = {"triangle": 2, "tetrahedron": 3, "prism": 3}
+NVERT = {"triangle": 3, "tetrahedron": 4, "prism": 6}
+
+# every function include/felocal.h declares
+EXPORTS = (
+    "fe_options_init", "fe_tabulate", "fe_local_dims", "fe_assemble_local", "fe_geometry", "fe_plan",
+    "fe_batch_create", "fe_batch_run", "fe_batch_destroy", "fe_batch_info", "fe_autotune",
+    "fe_strerror", "fe_release_caches", "fe_version",
+)
+
+
+class FeError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} (code {code})")
+
+
+class fe_options_t(ctypes.Structure):
+    _fields_ = [
+        ("qdeg", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("mode", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("mu", ctypes.c_double),
+        ("lambda_", ctypes.c_double),
+        ("d_status", ctypes.c_void_p),
+        ("th_bytes", ctypes.c_size_t),
+        ("validate", ctypes.c_int),
+    ]
+
+
+class fe_plan_t(ctypes.Structure):
+    _fields_ = [
+        ("n_monomials", ctypes.c_int),
+        ("preevaluated", ctypes.c_int * 4),
+        ("theta_se", ctypes.c_double * 4),
+        ("theta_pre", ctypes.c_double * 4),
+        ("iota", ctypes.c_int * 4),
+        ("rho", ctypes.c_int * 4),
+        ("table_bytes", ctypes.c_size_t * 4),
+        ("th_bytes", ctypes.c_size_t),
+        ("cost", ctypes.c_double),
+        ("mode", ctypes.c_int),
+    ]
+
+
+class fe_subbatch_t(ctypes.Structure):
+    _fields_ = [
+        ("form", ctypes.c_int),
+        ("cell", ctypes.c_int),
+        ("degree", ctypes.c_int),
+        ("qdeg", ctypes.c_int),
+        ("n_elems", ctypes.c_int64),
+        ("coords", ctypes.c_void_p),
+        ("coeff_dofs", ctypes.c_void_p),
+        ("out_A", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1604_05872_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        vp = ctypes.c_void_p
+        L.fe_options_init.argtypes = [ctypes.POINTER(fe_options_t)]
+        L.fe_options_init.restype = None
+        L.fe_tabulate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int)]
+        L.fe_local_dims.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int)]
+        L.fe_assemble_local.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, vp, vp, vp,
+                                        ctypes.POINTER(fe_options_t)]
+        L.fe_geometry.argtypes = [ctypes.c_int, ctypes.c_int64, vp, vp, vp, vp]
+        L.fe_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
+                              ctypes.POINTER(fe_plan_t)]
+        L.fe_batch_create.argtypes = [ctypes.POINTER(fe_subbatch_t), ctypes.c_int, ctypes.POINTER(fe_options_t),
+                                      ctypes.POINTER(vp)]
+        L.fe_batch_run.argtypes = [vp, vp]
+        L.fe_batch_destroy.argtypes = [vp]
+        L.fe_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)]
+        L.fe_autotune.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, vp, vp, vp,
+                                  ctypes.POINTER(fe_options_t), dp]
+        L.fe_strerror.argtypes = [ctypes.c_int]
+        L.fe_strerror.restype = ctypes.c_char_p
+        L.fe_release_caches.argtypes = []
+        L.fe_release_caches.restype = None
+        L.fe_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().fe_strerror(int(code)).decode()
+
+
+def fe_version() -> str:
+    return lib().fe_version().decode()
+
+
+def _check(rc: int, where: str):
+    if rc != FE_OK:
+        raise FeError(rc, where)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _f64_dev(t, name):
+    if t is None:
+        return
+    import torch
+
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 tensor on the GPU")
+
+
+def make_options(qdeg=-1, precision="fp64", mode="auto", stream=None, mu=1.0, lam=10.0, status=None,
+                 th_bytes=0, validate=False, need_stream=True) -> fe_options_t:
+    o = fe_options_t()
+    lib().fe_options_init(ctypes.byref(o))
+    o.qdeg = int(qdeg)
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    o.stream = _stream(stream).value if need_stream else None
+    o.mu = float(mu)
+    o.lambda_ = float(lam)
+    o.d_status = status.data_ptr() if status is not None else None
+    o.th_bytes = int(th_bytes)
+    o.validate = 1 if validate else 0
+    return o
+
+
+def fe_local_dims(form: str, cell: str, degree: int):
+    n, nc = ctypes.c_int(), ctypes.c_int()
+    _check(lib().fe_local_dims(FORMS[form], CELLS[cell], int(degree), ctypes.byref(n), ctypes.byref(nc)),
+           "fe_local_dims")
+    return n.value, nc.value
+
+
+def fe_tabulate(cell: str, degree: int, qdeg: int, rule_only: bool = False):
+    """Quadrature rule and tabulated basis (host arrays).  rule_only needs no GPU."""
+    L = lib()
+    info = (ctypes.c_int * 3)()
+    _check(L.fe_tabulate(CELLS[cell], int(degree), int(qdeg), None, None, None, None, info), "fe_tabulate")
+    nq, nb, d = info[0], info[1], info[2]
+    X = np.zeros((nq, d))
+    W = np.zeros(nq)
+    dp = ctypes.POINTER(ctypes.c_double)
+    if rule_only:
+        _check(L.fe_tabulate(CELLS[cell], int(degree), int(qdeg), X.ctypes.data_as(dp), W.ctypes.data_as(dp),
+                             None, None, info), "fe_tabulate")
+        return {"points": X, "weights": W}
+    phi = np.zeros((nq, nb))
+    dphi = np.zeros((nq, nb, d))
+    _check(L.fe_tabulate(CELLS[cell], int(degree), int(qdeg), X.ctypes.data_as(dp), W.ctypes.data_as(dp),
+                         phi.ctypes.data_as(dp), dphi.ctypes.data_as(dp), info), "fe_tabulate")
+    return {"points": X, "weights": W, "phi": phi, "dphi": dphi}
+
+
+def fe_assemble_local(form: str, cell: str, degree: int, coords, coeff, out, qdeg: int = -1,
+                      precision: str = "fp64", mode: str = "auto", stream=None, mu: float = 1.0,
+                      lam: float = 10.0, status=None, th_bytes: int = 0, validate: bool = False):
+    """Element matrices of `form` into `out` [E][n][n] (asynchronous on the stream)."""
+    _f64_dev(coords, "coords")
+    _f64_dev(coeff, "coeff")
+    _f64_dev(out, "out")
+    E = int(coords.shape[0])
+    n, nc = fe_local_dims(form, cell, degree)
+    if tuple(coords.shape) != (E, NVERT[cell], GDIM[cell]):
+        raise ValueError(f"coords must be [E][{NVERT[cell]}][{GDIM[cell]}]")
+    if tuple(out.shape[-2:]) != (n, n) or out.numel() != E * n * n:
+        raise ValueError(f"out must be [E][{n}][{n}]")
+    if nc and (coeff is None or coeff.numel() != E * nc):
+        raise ValueError(f"coeff must hold {nc} values per element")
+    o = make_options(qdeg, precision, mode, stream, mu, lam, status, th_bytes, validate)
+    _check(lib().fe_assemble_local(FORMS[form], CELLS[cell], int(degree), E, _ptr(coords), _ptr(coeff),
+                                   _ptr(out), ctypes.byref(o)), "fe_assemble_local")
+    return out
+
+
+def fe_geometry(cell: str, coords, det, kinv, stream=None):
+    _f64_dev(coords, "coords")
+    _f64_dev(det, "det")
+    _f64_dev(kinv, "kinv")
+    _check(lib().fe_geometry(CELLS[cell], int(coords.shape[0]), _ptr(coords), _ptr(det), _ptr(kinv),
+                             _stream(stream)), "fe_geometry")
+
+
+def fe_plan(form: str, cell: str, degree: int, qdeg: int = -1, th_bytes: int = 0) -> dict:
+    p = fe_plan_t()
+    _check(lib().fe_plan(FORMS[form], CELLS[cell], int(degree), int(qdeg), int(th_bytes), ctypes.byref(p)),
+           "fe_plan")
+    m = p.n_monomials
+    return {
+        "n_monomials": m,
+        "preevaluated": [bool(p.preevaluated[i]) for i in range(m)],
+        "theta_se": [p.theta_se[i] for i in range(m)],
+        "theta_pre": [p.theta_pre[i] for i in range(m)],
+        "iota": [p.iota[i] for i in range(m)],
+        "rho": [p.rho[i] for i in range(m)],
+        "table_bytes": [p.table_bytes[i] for i in range(m)],
+        "th_bytes": p.th_bytes,
+        "cost": p.cost,
+        "mode": {v: k for k, v in MODES.items()}[p.mode],
+    }
+
+
+def fe_autotune(form: str, cell: str, degree: int, coords, coeff, out, qdeg: int = -1,
+                precision: str = "fp64", mode: str = "auto", stream=None, mu: float = 1.0, lam: float = 10.0) -> float:
+    _f64_dev(coords, "coords")
+    _f64_dev(out, "out")
+    o = make_options(qdeg, precision, mode, stream, mu, lam)
+    best = ctypes.c_double()
+    _check(lib().fe_autotune(FORMS[form], CELLS[cell], int(degree), int(coords.shape[0]), _ptr(coords),
+                             _ptr(coeff), _ptr(out), ctypes.byref(o), ctypes.byref(best)), "fe_autotune")
+    return best.value
+
+
+class Batch:
+    """fe_batch_create / fe_batch_run / fe_batch_destroy.  `subs` is a list of
+    dicts with form, cell, degree, coords, coeff (or None), out, qdeg (opt)."""
+
+    def __init__(self, subs, stream=None, status=None):
+        arr = (fe_subbatch_t * len(subs))()
+        self._keep = []
+        for i, s in enumerate(subs):
+            _f64_dev(s["coords"], "coords")
+            _f64_dev(s["out"], "out")
+            arr[i].form = FORMS[s["form"]]
+            arr[i].cell = CELLS[s["cell"]]
+            arr[i].degree = int(s["degree"])
+            arr[i].qdeg = int(s.get("qdeg", -1))
+            arr[i].n_elems = int(s["coords"].shape[0])
+            arr[i].coords = s["coords"].data_ptr()
+            arr[i].coeff_dofs = s["coeff"].data_ptr() if s.get("coeff") is not None else None
+            arr[i].out_A = s["out"].data_ptr()
+            self._keep.append(s)
+        o = make_options(stream=stream, status=status)
+        h = ctypes.c_void_p()
+        _check(lib().fe_batch_create(arr, len(subs), ctypes.byref(o), ctypes.byref(h)), "fe_batch_create")
+        self.handle = h
+
+    def run(self, stream=None):
+        _check(lib().fe_batch_run(self.handle, _stream(stream)), "fe_batch_run")
+
+    def info(self):
+        nt, g = ctypes.c_int64(), ctypes.c_int()
+        _check(lib().fe_batch_info(self.handle, ctypes.byref(nt), ctypes.byref(g)), "fe_batch_info")
+        return nt.value, g.value
+
+    def close(self):
+        if self.handle:
+            _check(lib().fe_batch_destroy(self.handle), "fe_batch_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fe_release_caches():
+    lib().fe_release_caches()

@@ -1,0 +1,320 @@
+"""Parity of the HIP library (through its C ABI) with the float64 CPU oracle.
+
+Metric: per element, max_jk |A_gpu - A_oracle| / max_jk |A_oracle|; the bars
+are 1e-12 for float64, 1e-4 for the bf16x3 split and 2e-6 for the fp32 split
+(the bounds stated in include/felocal.h).  Small cases span several tiles and
+a ragged tail; the full-size workloads are checked on sampled elements."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_05872_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1604_05872_amd import felocal  # noqa: E402
+
+CELLS = ["triangle", "tetrahedron", "prism"]
+TOL = {"fp64": 1e-12, "fp32": 2e-6, "bf16x3": 1e-4}
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def mesh(cell, E, seed):
+    coords, V, cells, h = inputs.first_elements(cell, E, seed)
+    return coords, V, cells, h
+
+
+def coefficients(form, cell, p, E, V, cells, h, seed):
+    if form == "elasticity":
+        return inputs.lame_p1(V.shape[0], cells, seed)
+    if form == "hyperelastic":
+        return inputs.displacement_dofs(E, oracle.TDIM[cell], oracle.nbasis(cell, p), h, p, seed)
+    return None
+
+
+def gpu_assemble(form, cell, p, coords, coeff=None, **kw):
+    n, _ = felocal.fe_local_dims(form, cell, p)
+    E = coords.shape[0]
+    out = torch.full((E, n, n), float("nan"), dtype=torch.float64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    felocal.fe_assemble_local(form, cell, p, dev(coords), dev(coeff) if coeff is not None else None, out,
+                              status=status, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), int(status.item())
+
+
+def normwise(A, B):
+    num = np.max(np.abs(A - B), axis=(1, 2))
+    den = np.max(np.abs(B), axis=(1, 2))
+    return num / den
+
+
+def oracle_cost(form, cell, p):
+    ns = oracle.nbasis(cell, p)
+    n = ns * (oracle.TDIM[cell] if form in ("elasticity", "hyperelastic") else 1)
+    nq = oracle.rule(cell, oracle.default_qdeg(form, cell, p))[1].size
+    per = {"mass": 2, "helmholtz": 8, "elasticity": 60, "hyperelastic": 40}[form]
+    return nq * n * n * per
+
+
+def case_size(form, cell, p, cap=1000):
+    return int(max(5, min(cap, 4e9 / oracle_cost(form, cell, p))))
+
+
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cell", CELLS)
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_tabulation_matches_oracle(cell, p):
+    log(f"tabulate {cell} P{p}")
+    for qdeg in (2 * p, 7):
+        t = felocal.fe_tabulate(cell, p, qdeg)
+        phi, dphi = oracle.basis(cell, p, t["points"])
+        assert np.max(np.abs(t["phi"] - phi)) < 1e-13
+        assert np.max(np.abs(t["dphi"] - dphi)) < 1e-11
+
+
+@pytest.mark.parametrize("cell", CELLS)
+def test_geometry_matches_oracle(cell):
+    log(f"geometry {cell}")
+    coords, *_ = mesh(cell, 777, seed=11)
+    d = oracle.TDIM[cell]
+    det = torch.zeros(coords.shape[0], dtype=torch.float64, device="cuda")
+    K = torch.zeros((coords.shape[0], d, d), dtype=torch.float64, device="cuda")
+    felocal.fe_geometry(cell, dev(coords), det, K)
+    torch.cuda.synchronize()
+    det, K = det.cpu().numpy(), K.cpu().numpy()
+    for e in range(0, coords.shape[0], 37):
+        J, dt, Ko, bad = oracle.geometry(cell, coords[e])
+        assert abs(det[e] - dt) <= 1e-14 * abs(dt)
+        assert np.max(np.abs(K[e] - Ko)) <= 1e-12 * np.max(np.abs(Ko))
+
+
+FP64_CASES = [(f, c, p) for f in ("mass", "helmholtz", "elasticity") for c in CELLS for p in (1, 2, 3, 4)] + \
+             [("hyperelastic", c, p) for c in CELLS for p in (1, 2, 3)]
+
+
+@pytest.mark.parametrize("form,cell,p", FP64_CASES)
+def test_fp64_parity(form, cell, p):
+    E = case_size(form, cell, p)
+    log(f"fp64 parity {form} {cell} P{p} E={E}")
+    coords, V, cells, h = mesh(cell, E, seed=100 + p)
+    cf = coefficients(form, cell, p, E, V, cells, h, seed=200 + p)
+    A, st = gpu_assemble(form, cell, p, coords, cf)
+    B, fl = oracle.assemble(form, cell, p, coords, cf)
+    assert st == fl == 0
+    assert np.isfinite(A).all()
+    assert normwise(A, B).max() <= TOL["fp64"]
+
+
+HELM_MODES = [("tetrahedron", 4, "preeval", 0), ("tetrahedron", 4, "quadrature", 0),
+              ("tetrahedron", 4, "auto", 65536), ("prism", 4, "auto", 0), ("prism", 3, "preeval", 0),
+              ("triangle", 3, "quadrature", 0), ("prism", 2, "auto", 1000)]
+
+
+@pytest.mark.parametrize("cell,p,mode,th", HELM_MODES)
+def test_helmholtz_modes_agree(cell, p, mode, th):
+    """Pre-evaluation, quadrature and both mixed plans give the same matrices."""
+    E = case_size("helmholtz", cell, p, cap=600)
+    log(f"helmholtz modes {cell} P{p} {mode} th={th} E={E}")
+    coords, *_ = mesh(cell, E, seed=7)
+    A, st = gpu_assemble("helmholtz", cell, p, coords, mode=mode, th_bytes=th)
+    B, _ = oracle.assemble("helmholtz", cell, p, coords)
+    assert st == 0 and normwise(A, B).max() <= TOL["fp64"]
+
+
+SPLIT_CASES = [(f, c, p) for f in ("elasticity", "hyperelastic") for (c, p) in
+               [("triangle", 1), ("triangle", 2), ("triangle", 3), ("triangle", 4), ("tetrahedron", 1),
+                ("tetrahedron", 2), ("prism", 1)]]
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("form,cell,p", SPLIT_CASES)
+def test_split_parity(form, cell, p, prec):
+    E = case_size(form, cell, p, cap=700)
+    log(f"split parity {form} {cell} P{p} {prec} E={E}")
+    coords, V, cells, h = mesh(cell, E, seed=300 + p)
+    cf = coefficients(form, cell, p, E, V, cells, h, seed=400 + p)
+    A, st = gpu_assemble(form, cell, p, coords, cf, precision=prec)
+    B, fl = oracle.assemble(form, cell, p, coords, cf)
+    assert st == fl == 0
+    err = normwise(A, B)
+    log(f"   max err {err.max():.3e}")
+    assert err.max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("form", ["mass", "helmholtz", "elasticity", "hyperelastic"])
+def test_degenerate_elements_flagged(form):
+    log(f"flagged {form}")
+    coords, V, cells, h = mesh("tetrahedron", 50, seed=3)
+    coords = coords.copy()
+    coords[7, 2] = coords[7, 1]            # two coincident vertices
+    coords[31, 3] = coords[31, 0]
+    cf = coefficients(form, "tetrahedron", 2, 50, V, cells, h, seed=5)
+    precs = ["fp64", "bf16x3"] if form in ("elasticity", "hyperelastic") else ["fp64"]
+    for prec in precs:
+        A, st = gpu_assemble(form, "tetrahedron", 2, coords, cf, precision=prec)
+        assert st == 2
+        assert np.isnan(A[[7, 31]]).all()
+        ok = np.ones(50, bool)
+        ok[[7, 31]] = False
+        assert np.isfinite(A[ok]).all()
+
+
+def test_hyperelastic_inverted_points_flagged_like_oracle():
+    log("hyperelastic inversion")
+    coords, V, cells, h = mesh("tetrahedron", 200, seed=9)
+    u = inputs.displacement_dofs(200, 3, 10, h, 2, seed=10, rel=0.6)
+    B, fl = oracle.assemble("hyperelastic", "tetrahedron", 2, coords, u)
+    bad = np.isnan(B[:, 0, 0])
+    assert fl == bad.sum() and 0 < fl < 200
+    for prec in ("fp64", "bf16x3", "fp32"):
+        A, st = gpu_assemble("hyperelastic", "tetrahedron", 2, coords, u, precision=prec)
+        assert st == fl
+        assert (np.isnan(A[:, 0, 0]) == bad).all()
+        assert normwise(A[~bad], B[~bad]).max() <= TOL[prec]
+
+
+def test_empty_and_coverage():
+    log("empty and coverage")
+    coords, *_ = mesh("tetrahedron", 300, seed=4)
+    n = 10
+    for mode in ("preeval", "quadrature"):
+        buf = torch.full((300 * n * n + 64,), float("nan"), dtype=torch.float64, device="cuda")
+        buf[-64:] = 12345.0
+        out = buf[:300 * n * n].view(300, n, n)
+        felocal.fe_assemble_local("helmholtz", "tetrahedron", 2, dev(coords), None, out, mode=mode)
+        torch.cuda.synchronize()
+        b = buf.cpu().numpy()
+        assert np.isfinite(b[:-64]).all()
+        assert (b[-64:] == 12345.0).all()
+    empty = torch.zeros((0, 4, 3), dtype=torch.float64, device="cuda")
+    outE = torch.zeros((0, n, n), dtype=torch.float64, device="cuda")
+    felocal.fe_assemble_local("helmholtz", "tetrahedron", 2, empty, None, outE)
+
+
+def test_nonaffine_prism_rejected_or_flagged():
+    log("non-affine prism")
+    coords, *_ = mesh("prism", 20, seed=6)
+    coords = coords.copy()
+    coords[5, 4, 2] += 0.01
+    with pytest.raises(felocal.FeError) as ei:
+        gpu_assemble("mass", "prism", 1, coords, validate=True)
+    assert ei.value.code == felocal.FE_ENONAFFINE
+    A, st = gpu_assemble("mass", "prism", 1, coords)
+    assert st == 1 and np.isnan(A[5]).all() and np.isfinite(np.delete(A, 5, axis=0)).all()
+
+
+def test_batch_bitwise_equal_to_separate_calls():
+    log("batch vs separate calls")
+    rng = np.random.default_rng(5)
+    specs = [("mass", "triangle", 1, 3000), ("helmholtz", "tetrahedron", 3, 1500), ("elasticity", "prism", 2, 200),
+             ("helmholtz", "prism", 4, 60), ("elasticity", "tetrahedron", 2, 999), ("mass", "prism", 3, 0),
+             ("helmholtz", "triangle", 4, 777)]
+    subs, refs = [], []
+    for i, (form, cell, p, E) in enumerate(specs):
+        coords, V, cells, h = mesh(cell, max(E, 1), seed=20 + i)
+        coords = coords[:E]
+        cf = coefficients(form, cell, p, E, V, cells[:E], h, seed=30 + i) if E else None
+        n, _ = felocal.fe_local_dims(form, cell, p)
+        out = torch.full((E, n, n), float("nan"), dtype=torch.float64, device="cuda")
+        subs.append(dict(form=form, cell=cell, degree=p, coords=dev(coords),
+                         coeff=dev(cf) if cf is not None else None, out=out))
+        if E:
+            refs.append(gpu_assemble(form, cell, p, coords, cf)[0])
+        else:
+            refs.append(np.zeros((0, n, n)))
+    b = felocal.Batch(subs)
+    ntiles, grid = b.info()
+    assert ntiles > 0 and grid > 0
+    results = []
+    for rep in range(3):
+        for s in subs:
+            s["out"].fill_(float("nan"))
+        b.run()
+        torch.cuda.synchronize()
+        results.append([s["out"].cpu().numpy() for s in subs])
+        _ = torch.ones(1000, device="cuda").sum().item()   # unrelated eager work between replays
+    b.close()
+    for res in results:
+        for got, ref in zip(res, refs):
+            assert np.array_equal(got, ref)
+
+
+# --------------------------------------------------------------------------
+# Full-size workloads, sampled elements
+# --------------------------------------------------------------------------
+
+def _sample(E, k, seed):
+    rng = np.random.default_rng(seed)
+    idx = np.unique(np.concatenate([[0, 1, E - 1, E - 2], rng.integers(0, E, size=k)]))
+    return idx
+
+
+def _full_check(form, cell, p, coords, cf, precs, k=64, extra_idx=None):
+    n, _ = felocal.fe_local_dims(form, cell, p)
+    E = coords.shape[0]
+    dc = dev(coords)
+    dcf = dev(cf) if cf is not None else None
+    out = torch.empty((E, n, n), dtype=torch.float64, device="cuda")
+    idx = _sample(E, k, seed=E)
+    if extra_idx is not None:
+        idx = np.unique(np.concatenate([idx, extra_idx]))
+    B, fl = oracle.assemble(form, cell, p, coords[idx], cf[idx] if cf is not None else None)
+    for prec in precs:
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+        felocal.fe_assemble_local(form, cell, p, dc, dcf, out, precision=prec, status=status)
+        torch.cuda.synchronize()
+        A = out[torch.from_numpy(idx).cuda()].cpu().numpy()
+        bad = np.isnan(B[:, 0, 0])
+        assert (np.isnan(A[:, 0, 0]) == bad).all()
+        assert normwise(A[~bad], B[~bad]).max() <= TOL[prec]
+        yield int(status.item())
+    del out
+    torch.cuda.empty_cache()
+
+
+def test_full_mass_triangles_4096():
+    log("full: mass P1 triangles 4096")
+    coords = inputs.mass_tri_workload(seed=1)
+    for st in _full_check("mass", "triangle", 1, coords, None, ["fp64"], k=4096):
+        assert st == 0
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_full_helmholtz_tets_750k(p):
+    log(f"full: helmholtz P{p} 750k tets")
+    coords, _, _ = inputs.tet_workload(50, seed=2)
+    for st in _full_check("helmholtz", "tetrahedron", p, coords, None, ["fp64"]):
+        assert st == 0
+
+
+def test_full_elasticity_p2_tets_2m():
+    log("full: elasticity P2 1.97M tets")
+    coords, V, cells = inputs.tet_workload(69, seed=3)
+    cf = inputs.lame_p1(V.shape[0], cells, seed=3)
+    for st in _full_check("elasticity", "tetrahedron", 2, coords, cf, ["fp64", "fp32", "bf16x3"]):
+        assert st == 0
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_full_hyperelastic_tets_1m(p):
+    log(f"full: hyperelastic P{p} 998k tets")
+    coords, V, cells = inputs.tet_workload(55, seed=4)
+    u = inputs.displacement_dofs(coords.shape[0], 3, oracle.nbasis("tetrahedron", p), 1.0 / 55, p, seed=40 + p)
+    flagged = np.nonzero(oracle.hyper_min_jf("tetrahedron", p, coords, u) <= 0)[0]
+    for st in _full_check("hyperelastic", "tetrahedron", p, coords, u, ["fp64", "fp32", "bf16x3"],
+                          extra_idx=flagged):
+        assert st == len(flagged)

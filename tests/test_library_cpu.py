@@ -1,0 +1,145 @@
+"""Host-side checks of the HIP library that need no GPU: exported symbols,
+dimensions, the library's own quadrature rules, the planner (Algorithm 3 and
+the cost function of Sec. 4.2) and synchronous argument errors."""
+import ctypes
+import json
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import exact_rational as er
+import oracle
+from paper_1604_05872_amd import felocal
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CELLS = ["triangle", "tetrahedron", "prism"]
+GOLDEN = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_examples.json")))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "felocal.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fe_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = felocal.lib()
+    names = header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(felocal.EXPORTS)
+    assert "gfx950" in felocal.fe_version()
+
+
+@pytest.mark.parametrize("cell", CELLS)
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_local_dims(cell, p):
+    ns = oracle.nbasis(cell, p)
+    d = oracle.TDIM[cell]
+    assert felocal.fe_local_dims("mass", cell, p) == (ns, 0)
+    assert felocal.fe_local_dims("helmholtz", cell, p) == (ns, 0)
+    assert felocal.fe_local_dims("elasticity", cell, p) == (d * ns, 2 * oracle.NVERT[cell])
+    assert felocal.fe_local_dims("hyperelastic", cell, p) == (d * ns, d * ns)
+
+
+@pytest.mark.parametrize("cell", CELLS)
+@pytest.mark.parametrize("qdeg", list(range(0, 13)))
+def test_library_rule_exact_and_equal_to_oracle(cell, qdeg):
+    r = felocal.fe_tabulate(cell, 1, qdeg, rule_only=True)
+    X, W = r["points"], r["weights"]
+    assert abs(W.sum() - oracle.REF_VOLUME[cell]) < 1e-15
+    D = max(qdeg, 0)
+    mons = ([(a, b) for a in range(D + 1) for b in range(D + 1 - a)] if cell == "triangle" else
+            [(a, b, c) for a in range(D + 1) for b in range(D + 1 - a) for c in range(D + 1 - a - b)]
+            if cell == "tetrahedron" else
+            [(a, b, c) for a in range(D + 1) for b in range(D + 1 - a) for c in range(D + 1)])
+    for e in mons:
+        approx = float(np.sum(W * np.prod(X ** np.array(e), axis=1)))
+        assert abs(approx - float(er.integrate(cell, e))) < 2e-16 + 1e-14 * float(er.integrate(cell, e))
+    # Gauss rules are unique: same point set and weights as the oracle's Newton construction
+    Xo, Wo = oracle.rule(cell, max(qdeg, 0))
+    ko = np.lexsort(Xo.T[::-1])
+    kl = np.lexsort(X.T[::-1])
+    assert np.max(np.abs(Xo[ko] - X[kl])) < 1e-14
+    assert np.max(np.abs(Wo[ko] - W[kl])) < 1e-15
+
+
+def test_planner_matches_paper_examples():
+    # rho: mass monomial 1, 2D Poisson 3 (Sec. 4.2)
+    pm = felocal.fe_plan("mass", "triangle", 2)
+    assert pm["rho"] == [1] and pm["iota"] == [1]
+    ph = felocal.fe_plan("helmholtz", "triangle", 2)
+    assert ph["rho"][0] == GOLDEN["rho"][1]["value"] and ph["rho"][1] == GOLDEN["rho"][0]["value"]
+    # iota = C(n+k-1, k): one P1 coefficient on a triangle (n = 3, k = 1) -> 3
+    pe = felocal.fe_plan("elasticity", "triangle", 2)
+    assert pe["iota"] == [GOLDEN["iota"][0]["value"]] * 2
+    for ex in GOLDEN["iota"]:
+        assert math.comb(ex["n"] + ex["k"] - 1, ex["k"]) == ex["value"]
+    # Fig. 3: the inner (j,k) body of the sharing-eliminated 2D Poisson is 4 ops per (i,j,k)
+    nq = oracle.rule("triangle", 4)[1].size
+    ns = oracle.nbasis("triangle", 2)
+    assert ph["theta_se"][0] == nq * ns * ns * GOLDEN["fig3_inner_ops_per_IJK"]["after_sharing_elimination_JK_term"]
+
+
+@pytest.mark.parametrize("cell", CELLS)
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_planner_decisions(cell, p):
+    big = 1 << 40
+    # with no memory bound, the scalar forms pre-evaluate every monomial
+    assert felocal.fe_plan("mass", cell, p, th_bytes=big)["mode"] == "preeval"
+    assert felocal.fe_plan("helmholtz", cell, p, th_bytes=big)["mode"] == "preeval"
+    # elasticity with P1 Lame fields and the hyperelastic form use quadrature
+    pe = felocal.fe_plan("elasticity", cell, p, th_bytes=big)
+    assert pe["mode"] == "quadrature" and not any(pe["preevaluated"])
+    if (cell, p) == ("tetrahedron", 2):   # the elasticity workload: theta > 0 for both monomials
+        assert all(tp > ts for tp, ts in zip(pe["theta_pre"], pe["theta_se"]))
+    phy = felocal.fe_plan("hyperelastic", cell, p, th_bytes=big)
+    assert phy["mode"] == "quadrature" and math.isinf(phy["theta_pre"][0])
+
+
+def test_planner_memory_threshold():
+    # prism P4 Helmholtz: 6 stiffness tables (270 KB) exceed a 64 KiB T_H, the
+    # mass table (45 KB) fits: a mixed plan (Fig. 5's two nests)
+    p = felocal.fe_plan("helmholtz", "prism", 4, th_bytes=65536)
+    assert p["preevaluated"] == [False, True] and p["mode"] == "quadrature"
+    assert p["table_bytes"][0] == 6 * 75 * 75 * 8
+    p = felocal.fe_plan("helmholtz", "prism", 4, th_bytes=1 << 30)
+    assert p["preevaluated"] == [True, True] and p["mode"] == "preeval"
+    p = felocal.fe_plan("helmholtz", "prism", 4, th_bytes=1000)
+    assert p["preevaluated"] == [False, False]
+    # tet P4 Helmholtz tables (7 x 35^2 x 8 = 68.6 KB) fit 160 KB, not 64 KiB
+    assert felocal.fe_plan("helmholtz", "tetrahedron", 4, th_bytes=160 * 1024)["mode"] == "preeval"
+    # at 64 KiB the gradient tables (58.8 KB) fit alone: pre-evaluate them, integrate the mass
+    assert felocal.fe_plan("helmholtz", "tetrahedron", 4, th_bytes=65536)["preevaluated"] == [True, False]
+    assert felocal.fe_plan("helmholtz", "tetrahedron", 4)["th_bytes"] >= 160 * 1024
+
+
+def test_argument_errors_are_synchronous():
+    L = felocal.lib()
+    o = felocal.fe_options_t()
+    L.fe_options_init(ctypes.byref(o))
+    assert L.fe_assemble_local(0, 0, 1, 10, None, None, None, ctypes.byref(o)) == felocal.FE_EINVAL
+    assert L.fe_assemble_local(0, 0, 5, 10, 8, None, 8, ctypes.byref(o)) == felocal.FE_EINVAL
+    assert L.fe_assemble_local(0, 0, 1, -1, 8, None, 8, ctypes.byref(o)) == felocal.FE_EINVAL
+    assert L.fe_assemble_local(0, 0, 1, 0, None, None, None, ctypes.byref(o)) == felocal.FE_OK
+    assert L.fe_assemble_local(7, 0, 1, 1, 8, None, 8, ctypes.byref(o)) == felocal.FE_EINVAL
+    assert L.fe_assemble_local(2, 1, 2, 1, 8, None, 8, ctypes.byref(o)) == felocal.FE_EINVAL   # no coefficients
+    o.precision = 2
+    assert L.fe_assemble_local(1, 1, 2, 1, 8, None, 8, ctypes.byref(o)) == felocal.FE_ENOTSUP   # split: vector forms
+    assert L.fe_assemble_local(2, 1, 3, 1, 8, 8, 8, ctypes.byref(o)) == felocal.FE_ENOTSUP      # n = 60 > 32
+    o.precision = 0
+    o.mode = 1
+    assert L.fe_assemble_local(2, 1, 2, 1, 8, 8, 8, ctypes.byref(o)) == felocal.FE_ENOTSUP      # no vector pre-evaluation
+    o.qdeg = 99
+    o.mode = 0
+    assert L.fe_assemble_local(0, 1, 2, 1, 8, None, 8, ctypes.byref(o)) == felocal.FE_EINVAL
+    assert L.fe_geometry(0, 5, None, None, None, None) == felocal.FE_EINVAL
+    assert L.fe_batch_run(None, None) == felocal.FE_EINVAL
+    assert L.fe_batch_destroy(None) == felocal.FE_EINVAL
+    assert "invalid" in felocal.strerror(felocal.FE_EINVAL)
+    info = (ctypes.c_int * 3)()
+    assert L.fe_tabulate(1, 4, 8, None, None, None, None, info) == 0 and list(info) == [125, 35, 3]
