@@ -94,6 +94,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-headline", action="store_true")
+    ap.add_argument("--workloads", default="mass,elasticity,hyperelastic,batch",
+                    help="comma list of the extra workloads to time")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device (a known-size kernel for the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); local assembly shards by element "
@@ -111,6 +115,14 @@ def main():
 
     def ev():
         return torch.cuda.Event(enable_timing=True)
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del src, dst
 
     # ------------------------------------------------------------------ headline
     log("headline: helmholtz P1-P4 on 750k tets")
@@ -185,7 +197,8 @@ def main():
 
     # ------------------------------------------------------------------ other workloads
     if not args.only_headline:
-        result["workloads"] = other_workloads(torch, felocal, inputs, stream, ev, max(3, args.steps // 2))
+        result["workloads"] = other_workloads(torch, felocal, inputs, stream, ev, max(3, args.steps // 2),
+                                             set(args.workloads.split(",")))
 
     # ------------------------------------------------------------------ CPU baseline (oracle)
     if not args.no_cpu_baseline:
@@ -205,7 +218,7 @@ def time_launch(torch, fn, stream, ev, reps):
     return a.elapsed_time(b) / reps
 
 
-def other_workloads(torch, felocal, inputs, stream, ev, reps):
+def other_workloads(torch, felocal, inputs, stream, ev, reps, which):
     res = []
 
     def record(name, form, cell, p, E, ms, prec="fp64", **extra):
@@ -221,6 +234,18 @@ def other_workloads(torch, felocal, inputs, stream, ev, reps):
         log(f"  {name} {prec}: {ms:.4f} ms, {row['elem_per_s']:.3e} elem/s, {row['alg_GBs']} GB/s")
 
     # mass P1 triangles, 4096 elements (launch-latency bound)
+    if "mass" in which:
+        mass_workload(torch, felocal, inputs, stream, ev, record)
+    if "elasticity" in which:
+        elasticity_workload(torch, felocal, inputs, stream, ev, record, reps)
+    if "hyperelastic" in which:
+        hyperelastic_workload(torch, felocal, inputs, stream, ev, record, reps)
+    if "batch" in which:
+        res.append(batch_workload(torch, felocal, inputs, stream, ev, reps))
+    return res
+
+
+def mass_workload(torch, felocal, inputs, stream, ev, record):
     log("mass P1 triangles 4096")
     c1 = torch.from_numpy(inputs.mass_tri_workload(seed=1)).cuda()
     o1 = torch.empty((4096, 3, 3), dtype=torch.float64, device="cuda")
@@ -228,7 +253,8 @@ def other_workloads(torch, felocal, inputs, stream, ev, reps):
                      stream, ev, 50)
     record("mass_tri_p1_4096", "mass", "triangle", 1, 4096, ms, note="launch-latency bound (0.49 MB)")
 
-    # elasticity P2 tets, 1,971,054 elements
+
+def elasticity_workload(torch, felocal, inputs, stream, ev, record, reps):
     log("elasticity P2 on 1.97M tets")
     cn, V, cells = inputs.tet_workload(69, seed=3)
     E3 = cn.shape[0]
@@ -242,7 +268,8 @@ def other_workloads(torch, felocal, inputs, stream, ev, reps):
     del o3, c3, cf3
     torch.cuda.empty_cache()
 
-    # hyperelastic P1, P2 tets, 998,250 elements
+
+def hyperelastic_workload(torch, felocal, inputs, stream, ev, record, reps):
     cn, V, cells = inputs.tet_workload(55, seed=4)
     E4 = cn.shape[0]
     c4 = torch.from_numpy(cn).cuda()
@@ -262,7 +289,8 @@ def other_workloads(torch, felocal, inputs, stream, ev, reps):
         torch.cuda.empty_cache()
     del c4
 
-    # mixed persistent batch, 16 sub-batches, one HIP graph
+
+def batch_workload(torch, felocal, inputs, stream, ev, reps):
     log("mixed batch: 16 sub-batches in one persistent graph launch")
     rng = np.random.default_rng(5)
     subs, tot_e, tot_b, tot_f = [], 0, 0, 0
@@ -290,14 +318,14 @@ def other_workloads(torch, felocal, inputs, stream, ev, reps):
                                                                  s["coeff"], s["out"]) for s in subs],
                       stream, ev, reps)
     b.close()
-    res.append({"workload": "mixed_batch_16", "elements": tot_e, "ms": round(ms, 4),
-                "elem_per_s": round(tot_e / (ms * 1e-3), 1), "alg_GBs": round(tot_b / (ms * 1e-3) / 1e9, 1),
-                "alg_GFLOPs": round(tot_f / (ms * 1e-3) / 1e9, 1), "tiles": ntiles, "grid": grid,
-                "separate_launches_ms": round(seq, 4), "sub_batches": desc})
+    row = {"workload": "mixed_batch_16", "elements": tot_e, "ms": round(ms, 4),
+           "elem_per_s": round(tot_e / (ms * 1e-3), 1), "alg_GBs": round(tot_b / (ms * 1e-3) / 1e9, 1),
+           "alg_GFLOPs": round(tot_f / (ms * 1e-3) / 1e9, 1), "tiles": ntiles, "grid": grid,
+           "separate_launches_ms": round(seq, 4), "sub_batches": desc}
     log(f"  mixed batch: {ms:.3f} ms graph vs {seq:.3f} ms separate launches, {tot_e} elements")
     del subs
     torch.cuda.empty_cache()
-    return res
+    return row
 
 
 def cpu_baseline(coords_np):

@@ -18,7 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fe_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_LIB = os.environ.get("FE_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 CELL = {"triangle": 0, "tetrahedron": 1, "prism": 2}
 FORM = {"mass": 0, "helmholtz": 1, "elasticity": 2, "hyperelastic": 3}
@@ -27,15 +27,17 @@ NVERT = {"triangle": 3, "tetrahedron": 4, "prism": 6}
 REF_VOLUME = {"triangle": 0.5, "tetrahedron": 1.0 / 6.0, "prism": 0.5}
 
 
-def build(force: bool = False) -> str:
+def build(force: bool = False, out: str | None = None, defines=()) -> str:
     """Compile the oracle with gcc (portable flags: it runs on other hosts)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+    target = out or _LIB
+    if force or not os.path.exists(target) or os.path.getmtime(target) < os.path.getmtime(_SRC):
+        tmp = target + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", _SRC, "-o", tmp, "-lm"]
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", *[f"-D{d}" for d in defines],
+             _SRC, "-o", tmp, "-lm"]
         )
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, target)
+    return target
 
 
 _lib = None

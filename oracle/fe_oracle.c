@@ -40,6 +40,10 @@
 #include <omp.h>
 #endif
 
+#ifndef ORC_MUTANT
+#define ORC_MUTANT 0   /* tests/test_oracle_mutants.py builds planted-mistake variants */
+#endif
+
 #define ORC_MAXQ1 16          /* max points per collapsed direction  */
 #define ORC_MAXNB 80          /* max scalar basis functions (prism P4 = 75) */
 #define ORC_MAXQ  (ORC_MAXQ1 * ORC_MAXQ1 * ORC_MAXQ1)
@@ -107,7 +111,7 @@ static void gauss_jacobi01(int m, int a, double *t, double *w)
         jacobi_eval(m, (long double)a, xs[i], &pn, &dpn);
         long double wx = powl(2.0L, a + 1) / ((1.0L - xs[i] * xs[i]) * dpn * dpn);
         t[i] = (double)(0.5L * (xs[i] + 1.0L));
-        w[i] = (double)(wx / powl(2.0L, a + 1));
+        w[i] = (double)(wx / powl(2.0L, a + 1 + (ORC_MUTANT == 5 ? 1 : 0)));
     }
 }
 
@@ -199,8 +203,8 @@ static void silvester_1d(int p, int a, double t, double *L, double *dL)
 {
     double v = 1.0, d = 0.0;
     for (int m = 0; m < a; ++m) {
-        double f = (p * t - m) / (m + 1.0);
-        double df = p / (m + 1.0);
+        double f = (p * t - m) / (m + 1.0 + (ORC_MUTANT == 6 ? 1.0 : 0.0));
+        double df = p / (m + 1.0 + (ORC_MUTANT == 6 ? 1.0 : 0.0));
         d = d * f + v * df;
         v = v * f;
     }
@@ -357,7 +361,7 @@ static double elasticity_pair(int d, int c, int e, const double *gj, const doubl
         tru += Eu[a * d + a];
         for (int b = 0; b < d; ++b) dd += Ev[a * d + b] * Eu[a * d + b];
     }
-    return 2.0 * mu * dd + lam * trv * tru;
+    return 2.0 * mu * dd + (ORC_MUTANT == 1 ? 0.0 : lam) * trv * tru;
 }
 
 /* Neo-Hookean first Piola stress P = mu (F - F^{-T}) + lam ln J F^{-T} and
@@ -380,9 +384,9 @@ static void neo_hookean(int d, const double *F, double mu, double lam, double *P
                      * d (F^{-T})_cb / d F_eg = -Fi[b][e] Fi[g][c]
                      * d lnJ / d F_eg = Fi[g][e]                            */
                     double v = mu * ((c == e && b == g) ? 1.0 : 0.0)
-                             + mu * Fi[b * d + e] * Fi[g * d + c]
+                             + (ORC_MUTANT == 2 ? -mu : mu) * Fi[b * d + e] * Fi[g * d + c]
                              + lam * Fi[g * d + e] * Fi[b * d + c]
-                             - lam * lnJ * Fi[b * d + e] * Fi[g * d + c];
+                             - (ORC_MUTANT == 7 ? 0.0 : lam) * lnJ * Fi[b * d + e] * Fi[g * d + c];
                     AA[((c * d + b) * d + e) * d + g] = v;
                 }
 }
@@ -434,12 +438,12 @@ int64_t orc_assemble(int form, int cell, int p, int qdeg, int64_t E,
             for (int i = 0; i < ns; ++i)
                 for (int b = 0; b < d; ++b) {
                     double s = 0.0;
-                    for (int a = 0; a < d; ++a) s += K[a * d + b] * dphi[i * d + a];
+                    for (int a = 0; a < d; ++a) s += (ORC_MUTANT == 3 ? K[b * d + a] : K[a * d + b]) * dphi[i * d + a];
                     g[i * d + b] = s;
                 }
             if (form == 0) {
                 for (int i = 0; i < ns; ++i)
-                    for (int j = 0; j < ns; ++j) A[i * n + j] += dx * phi[i] * phi[j];
+                    for (int j = 0; j < ns; ++j) A[i * n + j] += dx * phi[i] * phi[ORC_MUTANT == 4 ? i : j];
             } else if (form == 1) {
                 for (int i = 0; i < ns; ++i)
                     for (int j = 0; j < ns; ++j) {

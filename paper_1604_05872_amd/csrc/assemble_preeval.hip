@@ -14,8 +14,7 @@ __global__ __launch_bounds__(512) void k_preeval(PreevalArgs a)
 template <int FORM, int CELL>
 static hipError_t go(const PreevalArgs& a, int block, int grid, hipStream_t s)
 {
-    constexpr int NT = n_tables(FORM, CELL);
-    const size_t lds = (size_t)a.chunk * NT * sizeof(double);
+    const size_t lds = preeval_lds_bytes(FORM, CELL, a.chunk);
     hipLaunchKernelGGL((k_preeval<FORM, CELL, preeval_mm(FORM)>), dim3(grid), dim3(block), lds, s, a);
     return hipGetLastError();
 }

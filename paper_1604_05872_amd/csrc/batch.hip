@@ -200,7 +200,8 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
             d.pa.epi = cfg.epi;
             d.pa.chunk = cfg.chunk;
             d.n_tiles = (sb.n_elems + cfg.chunk - 1) / cfg.chunk;
-            lds = std::max(lds, (size_t)cfg.chunk * n_tables(sb.form, sb.cell) * sizeof(double));
+            lds = std::max(lds, preeval_lds_bytes(sb.form, sb.cell, cfg.chunk));
+            d.pa.nt = store_mode();
         } else {
             const int kb = quad_kb(sb.cell, sb.degree);
             d.variant = variant_id(1, sb.form, sb.cell, (kb == 5) ? 0 : 1);
@@ -217,8 +218,10 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
             d.qa.E = sb.n_elems;
             d.qa.nq = t->nq;
             d.qa.ns = t->nb;
+            d.qa.collapse = (sb.form == FE_ELASTICITY && sb.degree == 1 && sb.cell != FE_PRISM) ? 1 : 0;
             d.qa.eb = cfg.eb;
             d.qa.qc = cfg.qc;
+            d.qa.nt = store_mode();
             d.n_tiles = (sb.n_elems + cfg.eb - 1) / cfg.eb;
             lds = std::max(lds, quad_lds_bytes(sb.form, sb.cell, t->nb, cfg.eb, cfg.qc));
         }

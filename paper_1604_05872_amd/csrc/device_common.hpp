@@ -104,9 +104,20 @@ __device__ __forceinline__ double inverse_small(const double (&F)[3][3], double 
     return det;
 }
 
-__device__ __forceinline__ void store_out(double* p, double v)
+// Output store.  nt = 1 marks the store non-temporal (streaming); nt = 0 is an
+// ordinary store, which lets L2 merge the partial lines that scattered row
+// segments produce before they reach HBM.
+__device__ __forceinline__ void store_out(double* p, double v, int nt)
 {
-    __builtin_nontemporal_store(v, p);
+    if (nt) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// Coalesced copy of `n` consecutive doubles from global memory into LDS by
+// the whole block.
+__device__ __forceinline__ void load_to_lds(double* __restrict__ dst, const double* __restrict__ src, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
 }  // namespace fe

@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -321,6 +322,25 @@ int fe_resolve_variant(int form, int cell, int degree, int qdeg, const fe_option
 
 namespace fe {
 
+// Output store mode: ordinary stores unless FE_NT_STORES=1 in the environment.
+int store_mode()
+{
+    static int mode = -1;
+    if (mode < 0) {
+        const char* v = std::getenv("FE_NT_STORES");
+        mode = (v && v[0] == '1') ? 1 : 0;
+    }
+    return mode;
+}
+
+// Generalised code motion (Sec. 3.2): with P1 on a simplex every gradient,
+// hence F, is invariant in the quadrature loop, so the vector forms hoist
+// the point loop and integrate the remaining scalar weights only.
+bool q_invariant(const Call& c)
+{
+    return is_vector_form(c.form) && c.degree == 1 && c.cell != PRISM;
+}
+
 // Launches one resolved call with an explicit configuration.
 int launch_call(const Call& c, const Config& cfg)
 {
@@ -339,14 +359,16 @@ int launch_call(const Call& c, const Config& cfg)
         a.E = c.E;
         a.nq = t->nq;
         a.ns = t->nb;
+        a.collapse = q_invariant(c) ? 1 : 0;
+        a.nt = store_mode();
         a.mu = c.mu;
         a.lam = c.lam;
-        const int nkb = t->nq <= 8 ? 1 : t->nq <= 16 ? 2 : 4;
+        const int nq_eff = a.collapse ? 1 : t->nq;
+        const int nqp = nq_eff <= 8 ? 8 : nq_eff <= 16 ? 16 : 32;
         const int64_t steps = (c.E + SPLIT_WAVES - 1) / SPLIT_WAVES;
         const int grid = (int)std::min<int64_t>(steps, (int64_t)cus * cfg.grid_per_cu);
-        const size_t lds = (c.cell == TRI ? split_lds_bytes<ELASTICITY, TRI>(t->nq, t->nb)
-                                          : split_lds_bytes<ELASTICITY, TET>(t->nq, t->nb));
-        e = launch_split(c.form, c.cell, c.prec == FE_SPLIT_FP32 ? SPLIT_FP32 : SPLIT_BF16X3, nkb, a, grid, lds,
+        const size_t lds = split_lds_bytes(c.cell, t->nq, t->nb);
+        e = launch_split(c.form, c.cell, c.prec == FE_SPLIT_FP32 ? SPLIT_FP32 : SPLIT_BF16X3, nqp, a, grid, lds,
                          c.stream);
         if (e != hipSuccess) return set_hip_error(e, "split-precision launch");
         return FE_OK;
@@ -361,6 +383,7 @@ int launch_call(const Call& c, const Config& cfg)
         a.nn = t->nb * t->nb;
         a.epi = cfg.epi;
         a.chunk = cfg.chunk;
+        a.nt = store_mode();
         const int64_t tiles = (c.E + a.chunk - 1) / a.chunk;
         const int grid = (int)std::min<int64_t>(tiles, (int64_t)cus * cfg.grid_per_cu);
         e = launch_preeval(c.form, c.cell, a, cfg.block, grid, c.stream);
@@ -381,6 +404,8 @@ int launch_call(const Call& c, const Config& cfg)
     a.E = c.E;
     a.nq = t->nq;
     a.ns = t->nb;
+    a.collapse = q_invariant(c) ? 1 : 0;
+    a.nt = store_mode();
     a.eb = cfg.eb;
     a.qc = cfg.qc;
     a.mu = c.mu;

@@ -37,7 +37,7 @@ inline hipError_t launch_quad(int form, int cell, int kb, const QuadArgs& a, int
     default: return launch_quad_hyperelastic(cell, kb, a, grid, lds, s);
     }
 }
-hipError_t launch_split(int form, int cell, int prec, int nkb, const SplitArgs& a, int grid, size_t lds,
+hipError_t launch_split(int form, int cell, int prec, int nqp, const SplitArgs& a, int grid, size_t lds,
                         hipStream_t s);
 
 // slot tile of the pre-evaluated kernel (registers per pass) per form
@@ -80,6 +80,11 @@ struct Config {
 };
 
 Config default_preeval_config(int nn, int mm);
+// LDS of one pre-evaluated tile: geometry tensors plus the staged coordinates
+inline size_t preeval_lds_bytes(int form, int cell, int chunk)
+{
+    return (size_t)chunk * (n_tables(form, cell) + cell_nv(cell) * cell_dim(cell)) * sizeof(double);
+}
 Config default_quad_config(int form, int cell, int p, int nq);
 size_t quad_lds_bytes(int form, int cell, int ns, int eb, int qc);
 
@@ -101,6 +106,7 @@ struct Call {
 };
 
 int launch_call(const Call& c, const Config& cfg);
+int store_mode();
 // configuration from the autotune cache, else the built-in default
 void lookup_config(const Call& c, Config* cfg);
 

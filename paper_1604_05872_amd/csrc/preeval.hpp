@@ -31,19 +31,21 @@ struct PreevalArgs {
     int nn;                 // n^2
     int epi;                // elements per step
     int chunk;              // elements per tile (multiple of epi)
+    int nt;                 // non-temporal output stores
 };
 
 template <int FORM, int CELL>
 constexpr int preeval_nt() { return n_tables(FORM, CELL); }
 
-// Geometry tensor of one element; returns nonzero when the element is flagged.
+// Geometry tensor of one element (vertices v); returns nonzero when the
+// element is flagged.
 template <int FORM, int CELL>
-__device__ __forceinline__ int preeval_coeffs(const double* __restrict__ coords, int64_t e, double* c)
+__device__ __forceinline__ int preeval_coeffs(const double* __restrict__ vsrc, double* c)
 {
     constexpr int D = cell_dim(CELL), NV = cell_nv(CELL);
     double v[NV * D];
 #pragma unroll
-    for (int k = 0; k < NV * D; ++k) v[k] = coords[e * (NV * D) + k];
+    for (int k = 0; k < NV * D; ++k) v[k] = vsrc[k];
     double K[3][3], adet;
     const int bad = affine_map<CELL>(v, K, adet);
     c[0] = adet;
@@ -70,18 +72,24 @@ __device__ __forceinline__ int preeval_coeffs(const double* __restrict__ coords,
 }
 
 // One tile of elements [e_begin, min(e_begin + chunk, E)).  sG: LDS of
-// chunk * NT doubles.  Every thread of the block must call it.
+// chunk * (NT + nv * d) doubles (geometry tensors, then the staged
+// coordinates).  Every thread of the block must call it.
 template <int FORM, int CELL, int MM>
 __device__ void preeval_tile(const PreevalArgs& a, int64_t e_begin, double* sG)
 {
     constexpr int NT = preeval_nt<FORM, CELL>();
+    constexpr int NVD = cell_nv(CELL) * cell_dim(CELL);
     const int tid = threadIdx.x, B = blockDim.x;
     const int64_t rem = a.E - e_begin;
     const int ne = rem < a.chunk ? (int)rem : a.chunk;
+    double* sV = sG + (size_t)a.chunk * NT;
 
+    // coordinates of the tile: one contiguous span, loaded coalesced
+    load_to_lds(sV, a.coords + e_begin * NVD, ne * NVD);
+    __syncthreads();
     for (int i = tid; i < ne; i += B) {
         double c[NT];
-        const int bad = preeval_coeffs<FORM, CELL>(a.coords, e_begin + i, c);
+        const int bad = preeval_coeffs<FORM, CELL>(sV + i * NVD, c);
         if (bad) {
 #pragma unroll
             for (int r = 0; r < NT; ++r) c[r] = __builtin_nan("");
@@ -115,18 +123,37 @@ __device__ void preeval_tile(const PreevalArgs& a, int64_t e_begin, double* sG)
                 for (int r = 0; r < NT; ++r) R[m][r] = 0.0;
             }
         }
-        for (int it = 0; it < steps; ++it) {
-            const int lim = ne - it * epi;
-            double* o = a.out + (e_begin + (int64_t)it * epi) * nn;
-            const double* g0 = sG + it * epi * NT;
+        if (epi == 1) {
+            // one element per step: its geometry tensor is shared by every slot
+            for (int it = 0; it < steps; ++it) {
+                double* o = a.out + (e_begin + (int64_t)it) * nn;
+                double g[NT];
 #pragma unroll
-            for (int m = 0; m < MM; ++m) {
-                if (el[m] < lim) {
-                    const double* g = g0 + el[m] * NT;
-                    double v = g[0] * R[m][0];
+                for (int r = 0; r < NT; ++r) g[r] = sG[it * NT + r];
 #pragma unroll
-                    for (int r = 1; r < NT; ++r) v = fma(g[r], R[m][r], v);
-                    store_out(o + fs[m], v);
+                for (int m = 0; m < MM; ++m) {
+                    if (el[m] == 0) {
+                        double v = g[0] * R[m][0];
+#pragma unroll
+                        for (int r = 1; r < NT; ++r) v = fma(g[r], R[m][r], v);
+                        store_out(o + fs[m], v, a.nt);
+                    }
+                }
+            }
+        } else {
+            for (int it = 0; it < steps; ++it) {
+                const int lim = ne - it * epi;
+                double* o = a.out + (e_begin + (int64_t)it * epi) * nn;
+                const double* g0 = sG + it * epi * NT;
+#pragma unroll
+                for (int m = 0; m < MM; ++m) {
+                    if (el[m] < lim) {
+                        const double* g = g0 + el[m] * NT;
+                        double v = g[0] * R[m][0];
+#pragma unroll
+                        for (int r = 1; r < NT; ++r) v = fma(g[r], R[m][r], v);
+                        store_out(o + fs[m], v, a.nt);
+                    }
                 }
             }
         }

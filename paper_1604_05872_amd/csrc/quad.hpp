@@ -43,8 +43,11 @@ struct QuadArgs {
                                  // (entries r >= 1 are used), else NULL
     int64_t E;
     int nq, ns;
+    int collapse;         // gradients invariant in q (P1 on a simplex): the
+                          // point loop is hoisted, one pass with summed weights
     int eb;               // elements per tile
     int qc;               // points per LDS chunk
+    int nt;               // non-temporal output stores
     double mu, lam;       // hyperelastic constants
 };
 
@@ -119,8 +122,9 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
 #pragma unroll
             for (int x = 0; x < NA; ++x) acc[kk][x] = 0.0;
 
-        for (int q0 = 0; q0 < nq; q0 += qc_max) {
-            const int qc = min(qc_max, nq - q0);
+        const int nq_loop = a.collapse ? 1 : nq;
+        for (int q0 = 0; q0 < nq_loop; q0 += qc_max) {
+            const int qc = min(qc_max, nq_loop - q0);
             // --- stage per-point data -------------------------------------
             for (int idx = tid; idx < qc * ns; idx += B) sPhi[idx] = a.phi[q0 * ns + idx];
             for (int idx = tid; idx < eb * qc * ns; idx += B) {
@@ -142,22 +146,46 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
             for (int idx = tid; idx < eb * qc; idx += B) {
                 const int i = idx / qc, qq = idx - i * qc;
                 const int64_t e = e_begin + i;
-                const double w = a.W[q0 + qq] * sEl[i * L::PER_ELEM + 9];
+                double wsum = a.W[q0 + qq];
+                if (a.collapse) {
+                    wsum = 0.0;
+                    for (int q = 0; q < nq; ++q) wsum += a.W[q];
+                }
+                const double w = wsum * sEl[i * L::PER_ELEM + 9];
                 double* pt = sPt + ((size_t)i * qc_max + qq) * ppt;
                 double* sw = pt + ns * D + (FORM == HYPERELASTIC ? ns * D + 9 : 0);
                 if (FORM == MASS || FORM == HELMHOLTZ) {
                     sw[0] = w;
                 } else if (FORM == ELASTICITY) {
                     const double* ce = a.coeff + e * 2 * NV;
-                    const double* ps = a.psi + (q0 + qq) * NV;
-                    double lam = 0.0, mu = 0.0;
+                    if (a.collapse) {
+                        // sum_q W_q lambda(X_q), sum_q W_q mu(X_q)
+                        double lam = 0.0, mu = 0.0;
+                        for (int q = 0; q < nq; ++q) {
+                            const double* ps = a.psi + q * NV;
+                            double l1 = 0.0, m1 = 0.0;
 #pragma unroll
-                    for (int l = 0; l < NV; ++l) {
-                        lam = fma(ce[l], ps[l], lam);
-                        mu = fma(ce[NV + l], ps[l], mu);
+                            for (int l = 0; l < NV; ++l) {
+                                l1 = fma(ce[l], ps[l], l1);
+                                m1 = fma(ce[NV + l], ps[l], m1);
+                            }
+                            lam = fma(a.W[q], l1, lam);
+                            mu = fma(a.W[q], m1, mu);
+                        }
+                        const double adet = sEl[i * L::PER_ELEM + 9];
+                        sw[0] = adet * lam;
+                        sw[1] = adet * mu;
+                    } else {
+                        const double* ps = a.psi + (q0 + qq) * NV;
+                        double lam = 0.0, mu = 0.0;
+#pragma unroll
+                        for (int l = 0; l < NV; ++l) {
+                            lam = fma(ce[l], ps[l], lam);
+                            mu = fma(ce[NV + l], ps[l], mu);
+                        }
+                        sw[0] = w * lam;
+                        sw[1] = w * mu;
                     }
-                    sw[0] = w * lam;
-                    sw[1] = w * mu;
                 } else {
                     // F = I + sum_k u_k (x) g_k at this point
                     const double* ue = a.coeff + e * (D * ns);
@@ -285,7 +313,7 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
                         double* row = o + (size_t)(c * ns + uj) * n + e2 * ns + k0;
 #pragma unroll
                         for (int kk = 0; kk < KB; ++kk)
-                            if (kk < kn) store_out(row + kk, bad ? nanv : acc[kk][c * D + e2]);
+                            if (kk < kn) store_out(row + kk, bad ? nanv : acc[kk][c * D + e2], a.nt);
                     }
             } else {
                 double* row = o + (size_t)uj * n + k0;
@@ -324,7 +352,7 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
 #pragma unroll
                             for (int r = 0; r < D * (D + 1) / 2; ++r) v = fma(gt[r], a.stiff_tables[(1 + r) * nn + jk], v);
                         }
-                        store_out(row + kk, bad ? nanv : v);
+                        store_out(row + kk, bad ? nanv : v, a.nt);
                     }
             }
         }

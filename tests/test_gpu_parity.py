@@ -114,9 +114,10 @@ def test_fp64_parity(form, cell, p):
     cf = coefficients(form, cell, p, E, V, cells, h, seed=200 + p)
     A, st = gpu_assemble(form, cell, p, coords, cf)
     B, fl = oracle.assemble(form, cell, p, coords, cf)
-    assert st == fl == 0
-    assert np.isfinite(A).all()
-    assert normwise(A, B).max() <= TOL["fp64"]
+    bad = np.isnan(B[:, 0, 0])
+    assert st == fl == bad.sum() and fl <= E // 100
+    assert (np.isnan(A[:, 0, 0]) == bad).all() and np.isfinite(A[~bad]).all()
+    assert normwise(A[~bad], B[~bad]).max() <= TOL["fp64"]
 
 
 HELM_MODES = [("tetrahedron", 4, "preeval", 0), ("tetrahedron", 4, "quadrature", 0),
@@ -149,8 +150,10 @@ def test_split_parity(form, cell, p, prec):
     cf = coefficients(form, cell, p, E, V, cells, h, seed=400 + p)
     A, st = gpu_assemble(form, cell, p, coords, cf, precision=prec)
     B, fl = oracle.assemble(form, cell, p, coords, cf)
-    assert st == fl == 0
-    err = normwise(A, B)
+    bad = np.isnan(B[:, 0, 0])          # det F <= 0 somewhere: flagged on both sides
+    assert st == fl == bad.sum() and fl <= E // 100
+    assert (np.isnan(A[:, 0, 0]) == bad).all()
+    err = normwise(A[~bad], B[~bad])
     log(f"   max err {err.max():.3e}")
     assert err.max() <= TOL[prec]
 

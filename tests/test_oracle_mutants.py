@@ -1,0 +1,44 @@
+"""The pins must catch plausible mistakes: each planted mistake (built into a
+separate copy of the oracle with -DORC_MUTANT=k, on the CPU) has to fail at
+least one pin of tests/test_oracle_pins.py."""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = {
+    1: ("dropped lambda div-div term (elasticity)", "elasticity"),
+    2: ("wrong sign of the F^{-T} derivative (hyperelastic tangent)", "hyper"),
+    3: ("transposed K in the physical gradient", "helmholtz or elasticity"),
+    4: ("wrong index phi_i phi_i in the mass integrand", "mass"),
+    5: ("Gauss-Jacobi weights off by a factor 2", "rule"),
+    6: ("wrong denominator in the Silvester factor", "basis"),
+    7: ("dropped lambda ln J term of the tangent", "hyper"),
+}
+
+PINS = {
+    1: "elasticity_exact_rational or elasticity_p1_textbook",
+    2: "hyper_tangent_is_residual_derivative",
+    3: "mass_and_helmholtz_exact_rational",
+    4: "mass_p1_triangle_closed_form or mass_and_helmholtz_exact_rational",
+    5: "rule_exact_to_degree",
+    6: "basis_kronecker",
+    7: "hyper_tangent_is_residual_derivative",
+}
+
+
+@pytest.mark.parametrize("k", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(k):
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = oracle.build(force=True, out=os.path.join(tmp, f"liboracle_m{k}.so"), defines=[f"ORC_MUTANT={k}"])
+        env = dict(os.environ, FE_ORACLE_LIB=lib)
+        r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", PINS[k]],
+                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+        assert r.returncode == 1 and "failed" in r.stdout, (MUTANTS[k], r.stdout[-2000:])
