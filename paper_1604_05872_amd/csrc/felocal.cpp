@@ -365,11 +365,11 @@ int launch_call(const Call& c, const Config& cfg)
         a.lam = c.lam;
         const int nq_eff = a.collapse ? 1 : t->nq;
         const int nqp = nq_eff <= 8 ? 8 : nq_eff <= 16 ? 16 : 32;
-        const int64_t steps = (c.E + SPLIT_WAVES - 1) / SPLIT_WAVES;
+        const int64_t steps = (c.E + SPLIT_WAVES * SPLIT_EB - 1) / (SPLIT_WAVES * SPLIT_EB);
         const int grid = (int)std::min<int64_t>(steps, (int64_t)cus * cfg.grid_per_cu);
         const size_t lds = split_lds_bytes(c.cell, t->nq, t->nb);
-        e = launch_split(c.form, c.cell, c.prec == FE_SPLIT_FP32 ? SPLIT_FP32 : SPLIT_BF16X3, nqp, a, grid, lds,
-                         c.stream);
+        e = launch_split(c.form, c.cell, c.degree, c.prec == FE_SPLIT_FP32 ? SPLIT_FP32 : SPLIT_BF16X3, nqp, a, grid,
+                         lds, c.stream);
         if (e != hipSuccess) return set_hip_error(e, "split-precision launch");
         return FE_OK;
     }

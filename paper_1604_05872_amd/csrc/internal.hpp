@@ -37,8 +37,24 @@ inline hipError_t launch_quad(int form, int cell, int kb, const QuadArgs& a, int
     default: return launch_quad_hyperelastic(cell, kb, a, grid, lds, s);
     }
 }
-hipError_t launch_split(int form, int cell, int prec, int nqp, const SplitArgs& a, int grid, size_t lds,
-                        hipStream_t s);
+hipError_t launch_split_elasticity_fp32(int cell, int p, int nqp, const SplitArgs& a, int grid, size_t lds,
+                                       hipStream_t s);
+hipError_t launch_split_elasticity_bf16x3(int cell, int p, int nqp, const SplitArgs& a, int grid, size_t lds,
+                                         hipStream_t s);
+hipError_t launch_split_hyperelastic_fp32(int cell, int p, int nqp, const SplitArgs& a, int grid, size_t lds,
+                                         hipStream_t s);
+hipError_t launch_split_hyperelastic_bf16x3(int cell, int p, int nqp, const SplitArgs& a, int grid, size_t lds,
+                                           hipStream_t s);
+// prec: 1 = fp32 operands, 2 = bf16 hi/lo split
+inline hipError_t launch_split(int form, int cell, int p, int prec, int nqp, const SplitArgs& a, int grid,
+                               size_t lds, hipStream_t s)
+{
+    if (form == ELASTICITY)
+        return prec == 1 ? launch_split_elasticity_fp32(cell, p, nqp, a, grid, lds, s)
+                         : launch_split_elasticity_bf16x3(cell, p, nqp, a, grid, lds, s);
+    return prec == 1 ? launch_split_hyperelastic_fp32(cell, p, nqp, a, grid, lds, s)
+                     : launch_split_hyperelastic_bf16x3(cell, p, nqp, a, grid, lds, s);
+}
 
 // slot tile of the pre-evaluated kernel (registers per pass) per form
 constexpr int preeval_mm(int form) { return form == MASS ? 16 : 8; }

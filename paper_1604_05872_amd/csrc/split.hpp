@@ -7,7 +7,9 @@
 //     P_lam = X^T diag(lam') X,   P_2 = X^T diag(mu' or alpha') X,
 //     D[j][k] = sum_b Pg[(b,j),(b,k)],  Pg = G^T diag(mu') G,
 //     A[(c,j),(e,k)] = P_lam[(c,j),(e,k)] + P_2[(e,j),(c,k)] + delta_ce D[j][k]
-// (for elasticity G = X, so Pg = P_2).  The products run on the matrix cores:
+// (for elasticity G = X, so Pg = P_2).  Each product is evaluated as a Gram
+// matrix Z^T diag(sign) Z of the square-root-scaled columns Z = sqrt|w| X,
+// so only one operand per product is rounded.  The products run on the matrix cores:
 // one wavefront per element, the element matrix (n = d*n_s <= 32) padded to a
 // 32x32 tile, the quadrature point as the reduction dimension (zero-padded).
 //
@@ -20,14 +22,18 @@
 //     with three products hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16
 //     (v_mfma_f32_32x32x8_bf16 when the rule has at most 8 points), dropping
 //     lo*lo (FE_SPLIT_BF16X3),
-// accumulated in fp32; the final three-term combination is float64.
+// accumulated in fp32; the three-term combination is summed in fp32 and
+// stored as float64.
 //
 // Each wavefront owns its LDS area and walks its own elements; no block-wide
 // barrier is taken after the tables are staged, so wavefronts of a block
 // overlap their VALU, matrix-core and store phases.  Per element:
-//   A. the element's coordinates and coefficients (prefetched into one
-//      register per lane during the previous element) go to LDS;
-//   B. one lane per quadrature point computes the float64 point data;
+//   A. (once per batch of SPLIT_EB elements) the batch's coordinates and
+//      coefficients, loaded into registers during the previous batch, go to
+//      LDS, and the loads of the next batch are issued, so one global round
+//      trip is hidden behind a whole batch;
+//   B. one lane per (element, quadrature point) of the batch computes the
+//      float64 point data for the whole batch;
 //   C. every lane builds exactly the operand entries the instruction layout
 //      assigns to it (column (c,j) = lane % 32) and runs the MFMAs;
 //   D. the block-transposed and trace terms are exchanged through LDS and the
@@ -62,24 +68,28 @@ struct SplitArgs {
 constexpr int SPLIT_WAVES = 4;
 constexpr int SPLIT_TILE_LD = 33;   // padded rows against bank conflicts
 constexpr int SPLIT_MAX_IN = 48;    // nv*d + coefficients of one element (at most 42 when n <= 32)
+constexpr int SPLIT_EB = 4;         // elements per wavefront batch (one global round trip)
+constexpr int SPLIT_PRE = (SPLIT_EB * SPLIT_MAX_IN + 63) / 64;   // prefetch registers per lane
 
 // per-wave LDS (bytes)
-constexpr int SPW_IN = 0;                                  // inputs [48] f64
-constexpr int SPW_W = SPW_IN + SPLIT_MAX_IN * 8;           // weights [32][4] f32
-constexpr int SPW_M = SPW_W + 32 * 4 * 4;                  // M^T per point [32][3][3] f32 (row c: M[0..2][c])
-constexpr int SPW_K = SPW_M + 32 * 9 * 4;                  // K^T [3][3] f32
-constexpr int SPW_FLAG = SPW_K + 12 * 4;
-constexpr int SPW_T2 = SPW_FLAG + 16;                      // P_2 tile [32][33] f32
+constexpr int SPW_IN = 0;                                          // inputs [EB][48] f64
+constexpr int SPW_W = SPW_IN + SPLIT_EB * SPLIT_MAX_IN * 8;        // weights [EB][32][4] f32
+constexpr int SPW_M = SPW_W + SPLIT_EB * 32 * 4 * 4;               // M^T [EB][32][3][3] f32
+constexpr int SPW_K = SPW_M + SPLIT_EB * 32 * 9 * 4;               // K^T [EB][12] f32
+constexpr int SPW_FLAG = SPW_K + SPLIT_EB * 12 * 4;                // flags [EB] (+pad)
+constexpr int SPW_GEO = SPW_FLAG + 16;                             // K [EB][9] f64, |det J| [EB] f64
+constexpr int SPW_T2 = SPW_GEO + SPLIT_EB * 10 * 8;        // P_2 tile [32][33] f32
 constexpr int SPW_TG = SPW_T2 + 32 * SPLIT_TILE_LD * 4;    // P_g tile [32][33] f32
 constexpr int SPLIT_WAVE_BYTES = SPW_TG + 32 * SPLIT_TILE_LD * 4;
 
 // block LDS: 4 wave areas, then W [nq] f64, psi [nq][nv] f64, reference
-// gradients [nq][ns][d] as f64 (for F) and as f32 (for the operands)
+// gradients [nq][ns][d] as f64 (for F) and as f32 zero-padded to 32 points
+// (for the operands)
 __host__ __device__ constexpr size_t split_lds_bytes(int cell, int nq, int ns)
 {
     return (size_t)SPLIT_WAVES * SPLIT_WAVE_BYTES +
            ((size_t)nq + (size_t)nq * cell_nv(cell) + (size_t)nq * ns * cell_dim(cell)) * 8 +
-           (size_t)nq * ns * cell_dim(cell) * 4;
+           (size_t)32 * ns * cell_dim(cell) * 4;
 }
 
 template <int FORM, int CELL>
@@ -96,23 +106,26 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// NQP: padded point count (8, 16 or 32).  Every thread of the block runs it.
-template <int FORM, int CELL, int PREC, int NQP>
+// P: polynomial degree (the scalar space size is then a compile-time
+// constant); NQP: padded point count (8, 16 or 32).  Every thread of the
+// block runs it.
+template <int FORM, int CELL, int PREC, int P, int NQP>
 __device__ void split_kernel_body(const SplitArgs& a, char* lds)
 {
     constexpr int D = cell_dim(CELL), NV = cell_nv(CELL), NVD = NV * D;
     constexpr bool HYP = (FORM == HYPERELASTIC);
+    constexpr int ns = n_scalar(CELL, P), n = D * ns;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int ns = a.ns, n = D * ns, nq_all = a.nq;
+    const int nq_all = a.nq;
     const int nq = a.collapse ? 1 : nq_all;     // points of the contraction
-    const int ncf = split_coeffs_per_elem<FORM, CELL>(ns);
-    const int nin = NVD + ncf;                   // inputs per element
+    constexpr int ncf = split_coeffs_per_elem<FORM, CELL>(ns);
+    constexpr int nin = NVD + ncf;               // inputs per element
 
     char* wl = lds + wave * SPLIT_WAVE_BYTES;
-    double* sIn = (double*)(wl + SPW_IN);
-    float* sW = (float*)(wl + SPW_W);
-    float* sMt = (float*)(wl + SPW_M);
-    float* sKt = (float*)(wl + SPW_K);
+    double* sBuf = (double*)(wl + SPW_IN);
+    float* sWall = (float*)(wl + SPW_W);
+    float* sMall = (float*)(wl + SPW_M);
+    float* sKall = (float*)(wl + SPW_K);
     int* sFlag = (int*)(wl + SPW_FLAG);
     float* tP2 = (float*)(wl + SPW_T2);
     float* tPg = (float*)(wl + SPW_TG);
@@ -124,40 +137,88 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
     // tables, once per block
     for (int i = tid; i < nq_all; i += blockDim.x) gW[i] = a.W[i];
     for (int i = tid; i < nq_all * NV; i += blockDim.x) gPsi[i] = a.psi[i];
-    for (int i = tid; i < nq_all * ns * D; i += blockDim.x) {
-        gTab[i] = a.dphi[i];
-        gTabF[i] = (float)a.dphi[i];
+    for (int i = tid; i < nq_all * ns * D; i += blockDim.x) gTab[i] = a.dphi[i];
+    for (int i = tid; i < 32 * ns * D; i += blockDim.x) gTabF[i] = i < nq * ns * D ? (float)a.dphi[i] : 0.f;
+    // padding points q >= nq carry zero weights and zero matrices
+    for (int i = lane; i < SPLIT_EB * 32 * 4; i += 64) {
+        const int q = (i >> 2) & 31;
+        if (q >= nq) ((float*)(wl + SPW_W))[i] = 0.f;
+    }
+    for (int i = lane; i < SPLIT_EB * 32 * 9; i += 64) {
+        const int q = (i / 9) & 31;
+        if (q >= nq) ((float*)(wl + SPW_M))[i] = 0.f;
     }
     // summed weights for the hoisted point loop of P1 simplices
     double wsum = 0.0;
     for (int q = 0; q < nq_all; ++q) wsum += a.W[q];
     __syncthreads();
 
-    int64_t e = (int64_t)blockIdx.x * SPLIT_WAVES + wave;
-    const int64_t stride = (int64_t)gridDim.x * SPLIT_WAVES;
-    auto fetch = [&](int64_t ee) -> double {
-        if (lane >= nin || ee >= a.E) return 0.0;
-        return lane < NVD ? a.coords[ee * NVD + lane] : a.coeff[ee * ncf + (lane - NVD)];
+    const int64_t stride = (int64_t)gridDim.x * SPLIT_WAVES * SPLIT_EB;
+    constexpr int nbatch_in = SPLIT_EB * nin;
+    double pre[SPLIT_PRE];
+    auto fetch = [&](int64_t first) {
+#pragma unroll
+        for (int k = 0; k < SPLIT_PRE; ++k) {
+            const int t = lane + 64 * k;
+            const int i = t / nin, x = t - (t / nin) * nin;
+            const int64_t ee = first + i;
+            pre[k] = 0.0;
+            if (t < nbatch_in && ee < a.E)
+                pre[k] = x < NVD ? a.coords[ee * NVD + x] : a.coeff[ee * ncf + (x - NVD)];
+        }
     };
-    double pre = fetch(e);
+    int64_t b0 = ((int64_t)blockIdx.x * SPLIT_WAVES + wave) * SPLIT_EB;
+    fetch(b0);
 
     const int col = lane & 31, half = lane >> 5;
+    // columns >= n only feed rows/columns of the 32x32 tile that are never
+    // stored, so their operand values just have to stay finite
     const bool cvalid = col < n;
     const int cc = cvalid ? col / ns : 0;
     const int cj = cvalid ? col - cc * ns : 0;
+    (void)cvalid;
+    static_assert(n <= 32 && nin <= SPLIT_MAX_IN, "element matrix must fit one 32x32 tile");
 
-    for (; e < a.E; e += stride) {
-        // --- A: inputs to LDS; prefetch the next element -------------------
-        if (lane < nin) sIn[lane] = pre;
-        pre = fetch(e + stride);
+    for (; b0 < a.E; b0 += stride) {
+        // --- A: this batch's inputs to LDS; loads of the next batch ----------
+#pragma unroll
+        for (int k = 0; k < SPLIT_PRE; ++k) {
+            const int t = lane + 64 * k;
+            if (t < nbatch_in) {
+                const int i = t / nin;
+                sBuf[i * SPLIT_MAX_IN + (t - i * nin)] = pre[k];
+            }
+        }
+        if (lane < SPLIT_EB) sFlag[lane] = 0;
+        fetch(b0 + stride);
         wave_sync();
 
-        // --- B: float64 point data, one lane per point ----------------------
-        int bad = 0;
-        if (lane < nq) {
-            const int q = lane;
+        // --- B0: geometry, one lane per element of the batch ------------------
+        double* sGeo = (double*)(wl + SPW_GEO);
+        if (lane < SPLIT_EB && b0 + lane < a.E) {
             double K[3][3], adet;
-            bad = affine_map<CELL>(sIn, K, adet);
+            const int bad = affine_map<CELL>(sBuf + lane * SPLIT_MAX_IN, K, adet);
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sGeo[lane * 10 + r * 3 + c] = (r < D && c < D) ? K[r][c] : 0.0;
+            sGeo[lane * 10 + 9] = adet;
+            if (bad) sFlag[lane] = 1;
+        }
+        wave_sync();
+
+        // --- B: float64 point data, one lane per (element, point) -----------
+        for (int t = lane; t < SPLIT_EB * nq; t += 64) {
+            const int ib = t / nq, q = t - ib * nq;
+            if (b0 + ib >= a.E) continue;
+            const double* sIn = sBuf + ib * SPLIT_MAX_IN;
+            double K[3][3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) K[r][c] = sGeo[ib * 10 + r * 3 + c];
+            const double adet = sGeo[ib * 10 + 9];
+            int bad = 0;
             const double w = (a.collapse ? wsum : gW[q]) * adet;
             double M[3][3];
             float w0, w1, w2 = 0.f;
@@ -230,9 +291,14 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                         M[r][c] = (r < D && c < D) ? s : 0.0;
                     }
             }
-            sW[q * 4 + 0] = w0;
-            sW[q * 4 + 1] = w1;
-            sW[q * 4 + 2] = w2;
+            // weights enter as square roots (P = Z^T Z with Z = sqrt(w) X); the
+            // sign of the possibly negative alpha' is kept separately
+            float* sW = sWall + ib * 32 * 4;
+            float* sMt = sMall + ib * 32 * 9;
+            sW[q * 4 + 0] = sqrtf(fabsf(w0));
+            sW[q * 4 + 1] = sqrtf(fabsf(w1));
+            sW[q * 4 + 2] = sqrtf(fabsf(w2));
+            sW[q * 4 + 3] = w1 < 0.f ? -0.f : 0.f;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -241,134 +307,127 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int r = 0; r < 3; ++r) sKt[c * 3 + r] = (r < D && c < D) ? (float)K[r][c] : 0.f;
+                    for (int r = 0; r < 3; ++r) sKall[ib * 12 + c * 3 + r] = (r < D && c < D) ? (float)K[r][c] : 0.f;
+            if (bad) sFlag[ib] = 1;
         }
-        bad = __any(bad) ? 1 : 0;
         wave_sync();
 
-        // --- C: operands and matrix-core products ---------------------------
-        float kc[3];
+        // --- C, D: per element of the batch ------------------------------------
+#pragma unroll 1
+        for (int ib = 0; ib < SPLIT_EB; ++ib) {
+            const int64_t e = b0 + ib;
+            if (e >= a.E) break;
+            const float* sW = sWall + ib * 32 * 4;
+            const float* sMt = sMall + ib * 32 * 9;
+            float kc[3];
 #pragma unroll
-        for (int b = 0; b < 3; ++b) kc[b] = sKt[cc * 3 + b];
+            for (int b = 0; b < 3; ++b) kc[b] = sKall[ib * 12 + cc * 3 + b];
 
-        v16f accL, acc2, accG;
+            v16f accL, acc2, accG;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            accL[r] = 0.f;
-            acc2[r] = 0.f;
-            accG[r] = 0.f;
-        }
-        // x (s for the hyperelastic form, else g) of the lane's column at
-        // point q with the weights of P_lam and P_2; g with the weight of P_g
-        auto colx = [&](int q, float& x, float& w1, float& w2) {
-            x = w1 = w2 = 0.f;
-            if (cvalid && q < nq) {
+            for (int r = 0; r < 16; ++r) {
+                accL[r] = 0.f;
+                acc2[r] = 0.f;
+                accG[r] = 0.f;
+            }
+            // Scaled columns at point q (zero at padding points):
+            //   z1 = sqrt(lam') x, z2 = sqrt|w2| x, z3 = sqrt(mu') g with
+            // x = s (hyperelastic) or g; P_lam = Z1^T Z1, P_2 = Z2^T diag(sign) Z2,
+            // P_g = Z3^T Z3.  The sign of a point is its sign bit (0 or
+            // 0x80000000), applied to the B operand by an exact bit flip.
+            auto colx = [&](int q) -> float {
                 const float* gh = gTabF + (q * ns + cj) * D;
                 const float* m = sMt + q * 9 + cc * 3;
-                float sx = m[0] * gh[0];
+                float x = m[0] * gh[0];
 #pragma unroll
-                for (int b = 1; b < D; ++b) sx = fmaf(m[b], gh[b], sx);
-                x = sx;
-                w1 = sW[q * 4 + 0];
-                w2 = sW[q * 4 + 1];
-            }
-        };
-        auto colg = [&](int q, float& g, float& w3) {
-            g = w3 = 0.f;
-            if (cvalid && q < nq) {
+                for (int b = 1; b < D; ++b) x = fmaf(m[b], gh[b], x);
+                return x;
+            };
+            auto colg = [&](int q) -> float {
                 const float* gh = gTabF + (q * ns + cj) * D;
-                float sg = kc[0] * gh[0];
+                float g = kc[0] * gh[0];
 #pragma unroll
-                for (int b = 1; b < D; ++b) sg = fmaf(kc[b], gh[b], sg);
-                g = sg;
-                w3 = sW[q * 4 + 2];
-            }
-        };
-        if (PREC == SPLIT_BF16X3) {
-            if (NQP == 8) {
-                auto gram4 = [&](const float* xv, const float* wv, v16f& acc) {
-                    v4bf xh, xl, yh, yl;
+                for (int b = 1; b < D; ++b) g = fmaf(kc[b], gh[b], g);
+                return sW[q * 4 + 2] * g;
+            };
+            auto sgn = [&](int q) -> unsigned { return __float_as_uint(sW[q * 4 + 3]); };
+            if (PREC == SPLIT_BF16X3) {
+                constexpr int KW = NQP == 8 ? 4 : 8;    // points per lane per instruction
+                typedef __bf16 vbf __attribute__((ext_vector_type(KW)));
+                typedef unsigned vu __attribute__((ext_vector_type(KW / 2)));
+                auto split = [&](const float* z, vbf& h, vbf& l) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const __bf16 h = (__bf16)xv[i];
-                        xh[i] = h;
-                        xl[i] = (__bf16)(xv[i] - (float)h);
-                        const float y = wv[i] * xv[i];
-                        const __bf16 yh_ = (__bf16)y;
-                        yh[i] = yh_;
-                        yl[i] = (__bf16)(y - (float)yh_);
+                    for (int i = 0; i < KW; ++i) {
+                        const __bf16 hi = (__bf16)z[i];
+                        h[i] = hi;
+                        l[i] = (__bf16)(z[i] - (float)hi);
                     }
-                    const v4s a_h = __builtin_bit_cast(v4s, xh), a_l = __builtin_bit_cast(v4s, xl);
-                    const v4s b_h = __builtin_bit_cast(v4s, yh), b_l = __builtin_bit_cast(v4s, yl);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a_l, b_h, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a_h, b_l, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a_h, b_h, acc, 0, 0, 0);
                 };
-                float xv[4], w1v[4], w2v[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) colx(4 * half + i, xv[i], w1v[i], w2v[i]);
-                gram4(xv, w1v, accL);
-                gram4(xv, w2v, acc2);
-                if (HYP) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) colg(4 * half + i, xv[i], w1v[i]);
-                    gram4(xv, w1v, accG);
-                }
-            } else {
-                auto gram8 = [&](const float* xv, const float* wv, v16f& acc) {
-                    v8bf xh, xl, yh, yl;
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        const __bf16 h = (__bf16)xv[i];
-                        xh[i] = h;
-                        xl[i] = (__bf16)(xv[i] - (float)h);
-                        const float y = wv[i] * xv[i];
-                        const __bf16 yh_ = (__bf16)y;
-                        yh[i] = yh_;
-                        yl[i] = (__bf16)(y - (float)yh_);
-                    }
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl, yh, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh, yl, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh, yh, acc, 0, 0, 0);
+                auto mma = [&](const vbf& x, const vbf& y, v16f& acc) {
+                    if constexpr (KW == 4)
+                        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(__builtin_bit_cast(v4s, x),
+                                                                       __builtin_bit_cast(v4s, y), acc, 0, 0, 0);
+                    else
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, acc, 0, 0, 0);
+                };
+                // hi*hi + hi*lo + lo*hi
+                auto gram = [&](const vbf& h, const vbf& l, const vbf& hb, const vbf& lb, v16f& acc) {
+                    mma(l, hb, acc);
+                    mma(h, lb, acc);
+                    mma(h, hb, acc);
                 };
 #pragma unroll 1
-                for (int kb = 0; kb < NQP / 16; ++kb) {
-                    float xv[8], w1v[8], w2v[8];
+                for (int kb = 0; kb < NQP / (2 * KW); ++kb) {
+                    const int q0 = 2 * KW * kb + KW * half;
+                    float x[KW], z[KW];
+                    vbf h, l;
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) colx(16 * kb + 8 * half + i, xv[i], w1v[i], w2v[i]);
-                    gram8(xv, w1v, accL);
-                    gram8(xv, w2v, acc2);
+                    for (int i = 0; i < KW; ++i) x[i] = colx(q0 + i);
+#pragma unroll
+                    for (int i = 0; i < KW; ++i) z[i] = sW[(q0 + i) * 4 + 0] * x[i];
+                    split(z, h, l);
+                    gram(h, l, h, l, accL);
+#pragma unroll
+                    for (int i = 0; i < KW; ++i) z[i] = sW[(q0 + i) * 4 + 1] * x[i];
+                    split(z, h, l);
+                    vu sm;
+#pragma unroll
+                    for (int i = 0; i < KW / 2; ++i) sm[i] = (sgn(q0 + 2 * i) >> 16) | sgn(q0 + 2 * i + 1);
+                    const vbf hb = __builtin_bit_cast(vbf, __builtin_bit_cast(vu, h) ^ sm);
+                    const vbf lb = __builtin_bit_cast(vbf, __builtin_bit_cast(vu, l) ^ sm);
+                    gram(h, l, hb, lb, acc2);
                     if (HYP) {
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) colg(16 * kb + 8 * half + i, xv[i], w1v[i]);
-                        gram8(xv, w1v, accG);
+                        for (int i = 0; i < KW; ++i) z[i] = colg(q0 + i);
+                        split(z, h, l);
+                        gram(h, l, h, l, accG);
+                    }
+                }
+            } else {
+#pragma unroll 2
+                for (int ks = 0; ks < NQP / 2; ++ks) {
+                    const int q = 2 * ks + half;
+                    const float x = colx(q);
+                    const float z1 = sW[q * 4 + 0] * x, z2 = sW[q * 4 + 1] * x;
+                    accL = __builtin_amdgcn_mfma_f32_32x32x2f32(z1, z1, accL, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(z2, __uint_as_float(__float_as_uint(z2) ^ sgn(q)),
+                                                                acc2, 0, 0, 0);
+                    if (HYP) {
+                        const float z3 = colg(q);
+                        accG = __builtin_amdgcn_mfma_f32_32x32x2f32(z3, z3, accG, 0, 0, 0);
                     }
                 }
             }
-        } else {
-#pragma unroll 2
-            for (int ks = 0; ks < NQP / 2; ++ks) {
-                float x, w1, w2;
-                colx(2 * ks + half, x, w1, w2);
-                accL = __builtin_amdgcn_mfma_f32_32x32x2f32(x, w1 * x, accL, 0, 0, 0);
-                acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(x, w2 * x, acc2, 0, 0, 0);
-                if (HYP) {
-                    float g, w3;
-                    colg(2 * ks + half, g, w3);
-                    accG = __builtin_amdgcn_mfma_f32_32x32x2f32(g, w3 * g, accG, 0, 0, 0);
-                }
-            }
-        }
 
-        // --- D: epilogue --------------------------------------------------
+            // --- D: epilogue ------------------------------------------------
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = 8 * (r >> 2) + 4 * half + (r & 3);
-            tP2[row * SPLIT_TILE_LD + col] = acc2[r];
-            if (HYP) tPg[row * SPLIT_TILE_LD + col] = accG[r];
-        }
-        wave_sync();
-        {
+            for (int r = 0; r < 16; ++r) {
+                const int row = 8 * (r >> 2) + 4 * half + (r & 3);
+                tP2[row * SPLIT_TILE_LD + col] = acc2[r];
+                if (HYP) tPg[row * SPLIT_TILE_LD + col] = accG[r];
+            }
+            wave_sync();
+            const bool bad = sFlag[ib] != 0;
             const float* tD = HYP ? tPg : tP2;
             double* o = a.out + e * (int64_t)n * n;
             const double nanv = __builtin_nan("");
@@ -378,19 +437,17 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                 if (row < n && col < n) {
                     const int c = row / ns, j = row - c * ns;
                     const int d2 = col / ns, k = col - d2 * ns;
-                    double v = (double)accL[r] + (double)tP2[(d2 * ns + j) * SPLIT_TILE_LD + c * ns + k];
+                    float v = accL[r] + tP2[(d2 * ns + j) * SPLIT_TILE_LD + c * ns + k];
                     if (c == d2) {
-                        double t = 0.0;
 #pragma unroll
-                        for (int b = 0; b < D; ++b) t += (double)tD[(b * ns + j) * SPLIT_TILE_LD + b * ns + k];
-                        v += t;
+                        for (int b = 0; b < D; ++b) v += tD[(b * ns + j) * SPLIT_TILE_LD + b * ns + k];
                     }
-                    store_out(o + (size_t)row * n + col, bad ? nanv : v, a.nt);
+                    store_out(o + (size_t)row * n + col, bad ? nanv : (double)v, a.nt);
                 }
             }
             if (bad && lane == 0 && a.status) atomicAdd(a.status, 1);
+            wave_sync();
         }
-        wave_sync();
     }
 }
 
