@@ -90,6 +90,27 @@ enum {
     FE_ENOMEM = -5      /* allocation failed, or a size limit exceeded     */
 };
 
+/* Launch shape override.  Every field 0 = automatic (the autotuner's choice
+ * for the variant when one is cached, else the built-in default); a nonzero
+ * field replaces that field of the automatic shape.
+ *   kernel       pre-evaluated mode: 1 = tiled kernel (tiles of `chunk`
+ *                consecutive elements staged through LDS), 2 = streaming
+ *                kernel (table entries held in registers for the whole
+ *                launch, which needs epi * n^2 <= 8 * block, 16 * block for
+ *                the mass form; visits of `chunk` consecutive elements)
+ *   block        threads of the pre-evaluated kernels (multiple of 64, <= 512)
+ *   epi          pre-evaluated: elements per step (1 <= epi <= block)
+ *   chunk        pre-evaluated: elements per tile or visit, a multiple of
+ *                epi (streaming: 0 = automatic, about 256 KiB of output)
+ *   eb, qc       quadrature kernel: elements per tile, points per LDS chunk
+ *   grid_per_cu  any kernel: at most this many resident blocks per CU
+ * A shape that the kernel cannot take (or whose LDS exceeds the device's
+ * per-block limit) is rejected with FE_EINVAL before any launch.  Fields
+ * that do not apply to the selected kernel are ignored. */
+typedef struct {
+    int kernel, block, epi, chunk, eb, qc, grid_per_cu;
+} fe_shape_t;
+
 typedef struct {
     int            qdeg;       /* -1: form default (mass, Helmholtz 2p;
                                   elasticity 2p-1, prisms 2p+1; hyperelastic 4);
@@ -108,6 +129,7 @@ typedef struct {
     int            validate;   /* nonzero: synchronously copy coords to the
                                   host and reject non-affine prisms with
                                   FE_ENONAFFINE before launching            */
+    fe_shape_t     shape;      /* launch shape override; zero = automatic   */
 } fe_options_t;
 
 /* Fills *opt with the defaults listed above. */
@@ -211,15 +233,18 @@ int fe_batch_destroy(fe_batch_t* batch);
 /* Number of work tiles and the persistent grid size of a batch. */
 int fe_batch_info(const fe_batch_t* batch, int64_t* n_tiles, int* grid);
 
-/* Autotuner: times the candidate tile shapes of the variant that serves
- * (form, cell, degree) on the given DEVICE inputs (n_elems >= 1) and stores
- * the fastest in the in-memory cache (and in the JSON file named by the
- * environment variable FE_AUTOTUNE_CACHE, if set).  Synchronous.  *best_ms
- * (may be NULL) receives the best time per launch.
+/* Autotuner: times the candidate launch shapes of the variant that serves
+ * (form, cell, degree) on the given DEVICE inputs (n_elems >= 1; out_A is
+ * overwritten) and stores the fastest in the in-memory cache (and in the
+ * JSON file named by the environment variable FE_AUTOTUNE_CACHE, if set).
+ * Synchronous.  *best_ms and *best_shape (either may be NULL) receive the
+ * best time per launch and its shape (kernel 1 or 2 for the pre-evaluated
+ * mode, 0 otherwise; chunk 0 = automatic visit length), which the caller can
+ * also pass back through fe_options_t.shape.  opt->shape is ignored.
  * Errors: FE_EINVAL, FE_ENOTSUP, FE_EHIP. */
 int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems,
                 const double* coords, const double* coeff_dofs, double* out_A,
-                const fe_options_t* opt, double* best_ms);
+                const fe_options_t* opt, double* best_ms, fe_shape_t* best_shape);
 
 /* Human-readable text for an FE_* code. */
 const char* fe_strerror(int code);

@@ -47,9 +47,10 @@ void load_file_locked()
         Config c;
         if (std::sscanf(line,
                         "{\"form\": %d, \"cell\": %d, \"degree\": %d, \"qdeg\": %d, \"mode\": %d, \"precision\": %d, "
-                        "\"block\": %d, \"epi\": %d, \"chunk\": %d, \"eb\": %d, \"qc\": %d, \"grid_per_cu\": %d",
+                        "\"block\": %d, \"epi\": %d, \"chunk\": %d, \"eb\": %d, \"qc\": %d, \"grid_per_cu\": %d, "
+                        "\"stream\": %d",
                         &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &c.block, &c.epi, &c.chunk, &c.eb, &c.qc,
-                        &c.grid_per_cu) == 12)
+                        &c.grid_per_cu, &c.stream) == 13)
             g_tuned[Key(v[0], v[1], v[2], v[3], v[4], v[5])] = c;
     }
     std::fclose(f);
@@ -58,7 +59,7 @@ void load_file_locked()
 Config default_for(const Call& c)
 {
     if (c.prec != FE_FP64) return Config();
-    if (c.mode == FE_MODE_PREEVAL) return default_preeval_config(c.tables->nb * c.tables->nb, preeval_mm(c.form));
+    if (c.mode == FE_MODE_PREEVAL) return default_preeval_config(c.form, c.tables->nb * c.tables->nb);
     return default_quad_config(c.form, c.cell, c.degree, c.tables->nq);
 }
 
@@ -76,21 +77,37 @@ std::vector<Config> candidates(const Call& c)
     }
     if (c.mode == FE_MODE_PREEVAL) {
         const int nn = c.tables->nb * c.tables->nb, mm = preeval_mm(c.form);
+        // streaming shapes: largest step that fits 4, 8 (mass 16) slots per thread
+        for (int block : {256, 320, 384, 448, 512}) {
+            for (int smm : {4, 8, 16}) {
+                if (smm == 16 && c.form != MASS) continue;
+                const int epi = std::min(block, smm * block / nn);
+                if (epi < 1 || preeval_stream_mm(c.form, epi * nn, block) != smm) continue;
+                if ((double)(epi * nn) / (smm * block) < 0.75) continue;
+                Config x;
+                x.block = block;
+                x.epi = epi;
+                x.stream = 1;
+                x.grid_per_cu = 8;   // capped by occupancy at launch
+                for (int t : {0, 4, 8, 16, 24, 32}) {
+                    x.chunk = t * epi;
+                    out.push_back(x);
+                }
+            }
+        }
         for (int block : {256, 320, 384, 512}) {
             for (int epi : {1, 2, 4, 8, 16, 32, 64}) {
                 const int m = (epi * nn + block - 1) / block;
                 if (m > 2 * mm || (epi > 1 && epi * nn > 8 * block * mm)) continue;
                 const double waste = 1.0 - (double)(epi * nn) / (m * block);
                 if (waste > 0.2) continue;
-                for (int per : {1, 2}) {
+                for (int per : {16, 256}) {
                     Config x;
                     x.block = block;
                     x.epi = epi;
-                    x.chunk = epi * std::max(1, per * 256 / epi);
-                    for (int g : {4, 8}) {
-                        x.grid_per_cu = g;
-                        out.push_back(x);
-                    }
+                    x.chunk = epi * std::max(1, per / epi);
+                    x.grid_per_cu = 8;
+                    out.push_back(x);
                 }
             }
         }
@@ -120,7 +137,7 @@ void lookup_config(const Call& c, Config* cfg)
         std::lock_guard<std::mutex> lk(g_tmu);
         load_file_locked();
         auto it = g_tuned.find(key_of(c));
-        if (it != g_tuned.end()) {
+        if (it != g_tuned.end() && check_config(c, it->second) == FE_OK) {
             *cfg = it->second;
             return;
         }
@@ -136,13 +153,17 @@ int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, co
 using namespace fe;
 
 extern "C" int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
-                           const double* coeff_dofs, double* out_A, const fe_options_t* opt, double* best_ms)
+                           const double* coeff_dofs, double* out_A, const fe_options_t* opt, double* best_ms,
+                           fe_shape_t* best_shape)
 {
     if (n_elems < 1) return FE_EINVAL;
     Call c;
     int rc = resolve_call(form, cell, degree, n_elems, coords, coeff_dofs, out_A, opt, &c);
     if (rc) return rc;
-    std::vector<Config> cands = candidates(c);
+    std::vector<Config> cands;
+    for (const Config& x : candidates(c))
+        if (check_config(c, x) == FE_OK) cands.push_back(x);
+    if (cands.empty()) return FE_EINVAL;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return set_hip_error(hipErrorUnknown, "autotune events");
@@ -181,14 +202,23 @@ extern "C" int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n
                 std::fprintf(f,
                              "{\"form\": %d, \"cell\": %d, \"degree\": %d, \"qdeg\": %d, \"mode\": %d, "
                              "\"precision\": %d, \"block\": %d, \"epi\": %d, \"chunk\": %d, \"eb\": %d, \"qc\": %d, "
-                             "\"grid_per_cu\": %d, \"ms\": %.6f}\n",
+                             "\"grid_per_cu\": %d, \"stream\": %d, \"ms\": %.6f}\n",
                              c.form, c.cell, c.degree, c.qdeg, c.mode, c.prec, best_cfg.block, best_cfg.epi,
-                             best_cfg.chunk, best_cfg.eb, best_cfg.qc, best_cfg.grid_per_cu, best);
+                             best_cfg.chunk, best_cfg.eb, best_cfg.qc, best_cfg.grid_per_cu, best_cfg.stream, best);
                 std::fclose(f);
             }
         }
     }
     if (best_ms) *best_ms = best;
+    if (best_shape) {
+        best_shape->kernel = (c.prec == FE_FP64 && c.mode == FE_MODE_PREEVAL) ? (best_cfg.stream ? 2 : 1) : 0;
+        best_shape->block = best_cfg.block;
+        best_shape->epi = best_cfg.epi;
+        best_shape->chunk = best_cfg.chunk;
+        best_shape->eb = best_cfg.eb;
+        best_shape->qc = best_cfg.qc;
+        best_shape->grid_per_cu = best_cfg.grid_per_cu;
+    }
     return FE_OK;
 }
 

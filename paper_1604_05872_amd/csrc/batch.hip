@@ -124,7 +124,7 @@ void destroy(fe_batch* b)
 // pre-evaluated tile shape with the persistent kernel's block of 256
 Config batch_preeval_config(const Config& tuned, int nn, int mm)
 {
-    if (tuned.block == 256) return tuned;
+    if (tuned.block == 256 && !tuned.stream) return tuned;
     Config best;
     best.block = 256;
     double best_w = 1e9;

@@ -126,7 +126,7 @@ int get_tables(int cell, int p, int qdeg, hipStream_t s, const RefTables** out)
     return FE_OK;
 }
 
-Config default_preeval_config(int nn, int mm)
+Config default_preeval_tiled_config(int nn, int mm)
 {
     // choose (block, epi) with the least idle slots, one pass when possible
     Config best;
@@ -149,6 +149,34 @@ Config default_preeval_config(int nn, int mm)
     }
     best.chunk = best.epi * std::max(1, 256 / best.epi);
     return best;
+}
+
+Config default_preeval_config(int form, int nn)
+{
+    // Streaming kernel when a step fits in registers: the fewest idle slots
+    // at 4 (else 8, mass 16) slots per thread, at least 1024 stores a step.
+    Config best;
+    double best_score = 1e9;
+    for (int block : {256, 320, 384, 448, 512}) {
+        for (int mm : {4, 8, 16}) {
+            if (mm == 16 && form != MASS) continue;
+            const int epi = std::min(block, mm * block / nn);
+            if (epi < 1) continue;
+            const int slots = epi * nn;
+            if (preeval_stream_mm(form, slots, block) != mm) continue;
+            const double score = 1.0 - (double)slots / (mm * block) + (slots < 1024 ? 0.3 : 0.0) +
+                                 (mm > 4 ? 0.05 * (mm / 8) : 0.0);
+            if (score < best_score - 1e-9) {
+                best_score = score;
+                best.block = block;
+                best.epi = epi;
+                best.chunk = 0;
+                best.stream = 1;
+            }
+        }
+    }
+    if (best_score < 1e9) return best;
+    return default_preeval_tiled_config(nn, preeval_mm(form));
 }
 
 Config default_quad_config(int form, int cell, int p, int nq)
@@ -384,6 +412,14 @@ int launch_call(const Call& c, const Config& cfg)
         a.epi = cfg.epi;
         a.chunk = cfg.chunk;
         a.nt = store_mode();
+        if (cfg.stream) {
+            if (cfg.epi < 1 || cfg.epi > cfg.block || cfg.chunk < 0 || cfg.chunk % cfg.epi ||
+                preeval_stream_mm(c.form, cfg.epi * a.nn, cfg.block) == 0)
+                return FE_EINVAL;   // a streaming step must fit in registers
+            e = launch_preeval_stream(c.form, c.cell, a, cfg.block, cfg.grid_per_cu, cus, c.stream);
+            if (e != hipSuccess) return set_hip_error(e, "pre-evaluated launch");
+            return FE_OK;
+        }
         const int64_t tiles = (c.E + a.chunk - 1) / a.chunk;
         const int grid = (int)std::min<int64_t>(tiles, (int64_t)cus * cfg.grid_per_cu);
         e = launch_preeval(c.form, c.cell, a, cfg.block, grid, c.stream);
@@ -418,6 +454,59 @@ int launch_call(const Call& c, const Config& cfg)
     return FE_OK;
 }
 
+size_t device_lds_per_block()
+{
+    static size_t lds[64] = {0};
+    int d = current_device();
+    if (d < 0 || d >= 64) return 64 * 1024;
+    if (lds[d] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, d) != hipSuccess || v <= 0)
+            v = 64 * 1024;
+        lds[d] = (size_t)v;
+    }
+    return lds[d];
+}
+
+int check_config(const Call& c, const Config& cfg)
+{
+    if (cfg.grid_per_cu < 1 || cfg.grid_per_cu > 64) return FE_EINVAL;
+    if (c.prec != FE_FP64) return FE_OK;
+    const RefTables* t = c.tables;
+    const size_t max_lds = device_lds_per_block();
+    if (c.mode == FE_MODE_PREEVAL) {
+        const int nn = t->nb * t->nb;
+        if (cfg.block < 64 || cfg.block > 512 || cfg.block % 64 || cfg.epi < 1 || cfg.epi > cfg.block)
+            return FE_EINVAL;
+        if (cfg.chunk < 0 || cfg.chunk % cfg.epi) return FE_EINVAL;
+        if (cfg.stream) {
+            if (preeval_stream_mm(c.form, cfg.epi * nn, cfg.block) == 0) return FE_EINVAL;
+            return preeval_stream_lds_bytes(c.form, c.cell, cfg.block, cfg.epi) <= max_lds ? FE_OK : FE_EINVAL;
+        }
+        if (cfg.chunk == 0) return FE_EINVAL;
+        return preeval_lds_bytes(c.form, c.cell, cfg.chunk) <= max_lds ? FE_OK : FE_EINVAL;
+    }
+    if (cfg.eb < 1 || cfg.qc < 1 || cfg.qc > t->nq) return FE_EINVAL;
+    return quad_lds_bytes(c.form, c.cell, t->nb, cfg.eb, cfg.qc) <= max_lds ? FE_OK : FE_EINVAL;
+}
+
+int final_config(const Call& c, Config* cfg)
+{
+    lookup_config(c, cfg);
+    const int* s = c.shape;   // kernel, block, epi, chunk, eb, qc, grid_per_cu
+    const Config autocfg = *cfg;
+    if (s[0]) cfg->stream = s[0] == 2;
+    if (s[1]) cfg->block = s[1];
+    if (s[2]) cfg->epi = s[2];
+    if (s[3]) cfg->chunk = s[3];
+    else if (cfg->stream != autocfg.stream || cfg->epi != autocfg.epi)
+        cfg->chunk = cfg->stream ? 0 : cfg->epi * std::max(1, 256 / cfg->epi);
+    if (s[4]) cfg->eb = s[4];
+    if (s[5]) cfg->qc = s[5];
+    if (s[6]) cfg->grid_per_cu = s[6];
+    return check_config(c, *cfg);
+}
+
 // Validates the arguments of fe_assemble_local and resolves them into a Call.
 int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
                  const double* coeff_dofs, double* out_A, const fe_options_t* opt, Call* c)
@@ -444,6 +533,12 @@ int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, co
     c->mu = o.mu;
     c->lam = o.lambda;
     c->stream = (hipStream_t)o.stream;
+    const int sh[7] = {o.shape.kernel, o.shape.block, o.shape.epi, o.shape.chunk,
+                       o.shape.eb,     o.shape.qc,    o.shape.grid_per_cu};
+    for (int i = 0; i < 7; ++i) {
+        if (sh[i] < 0 || (i == 0 && sh[i] > 2)) return FE_EINVAL;
+        c->shape[i] = sh[i];
+    }
     if (n_elems == 0) return FE_OK;
     if (!coords || !out_A) return FE_EINVAL;
     if (is_vector_form(form) && !coeff_dofs) return FE_EINVAL;
@@ -468,7 +563,8 @@ int fe_assemble_local(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elem
     int rc = resolve_call(form, cell, degree, n_elems, coords, coeff_dofs, out_A, opt, &c);
     if (rc || n_elems == 0) return rc;
     Config cfg;
-    lookup_config(c, &cfg);
+    rc = final_config(c, &cfg);
+    if (rc) return rc;
     return launch_call(c, cfg);
 }
 

@@ -24,6 +24,10 @@ hipError_t launch_geometry(int cell, int64_t E, const double* coords, double* de
 
 // assemble_*.hip
 hipError_t launch_preeval(int form, int cell, const PreevalArgs& a, int block, int grid, hipStream_t s);
+// streaming pre-evaluated kernel: persistent grid of at most max_per_cu
+// resident blocks per CU
+hipError_t launch_preeval_stream(int form, int cell, const PreevalArgs& a, int block, int max_per_cu, int cus,
+                                 hipStream_t s);
 hipError_t launch_quad_mass(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_quad_helmholtz(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_quad_elasticity(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
@@ -58,6 +62,18 @@ inline hipError_t launch_split(int form, int cell, int p, int prec, int nqp, con
 
 // slot tile of the pre-evaluated kernel (registers per pass) per form
 constexpr int preeval_mm(int form) { return form == MASS ? 16 : 8; }
+// Slots per thread of the streaming kernel for `slots` = epi * n^2 entries
+// per step: 4, 8 (or 16 for the one-table mass form); 0 when a step does
+// not fit in registers (the tiled kernel is used then).
+constexpr int preeval_stream_mm(int form, int slots, int block)
+{
+    return slots <= 4 * block ? 4 : slots <= 8 * block ? 8 : (form == MASS && slots <= 16 * block) ? 16 : 0;
+}
+// (upper bound: a geometry group is at most block / epi steps)
+inline size_t preeval_stream_lds_bytes(int form, int cell, int block, int epi)
+{
+    return (size_t)2 * (block / epi) * epi * n_tables(form, cell) * sizeof(double);
+}
 // k-block width of the quadrature kernel
 constexpr int quad_kb(int cell, int p)
 {
@@ -89,13 +105,16 @@ int set_hip_error(hipError_t e, const char* where);
 struct Config {
     int block = 256;
     int epi = 1;      // pre-evaluated: elements per step
-    int chunk = 256;  // pre-evaluated: elements per tile
+    int chunk = 256;  // pre-evaluated: elements per tile (streaming: per visit, 0 = automatic)
     int eb = 1;       // quadrature: elements per tile
     int qc = 1;       // quadrature: points per LDS chunk
     int grid_per_cu = 8;
+    int stream = 0;   // pre-evaluated: 1 = streaming kernel, 0 = tiled kernel
 };
 
-Config default_preeval_config(int nn, int mm);
+// pre-evaluated kernel: streaming when a step fits in registers, else tiled
+Config default_preeval_config(int form, int nn);
+Config default_preeval_tiled_config(int nn, int mm);
 // LDS of one pre-evaluated tile: geometry tensors plus the staged coordinates
 inline size_t preeval_lds_bytes(int form, int cell, int chunk)
 {
@@ -108,6 +127,7 @@ size_t quad_lds_bytes(int form, int cell, int ns, int eb, int qc);
 struct Call {
     int form = 0, cell = 0, degree = 1, qdeg = 2;
     int mode = 0;       // FE_MODE_PREEVAL or FE_MODE_QUADRATURE
+    int shape[7] = {0, 0, 0, 0, 0, 0, 0};   // caller's launch-shape override (fe_shape_t order)
     int mass_pre = 0;   // Helmholtz quadrature: bit 0 mass monomial pre-evaluated,
                         // bit 1 gradient monomial pre-evaluated
     int prec = 0;       // fe_precision_t
@@ -125,5 +145,10 @@ int launch_call(const Call& c, const Config& cfg);
 int store_mode();
 // configuration from the autotune cache, else the built-in default
 void lookup_config(const Call& c, Config* cfg);
+// 0 when the kernel selected by c can take cfg, else FE_EINVAL
+int check_config(const Call& c, const Config& cfg);
+// automatic shape with the caller's override applied and checked
+int final_config(const Call& c, Config* cfg);
+size_t device_lds_per_block();
 
 }  // namespace fe

@@ -161,4 +161,133 @@ __device__ void preeval_tile(const PreevalArgs& a, int64_t e_begin, double* sG)
     __syncthreads();
 }
 
+// Streaming variant, used when one step's slots fit in registers
+// (epi * n^2 <= blockDim * MM): every block loads its table entries once and
+// keeps them for the whole launch.  The grid is persistent and the steps of
+// epi consecutive elements are grouped into visits of T = chunk / epi
+// consecutive steps; block b (after the XCD-aware renumbering below) takes
+// the visits b, b + G, b + 2G, ..., so the grid writes one window of G
+// visits that sweeps through the output, each block one contiguous run at a
+// time.  Geometry tensors are produced one element per thread for the next
+// S = min(T, blockDim / epi) steps of the block at a time, double-buffered in
+// LDS: the coordinate loads of the next group are issued before the stores of
+// the current group.  sG: 2 * S * epi * NT doubles.
+template <int FORM, int CELL, int MM>
+__device__ void preeval_stream(const PreevalArgs& a, double* sG)
+{
+    constexpr int NT = preeval_nt<FORM, CELL>();
+    constexpr int NVD = cell_nv(CELL) * cell_dim(CELL);
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int nn = a.nn, epi = a.epi;
+    const int G = gridDim.x;
+    // Consecutive workgroups are dealt to the 8 XCDs in turn; renumber them
+    // so that consecutive logical blocks (adjacent visits, hence adjacent
+    // coordinates and output lines) share an XCD and its L2.
+    const int b = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+    const int T = a.chunk / epi;                    // steps per visit
+    const int64_t nsteps = (a.E + epi - 1) / epi;
+    const int64_t nvisits = (nsteps + T - 1) / T;
+    if (b >= nvisits) return;
+    const int64_t K = ((nvisits - 1 - b) / G + 1) * T;   // local steps (the last visit may run past the end)
+    // Steps per geometry group: at most one visit, so that a group's
+    // coordinates are one contiguous range (one page) of the input.
+    const int S = T < B / epi ? T : B / epi;
+    const int GE = S * epi;                         // elements per group (<= B)
+
+    // table entries of this thread's slots (one pass covers a step)
+    double R[MM][NT];
+    int el[MM], jk[MM];
+#pragma unroll
+    for (int m = 0; m < MM; ++m) {
+        const int f = tid + B * m;
+        if (f < epi * nn) {
+            el[m] = f / nn;
+            jk[m] = f - el[m] * nn;
+#pragma unroll
+            for (int r = 0; r < NT; ++r) R[m][r] = a.tables[r * nn + jk[m]];
+        } else {
+            el[m] = 1 << 30;
+            jk[m] = 0;
+#pragma unroll
+            for (int r = 0; r < NT; ++r) R[m][r] = 0.0;
+        }
+    }
+
+    // coordinates of this thread's element in group g (registers)
+    double v[NVD];
+    bool have = false;
+    auto fetch = [&](int64_t g) {
+        const int64_t L = g * S + tid / epi;
+        const int64_t e = ((b + (L / T) * G) * T + L % T) * epi + tid % epi;
+        have = tid < GE && L < K && e < a.E;
+        if (have) {
+#pragma unroll
+            for (int i = 0; i < NVD; ++i) v[i] = a.coords[e * NVD + i];
+        }
+    };
+    auto geometry = [&](double* dst) {
+        if (have) {
+            double c[NT];
+            if (preeval_coeffs<FORM, CELL>(v, c)) {
+#pragma unroll
+                for (int r = 0; r < NT; ++r) c[r] = __builtin_nan("");
+                if (a.status) atomicAdd(a.status, 1);
+            }
+#pragma unroll
+            for (int r = 0; r < NT; ++r) dst[tid * NT + r] = c[r];
+        }
+    };
+
+    fetch(0);
+    geometry(sG);
+    __syncthreads();
+    for (int64_t g = 0; g * S < K; ++g) {
+        fetch(g + 1);
+        const double* g0 = sG + (g & 1) * GE * NT;
+        const int ns_here = (int)(K - g * S < S ? K - g * S : S);
+        // visit and step within it of the group's first local step
+        int64_t vq = (g * S) / T;
+        int vr = (int)((g * S) % T);
+        for (int i = 0; i < ns_here; ++i) {
+            const int64_t e0 = ((b + vq * G) * T + vr) * epi;
+            if (++vr == T) {
+                vr = 0;
+                ++vq;
+            }
+            if (e0 >= a.E) continue;
+            const int64_t rem = a.E - e0;
+            const int lim = rem < epi ? (int)rem : epi;
+            double* o = a.out + e0 * nn;
+            const double* gi = g0 + i * epi * NT;
+            if (epi == 1) {
+                double gg[NT];
+#pragma unroll
+                for (int r = 0; r < NT; ++r) gg[r] = gi[r];
+#pragma unroll
+                for (int m = 0; m < MM; ++m) {
+                    if (el[m] == 0) {
+                        double x = gg[0] * R[m][0];
+#pragma unroll
+                        for (int r = 1; r < NT; ++r) x = fma(gg[r], R[m][r], x);
+                        store_out(o + jk[m], x, a.nt);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < MM; ++m) {
+                    if (el[m] < lim) {
+                        const double* gm = gi + el[m] * NT;
+                        double x = gm[0] * R[m][0];
+#pragma unroll
+                        for (int r = 1; r < NT; ++r) x = fma(gm[r], R[m][r], x);
+                        store_out(o + el[m] * nn + jk[m], x, a.nt);
+                    }
+                }
+            }
+        }
+        geometry(sG + ((g + 1) & 1) * GE * NT);
+        __syncthreads();
+    }
+}
+
 }  // namespace fe

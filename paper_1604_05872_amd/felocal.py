@@ -37,6 +37,10 @@ class FeError(RuntimeError):
         super().__init__(f"{where}: {strerror(code)} (code {code})")
 
 
+class fe_shape_t(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int) for f in ("kernel", "block", "epi", "chunk", "eb", "qc", "grid_per_cu")]
+
+
 class fe_options_t(ctypes.Structure):
     _fields_ = [
         ("qdeg", ctypes.c_int),
@@ -48,6 +52,7 @@ class fe_options_t(ctypes.Structure):
         ("d_status", ctypes.c_void_p),
         ("th_bytes", ctypes.c_size_t),
         ("validate", ctypes.c_int),
+        ("shape", fe_shape_t),
     ]
 
 
@@ -154,7 +159,7 @@ def _f64_dev(t, name):
 
 
 def make_options(qdeg=-1, precision="fp64", mode="auto", stream=None, mu=1.0, lam=10.0, status=None,
-                 th_bytes=0, validate=False, need_stream=True) -> fe_options_t:
+                 th_bytes=0, validate=False, need_stream=True, shape=None) -> fe_options_t:
     o = fe_options_t()
     lib().fe_options_init(ctypes.byref(o))
     o.qdeg = int(qdeg)
@@ -166,6 +171,8 @@ def make_options(qdeg=-1, precision="fp64", mode="auto", stream=None, mu=1.0, la
     o.d_status = status.data_ptr() if status is not None else None
     o.th_bytes = int(th_bytes)
     o.validate = 1 if validate else 0
+    for k, v in (shape or {}).items():
+        setattr(o.shape, k, int(v))
     return o
 
 
@@ -198,8 +205,12 @@ def fe_tabulate(cell: str, degree: int, qdeg: int, rule_only: bool = False):
 
 def fe_assemble_local(form: str, cell: str, degree: int, coords, coeff, out, qdeg: int = -1,
                       precision: str = "fp64", mode: str = "auto", stream=None, mu: float = 1.0,
-                      lam: float = 10.0, status=None, th_bytes: int = 0, validate: bool = False):
-    """Element matrices of `form` into `out` [E][n][n] (asynchronous on the stream)."""
+                      lam: float = 10.0, status=None, th_bytes: int = 0, validate: bool = False,
+                      shape: dict | None = None):
+    """Element matrices of `form` into `out` [E][n][n] (asynchronous on the stream).
+
+    shape: optional launch-shape override, keys of fe_shape_t (kernel: 1 tiled,
+    2 streaming; block, epi, chunk, eb, qc, grid_per_cu)."""
     _f64_dev(coords, "coords")
     _f64_dev(coeff, "coeff")
     _f64_dev(out, "out")
@@ -211,7 +222,7 @@ def fe_assemble_local(form: str, cell: str, degree: int, coords, coeff, out, qde
         raise ValueError(f"out must be [E][{n}][{n}]")
     if nc and (coeff is None or coeff.numel() != E * nc):
         raise ValueError(f"coeff must hold {nc} values per element")
-    o = make_options(qdeg, precision, mode, stream, mu, lam, status, th_bytes, validate)
+    o = make_options(qdeg, precision, mode, stream, mu, lam, status, th_bytes, validate, shape=shape)
     _check(lib().fe_assemble_local(FORMS[form], CELLS[cell], int(degree), E, _ptr(coords), _ptr(coeff),
                                    _ptr(out), ctypes.byref(o)), "fe_assemble_local")
     return out
@@ -245,13 +256,19 @@ def fe_plan(form: str, cell: str, degree: int, qdeg: int = -1, th_bytes: int = 0
 
 
 def fe_autotune(form: str, cell: str, degree: int, coords, coeff, out, qdeg: int = -1,
-                precision: str = "fp64", mode: str = "auto", stream=None, mu: float = 1.0, lam: float = 10.0) -> float:
+                precision: str = "fp64", mode: str = "auto", stream=None, mu: float = 1.0, lam: float = 10.0,
+                return_shape: bool = False):
+    """Best time per launch in ms (and, with return_shape, the chosen launch shape as a dict)."""
     _f64_dev(coords, "coords")
     _f64_dev(out, "out")
     o = make_options(qdeg, precision, mode, stream, mu, lam)
     best = ctypes.c_double()
+    shape = fe_shape_t()
     _check(lib().fe_autotune(FORMS[form], CELLS[cell], int(degree), int(coords.shape[0]), _ptr(coords),
-                             _ptr(coeff), _ptr(out), ctypes.byref(o), ctypes.byref(best)), "fe_autotune")
+                             _ptr(coeff), _ptr(out), ctypes.byref(o), ctypes.byref(best), ctypes.byref(shape)),
+           "fe_autotune")
+    if return_shape:
+        return best.value, {f: getattr(shape, f) for f, _ in fe_shape_t._fields_}
     return best.value
 
 

@@ -136,6 +136,92 @@ def test_helmholtz_modes_agree(cell, p, mode, th):
     assert st == 0 and normwise(A, B).max() <= TOL["fp64"]
 
 
+# Launch shapes of the pre-evaluated kernels: streaming (kernel 2) with one-step
+# and multi-step visits, and tiled (kernel 1), with small persistent grids so
+# that every block walks several groups, visits or tiles, ragged element
+# counts, a ragged last step and a ragged last visit.
+SHAPES = [
+    ("mass", "triangle", 1, dict(kernel=2, block=64, epi=64, chunk=64, grid_per_cu=1), 40001),
+    ("mass", "triangle", 1, dict(kernel=2, block=64, epi=64, chunk=192, grid_per_cu=1), 40001),
+    ("helmholtz", "tetrahedron", 2, dict(kernel=2, block=64, epi=5, chunk=5, grid_per_cu=1), 40003),
+    ("helmholtz", "tetrahedron", 2, dict(kernel=2, block=64, epi=5, chunk=35, grid_per_cu=1), 40003),
+    ("helmholtz", "tetrahedron", 2, dict(kernel=2, block=512, epi=20, grid_per_cu=1), 30011),
+    ("helmholtz", "tetrahedron", 4, dict(kernel=2, block=320, epi=1, chunk=3, grid_per_cu=1), 1501),
+    ("helmholtz", "tetrahedron", 4, dict(kernel=2, block=256, epi=1, chunk=1, grid_per_cu=2), 1501),
+    ("helmholtz", "prism", 3, dict(kernel=2, block=448, epi=1, chunk=2, grid_per_cu=1), 777),
+    ("mass", "prism", 4, dict(kernel=2, block=384, epi=1, grid_per_cu=1), 613),
+    ("helmholtz", "tetrahedron", 2, dict(kernel=1, block=256, epi=3, chunk=9, grid_per_cu=1), 5003),
+    ("helmholtz", "triangle", 4, dict(kernel=1, block=320, epi=4, chunk=64, grid_per_cu=2), 3001),
+    ("helmholtz", "prism", 4, dict(kernel=1, block=512, epi=1, chunk=16, grid_per_cu=1), 555),
+]
+
+
+@pytest.mark.parametrize("form,cell,p,shape,E", SHAPES)
+def test_preeval_shapes(form, cell, p, shape, E):
+    log(f"pre-evaluated shape {form} {cell} P{p} {shape} E={E}")
+    coords, *_ = mesh(cell, E, seed=11 + p)
+    A, st = gpu_assemble(form, cell, p, coords, mode="preeval", shape=shape)
+    B, fl = oracle.assemble(form, cell, p, coords)
+    bad = np.isnan(B[:, 0, 0])
+    assert st == fl == bad.sum()
+    assert (np.isnan(A[:, 0, 0]) == bad).all() and np.isfinite(A[~bad]).all()
+    assert normwise(A[~bad], B[~bad]).max() <= TOL["fp64"]
+
+
+AUTOTUNE_CASES = [("helmholtz", "tetrahedron", 3, 4001), ("mass", "prism", 2, 3001), ("helmholtz", "prism", 4, 301),
+                  ("elasticity", "tetrahedron", 2, 1201)]
+
+
+@pytest.mark.parametrize("form,cell,p,E", AUTOTUNE_CASES)
+def test_autotune_shape_roundtrip(form, cell, p, E):
+    """The autotuner's choice is used afterwards, and its reported shape is a
+    valid override that gives the same matrices."""
+    log(f"autotune {form} {cell} P{p} E={E}")
+    coords, V, cells, h = mesh(cell, E, seed=21)
+    cf = coefficients(form, cell, p, E, V, cells, h, seed=22)
+    n, _ = felocal.fe_local_dims(form, cell, p)
+    out = torch.empty((E, n, n), dtype=torch.float64, device="cuda")
+    ms, shape = felocal.fe_autotune(form, cell, p, dev(coords), dev(cf) if cf is not None else None, out,
+                                    return_shape=True)
+    assert ms > 0
+    preeval = form in ("mass", "helmholtz") and felocal.fe_plan(form, cell, p)["mode"] == "preeval"
+    assert (shape["kernel"] in (1, 2)) if preeval else shape["kernel"] == 0
+    B, _ = oracle.assemble(form, cell, p, coords, cf)
+    A1, st1 = gpu_assemble(form, cell, p, coords, cf)
+    shape = {k: v for k, v in shape.items() if v}
+    A2, st2 = gpu_assemble(form, cell, p, coords, cf, shape=shape)
+    assert st1 == st2 == 0
+    assert normwise(A1, B).max() <= TOL["fp64"] and normwise(A2, B).max() <= TOL["fp64"]
+
+
+BAD_SHAPES = [
+    ("helmholtz", "tetrahedron", 4, "preeval", dict(kernel=2, block=256, epi=2)),   # 2450 > 8 * 256 slots
+    ("helmholtz", "prism", 4, "preeval", dict(kernel=2, block=512, epi=1)),         # 5625 > 8 * 512 slots
+    ("helmholtz", "tetrahedron", 2, "preeval", dict(kernel=1, block=256, epi=3, chunk=10)),   # not a multiple
+    ("helmholtz", "tetrahedron", 2, "preeval", dict(kernel=2, block=256, epi=3, chunk=10)),   # of epi
+    ("helmholtz", "tetrahedron", 2, "preeval", dict(block=1024)),                   # above the kernel's bound
+    ("helmholtz", "tetrahedron", 2, "preeval", dict(block=96)),                     # not whole wavefronts
+    ("helmholtz", "tetrahedron", 2, "preeval", dict(block=256, epi=300)),           # epi above block
+    ("helmholtz", "tetrahedron", 2, "preeval", dict(kernel=1, block=256, epi=1, chunk=100000)),   # LDS limit
+    ("elasticity", "tetrahedron", 2, "quadrature", dict(qc=1000)),                  # more points than the rule
+    ("elasticity", "tetrahedron", 2, "quadrature", dict(eb=100000)),                # LDS above the limit
+]
+
+
+@pytest.mark.parametrize("form,cell,p,mode,shape", BAD_SHAPES)
+def test_bad_shapes_rejected(form, cell, p, mode, shape):
+    log(f"rejected shape {form} {cell} P{p} {mode} {shape}")
+    coords, V, cells, h = mesh(cell, 50, seed=3)
+    cf = coefficients(form, cell, p, 50, V, cells, h, seed=4)
+    n, _ = felocal.fe_local_dims(form, cell, p)
+    out = torch.full((50, n, n), float("nan"), dtype=torch.float64, device="cuda")
+    with pytest.raises(felocal.FeError):
+        felocal.fe_assemble_local(form, cell, p, dev(coords), dev(cf) if cf is not None else None, out,
+                                  mode=mode, shape=shape)
+    torch.cuda.synchronize()
+    assert torch.isnan(out).all()
+
+
 SPLIT_CASES = [(f, c, p) for f in ("elasticity", "hyperelastic") for (c, p) in
                [("triangle", 1), ("triangle", 2), ("triangle", 3), ("triangle", 4), ("tetrahedron", 1),
                 ("tetrahedron", 2), ("prism", 1)]]

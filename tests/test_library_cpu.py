@@ -137,6 +137,14 @@ def test_argument_errors_are_synchronous():
     o.qdeg = 99
     o.mode = 0
     assert L.fe_assemble_local(0, 1, 2, 1, 8, None, 8, ctypes.byref(o)) == felocal.FE_EINVAL
+    o.qdeg = -1
+    for field, bad in (("kernel", 3), ("kernel", -1), ("block", -64), ("epi", -1), ("chunk", -2), ("eb", -1),
+                       ("qc", -3), ("grid_per_cu", -1)):
+        setattr(o.shape, field, bad)
+        assert L.fe_assemble_local(0, 1, 2, 0, None, None, None, ctypes.byref(o)) == felocal.FE_EINVAL
+        setattr(o.shape, field, 0)
+    o.shape.kernel = 2
+    assert L.fe_assemble_local(0, 1, 2, 0, None, None, None, ctypes.byref(o)) == felocal.FE_OK
     assert L.fe_geometry(0, 5, None, None, None, None) == felocal.FE_EINVAL
     assert L.fe_batch_run(None, None) == felocal.FE_EINVAL
     assert L.fe_batch_destroy(None) == felocal.FE_EINVAL
