@@ -12,6 +12,9 @@ and split), and a 16-sub-batch mixed persistent launch replayed from a HIP
 graph.  Inputs are seeded synthetic meshes resident in HBM before timing.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       python bench.py summarize-trace DB_DIR OUT.md TITLE COMMAND [NAME_FILTER]
+       python bench.py summarize-traffic FETCH_DIR WRITE_DIR OUT.md TITLE CMD_FETCH CMD_WRITE
+(the last two turn rocprofv3 output into the text summaries under profiles/).
 """
 from __future__ import annotations
 
@@ -29,6 +32,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_preeval_stream_helmholtz_tet_p4_750k.traffic.md")
+# sources that make up the pre-evaluated kernels: a profile of their HBM
+# traffic is only reported while these are unchanged
+PREEVAL_SOURCES = ["include/felocal.h", "paper_1604_05872_amd/csrc/fe_common.hpp",
+                   "paper_1604_05872_amd/csrc/device_common.hpp", "paper_1604_05872_amd/csrc/preeval.hpp",
+                   "paper_1604_05872_amd/csrc/assemble_preeval.hip", "paper_1604_05872_amd/csrc/internal.hpp"]
 
 
 def log(msg):
@@ -184,10 +193,12 @@ def main():
     dom = max(kern_ms, key=kern_ms.get)
     dom_bytes = alg_bytes("helmholtz", "tetrahedron", dom) * E
     achieved = dom_bytes / (kern_ms[dom] * 1e-3) / 1e9
-    kname = "k_preeval" if tuned.get(f"P{dom}", {}).get("kernel") == 1 else "k_preeval_stream"
+    dom_shape = tuned.get(f"P{dom}", {})
+    kname = "k_preeval" if dom_shape.get("kernel") == 1 else "k_preeval_stream"
     roofline = {"kernel": f"{kname}<HELMHOLTZ,TET> P{dom}", "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None, "bytes_per_launch": dom_bytes, "ms_per_launch": round(kern_ms[dom], 4)}
+    roofline.update(profiled_traffic(kname, dom_shape))
     step_bytes = sum(alg_bytes("helmholtz", "tetrahedron", p) for p in (1, 2, 3, 4)) * E
     step_flops = sum(alg_flops("helmholtz", "tetrahedron", p) for p in (1, 2, 3, 4)) * E
     del outs
@@ -217,6 +228,119 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(coords_np)
     print(json.dumps(result), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries (profiles/) and the measured HBM traffic
+# ---------------------------------------------------------------------------
+
+def sources_sha256(paths=PREEVAL_SOURCES):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kname, shape):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    profile, when it was taken with the current kernel sources and the same
+    launch shape; else traffic stays null."""
+    if not os.path.exists(TRAFFIC_PROFILE) or not shape:
+        return {}
+    rec = None
+    with open(TRAFFIC_PROFILE) as f:
+        for line in f:
+            if line.startswith("<!-- dominant "):
+                rec = json.loads(line[len("<!-- dominant "):].rsplit("-->", 1)[0])
+    if rec is None or rec.get("sources_sha256") != sources_sha256():
+        return {"traffic_note": "counters predate the current kernel sources"}
+    if not rec.get("kernel", "").startswith(kname + "<") or rec.get("block") != shape.get("block"):
+        return {"traffic_note": "counters were taken with another launch shape"}
+    return {"traffic": rec["fetch_bytes"] + rec["write_bytes"], "traffic_fetch": rec["fetch_bytes"],
+            "traffic_write": rec["write_bytes"], "traffic_profile": os.path.relpath(TRAFFIC_PROFILE, ROOT)}
+
+
+def _rocpd(path_dir):
+    import glob
+    import sqlite3
+    dbs = sorted(glob.glob(os.path.join(path_dir, "**", "*_results.db"), recursive=True))
+    if not dbs:
+        raise SystemExit(f"no rocprofv3 *_results.db under {path_dir}")
+    return sqlite3.connect(dbs[0])
+
+
+def _short(name):
+    name = name.replace("void ", "").replace("fe::", "").replace("(anonymous namespace)::", "")
+    return name.split("(")[0] if name.startswith("k_") else name[:60]
+
+
+def summarize_trace(db_dir, out, title, command, only=""):
+    """Per-kernel duration statistics of a --kernel-trace run, one row per
+    (kernel, block, grid, LDS); `only` keeps kernels whose name contains it."""
+    cur = _rocpd(db_dir).cursor()
+    rows = [r for r in cur.execute("select name, workgroup_x, grid_x, lds_size, duration from kernels").fetchall()
+            if only in r[0]]
+    agg = {}
+    for name, wg, grid, lds, dur in rows:
+        agg.setdefault((_short(name), wg, grid // max(1, wg), lds), []).append(dur)
+    total = sum(sum(v) for v in agg.values())
+    lines = [f"# {title}", "", "Command (from the repository root on the GPU host):", "", "```", command, "```", "",
+             f"{len(rows)} dispatches.  Durations from the kernel trace (ns -> us).", "",
+             "| kernel | block | grid | LDS B | calls | avg us | min us | max us | share |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for (name, wg, grid, lds), d in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{name}` | {wg} | {grid} | {lds} | {len(d)} | {np.mean(d) / 1e3:.2f} | "
+                     f"{min(d) / 1e3:.2f} | {max(d) / 1e3:.2f} | {100 * sum(d) / total:.1f}% |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_traffic(fetch_dir, write_dir, out, title, command_fetch, command_write):
+    """FETCH_SIZE / WRITE_SIZE per dispatch (two counter runs), scaled by what
+    the same counters read for a 1 GiB device copy (1 GiB read + 1 GiB
+    written) in the same runs."""
+    def load(d, counter):
+        cur = _rocpd(d).cursor()
+        q = ("select k.name, k.workgroup_x, k.grid_x, k.lds_size, p.counter_value from pmc_events p join kernels k "
+             "on k.dispatch_id = p.dispatch_id where p.counter_name = ?")
+        agg = {}
+        for name, wg, grid, lds, v in cur.execute(q, (counter,)).fetchall():
+            agg.setdefault((name, wg, grid // max(1, wg), lds), []).append(v)
+        return agg
+    fa, wa = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy_f = [v for k, v in fa.items() if "copyBuffer" in k[0]]
+    copy_w = [v for k, v in wa.items() if "copyBuffer" in k[0]]
+    if not copy_f or not copy_w:
+        raise SystemExit("no 1 GiB calibration copy in the counter runs (bench.py --calibrate-copy)")
+    gib_kib = float(1 << 20)
+    sf, sw = gib_kib / max(copy_f[0]), gib_kib / max(copy_w[0])
+    lines = [f"# {title}", "", "Counter runs (from the repository root on the GPU host):", "", "```", command_fetch,
+             command_write, "```", "",
+             f"Calibration: the 1 GiB device copy reads FETCH_SIZE {max(copy_f[0]):.1f} KiB and WRITE_SIZE "
+             f"{max(copy_w[0]):.1f} KiB per dispatch, so HBM bytes = FETCH_SIZE x {sf:.4f} KiB and "
+             f"WRITE_SIZE x {sw:.4f} KiB.", "",
+             "| kernel | block | grid | LDS B | dispatches | fetch MB/dispatch | write MB/dispatch |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    best = None
+    for key in sorted(fa, key=lambda k: -np.mean(wa.get(k, [0]))):
+        name, wg, grid, lds = key
+        if "fe::" not in name:
+            continue
+        fb = float(np.mean(fa[key])) * sf * 1024
+        wb = float(np.mean(wa.get(key, [0]))) * sw * 1024
+        lines.append(f"| `{_short(name)}` | {wg} | {grid} | {lds} | {len(fa[key])} | {fb / 1e6:.1f} | "
+                     f"{wb / 1e6:.1f} |")
+        if best is None:
+            best = {"kernel": _short(name), "block": wg, "grid": grid, "fetch_bytes": round(fb),
+                    "write_bytes": round(wb), "sources_sha256": sources_sha256()}
+    lines += ["", "The kernel with the most bytes written is the one whose traffic bench.py reports:", "",
+              "<!-- dominant " + json.dumps(best) + " -->"]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def time_launch(torch, fn, stream, ev, reps):
@@ -369,4 +493,11 @@ def cpu_baseline(coords_np):
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize-trace":
+        # summarize-trace DB_DIR OUT.md TITLE COMMAND [NAME_FILTER]
+        summarize_trace(*sys.argv[2:7])
+    elif len(sys.argv) > 1 and sys.argv[1] == "summarize-traffic":
+        # summarize-traffic FETCH_DIR WRITE_DIR OUT.md TITLE COMMAND_FETCH COMMAND_WRITE
+        summarize_traffic(*sys.argv[2:8])
+    else:
+        main()
