@@ -368,7 +368,8 @@ def other_workloads(torch, felocal, inputs, stream, ev, reps, which):
                "frac_fp64": round(F / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
         row.update(extra)
         res.append(row)
-        log(f"  {name} {prec}: {ms:.4f} ms, {row['elem_per_s']:.3e} elem/s, {row['alg_GBs']} GB/s")
+        log(f"  {name} {prec} {extra.get('kernel', '')}: {ms:.4f} ms, {row['elem_per_s']:.3e} elem/s, "
+            f"{row['alg_GBs']} GB/s")
 
     # mass P1 triangles, 4096 elements (launch-latency bound)
     if "mass" in which:
@@ -391,6 +392,13 @@ def mass_workload(torch, felocal, inputs, stream, ev, record):
     record("mass_tri_p1_4096", "mass", "triangle", 1, 4096, ms, note="launch-latency bound (0.49 MB)")
 
 
+# float64 through the VALU quadrature kernel (launch-shape kernel 3) and the
+# default matrix-core Gram kernel, then the two split precisions
+FP64_AND_SPLIT = [("fp64", {"kernel": 3}), ("fp64", None), ("fp32", None), ("bf16x3", None)]
+KERNEL_NAME = {("fp64", True): "k_quad (VALU)", ("fp64", False): "k_gram64 (f64 MFMA)",
+               ("fp32", False): "k_split fp32 MFMA", ("bf16x3", False): "k_split bf16x3 MFMA"}
+
+
 def elasticity_workload(torch, felocal, inputs, stream, ev, record, reps):
     log("elasticity P2 on 1.97M tets")
     cn, V, cells = inputs.tet_workload(69, seed=3)
@@ -398,10 +406,10 @@ def elasticity_workload(torch, felocal, inputs, stream, ev, record, reps):
     c3 = torch.from_numpy(cn).cuda()
     cf3 = torch.from_numpy(inputs.lame_p1(V.shape[0], cells, seed=3)).cuda()
     o3 = torch.empty((E3, 30, 30), dtype=torch.float64, device="cuda")
-    for prec in ("fp64", "fp32", "bf16x3"):
+    for prec, kern in FP64_AND_SPLIT:
         ms = time_launch(torch, lambda: felocal.fe_assemble_local("elasticity", "tetrahedron", 2, c3, cf3, o3,
-                                                                  precision=prec), stream, ev, reps)
-        record("elasticity_tet_p2_2m", "elasticity", "tetrahedron", 2, E3, ms, prec)
+                                                                  precision=prec, shape=kern), stream, ev, reps)
+        record("elasticity_tet_p2_2m", "elasticity", "tetrahedron", 2, E3, ms, prec, kernel=KERNEL_NAME[prec, bool(kern)])
     del o3, c3, cf3
     torch.cuda.empty_cache()
 
@@ -416,12 +424,13 @@ def hyperelastic_workload(torch, felocal, inputs, stream, ev, record, reps):
         u = torch.from_numpy(inputs.displacement_dofs(E4, 3, ns, 1.0 / 55, p, seed=40 + p)).cuda()
         o4 = torch.empty((E4, 3 * ns, 3 * ns), dtype=torch.float64, device="cuda")
         st = torch.zeros(1, dtype=torch.int32, device="cuda")
-        for prec in ("fp64", "fp32", "bf16x3"):
+        for prec, kern in FP64_AND_SPLIT:
             st.zero_()
             ms = time_launch(torch, lambda: felocal.fe_assemble_local("hyperelastic", "tetrahedron", p, c4, u, o4,
-                                                                      precision=prec, status=st), stream, ev, reps)
+                                                                      precision=prec, status=st, shape=kern),
+                             stream, ev, reps)
             record(f"hyperelastic_tet_p{p}_1m", "hyperelastic", "tetrahedron", p, E4, ms, prec,
-                   flagged_per_launch=int(st.item()) // (reps + 1))
+                   kernel=KERNEL_NAME[prec, bool(kern)], flagged_per_launch=int(st.item()) // (reps + 1))
         del o4, u
         torch.cuda.empty_cache()
     del c4

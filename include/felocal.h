@@ -97,7 +97,12 @@ enum {
  *                consecutive elements staged through LDS), 2 = streaming
  *                kernel (table entries held in registers for the whole
  *                launch, which needs epi * n^2 <= 8 * block, 16 * block for
- *                the mass form; visits of `chunk` consecutive elements)
+ *                the mass form; visits of `chunk` consecutive elements);
+ *                quadrature mode: 3 = VALU kernel (any size), 4 = matrix-
+ *                core Gram kernel (vector forms with n <= 32, n_s <= 16 and
+ *                at most 32 points; the only kernel of the split
+ *                precisions).  A kernel that does not serve the call's mode
+ *                and precision is rejected.
  *   block        threads of the pre-evaluated kernels (multiple of 64, <= 512)
  *   epi          pre-evaluated: elements per step (1 <= epi <= block)
  *   chunk        pre-evaluated: elements per tile or visit, a multiple of

@@ -48,9 +48,9 @@ void load_file_locked()
         if (std::sscanf(line,
                         "{\"form\": %d, \"cell\": %d, \"degree\": %d, \"qdeg\": %d, \"mode\": %d, \"precision\": %d, "
                         "\"block\": %d, \"epi\": %d, \"chunk\": %d, \"eb\": %d, \"qc\": %d, \"grid_per_cu\": %d, "
-                        "\"stream\": %d",
+                        "\"variant\": %d",
                         &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &c.block, &c.epi, &c.chunk, &c.eb, &c.qc,
-                        &c.grid_per_cu, &c.stream) == 13)
+                        &c.grid_per_cu, &c.variant) == 13)
             g_tuned[Key(v[0], v[1], v[2], v[3], v[4], v[5])] = c;
     }
     std::fclose(f);
@@ -60,6 +60,11 @@ Config default_for(const Call& c)
 {
     if (c.prec != FE_FP64) return Config();
     if (c.mode == FE_MODE_PREEVAL) return default_preeval_config(c.form, c.tables->nb * c.tables->nb);
+    if (gram64_eligible(c)) {
+        Config x;
+        x.variant = 1;   // float64 matrix-core Gram kernel
+        return x;
+    }
     return default_quad_config(c.form, c.cell, c.degree, c.tables->nq);
 }
 
@@ -87,7 +92,7 @@ std::vector<Config> candidates(const Call& c)
                 Config x;
                 x.block = block;
                 x.epi = epi;
-                x.stream = 1;
+                x.variant = 1;
                 x.grid_per_cu = 8;   // capped by occupancy at launch
                 for (int t : {0, 4, 8, 16, 24, 32}) {
                     x.chunk = t * epi;
@@ -114,10 +119,18 @@ std::vector<Config> candidates(const Call& c)
         if (out.empty()) out.push_back(base);
         return out;
     }
+    if (gram64_eligible(c))
+        for (int g : {2, 4, 8}) {
+            Config x;
+            x.variant = 1;
+            x.grid_per_cu = g;
+            out.push_back(x);
+        }
+    const Config vb = default_quad_config(c.form, c.cell, c.degree, c.tables->nq);
     for (int div : {1, 2, 4}) {
         for (int g : {4, 8}) {
-            Config x = base;
-            x.eb = std::max(1, base.eb / div);
+            Config x = vb;
+            x.eb = std::max(1, vb.eb / div);
             const int D = cell_dim(c.cell), ns = c.tables->nb;
             const int ppt = ns * D + (c.form == HYPERELASTIC ? ns * D + 9 : 0) + 3;
             const size_t per_q = ((size_t)ns + (size_t)x.eb * ppt) * 8;
@@ -202,16 +215,18 @@ extern "C" int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n
                 std::fprintf(f,
                              "{\"form\": %d, \"cell\": %d, \"degree\": %d, \"qdeg\": %d, \"mode\": %d, "
                              "\"precision\": %d, \"block\": %d, \"epi\": %d, \"chunk\": %d, \"eb\": %d, \"qc\": %d, "
-                             "\"grid_per_cu\": %d, \"stream\": %d, \"ms\": %.6f}\n",
+                             "\"grid_per_cu\": %d, \"variant\": %d, \"ms\": %.6f}\n",
                              c.form, c.cell, c.degree, c.qdeg, c.mode, c.prec, best_cfg.block, best_cfg.epi,
-                             best_cfg.chunk, best_cfg.eb, best_cfg.qc, best_cfg.grid_per_cu, best_cfg.stream, best);
+                             best_cfg.chunk, best_cfg.eb, best_cfg.qc, best_cfg.grid_per_cu, best_cfg.variant, best);
                 std::fclose(f);
             }
         }
     }
     if (best_ms) *best_ms = best;
     if (best_shape) {
-        best_shape->kernel = (c.prec == FE_FP64 && c.mode == FE_MODE_PREEVAL) ? (best_cfg.stream ? 2 : 1) : 0;
+        best_shape->kernel = c.prec != FE_FP64             ? 4
+                             : c.mode == FE_MODE_PREEVAL ? (best_cfg.variant ? 2 : 1)
+                                                         : (best_cfg.variant ? 4 : 3);
         best_shape->block = best_cfg.block;
         best_shape->epi = best_cfg.epi;
         best_shape->chunk = best_cfg.chunk;

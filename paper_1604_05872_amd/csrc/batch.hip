@@ -124,7 +124,7 @@ void destroy(fe_batch* b)
 // pre-evaluated tile shape with the persistent kernel's block of 256
 Config batch_preeval_config(const Config& tuned, int nn, int mm)
 {
-    if (tuned.block == 256 && !tuned.stream) return tuned;
+    if (tuned.block == 256 && !tuned.variant) return tuned;
     Config best;
     best.block = 256;
     double best_w = 1e9;
@@ -203,6 +203,8 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
             lds = std::max(lds, preeval_lds_bytes(sb.form, sb.cell, cfg.chunk));
             d.pa.nt = store_mode();
         } else {
+            // the persistent kernel runs the VALU quadrature tile
+            if (cfg.variant) cfg = default_quad_config(sb.form, sb.cell, sb.degree, t->nq);
             const int kb = quad_kb(sb.cell, sb.degree);
             d.variant = variant_id(1, sb.form, sb.cell, (kb == 5) ? 0 : 1);
             d.qa.coords = sb.coords;

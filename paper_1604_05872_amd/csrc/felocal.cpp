@@ -14,6 +14,7 @@
 #include <tuple>
 #include <vector>
 
+#include "gram64.hpp"
 #include "internal.hpp"
 #include "preeval.hpp"
 #include "quad.hpp"
@@ -171,7 +172,7 @@ Config default_preeval_config(int form, int nn)
                 best.block = block;
                 best.epi = epi;
                 best.chunk = 0;
-                best.stream = 1;
+                best.variant = 1;
             }
         }
     }
@@ -369,13 +370,24 @@ bool q_invariant(const Call& c)
     return is_vector_form(c.form) && c.degree == 1 && c.cell != PRISM;
 }
 
+bool gram64_eligible(const Call& c)
+{
+    if (!is_vector_form(c.form) || n_rows(c.form, c.cell, c.degree) > 32) return false;
+    if (n_scalar(c.cell, c.degree) > 16) return false;
+    const int nq = q_invariant(c) ? 1 : c.tables->nq;
+    return nq <= 32;
+}
+
+int split_nqp(int nq) { return nq <= 8 ? 8 : nq <= 16 ? 16 : 32; }
+int gram64_nqp(int nq) { return nq <= 4 ? 4 : nq <= 8 ? 8 : nq <= 16 ? 16 : nq <= 28 ? 28 : 32; }
+
 // Launches one resolved call with an explicit configuration.
 int launch_call(const Call& c, const Config& cfg)
 {
     const RefTables* t = c.tables;
     const int cus = device_cus();
     hipError_t e;
-    if (c.prec != FE_FP64) {
+    if (c.prec != FE_FP64 || (c.mode == FE_MODE_QUADRATURE && cfg.variant)) {
         SplitArgs a;
         a.coords = c.coords;
         a.coeff = c.coeff;
@@ -392,7 +404,18 @@ int launch_call(const Call& c, const Config& cfg)
         a.mu = c.mu;
         a.lam = c.lam;
         const int nq_eff = a.collapse ? 1 : t->nq;
-        const int nqp = nq_eff <= 8 ? 8 : nq_eff <= 16 ? 16 : 32;
+        if (c.prec == FE_FP64) {
+            if (!gram64_eligible(c)) return FE_EINVAL;
+            const int nqp = gram64_nqp(nq_eff);
+            const int64_t steps = (c.E + G64_WAVES * G64_EB - 1) / (G64_WAVES * G64_EB);
+            const int grid = (int)std::min<int64_t>(steps, (int64_t)cus * cfg.grid_per_cu);
+            const size_t lds = gram64_lds_bytes(c.form, c.cell, nqp, t->nq, t->nb);
+            e = c.form == ELASTICITY ? launch_gram64_elasticity(c.cell, c.degree, nqp, a, grid, lds, c.stream)
+                                     : launch_gram64_hyperelastic(c.cell, c.degree, nqp, a, grid, lds, c.stream);
+            if (e != hipSuccess) return set_hip_error(e, "float64 matrix-core launch");
+            return FE_OK;
+        }
+        const int nqp = split_nqp(nq_eff);
         const int64_t steps = (c.E + SPLIT_WAVES * SPLIT_EB - 1) / (SPLIT_WAVES * SPLIT_EB);
         const int grid = (int)std::min<int64_t>(steps, (int64_t)cus * cfg.grid_per_cu);
         const size_t lds = split_lds_bytes(c.cell, t->nq, t->nb);
@@ -412,7 +435,7 @@ int launch_call(const Call& c, const Config& cfg)
         a.epi = cfg.epi;
         a.chunk = cfg.chunk;
         a.nt = store_mode();
-        if (cfg.stream) {
+        if (cfg.variant) {
             if (cfg.epi < 1 || cfg.epi > cfg.block || cfg.chunk < 0 || cfg.chunk % cfg.epi ||
                 preeval_stream_mm(c.form, cfg.epi * a.nn, cfg.block) == 0)
                 return FE_EINVAL;   // a streaming step must fit in registers
@@ -479,12 +502,17 @@ int check_config(const Call& c, const Config& cfg)
         if (cfg.block < 64 || cfg.block > 512 || cfg.block % 64 || cfg.epi < 1 || cfg.epi > cfg.block)
             return FE_EINVAL;
         if (cfg.chunk < 0 || cfg.chunk % cfg.epi) return FE_EINVAL;
-        if (cfg.stream) {
+        if (cfg.variant) {
             if (preeval_stream_mm(c.form, cfg.epi * nn, cfg.block) == 0) return FE_EINVAL;
             return preeval_stream_lds_bytes(c.form, c.cell, cfg.block, cfg.epi) <= max_lds ? FE_OK : FE_EINVAL;
         }
         if (cfg.chunk == 0) return FE_EINVAL;
         return preeval_lds_bytes(c.form, c.cell, cfg.chunk) <= max_lds ? FE_OK : FE_EINVAL;
+    }
+    if (cfg.variant) {
+        if (!gram64_eligible(c)) return FE_EINVAL;
+        const int nq = q_invariant(c) ? 1 : t->nq;
+        return gram64_lds_bytes(c.form, c.cell, gram64_nqp(nq), t->nq, t->nb) <= max_lds ? FE_OK : FE_EINVAL;
     }
     if (cfg.eb < 1 || cfg.qc < 1 || cfg.qc > t->nq) return FE_EINVAL;
     return quad_lds_bytes(c.form, c.cell, t->nb, cfg.eb, cfg.qc) <= max_lds ? FE_OK : FE_EINVAL;
@@ -495,12 +523,24 @@ int final_config(const Call& c, Config* cfg)
     lookup_config(c, cfg);
     const int* s = c.shape;   // kernel, block, epi, chunk, eb, qc, grid_per_cu
     const Config autocfg = *cfg;
-    if (s[0]) cfg->stream = s[0] == 2;
+    if (s[0]) {
+        // 1, 2: tiled or streaming pre-evaluated kernel; 3, 4: VALU or matrix-core quadrature
+        const bool pre = c.mode == FE_MODE_PREEVAL && c.prec == FE_FP64;
+        if (pre != (s[0] <= 2) || (c.prec != FE_FP64 && s[0] != 4)) return FE_EINVAL;
+        if (c.prec == FE_FP64) {
+            const int v = (s[0] == 2 || s[0] == 4) ? 1 : 0;
+            if (!pre && v != autocfg.variant) {
+                *cfg = v ? Config() : default_quad_config(c.form, c.cell, c.degree, c.tables->nq);
+                cfg->variant = v;
+            }
+            cfg->variant = v;
+        }
+    }
     if (s[1]) cfg->block = s[1];
     if (s[2]) cfg->epi = s[2];
     if (s[3]) cfg->chunk = s[3];
-    else if (cfg->stream != autocfg.stream || cfg->epi != autocfg.epi)
-        cfg->chunk = cfg->stream ? 0 : cfg->epi * std::max(1, 256 / cfg->epi);
+    else if (c.mode == FE_MODE_PREEVAL && (cfg->variant != autocfg.variant || cfg->epi != autocfg.epi))
+        cfg->chunk = cfg->variant ? 0 : cfg->epi * std::max(1, 256 / cfg->epi);
     if (s[4]) cfg->eb = s[4];
     if (s[5]) cfg->qc = s[5];
     if (s[6]) cfg->grid_per_cu = s[6];
@@ -536,7 +576,7 @@ int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, co
     const int sh[7] = {o.shape.kernel, o.shape.block, o.shape.epi, o.shape.chunk,
                        o.shape.eb,     o.shape.qc,    o.shape.grid_per_cu};
     for (int i = 0; i < 7; ++i) {
-        if (sh[i] < 0 || (i == 0 && sh[i] > 2)) return FE_EINVAL;
+        if (sh[i] < 0 || (i == 0 && sh[i] > 4)) return FE_EINVAL;
         c->shape[i] = sh[i];
     }
     if (n_elems == 0) return FE_OK;

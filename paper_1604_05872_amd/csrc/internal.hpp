@@ -49,6 +49,10 @@ hipError_t launch_split_hyperelastic_fp32(int cell, int p, int nqp, const SplitA
                                          hipStream_t s);
 hipError_t launch_split_hyperelastic_bf16x3(int cell, int p, int nqp, const SplitArgs& a, int grid, size_t lds,
                                            hipStream_t s);
+hipError_t launch_gram64_elasticity(int cell, int p, int nqp, const SplitArgs& a, int grid, size_t lds,
+                                    hipStream_t s);
+hipError_t launch_gram64_hyperelastic(int cell, int p, int nqp, const SplitArgs& a, int grid, size_t lds,
+                                      hipStream_t s);
 // prec: 1 = fp32 operands, 2 = bf16 hi/lo split
 inline hipError_t launch_split(int form, int cell, int p, int prec, int nqp, const SplitArgs& a, int grid,
                                size_t lds, hipStream_t s)
@@ -109,7 +113,8 @@ struct Config {
     int eb = 1;       // quadrature: elements per tile
     int qc = 1;       // quadrature: points per LDS chunk
     int grid_per_cu = 8;
-    int stream = 0;   // pre-evaluated: 1 = streaming kernel, 0 = tiled kernel
+    int variant = 0;  // pre-evaluated: 1 = streaming, 0 = tiled kernel;
+                      // quadrature: 1 = float64 matrix-core Gram kernel, 0 = VALU kernel
 };
 
 // pre-evaluated kernel: streaming when a step fits in registers, else tiled
@@ -145,6 +150,12 @@ int launch_call(const Call& c, const Config& cfg);
 int store_mode();
 // configuration from the autotune cache, else the built-in default
 void lookup_config(const Call& c, Config* cfg);
+// the float64 matrix-core kernel serves this call (vector form, n <= 32,
+// at most 32 contraction points)
+bool gram64_eligible(const Call& c);
+// padded point count of the matrix-core kernels for nq contraction points
+int split_nqp(int nq);
+int gram64_nqp(int nq);
 // 0 when the kernel selected by c can take cfg, else FE_EINVAL
 int check_config(const Call& c, const Config& cfg);
 // automatic shape with the caller's override applied and checked

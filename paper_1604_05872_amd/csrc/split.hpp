@@ -40,6 +40,7 @@
 //      element matrix is stored row by row.
 #pragma once
 #include "device_common.hpp"
+#include "vector_point.hpp"
 
 namespace fe {
 
@@ -73,7 +74,7 @@ constexpr int SPLIT_PRE = (SPLIT_EB * SPLIT_MAX_IN + 63) / 64;   // prefetch reg
 
 // per-wave LDS (bytes)
 constexpr int SPW_IN = 0;                                          // inputs [EB][48] f64
-constexpr int SPW_W = SPW_IN + SPLIT_EB * SPLIT_MAX_IN * 8;        // weights [EB][32][4] f32
+constexpr int SPW_W = SPW_IN + SPLIT_EB * SPLIT_MAX_IN * 8;        // signed weight roots [EB][32][4] f32
 constexpr int SPW_M = SPW_W + SPLIT_EB * 32 * 4 * 4;               // M^T [EB][32][3][3] f32
 constexpr int SPW_K = SPW_M + SPLIT_EB * 32 * 9 * 4;               // K^T [EB][12] f32
 constexpr int SPW_FLAG = SPW_K + SPLIT_EB * 12 * 4;                // flags [EB] (+pad)
@@ -151,6 +152,7 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
     // summed weights for the hoisted point loop of P1 simplices
     double wsum = 0.0;
     for (int q = 0; q < nq_all; ++q) wsum += a.W[q];
+    const PointTables pt{gW, gPsi, gTab, nq_all, a.collapse, wsum, a.mu, a.lam};
     __syncthreads();
 
     const int64_t stride = (int64_t)gridDim.x * SPLIT_WAVES * SPLIT_EB;
@@ -208,97 +210,25 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
         wave_sync();
 
         // --- B: float64 point data, one lane per (element, point) -----------
+#pragma unroll 1
         for (int t = lane; t < SPLIT_EB * nq; t += 64) {
             const int ib = t / nq, q = t - ib * nq;
             if (b0 + ib >= a.E) continue;
-            const double* sIn = sBuf + ib * SPLIT_MAX_IN;
             double K[3][3];
 #pragma unroll
             for (int r = 0; r < 3; ++r)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) K[r][c] = sGeo[ib * 10 + r * 3 + c];
             const double adet = sGeo[ib * 10 + 9];
-            int bad = 0;
-            const double w = (a.collapse ? wsum : gW[q]) * adet;
-            double M[3][3];
-            float w0, w1, w2 = 0.f;
-            if (!HYP) {
-                const double* ce = sIn + NVD;
-                double lam = 0.0, mu = 0.0;
-                if (a.collapse) {
-                    for (int qq = 0; qq < nq_all; ++qq) {
-                        double l1 = 0.0, m1 = 0.0;
-#pragma unroll
-                        for (int l = 0; l < NV; ++l) {
-                            l1 = fma(ce[l], gPsi[qq * NV + l], l1);
-                            m1 = fma(ce[NV + l], gPsi[qq * NV + l], m1);
-                        }
-                        lam = fma(gW[qq], l1, lam);
-                        mu = fma(gW[qq], m1, mu);
-                    }
-                    w0 = (float)(adet * lam);
-                    w1 = (float)(adet * mu);
-                } else {
-#pragma unroll
-                    for (int l = 0; l < NV; ++l) {
-                        lam = fma(ce[l], gPsi[q * NV + l], lam);
-                        mu = fma(ce[NV + l], gPsi[q * NV + l], mu);
-                    }
-                    w0 = (float)(w * lam);
-                    w1 = (float)(w * mu);
-                }
-#pragma unroll
-                for (int r = 0; r < 3; ++r)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) M[r][c] = (r < D && c < D) ? K[r][c] : 0.0;
-            } else {
-                // H = sum_k u_k (x) grad_X phi_k ; F = I + H K
-                const double* ue = sIn + NVD;
-                double H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-                for (int k = 0; k < ns; ++k) {
-                    const double* dg = gTab + (q * ns + k) * D;
-#pragma unroll
-                    for (int r = 0; r < D; ++r) {
-                        const double ur = ue[r * ns + k];
-#pragma unroll
-                        for (int c = 0; c < D; ++c) H[r][c] = fma(ur, dg[c], H[r][c]);
-                    }
-                }
-                double F[3][3], Fi[3][3];
-#pragma unroll
-                for (int r = 0; r < 3; ++r)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        double s = (r == b) ? 1.0 : 0.0;
-#pragma unroll
-                        for (int c = 0; c < D; ++c) s = fma(H[r][c], K[c][b], s);
-                        F[r][b] = s;
-                    }
-                const double jf = inverse_small<D>(F, Fi);
-                bad |= !(jf > 0.0);
-                const double lnj = log(jf);
-                w0 = (float)(w * a.lam);
-                w1 = (float)(w * (a.mu - a.lam * lnj));
-                w2 = (float)(w * a.mu);
-                // M = K F^{-1}: s_c = sum_a M[a][c] dphi/dX_a
-#pragma unroll
-                for (int r = 0; r < 3; ++r)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int b = 0; b < D; ++b) s = fma(K[r][b], Fi[b][c], s);
-                        M[r][c] = (r < D && c < D) ? s : 0.0;
-                    }
-            }
-            // weights enter as square roots (P = Z^T Z with Z = sqrt(w) X); the
-            // sign of the possibly negative alpha' is kept separately
+            double w0, w1, w2, M[3][3];
+            const int bad =
+                vector_point_data<FORM, CELL, ns>(sBuf + ib * SPLIT_MAX_IN, K, adet, q, pt, w0, w1, w2, M);
+            // signed square roots of the three product weights (fp32)
             float* sW = sWall + ib * 32 * 4;
             float* sMt = sMall + ib * 32 * 9;
-            sW[q * 4 + 0] = sqrtf(fabsf(w0));
-            sW[q * 4 + 1] = sqrtf(fabsf(w1));
-            sW[q * 4 + 2] = sqrtf(fabsf(w2));
-            sW[q * 4 + 3] = w1 < 0.f ? -0.f : 0.f;
+            sW[q * 4 + 0] = (float)signed_root(w0);
+            sW[q * 4 + 1] = (float)signed_root(w1);
+            sW[q * 4 + 2] = (float)signed_root(w2);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -330,11 +260,11 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                 acc2[r] = 0.f;
                 accG[r] = 0.f;
             }
-            // Scaled columns at point q (zero at padding points):
-            //   z1 = sqrt(lam') x, z2 = sqrt|w2| x, z3 = sqrt(mu') g with
-            // x = s (hyperelastic) or g; P_lam = Z1^T Z1, P_2 = Z2^T diag(sign) Z2,
-            // P_g = Z3^T Z3.  The sign of a point is its sign bit (0 or
-            // 0x80000000), applied to the B operand by an exact bit flip.
+            // Scaled columns at point q (zero at padding points): with the signed
+            // roots r_t of the weights, z_t = |r_t| x enters as the A operand and
+            // sign(r_t) z_t as the B operand (an exact sign-bit flip), for
+            //   P_lam = Z_0^T S_0 Z_0, P_2 = Z_1^T S_1 Z_1, P_g = Z_2^T S_2 Z_2,
+            // x = s (hyperelastic) or g, and g for P_g.
             auto colx = [&](int q) -> float {
                 const float* gh = gTabF + (q * ns + cj) * D;
                 const float* m = sMt + q * 9 + cc * 3;
@@ -348,21 +278,13 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                 float g = kc[0] * gh[0];
 #pragma unroll
                 for (int b = 1; b < D; ++b) g = fmaf(kc[b], gh[b], g);
-                return sW[q * 4 + 2] * g;
+                return g;
             };
-            auto sgn = [&](int q) -> unsigned { return __float_as_uint(sW[q * 4 + 3]); };
+            auto sgn = [&](int q, int t) -> unsigned { return __float_as_uint(sW[q * 4 + t]) & 0x80000000u; };
             if (PREC == SPLIT_BF16X3) {
                 constexpr int KW = NQP == 8 ? 4 : 8;    // points per lane per instruction
                 typedef __bf16 vbf __attribute__((ext_vector_type(KW)));
                 typedef unsigned vu __attribute__((ext_vector_type(KW / 2)));
-                auto split = [&](const float* z, vbf& h, vbf& l) {
-#pragma unroll
-                    for (int i = 0; i < KW; ++i) {
-                        const __bf16 hi = (__bf16)z[i];
-                        h[i] = hi;
-                        l[i] = (__bf16)(z[i] - (float)hi);
-                    }
-                };
                 auto mma = [&](const vbf& x, const vbf& y, v16f& acc) {
                     if constexpr (KW == 4)
                         acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(__builtin_bit_cast(v4s, x),
@@ -370,8 +292,22 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                     else
                         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, acc, 0, 0, 0);
                 };
-                // hi*hi + hi*lo + lo*hi
-                auto gram = [&](const vbf& h, const vbf& l, const vbf& hb, const vbf& lb, v16f& acc) {
+                // split |r_t| x into bf16 hi + lo; hi*hi + hi*lo + lo*hi with the
+                // point signs on the B operand
+                auto product = [&](const float* x, int q0, int t, v16f& acc) {
+                    vbf h, l;
+#pragma unroll
+                    for (int i = 0; i < KW; ++i) {
+                        const float z = fabsf(sW[(q0 + i) * 4 + t]) * x[i];
+                        const __bf16 hi = (__bf16)z;
+                        h[i] = hi;
+                        l[i] = (__bf16)(z - (float)hi);
+                    }
+                    vu sm;
+#pragma unroll
+                    for (int i = 0; i < KW / 2; ++i) sm[i] = (sgn(q0 + 2 * i, t) >> 16) | sgn(q0 + 2 * i + 1, t);
+                    const vbf hb = __builtin_bit_cast(vbf, __builtin_bit_cast(vu, h) ^ sm);
+                    const vbf lb = __builtin_bit_cast(vbf, __builtin_bit_cast(vu, l) ^ sm);
                     mma(l, hb, acc);
                     mma(h, lb, acc);
                     mma(h, hb, acc);
@@ -379,28 +315,15 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
 #pragma unroll 1
                 for (int kb = 0; kb < NQP / (2 * KW); ++kb) {
                     const int q0 = 2 * KW * kb + KW * half;
-                    float x[KW], z[KW];
-                    vbf h, l;
+                    float x[KW];
 #pragma unroll
                     for (int i = 0; i < KW; ++i) x[i] = colx(q0 + i);
-#pragma unroll
-                    for (int i = 0; i < KW; ++i) z[i] = sW[(q0 + i) * 4 + 0] * x[i];
-                    split(z, h, l);
-                    gram(h, l, h, l, accL);
-#pragma unroll
-                    for (int i = 0; i < KW; ++i) z[i] = sW[(q0 + i) * 4 + 1] * x[i];
-                    split(z, h, l);
-                    vu sm;
-#pragma unroll
-                    for (int i = 0; i < KW / 2; ++i) sm[i] = (sgn(q0 + 2 * i) >> 16) | sgn(q0 + 2 * i + 1);
-                    const vbf hb = __builtin_bit_cast(vbf, __builtin_bit_cast(vu, h) ^ sm);
-                    const vbf lb = __builtin_bit_cast(vbf, __builtin_bit_cast(vu, l) ^ sm);
-                    gram(h, l, hb, lb, acc2);
+                    product(x, q0, 0, accL);
+                    product(x, q0, 1, acc2);
                     if (HYP) {
 #pragma unroll
-                        for (int i = 0; i < KW; ++i) z[i] = colg(q0 + i);
-                        split(z, h, l);
-                        gram(h, l, h, l, accG);
+                        for (int i = 0; i < KW; ++i) x[i] = colg(q0 + i);
+                        product(x, q0, 2, accG);
                     }
                 }
             } else {
@@ -408,13 +331,12 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                 for (int ks = 0; ks < NQP / 2; ++ks) {
                     const int q = 2 * ks + half;
                     const float x = colx(q);
-                    const float z1 = sW[q * 4 + 0] * x, z2 = sW[q * 4 + 1] * x;
-                    accL = __builtin_amdgcn_mfma_f32_32x32x2f32(z1, z1, accL, 0, 0, 0);
-                    acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(z2, __uint_as_float(__float_as_uint(z2) ^ sgn(q)),
-                                                                acc2, 0, 0, 0);
+                    const float r0 = sW[q * 4 + 0], r1 = sW[q * 4 + 1];
+                    accL = __builtin_amdgcn_mfma_f32_32x32x2f32(fabsf(r0) * x, r0 * x, accL, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(fabsf(r1) * x, r1 * x, acc2, 0, 0, 0);
                     if (HYP) {
-                        const float z3 = colg(q);
-                        accG = __builtin_amdgcn_mfma_f32_32x32x2f32(z3, z3, accG, 0, 0, 0);
+                        const float g = colg(q), r2 = sW[q * 4 + 2];
+                        accG = __builtin_amdgcn_mfma_f32_32x32x2f32(fabsf(r2) * g, r2 * g, accG, 0, 0, 0);
                     }
                 }
             }

@@ -185,7 +185,7 @@ def test_autotune_shape_roundtrip(form, cell, p, E):
                                     return_shape=True)
     assert ms > 0
     preeval = form in ("mass", "helmholtz") and felocal.fe_plan(form, cell, p)["mode"] == "preeval"
-    assert (shape["kernel"] in (1, 2)) if preeval else shape["kernel"] == 0
+    assert (shape["kernel"] in (1, 2)) if preeval else shape["kernel"] in (3, 4)
     B, _ = oracle.assemble(form, cell, p, coords, cf)
     A1, st1 = gpu_assemble(form, cell, p, coords, cf)
     shape = {k: v for k, v in shape.items() if v}
@@ -203,8 +203,11 @@ BAD_SHAPES = [
     ("helmholtz", "tetrahedron", 2, "preeval", dict(block=96)),                     # not whole wavefronts
     ("helmholtz", "tetrahedron", 2, "preeval", dict(block=256, epi=300)),           # epi above block
     ("helmholtz", "tetrahedron", 2, "preeval", dict(kernel=1, block=256, epi=1, chunk=100000)),   # LDS limit
-    ("elasticity", "tetrahedron", 2, "quadrature", dict(qc=1000)),                  # more points than the rule
-    ("elasticity", "tetrahedron", 2, "quadrature", dict(eb=100000)),                # LDS above the limit
+    ("elasticity", "tetrahedron", 2, "quadrature", dict(kernel=3, qc=1000)),        # more points than the rule
+    ("elasticity", "tetrahedron", 2, "quadrature", dict(kernel=3, eb=100000)),      # LDS above the limit
+    ("elasticity", "tetrahedron", 3, "quadrature", dict(kernel=4)),                 # n = 60 > 32
+    ("elasticity", "tetrahedron", 2, "quadrature", dict(kernel=2)),                 # a pre-evaluated kernel
+    ("helmholtz", "tetrahedron", 2, "preeval", dict(kernel=4)),                     # a quadrature kernel
 ]
 
 
@@ -220,6 +223,55 @@ def test_bad_shapes_rejected(form, cell, p, mode, shape):
                                   mode=mode, shape=shape)
     torch.cuda.synchronize()
     assert torch.isnan(out).all()
+
+
+MFMA_CELLS = [("triangle", 1), ("triangle", 2), ("triangle", 3), ("triangle", 4), ("tetrahedron", 1),
+              ("tetrahedron", 2), ("prism", 1)]
+VECTOR_MFMA_CASES = [(f, c, p) for f in ("elasticity", "hyperelastic") for (c, p) in MFMA_CELLS]
+
+
+@pytest.mark.parametrize("kernel", [3, 4])
+@pytest.mark.parametrize("form,cell,p", VECTOR_MFMA_CASES)
+def test_fp64_vector_kernels(form, cell, p, kernel):
+    """Both float64 quadrature kernels of the vector forms: the VALU kernel
+    (3) and the matrix-core Gram kernel (4)."""
+    E = case_size(form, cell, p, cap=700)
+    log(f"fp64 vector kernel {kernel} {form} {cell} P{p} E={E}")
+    coords, V, cells, h = mesh(cell, E, seed=300 + p)
+    cf = coefficients(form, cell, p, E, V, cells, h, seed=400 + p)
+    A, st = gpu_assemble(form, cell, p, coords, cf, shape=dict(kernel=kernel))
+    B, fl = oracle.assemble(form, cell, p, coords, cf)
+    bad = np.isnan(B[:, 0, 0])
+    assert st == fl == bad.sum()
+    assert (np.isnan(A[:, 0, 0]) == bad).all() and np.isfinite(A[~bad]).all()
+    assert normwise(A[~bad], B[~bad]).max() <= TOL["fp64"]
+
+
+# Indefinite point weights: a Lame field shifted below zero (lambda or mu),
+# and a negative hyperelastic lambda, through every precision.
+SIGNED_CASES = [("elasticity", "tetrahedron", 2, 0), ("elasticity", "triangle", 3, 0),
+                ("elasticity", "tetrahedron", 1, 1), ("elasticity", "prism", 1, 1),
+                ("hyperelastic", "tetrahedron", 2, 0), ("hyperelastic", "triangle", 2, 0)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("form,cell,p,field", SIGNED_CASES)
+def test_negative_coefficients(form, cell, p, field, prec):
+    E = 300
+    log(f"signed weights {form} {cell} P{p} field={field} {prec}")
+    coords, V, cells, h = mesh(cell, E, seed=31)
+    kw = {}
+    if form == "elasticity":
+        cf = inputs.lame_p1(V.shape[0], cells, seed=32).copy()
+        cf[:, field, :] -= 1.1 if field == 0 else 0.9    # values in [-0.6, 0.9] or [-0.4, 1.1]
+    else:
+        cf = coefficients(form, cell, p, E, V, cells, h, seed=33)
+        kw = dict(mu=1.0, lam=-0.4)
+    A, st = gpu_assemble(form, cell, p, coords, cf, precision=prec, **kw)
+    B, fl = oracle.assemble(form, cell, p, coords, cf, **kw)
+    bad = np.isnan(B[:, 0, 0])
+    assert st == fl == bad.sum()
+    assert normwise(A[~bad], B[~bad]).max() <= TOL[prec]
 
 
 SPLIT_CASES = [(f, c, p) for f in ("elasticity", "hyperelastic") for (c, p) in

@@ -138,7 +138,7 @@ def test_argument_errors_are_synchronous():
     o.mode = 0
     assert L.fe_assemble_local(0, 1, 2, 1, 8, None, 8, ctypes.byref(o)) == felocal.FE_EINVAL
     o.qdeg = -1
-    for field, bad in (("kernel", 3), ("kernel", -1), ("block", -64), ("epi", -1), ("chunk", -2), ("eb", -1),
+    for field, bad in (("kernel", 5), ("kernel", -1), ("block", -64), ("epi", -1), ("chunk", -2), ("eb", -1),
                        ("qc", -3), ("grid_per_cu", -1)):
         setattr(o.shape, field, bad)
         assert L.fe_assemble_local(0, 1, 2, 0, None, None, None, ctypes.byref(o)) == felocal.FE_EINVAL
