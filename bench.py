@@ -9,7 +9,8 @@ Also measured (fields "workloads"): P1 triangle mass on 4,096 elements,
 vector P2 elasticity on 1,971,054 tetrahedra (float64 and the split-precision
 MFMA variants), the neo-Hookean tangent on 998,250 tetrahedra (P1, P2; float64
 and split), and a 16-sub-batch mixed persistent launch replayed from a HIP
-graph.  Inputs are seeded synthetic meshes resident in HBM before timing.
+graph (one persistent work-queue kernel per kernel variant).  Inputs are seeded
+synthetic meshes resident in HBM before timing.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
        python bench.py summarize-trace DB_DIR OUT.md TITLE COMMAND [NAME_FILTER]
@@ -437,7 +438,7 @@ def hyperelastic_workload(torch, felocal, inputs, stream, ev, record, reps):
 
 
 def batch_workload(torch, felocal, inputs, stream, ev, reps):
-    log("mixed batch: 16 sub-batches in one persistent graph launch")
+    log("mixed batch: 16 sub-batches, one graph launch of per-variant persistent kernels")
     rng = np.random.default_rng(5)
     subs, tot_e, tot_b, tot_f = [], 0, 0, 0
     desc = []

@@ -210,14 +210,19 @@ typedef struct {
 int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int qdeg, size_t th_bytes,
             fe_plan_t* plan);
 
-/* Mixed batches: several (form, cell, degree) sub-batches executed by one
- * persistent kernel that takes element tiles from a device work queue, the
- * whole launch captured once in a HIP graph and replayed by fe_batch_run.
+/* Mixed batches: several (form, cell, degree) sub-batches in one HIP graph,
+ * replayed by fe_batch_run with one graph launch.  Sub-batches are grouped by
+ * kernel variant; each group runs as one persistent kernel, specialised for
+ * the variant, whose workgroups take element tiles from the group's device
+ * work queue, and the groups run on parallel branches of the graph.
  * All sub-batch pointers are DEVICE pointers owned by the caller and must
  * stay valid until fe_batch_destroy.  Every sub-batch uses FE_FP64 and the
- * mode Algorithm 3 chooses for it; tile sizes come from the autotune cache
- * (fe_autotune) when present, else from built-in defaults.
- * Errors: FE_EINVAL, FE_ENOTSUP, FE_ENOMEM, FE_EHIP. */
+ * mode Algorithm 3 chooses for it (tiled pre-evaluated or VALU quadrature
+ * tiles); tile sizes come from the autotune cache (fe_autotune) when
+ * present, else from built-in defaults.  Sub-batches with no elements are
+ * allowed and do nothing.  Replays on one stream are ordered; replays of
+ * one batch on different streams at once race on its work queues.
+ * Errors: FE_EINVAL, FE_ENOTSUP (hyperelastic), FE_ENOMEM, FE_EHIP. */
 typedef struct fe_subbatch {
     fe_form_t     form;
     fe_cell_t     cell;
@@ -235,7 +240,8 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
                     fe_batch_t** batch);
 int fe_batch_run(fe_batch_t* batch, void* stream);
 int fe_batch_destroy(fe_batch_t* batch);
-/* Number of work tiles and the persistent grid size of a batch. */
+/* Number of work tiles and the total workgroups of the persistent kernels
+ * of a batch. */
 int fe_batch_info(const fe_batch_t* batch, int64_t* n_tiles, int* grid);
 
 /* Autotuner: times the candidate launch shapes of the variant that serves

@@ -5,7 +5,7 @@
 namespace fe {
 
 template <int CELL, int P, int NQP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gram64_elasticity(SplitArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gram64_elasticity(SplitArgs a)
 {
     extern __shared__ char lds_bytes[];
     gram64_kernel_body<ELASTICITY, CELL, P, NQP>(a, lds_bytes);

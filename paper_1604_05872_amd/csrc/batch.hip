@@ -1,11 +1,14 @@
-// Mixed batches: sub-batches of different (form, cell, degree) run in ONE
-// persistent kernel.  The host turns every sub-batch into element tiles with
-// the tile shape of its variant (from the autotune cache or the defaults) and
-// lays the tiles out as one global index range; each workgroup repeatedly
-// takes the next tile index from a device counter and runs the matching
-// device routine (the same tile routines the standalone kernels use).  The
-// counter reset (a one-thread kernel, not a memset node) and the persistent
-// launch are captured once into a HIP graph; fe_batch_run replays it.
+// Mixed batches: sub-batches of different (form, cell, degree) in one
+// HIP graph of persistent work-queue kernels.  The host turns every
+// sub-batch into element tiles with the tile shape of its variant (from the
+// autotune cache or the defaults) and groups the sub-batches by kernel
+// variant (kind, form, cell, k-block width).  Each group gets one persistent
+// kernel, specialised for its variant so that it runs at that variant's
+// register budget and occupancy (one kernel for every variant would run all
+// of them at the worst one), whose workgroups repeatedly take the next tile
+// of the group from a device counter.  A one-block kernel clears the
+// counters (no memset node), the group kernels are captured on parallel
+// branches of one graph, and fe_batch_run replays it with one graph launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,13 +22,12 @@
 
 namespace fe {
 
-// Variants the persistent kernel can run (FP64): kind 0 = pre-evaluated,
-// kind 1 = quadrature; the switch below enumerates every (kind, form, cell,
-// kb) instance.
+// kind 0 = pre-evaluated (2 forms x 3 cells), kind 1 = quadrature (3 forms x
+// 3 cells x 2 k-block widths): 24 variants
+constexpr int N_VARIANTS = 24;
+
 struct SubDesc {
-    int variant;          // index into the dispatch switch
-    int pad_;
-    int64_t tile_begin;   // first global tile of this sub-batch
+    int64_t tile_begin;   // first tile of this sub-batch within its group
     int64_t n_tiles;
     PreevalArgs pa;
     QuadArgs qa;
@@ -33,18 +35,25 @@ struct SubDesc {
 
 __host__ __device__ constexpr int variant_id(int kind, int form, int cell, int kb_small)
 {
-    // kind 0: 2 forms x 3 cells; kind 1: 3 forms x 3 cells x 2 k-block widths
     return kind == 0 ? form * 3 + cell : 6 + (form * 3 + cell) * 2 + kb_small;
 }
 
-template <int FORM, int CELL, int KB>
-__device__ __forceinline__ void run_quad(const SubDesc& d, int64_t local, double* lds)
+template <int VID>
+__device__ __forceinline__ void run_tile(const SubDesc& d, int64_t local, double* lds)
 {
-    quad_tile<FORM, CELL, KB>(d.qa, local * d.qa.eb, lds);
+    if constexpr (VID < 6) {
+        constexpr int FORM = VID / 3, CELL = VID % 3;
+        preeval_tile<FORM, CELL, preeval_mm(FORM)>(d.pa, local * d.pa.chunk, lds);
+    } else {
+        constexpr int v = VID - 6, FORM = (v / 2) / 3, CELL = (v / 2) % 3;
+        constexpr int KB = (v % 2) ? (CELL == TET ? 4 : 3) : 5;
+        quad_tile<FORM, CELL, KB>(d.qa, local * d.qa.eb, lds);
+    }
 }
 
-__global__ __launch_bounds__(256) void k_batch(const SubDesc* __restrict__ subs, int n_subs, int64_t total,
-                                               unsigned long long* counter)
+template <int VID>
+__global__ __launch_bounds__(256) void k_batch_group(const SubDesc* __restrict__ subs, int n_subs, int64_t total,
+                                                     unsigned long long* counter)
 {
     extern __shared__ double lds[];
     __shared__ long long s_tile;
@@ -60,51 +69,53 @@ __global__ __launch_bounds__(256) void k_batch(const SubDesc* __restrict__ subs,
             if (subs[mid].tile_begin <= tile) lo = mid;
             else hi = mid - 1;
         }
-        const SubDesc& d = subs[lo];
-        const int64_t local = tile - d.tile_begin;
-        switch (d.variant) {
-        case variant_id(0, MASS, TRI, 0): preeval_tile<MASS, TRI, preeval_mm(MASS)>(d.pa, local * d.pa.chunk, lds); break;
-        case variant_id(0, MASS, TET, 0): preeval_tile<MASS, TET, preeval_mm(MASS)>(d.pa, local * d.pa.chunk, lds); break;
-        case variant_id(0, MASS, PRISM, 0): preeval_tile<MASS, PRISM, preeval_mm(MASS)>(d.pa, local * d.pa.chunk, lds); break;
-        case variant_id(0, HELMHOLTZ, TRI, 0): preeval_tile<HELMHOLTZ, TRI, preeval_mm(HELMHOLTZ)>(d.pa, local * d.pa.chunk, lds); break;
-        case variant_id(0, HELMHOLTZ, TET, 0): preeval_tile<HELMHOLTZ, TET, preeval_mm(HELMHOLTZ)>(d.pa, local * d.pa.chunk, lds); break;
-        case variant_id(0, HELMHOLTZ, PRISM, 0): preeval_tile<HELMHOLTZ, PRISM, preeval_mm(HELMHOLTZ)>(d.pa, local * d.pa.chunk, lds); break;
-        case variant_id(1, MASS, TRI, 1): run_quad<MASS, TRI, 3>(d, local, lds); break;
-        case variant_id(1, MASS, TRI, 0): run_quad<MASS, TRI, 5>(d, local, lds); break;
-        case variant_id(1, MASS, TET, 1): run_quad<MASS, TET, 4>(d, local, lds); break;
-        case variant_id(1, MASS, TET, 0): run_quad<MASS, TET, 5>(d, local, lds); break;
-        case variant_id(1, MASS, PRISM, 1): run_quad<MASS, PRISM, 3>(d, local, lds); break;
-        case variant_id(1, MASS, PRISM, 0): run_quad<MASS, PRISM, 5>(d, local, lds); break;
-        case variant_id(1, HELMHOLTZ, TRI, 1): run_quad<HELMHOLTZ, TRI, 3>(d, local, lds); break;
-        case variant_id(1, HELMHOLTZ, TRI, 0): run_quad<HELMHOLTZ, TRI, 5>(d, local, lds); break;
-        case variant_id(1, HELMHOLTZ, TET, 1): run_quad<HELMHOLTZ, TET, 4>(d, local, lds); break;
-        case variant_id(1, HELMHOLTZ, TET, 0): run_quad<HELMHOLTZ, TET, 5>(d, local, lds); break;
-        case variant_id(1, HELMHOLTZ, PRISM, 1): run_quad<HELMHOLTZ, PRISM, 3>(d, local, lds); break;
-        case variant_id(1, HELMHOLTZ, PRISM, 0): run_quad<HELMHOLTZ, PRISM, 5>(d, local, lds); break;
-        case variant_id(1, ELASTICITY, TRI, 1): run_quad<ELASTICITY, TRI, 3>(d, local, lds); break;
-        case variant_id(1, ELASTICITY, TRI, 0): run_quad<ELASTICITY, TRI, 5>(d, local, lds); break;
-        case variant_id(1, ELASTICITY, TET, 1): run_quad<ELASTICITY, TET, 4>(d, local, lds); break;
-        case variant_id(1, ELASTICITY, TET, 0): run_quad<ELASTICITY, TET, 5>(d, local, lds); break;
-        case variant_id(1, ELASTICITY, PRISM, 1): run_quad<ELASTICITY, PRISM, 3>(d, local, lds); break;
-        case variant_id(1, ELASTICITY, PRISM, 0): run_quad<ELASTICITY, PRISM, 5>(d, local, lds); break;
-        default: break;
-        }
+        run_tile<VID>(subs[lo], tile - subs[lo].tile_begin, lds);
     }
 }
 
-__global__ void k_reset_counter(unsigned long long* counter) { *counter = 0ULL; }
+__global__ void k_reset_counters(unsigned long long* counters, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) counters[i] = 0ULL;
+}
+
+// runtime variant id -> the group kernel's launch and occupancy
+template <int V = 0>
+hipError_t launch_group(int vid, int grid, size_t lds, hipStream_t s, const SubDesc* subs, int n, int64_t total,
+                        unsigned long long* ctr)
+{
+    if (vid == V) {
+        hipLaunchKernelGGL((k_batch_group<V>), dim3(grid), dim3(256), lds, s, subs, n, total, ctr);
+        return hipGetLastError();
+    }
+    if constexpr (V + 1 < N_VARIANTS) return launch_group<V + 1>(vid, grid, lds, s, subs, n, total, ctr);
+    return hipErrorInvalidValue;
+}
+
+template <int V = 0>
+hipError_t group_occupancy(int vid, size_t lds, int* per_cu)
+{
+    if (vid == V) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch_group<V>, 256, lds);
+    if constexpr (V + 1 < N_VARIANTS) return group_occupancy<V + 1>(vid, lds, per_cu);
+    return hipErrorInvalidValue;
+}
 
 }  // namespace fe
 
 using namespace fe;
 
 struct fe_batch {
-    SubDesc* d_subs = nullptr;
-    unsigned long long* d_counter = nullptr;
-    int n_subs = 0;
+    struct Group {
+        int vid = 0;
+        int n_subs = 0;
+        int64_t total = 0;
+        int grid = 0;
+        size_t lds = 0;
+        SubDesc* d_subs = nullptr;
+    };
+    std::vector<Group> groups;
+    unsigned long long* d_counters = nullptr;
     int64_t total = 0;
     int grid = 0;
-    size_t lds = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -116,28 +127,34 @@ void destroy(fe_batch* b)
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    if (b->d_subs) (void)hipFree(b->d_subs);
-    if (b->d_counter) (void)hipFree(b->d_counter);
+    for (auto& g : b->groups)
+        if (g.d_subs) (void)hipFree(g.d_subs);
+    if (b->d_counters) (void)hipFree(b->d_counters);
     delete b;
 }
 
-// pre-evaluated tile shape with the persistent kernel's block of 256
+// pre-evaluated tile shape with the group kernel's block of 256: the fewest
+// idle slots, and tiles of about 256 KiB of output
 Config batch_preeval_config(const Config& tuned, int nn, int mm)
 {
-    if (tuned.block == 256 && !tuned.variant) return tuned;
     Config best;
     best.block = 256;
-    double best_w = 1e9;
-    for (int epi = 1; epi <= 64; ++epi) {
-        const int slots = epi * nn, m = (slots + 255) / 256;
-        if (m > mm && epi > 1) break;
-        const double w = (double)(m * 256 - slots) / (m * 256) + (slots < 512 ? 0.5 : 0.0);
-        if (w < best_w - 1e-9) {
-            best_w = w;
-            best.epi = epi;
+    if (tuned.block == 256 && !tuned.variant) {
+        best = tuned;
+    } else {
+        double best_w = 1e9;
+        for (int epi = 1; epi <= 64; ++epi) {
+            const int slots = epi * nn, m = (slots + 255) / 256;
+            if (m > mm && epi > 1) break;
+            const double w = (double)(m * 256 - slots) / (m * 256) + (slots < 512 ? 0.5 : 0.0);
+            if (w < best_w - 1e-9) {
+                best_w = w;
+                best.epi = epi;
+            }
         }
     }
-    best.chunk = best.epi * std::max(1, 256 / best.epi);
+    const int steps = std::max(1, (int)((256 * 1024) / ((int64_t)best.epi * nn * 8)));
+    best.chunk = best.epi * std::min(steps, std::max(1, 256 / best.epi));
     best.grid_per_cu = tuned.grid_per_cu;
     return best;
 }
@@ -157,9 +174,8 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
     else fe_options_init(&o);
     if (o.precision != FE_FP64) return FE_ENOTSUP;
     hipStream_t s = (hipStream_t)o.stream;
-    std::vector<SubDesc> h(n_subs);
-    int64_t total = 0;
-    size_t lds = 0;
+    std::vector<std::vector<SubDesc>> by_vid(N_VARIANTS);
+    std::vector<size_t> lds_vid(N_VARIANTS, 0);
     for (int i = 0; i < n_subs; ++i) {
         const fe_subbatch_t& sb = subs[i];
         if ((int)sb.form < 0 || (int)sb.form > 2 || (int)sb.cell < 0 || (int)sb.cell > 2 || sb.degree < 1 ||
@@ -180,17 +196,19 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
         c.E = sb.n_elems;
         int rc = fe_resolve_variant(sb.form, sb.cell, sb.degree, qdeg, &so, &c.mode, &c.mass_pre);
         if (rc) return rc;
+        if (sb.n_elems == 0) continue;
         rc = get_tables(sb.cell, sb.degree, qdeg, s, &c.tables);
         if (rc) return rc;
         const RefTables* t = c.tables;
         Config cfg;
         lookup_config(c, &cfg);
-        SubDesc& d = h[i];
+        SubDesc d;
         std::memset(&d, 0, sizeof(d));
-        d.tile_begin = total;
+        int vid;
+        size_t lds;
         if (c.mode == FE_MODE_PREEVAL) {
             cfg = batch_preeval_config(cfg, t->nb * t->nb, preeval_mm(sb.form));
-            d.variant = variant_id(0, sb.form, sb.cell, 0);
+            vid = variant_id(0, sb.form, sb.cell, 0);
             d.pa.coords = sb.coords;
             d.pa.tables = t->dR;
             d.pa.out = sb.out_A;
@@ -199,14 +217,14 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
             d.pa.nn = t->nb * t->nb;
             d.pa.epi = cfg.epi;
             d.pa.chunk = cfg.chunk;
-            d.n_tiles = (sb.n_elems + cfg.chunk - 1) / cfg.chunk;
-            lds = std::max(lds, preeval_lds_bytes(sb.form, sb.cell, cfg.chunk));
             d.pa.nt = store_mode();
+            d.n_tiles = (sb.n_elems + cfg.chunk - 1) / cfg.chunk;
+            lds = preeval_lds_bytes(sb.form, sb.cell, cfg.chunk);
         } else {
-            // the persistent kernel runs the VALU quadrature tile
+            // the group kernels run the VALU quadrature tile
             if (cfg.variant) cfg = default_quad_config(sb.form, sb.cell, sb.degree, t->nq);
             const int kb = quad_kb(sb.cell, sb.degree);
-            d.variant = variant_id(1, sb.form, sb.cell, (kb == 5) ? 0 : 1);
+            vid = variant_id(1, sb.form, sb.cell, (kb == 5) ? 0 : 1);
             d.qa.coords = sb.coords;
             d.qa.coeff = sb.coeff_dofs;
             d.qa.out = sb.out_A;
@@ -225,36 +243,79 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
             d.qa.qc = cfg.qc;
             d.qa.nt = store_mode();
             d.n_tiles = (sb.n_elems + cfg.eb - 1) / cfg.eb;
-            lds = std::max(lds, quad_lds_bytes(sb.form, sb.cell, t->nb, cfg.eb, cfg.qc));
+            lds = quad_lds_bytes(sb.form, sb.cell, t->nb, cfg.eb, cfg.qc);
         }
-        total += d.n_tiles;
+        auto& grp = by_vid[vid];
+        d.tile_begin = grp.empty() ? 0 : grp.back().tile_begin + grp.back().n_tiles;
+        grp.push_back(d);
+        lds_vid[vid] = std::max(lds_vid[vid], lds);
     }
     fe_batch* b = new fe_batch();
-    b->n_subs = n_subs;
-    b->total = total;
-    b->lds = lds;
-    hipError_t e = hipMalloc((void**)&b->d_subs, sizeof(SubDesc) * n_subs);
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_counter, sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMemcpy(b->d_subs, h.data(), sizeof(SubDesc) * n_subs, hipMemcpyHostToDevice);
-    int per_cu = 0;
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, 256, lds);
+    hipError_t e = hipSuccess;
+    const int cus = device_cus();
+    for (int v = 0; v < N_VARIANTS && e == hipSuccess; ++v) {
+        if (by_vid[v].empty()) continue;
+        fe_batch::Group g;
+        g.vid = v;
+        g.n_subs = (int)by_vid[v].size();
+        g.total = by_vid[v].back().tile_begin + by_vid[v].back().n_tiles;
+        g.lds = lds_vid[v];
+        int per_cu = 0;
+        e = group_occupancy(v, g.lds, &per_cu);
+        if (e != hipSuccess) break;
+        g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.total, (int64_t)cus * std::max(1, per_cu)));
+        e = hipMalloc((void**)&g.d_subs, sizeof(SubDesc) * g.n_subs);
+        if (e == hipSuccess)
+            e = hipMemcpy(g.d_subs, by_vid[v].data(), sizeof(SubDesc) * g.n_subs, hipMemcpyHostToDevice);
+        b->total += g.total;
+        b->grid += g.grid;
+        b->groups.push_back(g);
+    }
+    const int ng = (int)b->groups.size();
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_counters, sizeof(unsigned long long) * std::max(1, ng));
     if (e != hipSuccess) {
         destroy(b);
         return set_hip_error(e, "fe_batch_create setup");
     }
-    per_cu = std::max(1, per_cu);
-    b->grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, (int64_t)device_cus() * per_cu));
-    // capture: counter reset + persistent launch
+    // capture: counter reset, then the group kernels on parallel branches
+    std::vector<hipStream_t> br(ng, nullptr);
+    std::vector<hipEvent_t> done(ng, nullptr);
     hipStream_t cs = nullptr;
+    hipEvent_t start = nullptr;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&start, hipEventDisableTiming);
+    for (int i = 0; i < ng && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&done[i], hipEventDisableTiming);
+    }
+    bool capturing = false;
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, cs, b->d_counter);
-        hipLaunchKernelGGL(k_batch, dim3(b->grid), dim3(256), lds, cs, b->d_subs, n_subs, total, b->d_counter);
-        hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
-        e = (e2 != hipSuccess) ? e2 : hipGetLastError();
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        capturing = e == hipSuccess;
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, cs, b->d_counters, ng);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(start, cs);
+    for (int i = 0; i < ng && e == hipSuccess; ++i) {
+        const fe_batch::Group& g = b->groups[i];
+        e = hipStreamWaitEvent(br[i], start, 0);
+        if (e == hipSuccess)
+            e = launch_group(g.vid, g.grid, g.lds, br[i], g.d_subs, g.n_subs, g.total, b->d_counters + i);
+        if (e == hipSuccess) e = hipEventRecord(done[i], br[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[i], 0);
+    }
+    if (capturing) {
+        const hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
+        if (e == hipSuccess) e = e2;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    for (int i = 0; i < ng; ++i) {
+        if (done[i]) (void)hipEventDestroy(done[i]);
+        if (br[i]) (void)hipStreamDestroy(br[i]);
+    }
+    if (start) (void)hipEventDestroy(start);
     if (cs) (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
         destroy(b);

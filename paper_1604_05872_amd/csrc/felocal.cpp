@@ -407,7 +407,8 @@ int launch_call(const Call& c, const Config& cfg)
         if (c.prec == FE_FP64) {
             if (!gram64_eligible(c)) return FE_EINVAL;
             const int nqp = gram64_nqp(nq_eff);
-            const int64_t steps = (c.E + G64_WAVES * G64_EB - 1) / (G64_WAVES * G64_EB);
+            const int per_block = G64_WAVES * g64_eb(c.form);
+            const int64_t steps = (c.E + per_block - 1) / per_block;
             const int grid = (int)std::min<int64_t>(steps, (int64_t)cus * cfg.grid_per_cu);
             const size_t lds = gram64_lds_bytes(c.form, c.cell, nqp, t->nq, t->nb);
             e = c.form == ELASTICITY ? launch_gram64_elasticity(c.cell, c.degree, nqp, a, grid, lds, c.stream)

@@ -19,7 +19,7 @@
 // B[l / 16][l % 16]; it holds D[l / 16 + 4 r][l % 16], r = 0..3.
 //
 // Schedule as in split.hpp: one wavefront per element, four wavefronts per
-// block with private LDS areas, batches of G64_EB elements whose inputs are
+// block with private LDS areas, batches of EB elements whose inputs are
 // prefetched one batch ahead, one lane per (element, point) for the point
 // data, then per element the MFMA products and an epilogue that reads the
 // transposed P_2 blocks (and D) from one LDS tile and stores from registers.
@@ -33,18 +33,23 @@ namespace fe {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int G64_WAVES = 4;
-constexpr int G64_EB = 2;                       // elements per wavefront batch
+// elements per wavefront batch: hyperelastic 2 (per-point matrices in LDS),
+// elasticity 4
+__host__ __device__ constexpr int g64_eb(int form) { return form == HYPERELASTIC ? 2 : 4; }
 constexpr int G64_TLD = 33;                     // padded tile rows
-constexpr int G64_PRE = (G64_EB * SPLIT_MAX_IN + 63) / 64;
+__host__ __device__ constexpr int g64_pre(int form) { return (g64_eb(form) * SPLIT_MAX_IN + 63) / 64; }
 
 // per-wave LDS layout (bytes) for a padded point count nqp
-__host__ __device__ constexpr int g64_off_rw() { return G64_EB * SPLIT_MAX_IN * 8; }
-__host__ __device__ constexpr int g64_off_m(int nqp) { return g64_off_rw() + G64_EB * nqp * 3 * 8; }
+__host__ __device__ constexpr int g64_off_rw(int form) { return g64_eb(form) * SPLIT_MAX_IN * 8; }
+__host__ __device__ constexpr int g64_off_m(int form, int nqp) { return g64_off_rw(form) + g64_eb(form) * nqp * 3 * 8; }
 __host__ __device__ constexpr int g64_off_geo(int form, int nqp)
 {
-    return g64_off_m(nqp) + (form == HYPERELASTIC ? G64_EB * nqp * 9 * 8 : 0);
+    return g64_off_m(form, nqp) + (form == HYPERELASTIC ? g64_eb(form) * nqp * 9 * 8 : 0);
 }
-__host__ __device__ constexpr int g64_off_flag(int form, int nqp) { return g64_off_geo(form, nqp) + G64_EB * 10 * 8; }
+__host__ __device__ constexpr int g64_off_flag(int form, int nqp)
+{
+    return g64_off_geo(form, nqp) + g64_eb(form) * 10 * 8;
+}
 __host__ __device__ constexpr int g64_off_t(int form, int nqp) { return g64_off_flag(form, nqp) + 16; }
 __host__ __device__ constexpr int g64_off_d(int form, int nqp) { return g64_off_t(form, nqp) + 32 * G64_TLD * 8; }
 __host__ __device__ constexpr int g64_wave_bytes(int form, int nqp)
@@ -74,8 +79,9 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
 
     char* wl = lds + wave * g64_wave_bytes(FORM, NQP);
     double* sIn = (double*)wl;
-    double* sRw = (double*)(wl + g64_off_rw());
-    double* sM = (double*)(wl + g64_off_m(NQP));
+    constexpr int EB = g64_eb(FORM), PRE = g64_pre(FORM);
+    double* sRw = (double*)(wl + g64_off_rw(FORM));
+    double* sM = (double*)(wl + g64_off_m(FORM, NQP));
     double* sGeo = (double*)(wl + g64_off_geo(FORM, NQP));
     int* sFlag = (int*)(wl + g64_off_flag(FORM, NQP));
     double* sT = (double*)(wl + g64_off_t(FORM, NQP));
@@ -88,22 +94,22 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
     for (int i = tid; i < nq_all * NV; i += blockDim.x) gPsi[i] = a.psi[i];
     for (int i = tid; i < nq_all * ns * D; i += blockDim.x) gTab[i] = a.dphi[i];
     // padding points q >= nq carry zero weights and zero matrices
-    for (int i = lane; i < G64_EB * NQP * 3; i += 64)
+    for (int i = lane; i < EB * NQP * 3; i += 64)
         if ((i / 3) % NQP >= nq) sRw[i] = 0.0;
     if (HYP)
-        for (int i = lane; i < G64_EB * NQP * 9; i += 64)
+        for (int i = lane; i < EB * NQP * 9; i += 64)
             if ((i / 9) % NQP >= nq) sM[i] = 0.0;
     double wsum = 0.0;
     for (int q = 0; q < nq_all; ++q) wsum += a.W[q];
     const PointTables pt{gW, gPsi, gTab, nq_all, a.collapse, wsum, a.mu, a.lam};
     __syncthreads();
 
-    const int64_t stride = (int64_t)gridDim.x * G64_WAVES * G64_EB;
-    constexpr int nbatch_in = G64_EB * nin;
-    double pre[G64_PRE];
+    const int64_t stride = (int64_t)gridDim.x * G64_WAVES * EB;
+    constexpr int nbatch_in = EB * nin;
+    double pre[PRE];
     auto fetch = [&](int64_t first) {
 #pragma unroll
-        for (int k = 0; k < G64_PRE; ++k) {
+        for (int k = 0; k < PRE; ++k) {
             const int t = lane + 64 * k;
             const int i = t / nin, x = t - (t / nin) * nin;
             const int64_t ee = first + i;
@@ -112,7 +118,7 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
                 pre[k] = x < NVD ? a.coords[ee * NVD + x] : a.coeff[ee * ncf + (x - NVD)];
         }
     };
-    int64_t b0 = ((int64_t)blockIdx.x * G64_WAVES + wave) * G64_EB;
+    int64_t b0 = ((int64_t)blockIdx.x * G64_WAVES + wave) * EB;
     fetch(b0);
 
     // this lane's operand columns (c, j) = col0, col1 and its point slot
@@ -129,19 +135,19 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
     for (; b0 < a.E; b0 += stride) {
         // --- A: inputs of this batch to LDS; loads of the next batch ----------
 #pragma unroll
-        for (int k = 0; k < G64_PRE; ++k) {
+        for (int k = 0; k < PRE; ++k) {
             const int t = lane + 64 * k;
             if (t < nbatch_in) {
                 const int i = t / nin;
                 sIn[i * SPLIT_MAX_IN + (t - i * nin)] = pre[k];
             }
         }
-        if (lane < G64_EB) sFlag[lane] = 0;
+        if (lane < EB) sFlag[lane] = 0;
         fetch(b0 + stride);
         wave_sync();
 
         // --- B0: geometry, one lane per element ------------------------------
-        if (lane < G64_EB && b0 + lane < a.E) {
+        if (lane < EB && b0 + lane < a.E) {
             double K[3][3], adet;
             const int bad = affine_map<CELL>(sIn + lane * SPLIT_MAX_IN, K, adet);
 #pragma unroll
@@ -155,7 +161,7 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
 
         // --- B: float64 point data, one lane per (element, point) -----------
 #pragma unroll 1
-        for (int t = lane; t < G64_EB * nq; t += 64) {
+        for (int t = lane; t < EB * nq; t += 64) {
             const int ib = t / nq, q = t - ib * nq;
             if (b0 + ib >= a.E) continue;
             double K[3][3];
@@ -183,7 +189,7 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
 
         // --- C, D: per element of the batch ------------------------------------
 #pragma unroll 1
-        for (int ib = 0; ib < G64_EB; ++ib) {
+        for (int ib = 0; ib < EB; ++ib) {
             const int64_t e = b0 + ib;
             if (e >= a.E) break;
             const double* rwe = sRw + ib * NQP * 3;

@@ -361,9 +361,12 @@ def test_nonaffine_prism_rejected_or_flagged():
 def test_batch_bitwise_equal_to_separate_calls():
     log("batch vs separate calls")
     rng = np.random.default_rng(5)
+    # groups with several sub-batches (mass triangles P1 and P2, Helmholtz
+    # tetrahedra P2 and P3, elasticity tetrahedra P2 twice) and an empty one
     specs = [("mass", "triangle", 1, 3000), ("helmholtz", "tetrahedron", 3, 1500), ("elasticity", "prism", 2, 200),
              ("helmholtz", "prism", 4, 60), ("elasticity", "tetrahedron", 2, 999), ("mass", "prism", 3, 0),
-             ("helmholtz", "triangle", 4, 777)]
+             ("helmholtz", "triangle", 4, 777), ("helmholtz", "tetrahedron", 2, 2500), ("mass", "triangle", 2, 1234),
+             ("elasticity", "tetrahedron", 2, 321)]
     subs, refs = [], []
     for i, (form, cell, p, E) in enumerate(specs):
         coords, V, cells, h = mesh(cell, max(E, 1), seed=20 + i)
@@ -374,7 +377,11 @@ def test_batch_bitwise_equal_to_separate_calls():
         subs.append(dict(form=form, cell=cell, degree=p, coords=dev(coords),
                          coeff=dev(cf) if cf is not None else None, out=out))
         if E:
-            refs.append(gpu_assemble(form, cell, p, coords, cf)[0])
+            # the batch runs the VALU quadrature tiles for the vector forms
+            kw = dict(shape=dict(kernel=3)) if form == "elasticity" else {}
+            ref = gpu_assemble(form, cell, p, coords, cf, **kw)[0]
+            assert normwise(ref, oracle.assemble(form, cell, p, coords, cf)[0]).max() <= TOL["fp64"]
+            refs.append(ref)
         else:
             refs.append(np.zeros((0, n, n)))
     b = felocal.Batch(subs)
