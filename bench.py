@@ -394,10 +394,15 @@ def mass_workload(torch, felocal, inputs, stream, ev, record):
 
 
 # float64 through the VALU quadrature kernel (launch-shape kernel 3) and the
-# default matrix-core Gram kernel, then the two split precisions
-FP64_AND_SPLIT = [("fp64", {"kernel": 3}), ("fp64", None), ("fp32", None), ("bf16x3", None)]
-KERNEL_NAME = {("fp64", True): "k_quad (VALU)", ("fp64", False): "k_gram64 (f64 MFMA)",
-               ("fp32", False): "k_split fp32 MFMA", ("bf16x3", False): "k_split bf16x3 MFMA"}
+# matrix-core Gram kernel (kernel 4; the default except for hoisted P1), then
+# the two split precisions
+FP64_AND_SPLIT = [("fp64", {"kernel": 3}), ("fp64", {"kernel": 4}), ("fp32", None), ("bf16x3", None)]
+
+
+def kernel_name(prec, shape):
+    if prec != "fp64":
+        return f"k_split {prec} MFMA"
+    return "k_quad (VALU)" if shape["kernel"] == 3 else "k_gram64 (f64 MFMA)"
 
 
 def elasticity_workload(torch, felocal, inputs, stream, ev, record, reps):
@@ -410,7 +415,7 @@ def elasticity_workload(torch, felocal, inputs, stream, ev, record, reps):
     for prec, kern in FP64_AND_SPLIT:
         ms = time_launch(torch, lambda: felocal.fe_assemble_local("elasticity", "tetrahedron", 2, c3, cf3, o3,
                                                                   precision=prec, shape=kern), stream, ev, reps)
-        record("elasticity_tet_p2_2m", "elasticity", "tetrahedron", 2, E3, ms, prec, kernel=KERNEL_NAME[prec, bool(kern)])
+        record("elasticity_tet_p2_2m", "elasticity", "tetrahedron", 2, E3, ms, prec, kernel=kernel_name(prec, kern))
     del o3, c3, cf3
     torch.cuda.empty_cache()
 
@@ -431,7 +436,7 @@ def hyperelastic_workload(torch, felocal, inputs, stream, ev, record, reps):
                                                                       precision=prec, status=st, shape=kern),
                              stream, ev, reps)
             record(f"hyperelastic_tet_p{p}_1m", "hyperelastic", "tetrahedron", p, E4, ms, prec,
-                   kernel=KERNEL_NAME[prec, bool(kern)], flagged_per_launch=int(st.item()) // (reps + 1))
+                   kernel=kernel_name(prec, kern), flagged_per_launch=int(st.item()) // (reps + 1))
         del o4, u
         torch.cuda.empty_cache()
     del c4

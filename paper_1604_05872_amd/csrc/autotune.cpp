@@ -60,9 +60,11 @@ Config default_for(const Call& c)
 {
     if (c.prec != FE_FP64) return Config();
     if (c.mode == FE_MODE_PREEVAL) return default_preeval_config(c.form, c.tables->nb * c.tables->nb);
-    if (gram64_eligible(c)) {
+    // float64 matrix-core Gram kernel where the point loop is not hoisted
+    // (with one point per element the VALU kernel is faster)
+    if (gram64_eligible(c) && !q_invariant(c)) {
         Config x;
-        x.variant = 1;   // float64 matrix-core Gram kernel
+        x.variant = 1;
         return x;
     }
     return default_quad_config(c.form, c.cell, c.degree, c.tables->nq);

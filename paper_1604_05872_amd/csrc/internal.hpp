@@ -153,6 +153,9 @@ void lookup_config(const Call& c, Config* cfg);
 // the float64 matrix-core kernel serves this call (vector form, n <= 32,
 // at most 32 contraction points)
 bool gram64_eligible(const Call& c);
+// P1 vector form on a simplex: every gradient is constant over the element,
+// so the point loop is hoisted (generalised code motion, Sec. 3.2)
+bool q_invariant(const Call& c);
 // padded point count of the matrix-core kernels for nq contraction points
 int split_nqp(int nq);
 int gram64_nqp(int nq);
