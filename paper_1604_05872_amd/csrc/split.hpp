@@ -223,12 +223,17 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
             double w0, w1, w2, M[3][3];
             const int bad =
                 vector_point_data<FORM, CELL, ns>(sBuf + ib * SPLIT_MAX_IN, K, adet, q, pt, w0, w1, w2, M);
-            // signed square roots of the three product weights (fp32)
+            // signed square roots of the three product weights (the operands
+            // are fp32, so the root is taken in fp32); bit t of the element's
+            // flag word records a negative weight of product t
             float* sW = sWall + ib * 32 * 4;
             float* sMt = sMall + ib * 32 * 9;
-            sW[q * 4 + 0] = (float)signed_root(w0);
-            sW[q * 4 + 1] = (float)signed_root(w1);
-            sW[q * 4 + 2] = (float)signed_root(w2);
+            const float f0 = (float)w0, f1 = (float)w1, f2 = (float)w2;
+            sW[q * 4 + 0] = copysignf(sqrtf(fabsf(f0)), f0);
+            sW[q * 4 + 1] = copysignf(sqrtf(fabsf(f1)), f1);
+            sW[q * 4 + 2] = copysignf(sqrtf(fabsf(f2)), f2);
+            const int neg = (f0 < 0.f ? 2 : 0) | (f1 < 0.f ? 4 : 0) | (f2 < 0.f ? 8 : 0);
+            if (neg) atomicOr(&sFlag[ib], neg);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -238,7 +243,7 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
                     for (int r = 0; r < 3; ++r) sKall[ib * 12 + c * 3 + r] = (r < D && c < D) ? (float)K[r][c] : 0.f;
-            if (bad) sFlag[ib] = 1;
+            if (bad) atomicOr(&sFlag[ib], 1);
         }
         wave_sync();
 
@@ -249,6 +254,7 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
             if (e >= a.E) break;
             const float* sW = sWall + ib * 32 * 4;
             const float* sMt = sMall + ib * 32 * 9;
+            const int negw = __builtin_amdgcn_readfirstlane(sFlag[ib]);
             float kc[3];
 #pragma unroll
             for (int b = 0; b < 3; ++b) kc[b] = sKall[ib * 12 + cc * 3 + b];
@@ -303,28 +309,48 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                         h[i] = hi;
                         l[i] = (__bf16)(z - (float)hi);
                     }
-                    vu sm;
+                    if (negw & (2 << t)) {   // uniform over the wavefront (one element)
+                        vu sm;
 #pragma unroll
-                    for (int i = 0; i < KW / 2; ++i) sm[i] = (sgn(q0 + 2 * i, t) >> 16) | sgn(q0 + 2 * i + 1, t);
-                    const vbf hb = __builtin_bit_cast(vbf, __builtin_bit_cast(vu, h) ^ sm);
-                    const vbf lb = __builtin_bit_cast(vbf, __builtin_bit_cast(vu, l) ^ sm);
-                    mma(l, hb, acc);
-                    mma(h, lb, acc);
-                    mma(h, hb, acc);
+                        for (int i = 0; i < KW / 2; ++i)
+                            sm[i] = (sgn(q0 + 2 * i, t) >> 16) | sgn(q0 + 2 * i + 1, t);
+                        const vbf hb = __builtin_bit_cast(vbf, __builtin_bit_cast(vu, h) ^ sm);
+                        const vbf lb = __builtin_bit_cast(vbf, __builtin_bit_cast(vu, l) ^ sm);
+                        mma(l, hb, acc);
+                        mma(h, lb, acc);
+                        mma(h, hb, acc);
+                    } else {
+                        mma(l, h, acc);
+                        mma(h, l, acc);
+                        mma(h, h, acc);
+                    }
                 };
 #pragma unroll 1
                 for (int kb = 0; kb < NQP / (2 * KW); ++kb) {
                     const int q0 = 2 * KW * kb + KW * half;
-                    float x[KW];
+                    float x[KW], g[KW];
+                    // x and g of the lane's column at its KW points, from one
+                    // read of the reference gradients
 #pragma unroll
-                    for (int i = 0; i < KW; ++i) x[i] = colx(q0 + i);
+                    for (int i = 0; i < KW; ++i) {
+                        const int q = q0 + i;
+                        const float* gh = gTabF + (q * ns + cj) * D;
+                        float gv[3];
+#pragma unroll
+                        for (int b = 0; b < D; ++b) gv[b] = gh[b];
+                        const float* m = sMt + q * 9 + cc * 3;
+                        float xv = m[0] * gv[0], g0 = kc[0] * gv[0];
+#pragma unroll
+                        for (int b = 1; b < D; ++b) {
+                            xv = fmaf(m[b], gv[b], xv);
+                            g0 = fmaf(kc[b], gv[b], g0);
+                        }
+                        x[i] = xv;
+                        g[i] = g0;
+                    }
                     product(x, q0, 0, accL);
                     product(x, q0, 1, acc2);
-                    if (HYP) {
-#pragma unroll
-                        for (int i = 0; i < KW; ++i) x[i] = colg(q0 + i);
-                        product(x, q0, 2, accG);
-                    }
+                    if (HYP) product(g, q0, 2, accG);
                 }
             } else {
 #pragma unroll 2
@@ -349,7 +375,7 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                 if (HYP) tPg[row * SPLIT_TILE_LD + col] = accG[r];
             }
             wave_sync();
-            const bool bad = sFlag[ib] != 0;
+            const bool bad = (negw & 1) != 0;
             const float* tD = HYP ? tPg : tP2;
             double* o = a.out + e * (int64_t)n * n;
             const double nanv = __builtin_nan("");
