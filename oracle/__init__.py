@@ -58,6 +58,9 @@ def lib():
                                    ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.c_double,
                                    dp, ctypes.c_int]
         L.orc_assemble.restype = ctypes.c_int64
+        L.orc_assemble_coef.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int64, dp, dp, dp, ctypes.c_int]
+        L.orc_assemble_coef.restype = ctypes.c_int64
         L.orc_hyper_residual.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                          dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
         L.orc_hyper_residual.restype = ctypes.c_int64
@@ -83,12 +86,13 @@ def nbasis(cell: str, p: int) -> int:
     return lib().orc_nbasis(CELL[cell], p)
 
 
-def default_qdeg(form: str, cell: str, p: int) -> int:
+def default_qdeg(form: str, cell: str, p: int, nf: int = 0) -> int:
     """Exact quadrature degree for each form (Sec. 7.1 uses exact quadrature):
-    mass and Helmholtz 2p; elasticity with P1 Lame fields 2(p-1)+1 on simplices
-    and 2p+1 on prisms (tensor-product degree); hyperelastic 4."""
+    mass and Helmholtz 2p, plus p per pre-multiplying coefficient function;
+    elasticity with P1 Lame fields 2(p-1)+1 on simplices and 2p+1 on prisms
+    (tensor-product degree); hyperelastic 4."""
     if form in ("mass", "helmholtz"):
-        return 2 * p
+        return (2 + nf) * p
     if form == "elasticity":
         return 2 * p + 1 if cell == "prism" else 2 * p - 1
     return 4
@@ -136,15 +140,25 @@ def local_dim(form: str, cell: str, p: int) -> int:
 
 
 def assemble(form: str, cell: str, p: int, coords, coeff=None, qdeg=None,
-             mu: float = 1.0, lam: float = 10.0, nthreads: int = 0):
-    """Element matrices [E][n][n] and the number of flagged elements."""
+             mu: float = 1.0, lam: float = 10.0, nthreads: int = 0, nf: int = 0):
+    """Element matrices [E][n][n] and the number of flagged elements.  For
+    mass and Helmholtz, nf > 0 pre-multiplies the form by nf coefficient
+    functions of degree p with DOFs coeff [E][nf][n_s]."""
     coords = _f64(coords)
     E = coords.shape[0]
     n = local_dim(form, cell, p)
     if qdeg is None:
-        qdeg = default_qdeg(form, cell, p)
+        qdeg = default_qdeg(form, cell, p, nf)
     out = np.empty((E, n, n))
     cf = _f64(coeff) if coeff is not None else None
+    if nf:
+        if form not in ("mass", "helmholtz") or cf is None or cf.size != E * nf * nbasis(cell, p):
+            raise ValueError("nf coefficient functions need mass/helmholtz and coeff [E][nf][n_s]")
+        flagged = lib().orc_assemble_coef(FORM[form], CELL[cell], p, qdeg, nf, E, _p(coords), _p(cf),
+                                          _p(out), nthreads)
+        if flagged < 0:
+            raise ValueError("oracle rejected arguments")
+        return out, int(flagged)
     if form in ("elasticity", "hyperelastic") and cf is None:
         raise ValueError("coefficients required")
     flagged = lib().orc_assemble(FORM[form], CELL[cell], p, qdeg, E, _p(coords), _p(cf),

@@ -27,7 +27,9 @@
  *          fastest; prism node (t,l) -> l*n_tri + t; vector spaces are
  *          component-blocked (row c*n_s + j).
  *   coords [E][nv][gdim]; elasticity coeff [E][2][nc] (lambda, then mu);
- *   hyperelastic coeff [E][gdim*n_s]; out [E][n][n] row = test, col = trial.
+ *   hyperelastic coeff [E][gdim*n_s]; mass / Helmholtz with nf
+ *   pre-multiplying coefficient functions coeff [E][nf][n_s];
+ *   out [E][n][n] row = test, col = trial.
  *
  * Pins: every function here is checked by the CPU test suite against exact
  * rational integration, closed forms, invariants and finite differences.
@@ -396,9 +398,31 @@ static void neo_hookean(int d, const double *F, double mu, double lam, double *P
  * Returns the number of elements flagged (degenerate map, non-affine prism,
  * or J_F <= 0 for the hyperelastic form); their blocks are filled with NaN.
  * ------------------------------------------------------------------------ */
+static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int64_t E,
+                             const double *coords, const double *coeff,
+                             double mu_c, double lam_c, double *out, int nthreads);
+
 int64_t orc_assemble(int form, int cell, int p, int qdeg, int64_t E,
                      const double *coords, const double *coeff,
                      double mu_c, double lam_c, double *out, int nthreads)
+{
+    return assemble_nest(form, cell, p, qdeg, 0, E, coords, coeff, mu_c, lam_c, out, nthreads);
+}
+
+/* Mass and Helmholtz pre-multiplied by nf coefficient functions (the
+ * experiment matrix of Sec. 7.1): the integrand is multiplied by
+ * prod_{i<nf} f_i(X_q), each f_i in the same Lagrange space as the test and
+ * trial functions, given by its element-local DOFs coeff[E][nf][n_s]. */
+int64_t orc_assemble_coef(int form, int cell, int p, int qdeg, int nf, int64_t E,
+                          const double *coords, const double *coeff, double *out, int nthreads)
+{
+    if (form < 0 || form > 1 || nf < 0 || nf > 3 || (nf > 0 && !coeff)) return -1;
+    return assemble_nest(form, cell, p, qdeg, nf, E, coords, coeff, 1.0, 10.0, out, nthreads);
+}
+
+static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int64_t E,
+                             const double *coords, const double *coeff,
+                             double mu_c, double lam_c, double *out, int nthreads)
 {
     int d = tdim_of(cell), nv = nvert_of(cell);
     int ns = orc_nbasis(cell, p);
@@ -434,6 +458,13 @@ int64_t orc_assemble(int form, int cell, int p, int qdeg, int64_t E,
         for (int q = 0; q < nq && !bad; ++q) {
             const double *phi = PHI + q * ns, *dphi = DPHI + q * ns * d;
             double dx = W[q] * fabs(detJ);
+            /* pre-multiplying coefficient functions f_i(X_q) = sum_l f_il Phi_l(X_q) */
+            for (int f = 0; f < nf; ++f) {
+                const double *cf = coeff + ((size_t)e * nf + f) * ns;
+                double fv = 0.0;
+                for (int l = 0; l < ns; ++l) fv += cf[l] * phi[ORC_MUTANT == 8 ? (l + 1) % ns : l];
+                if (!(ORC_MUTANT == 9 && f > 0)) dx *= fv;
+            }
             /* physical gradients g_i[b] = sum_a dX_a/dx_b dPhi_i/dX_a */
             for (int i = 0; i < ns; ++i)
                 for (int b = 0; b < d; ++b) {

@@ -302,3 +302,52 @@ def elasticity(cell, p, verts, lam_dofs, mu_dofs):
                                 s += WM[a][b][j][k] * sum(K[a][x] * K[b][x] for x in range(d))
                     A[c * ns + j][e * ns + k] = adet * s
     return A
+
+
+# ----------------------------------------------------------------------------
+# Forms pre-multiplied by coefficient functions (Sec. 7.1's nf)
+# ----------------------------------------------------------------------------
+
+def _poly_mul(P, Q):
+    out = {}
+    for e1, c1 in P.items():
+        for e2, c2 in Q.items():
+            e = tuple(x + y for x, y in zip(e1, e2))
+            out[e] = out.get(e, 0) + c1 * c2
+    return out
+
+
+def coefficient_weight(cell: str, p: int, fields):
+    """prod_i f_i as a polynomial dict, f_i = sum_l fields[i][l] phi_l (degree p)."""
+    ex, C = lagrange(cell, p)
+    V = _val_coeffs(ex, C)
+    w = {tuple(0 for _ in range(TDIM[cell])): Fr(1)}
+    for f in fields:
+        fi = {}
+        for l, dof in enumerate(f):
+            for e, c in V[l].items():
+                fi[e] = fi.get(e, 0) + Fr(dof) * c
+        w = _poly_mul(w, fi)
+    return w
+
+
+def weighted_mass(cell, p, verts, fields):
+    _, adet, _ = affine(cell, verts)
+    ex, C = lagrange(cell, p)
+    V = _val_coeffs(ex, C)
+    M = _bilinear(cell, V, V, weight=coefficient_weight(cell, p, fields))
+    return [[adet * x for x in row] for row in M]
+
+
+def weighted_helmholtz(cell, p, verts, fields):
+    d = TDIM[cell]
+    _, adet, K = affine(cell, verts)
+    ex, C = lagrange(cell, p)
+    w = coefficient_weight(cell, p, fields)
+    D = [_deriv_coeffs(ex, C, a) for a in range(d)]
+    G = [[sum(K[a][b] * K[c][b] for b in range(d)) for c in range(d)] for a in range(d)]
+    Kr = [[_bilinear(cell, D[a], D[b], weight=w) for b in range(d)] for a in range(d)]
+    M = weighted_mass(cell, p, verts, fields)
+    n = len(M)
+    return [[M[j][k] + adet * sum(G[a][b] * Kr[a][b][j][k] for a in range(d) for b in range(d))
+             for k in range(n)] for j in range(n)]

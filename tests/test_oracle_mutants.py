@@ -20,6 +20,8 @@ MUTANTS = {
     5: ("Gauss-Jacobi weights off by a factor 2", "rule"),
     6: ("wrong denominator in the Silvester factor", "basis"),
     7: ("dropped lambda ln J term of the tangent", "hyper"),
+    8: ("coefficient function evaluated with a shifted basis index", "coefficients"),
+    9: ("only the first pre-multiplying coefficient function applied", "coefficients"),
 }
 
 PINS = {
@@ -30,6 +32,8 @@ PINS = {
     5: "rule_exact_to_degree",
     6: "basis_kronecker",
     7: "hyper_tangent_is_residual_derivative",
+    8: "coefficient_fields_exact_rational",
+    9: "coefficient_fields_exact_rational or coefficient_fields_invariants",
 }
 
 

@@ -166,6 +166,48 @@ def test_mass_and_helmholtz_exact_rational(cell, p):
         assert normwise(Ah[0], er.helmholtz(cell, p, verts)) < 1e-14
 
 
+COEF_EXACT = [("triangle", 1, 3), ("triangle", 2, 2), ("triangle", 3, 1), ("tetrahedron", 1, 3),
+              ("tetrahedron", 2, 2), ("prism", 1, 2)]
+
+
+@pytest.mark.parametrize("cell,p,nfmax", COEF_EXACT)
+def test_coefficient_fields_exact_rational(cell, p, nfmax):
+    """Mass and Helmholtz pre-multiplied by nf coefficient functions of degree
+    p (Sec. 7.1): exact integrals of the polynomial weight prod_i f_i."""
+    ns = oracle.nbasis(cell, p)
+    rng = np.random.default_rng(100 + p)
+    verts = IMAGES[cell][0]
+    v = fverts(verts)
+    for nf in range(1, nfmax + 1):
+        fields = [[Fr(int(rng.integers(-3, 6)), int(rng.integers(1, 4))) for _ in range(ns)] for _ in range(nf)]
+        cf = np.array([[float(x) for x in f] for f in fields])[None]
+        Am, _ = oracle.assemble("mass", cell, p, v[None], cf, nf=nf)
+        Ah, _ = oracle.assemble("helmholtz", cell, p, v[None], cf, nf=nf)
+        assert normwise(Am[0], er.weighted_mass(cell, p, verts, fields)) < 1e-13
+        assert normwise(Ah[0], er.weighted_helmholtz(cell, p, verts, fields)) < 1e-13
+
+
+def test_coefficient_fields_invariants():
+    """Constant fields scale the form by the product of the constants, and a
+    field's DOFs enter linearly and symmetrically in the field order."""
+    coords = inputs.tet_workload(2, seed=5)[0][:10]
+    rng = np.random.default_rng(3)
+    for p in (1, 2, 3):
+        ns = oracle.nbasis("tetrahedron", p)
+        H0, _ = oracle.assemble("helmholtz", "tetrahedron", p, coords)
+        const = np.stack([np.full((10, ns), 1.5), np.full((10, ns), -0.5)], axis=1)
+        H2, _ = oracle.assemble("helmholtz", "tetrahedron", p, coords, const, nf=2)
+        assert np.max(np.abs(H2 + 0.75 * H0)) < 1e-13 * np.max(np.abs(H0))
+        f = rng.uniform(0.5, 2.0, size=(10, 2, ns))
+        A, _ = oracle.assemble("mass", "tetrahedron", p, coords, f, nf=2)
+        B, _ = oracle.assemble("mass", "tetrahedron", p, coords, f[:, ::-1].copy(), nf=2)
+        assert np.max(np.abs(A - B)) < 1e-13 * np.max(np.abs(A))
+        g = f.copy()
+        g[:, 0] *= 3.0
+        C, _ = oracle.assemble("mass", "tetrahedron", p, coords, g, nf=2)
+        assert np.max(np.abs(C - 3.0 * A)) < 1e-13 * np.max(np.abs(A))
+
+
 @pytest.mark.parametrize("cell", CELLS)
 def test_helmholtz_invariants(cell):
     rng = np.random.default_rng(11)
