@@ -93,7 +93,8 @@ enum {
 /* Launch shape override.  Every field 0 = automatic (the autotuner's choice
  * for the variant when one is cached, else the built-in default); a nonzero
  * field replaces that field of the automatic shape.
- *   kernel       pre-evaluated mode: 1 = tiled kernel (tiles of `chunk`
+ *   kernel       pre-evaluated mode (nf = 0; with nf > 0 one kernel
+ *                serves the mode and only grid_per_cu applies): 1 = tiled kernel (tiles of `chunk`
  *                consecutive elements staged through LDS), 2 = streaming
  *                kernel (table entries held in registers for the whole
  *                launch, which needs epi * n^2 <= 8 * block, 16 * block for
@@ -135,6 +136,13 @@ typedef struct {
                                   host and reject non-affine prisms with
                                   FE_ENONAFFINE before launching            */
     fe_shape_t     shape;      /* launch shape override; zero = automatic   */
+    int            nf;         /* mass and Helmholtz only: the form is pre-
+                                  multiplied by nf (0..3) coefficient
+                                  functions f_i of the same Lagrange degree
+                                  as the test and trial functions (the
+                                  experiment matrix of Sec. 7.1); coeff_dofs
+                                  is then [E][nf][n_s] and the default rule
+                                  exact degree (2 + nf) * degree.  Default 0 */
 } fe_options_t;
 
 /* Fills *opt with the defaults listed above. */
@@ -203,11 +211,14 @@ typedef struct {
 } fe_plan_t;
 
 /* qdeg = -1 for the form default; th_bytes = 0 for the LDS capacity of one
- * compute unit (160 KiB when no device is present).  A plan may pre-evaluate
- * only some monomials (Fig. 5): mode is then FE_MODE_QUADRATURE and the
- * quadrature kernel adds the pre-evaluated monomials' tables.
+ * compute unit (160 KiB when no device is present); nf as in fe_options_t
+ * (mass and Helmholtz; iota = C(n_s + nf - 1, nf), Sec. 4.2).  A plan may
+ * pre-evaluate only some monomials (Fig. 5): mode is then
+ * FE_MODE_QUADRATURE and, with nf = 0, the quadrature kernel adds the
+ * pre-evaluated monomials' tables; with nf > 0 such a mixed plan is executed
+ * in quadrature mode.
  * Errors: FE_EINVAL. */
-int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int qdeg, size_t th_bytes,
+int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int qdeg, size_t th_bytes,
             fe_plan_t* plan);
 
 /* Mixed batches: several (form, cell, degree) sub-batches in one HIP graph,
@@ -222,7 +233,8 @@ int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int qdeg, size_t th_byte
  * present, else from built-in defaults.  Sub-batches with no elements are
  * allowed and do nothing.  Replays on one stream are ordered; replays of
  * one batch on different streams at once race on its work queues.
- * Errors: FE_EINVAL, FE_ENOTSUP (hyperelastic), FE_ENOMEM, FE_EHIP. */
+ * Coefficient functions (fe_options_t.nf) are not supported in batches.
+ * Errors: FE_EINVAL, FE_ENOTSUP (hyperelastic, nf > 0), FE_ENOMEM, FE_EHIP. */
 typedef struct fe_subbatch {
     fe_form_t     form;
     fe_cell_t     cell;

@@ -26,12 +26,12 @@ namespace fe {
 
 namespace {
 
-using Key = std::tuple<int, int, int, int, int, int>;
+using Key = std::tuple<int, int, int, int, int, int, int>;
 std::mutex g_tmu;
 std::map<Key, Config> g_tuned;
 bool g_loaded = false;
 
-Key key_of(const Call& c) { return Key(c.form, c.cell, c.degree, c.qdeg, c.mode, c.prec); }
+Key key_of(const Call& c) { return Key(c.form, c.cell, c.degree, c.qdeg, c.mode, c.prec, c.nf); }
 
 void load_file_locked()
 {
@@ -43,15 +43,15 @@ void load_file_locked()
     if (!f) return;
     char line[512];
     while (std::fgets(line, sizeof line, f)) {
-        int v[6];
+        int v[7];
         Config c;
         if (std::sscanf(line,
                         "{\"form\": %d, \"cell\": %d, \"degree\": %d, \"qdeg\": %d, \"mode\": %d, \"precision\": %d, "
                         "\"block\": %d, \"epi\": %d, \"chunk\": %d, \"eb\": %d, \"qc\": %d, \"grid_per_cu\": %d, "
-                        "\"variant\": %d",
+                        "\"variant\": %d, \"nf\": %d",
                         &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &c.block, &c.epi, &c.chunk, &c.eb, &c.qc,
-                        &c.grid_per_cu, &c.variant) == 13)
-            g_tuned[Key(v[0], v[1], v[2], v[3], v[4], v[5])] = c;
+                        &c.grid_per_cu, &c.variant, &v[6]) == 14)
+            g_tuned[Key(v[0], v[1], v[2], v[3], v[4], v[5], v[6])] = c;
     }
     std::fclose(f);
 }
@@ -59,6 +59,7 @@ void load_file_locked()
 Config default_for(const Call& c)
 {
     if (c.prec != FE_FP64) return Config();
+    if (c.mode == FE_MODE_PREEVAL && c.nf > 0) return Config();
     if (c.mode == FE_MODE_PREEVAL) return default_preeval_config(c.form, c.tables->nb * c.tables->nb);
     // float64 matrix-core Gram kernel where the point loop is not hoisted
     // (with one point per element the VALU kernel is faster)
@@ -77,6 +78,14 @@ std::vector<Config> candidates(const Call& c)
     if (c.prec != FE_FP64) {
         for (int g : {4, 8, 16}) {
             Config x = base;
+            x.grid_per_cu = g;
+            out.push_back(x);
+        }
+        return out;
+    }
+    if (c.mode == FE_MODE_PREEVAL && c.nf > 0) {
+        for (int g : {2, 4, 8, 16}) {
+            Config x;
             x.grid_per_cu = g;
             out.push_back(x);
         }
@@ -217,18 +226,19 @@ extern "C" int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n
                 std::fprintf(f,
                              "{\"form\": %d, \"cell\": %d, \"degree\": %d, \"qdeg\": %d, \"mode\": %d, "
                              "\"precision\": %d, \"block\": %d, \"epi\": %d, \"chunk\": %d, \"eb\": %d, \"qc\": %d, "
-                             "\"grid_per_cu\": %d, \"variant\": %d, \"ms\": %.6f}\n",
+                             "\"grid_per_cu\": %d, \"variant\": %d, \"nf\": %d, \"ms\": %.6f}\n",
                              c.form, c.cell, c.degree, c.qdeg, c.mode, c.prec, best_cfg.block, best_cfg.epi,
-                             best_cfg.chunk, best_cfg.eb, best_cfg.qc, best_cfg.grid_per_cu, best_cfg.variant, best);
+                             best_cfg.chunk, best_cfg.eb, best_cfg.qc, best_cfg.grid_per_cu, best_cfg.variant, c.nf, best);
                 std::fclose(f);
             }
         }
     }
     if (best_ms) *best_ms = best;
     if (best_shape) {
-        best_shape->kernel = c.prec != FE_FP64             ? 4
-                             : c.mode == FE_MODE_PREEVAL ? (best_cfg.variant ? 2 : 1)
-                                                         : (best_cfg.variant ? 4 : 3);
+        best_shape->kernel = c.prec != FE_FP64                  ? 4
+                             : c.mode == FE_MODE_PREEVAL && c.nf ? 0   // a single kernel
+                             : c.mode == FE_MODE_PREEVAL         ? (best_cfg.variant ? 2 : 1)
+                                                                 : (best_cfg.variant ? 4 : 3);
         best_shape->block = best_cfg.block;
         best_shape->epi = best_cfg.epi;
         best_shape->chunk = best_cfg.chunk;

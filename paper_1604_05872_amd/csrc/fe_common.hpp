@@ -55,9 +55,11 @@ FE_HD constexpr int rule_size(int cell, int qdeg)
                          : (qdeg <= 2 ? 3 : rule_m(qdeg) * rule_m(qdeg)) * rule_m(qdeg);
 }
 
-FE_HD constexpr int default_qdeg(int form, int cell, int p)
+// exact degree; mass and Helmholtz gain p per pre-multiplying coefficient
+// function (nf, Sec. 7.1)
+FE_HD constexpr int default_qdeg(int form, int cell, int p, int nf = 0)
 {
-    return (form == MASS || form == HELMHOLTZ) ? 2 * p
+    return (form == MASS || form == HELMHOLTZ) ? (2 + nf) * p
          : form == ELASTICITY ? (cell == PRISM ? 2 * p + 1 : 2 * p - 1)
                               : 4;
 }

@@ -27,6 +27,7 @@ namespace {
 std::mutex g_mu;
 thread_local std::string g_hip_msg = "no HIP error recorded";
 std::map<std::tuple<int, int, int, int>, RefTables*> g_tables;   // (device, cell, p, qdeg)
+std::map<std::tuple<int, int, int, int, int, int>, CoefTables*> g_coef;   // (device, form, cell, p, qdeg, nf)
 
 int current_device()
 {
@@ -123,6 +124,54 @@ int get_tables(int cell, int p, int qdeg, hipStream_t s, const RefTables** out)
         return set_hip_error(e, "building reference tables");
     }
     g_tables[key] = t;
+    *out = t;
+    return FE_OK;
+}
+
+// Builds (once) the multisets and the coefficient-expanded reference tensors
+// of (form, cell, p, qdeg, nf) on the current device.
+int get_coef_tables(int form, int cell, int p, int qdeg, int nf, hipStream_t s, const CoefTables** out)
+{
+    const RefTables* rt = nullptr;
+    int rc = get_tables(cell, p, qdeg, s, &rt);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_tuple(current_device(), form, cell, p, qdeg, nf);
+    auto it = g_coef.find(key);
+    if (it != g_coef.end()) {
+        *out = it->second;
+        return FE_OK;
+    }
+    const int nb = rt->nb;
+    // sorted multisets l_1 <= ... <= l_nf, lexicographic
+    std::vector<int> combos;
+    std::vector<int> cur(nf, 0);
+    for (;;) {
+        combos.insert(combos.end(), cur.begin(), cur.end());
+        int i = nf - 1;
+        while (i >= 0 && cur[i] == nb - 1) --i;
+        if (i < 0) break;
+        ++cur[i];
+        for (int k = i + 1; k < nf; ++k) cur[k] = cur[i];
+    }
+    CoefTables* t = new CoefTables();
+    t->iota = (int)(combos.size() / nf);
+    const int nr = n_tables(form, cell);
+    t->nt = nr * t->iota;
+    hipError_t e = hipMalloc((void**)&t->dCombos, combos.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void**)&t->dR, (size_t)t->nt * nb * nb * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(t->dCombos, combos.data(), combos.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_coef_tables(rt->nq, nb, rt->d, nf, t->iota, nr, rt->dW, rt->dphi, rt->ddphi, t->dCombos, t->dR, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        if (t->dCombos) (void)hipFree(t->dCombos);
+        if (t->dR) (void)hipFree(t->dR);
+        delete t;
+        return set_hip_error(e, "building coefficient tables");
+    }
+    g_coef[key] = t;
     *out = t;
     return FE_OK;
 }
@@ -339,10 +388,13 @@ int fe_resolve_variant(int form, int cell, int degree, int qdeg, const fe_option
         return FE_OK;
     }
     fe_plan_t plan;
-    int rc = fe_plan((fe_form_t)form, (fe_cell_t)cell, degree, qdeg, o->th_bytes, &plan);
+    int rc = fe_plan((fe_form_t)form, (fe_cell_t)cell, degree, o->nf, qdeg, o->th_bytes, &plan);
     if (rc) return rc;
     *mode_out = plan.mode;
-    if (form == HELMHOLTZ && plan.mode == FE_MODE_QUADRATURE)
+    // a mixed Helmholtz plan adds the pre-evaluated monomial's tables in the
+    // quadrature kernel (nf = 0); with coefficient functions it runs as
+    // quadrature throughout
+    if (form == HELMHOLTZ && plan.mode == FE_MODE_QUADRATURE && o->nf == 0)
         *mass_pre = (plan.preevaluated[1] ? 1 : 0) | (plan.preevaluated[0] ? 2 : 0);
     return FE_OK;
 }
@@ -425,6 +477,15 @@ int launch_call(const Call& c, const Config& cfg)
         if (e != hipSuccess) return set_hip_error(e, "split-precision launch");
         return FE_OK;
     }
+    if (c.mode == FE_MODE_PREEVAL && c.nf > 0) {
+        const CoefTables* ct = nullptr;
+        int rc = get_coef_tables(c.form, c.cell, c.degree, c.qdeg, c.nf, c.stream, &ct);
+        if (rc) return rc;
+        e = launch_preeval_coef(c.form, c.cell, c.coords, c.coeff, c.out, c.status, ct->dR, ct->dCombos, c.E, t->nb,
+                                c.nf, ct->iota, cfg.grid_per_cu, cus, c.stream);
+        if (e != hipSuccess) return set_hip_error(e, "coefficient pre-evaluated launch");
+        return FE_OK;
+    }
     if (c.mode == FE_MODE_PREEVAL) {
         PreevalArgs a;
         a.coords = c.coords;
@@ -470,6 +531,7 @@ int launch_call(const Call& c, const Config& cfg)
     a.qc = cfg.qc;
     a.mu = c.mu;
     a.lam = c.lam;
+    a.nf = c.nf;
     const int64_t tiles = (c.E + a.eb - 1) / a.eb;
     const int grid = (int)std::min<int64_t>(tiles, (int64_t)cus * cfg.grid_per_cu);
     const size_t lds = quad_lds_bytes(c.form, c.cell, t->nb, a.eb, a.qc);
@@ -498,6 +560,16 @@ int check_config(const Call& c, const Config& cfg)
     if (c.prec != FE_FP64) return FE_OK;
     const RefTables* t = c.tables;
     const size_t max_lds = device_lds_per_block();
+    if (c.mode == FE_MODE_PREEVAL && c.nf > 0) {
+        // one wavefront per block; the element rows of a 16-element tile
+        // (n_tables * iota of them) sit in LDS
+        long iota = 1;
+        for (int i = 1; i <= c.nf; ++i) iota = iota * (t->nb + i - 1) / i;
+        const long ntp = (n_tables(c.form, c.cell) * iota + 7) / 8 * 8;
+        return preeval_coef_lds_bytes(c.form, c.cell, (int)std::min<long>(ntp, 1L << 30), c.nf, t->nb) <= max_lds
+                   ? FE_OK
+                   : FE_EINVAL;
+    }
     if (c.mode == FE_MODE_PREEVAL) {
         const int nn = t->nb * t->nb;
         if (cfg.block < 64 || cfg.block > 512 || cfg.block % 64 || cfg.epi < 1 || cfg.epi > cfg.block)
@@ -559,8 +631,11 @@ int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, co
         n_elems < 0)
         return FE_EINVAL;
     if ((int)o.precision < 0 || (int)o.precision > 2 || (int)o.mode < 0 || (int)o.mode > 2) return FE_EINVAL;
-    const int qdeg = o.qdeg < 0 ? default_qdeg(form, cell, degree) : o.qdeg;
+    if (o.nf < 0 || o.nf > 3) return FE_EINVAL;
+    if (o.nf > 0 && (is_vector_form(form) || o.precision != FE_FP64)) return FE_ENOTSUP;
+    const int qdeg = o.qdeg < 0 ? default_qdeg(form, cell, degree, o.nf) : o.qdeg;
     if (qdeg > MAX_QDEG) return FE_EINVAL;
+    c->nf = o.nf;
     c->form = form;
     c->cell = cell;
     c->degree = degree;
@@ -582,7 +657,7 @@ int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, co
     }
     if (n_elems == 0) return FE_OK;
     if (!coords || !out_A) return FE_EINVAL;
-    if (is_vector_form(form) && !coeff_dofs) return FE_EINVAL;
+    if ((is_vector_form(form) || o.nf > 0) && !coeff_dofs) return FE_EINVAL;
     if (form == HYPERELASTIC && !(std::isfinite(o.mu) && std::isfinite(o.lambda))) return FE_EINVAL;
     int rc = fe_resolve_variant(form, cell, degree, qdeg, &o, &c->mode, &c->mass_pre);
     if (rc) return rc;

@@ -28,6 +28,13 @@ hipError_t launch_preeval(int form, int cell, const PreevalArgs& a, int block, i
 // resident blocks per CU
 hipError_t launch_preeval_stream(int form, int cell, const PreevalArgs& a, int block, int max_per_cu, int cus,
                                  hipStream_t s);
+// preeval_coef.hip: pre-evaluation with nf pre-multiplying coefficient functions
+hipError_t launch_coef_tables(int nq, int nb, int d, int nf, int iota, int nr, const double* W, const double* phi,
+                              const double* dphi, const int* combos, double* R, hipStream_t s);
+hipError_t launch_preeval_coef(int form, int cell, const double* coords, const double* coeff, double* out,
+                               int* status, const double* R, const int* combos, int64_t E, int nb, int nf,
+                               int iota, int grid_per_cu, int cus, hipStream_t s);
+size_t preeval_coef_lds_bytes(int form, int cell, int ntp, int nf, int nb);
 hipError_t launch_quad_mass(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_quad_helmholtz(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_quad_elasticity(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
@@ -99,8 +106,17 @@ struct RefTables {
     double* dR = nullptr;              // [1 + d(d+1)/2][nb][nb] pre-evaluated tensors
 };
 
+// Tables of the pre-evaluation with nf coefficient functions: the sorted
+// multisets S of nf basis indices and R[(r, S)][j][k], device resident.
+struct CoefTables {
+    int iota = 0, nt = 0;
+    int* dCombos = nullptr;   // [iota][nf]
+    double* dR = nullptr;     // [nt][nb][nb]
+};
+
 // felocal.cpp
 int get_tables(int cell, int p, int qdeg, hipStream_t s, const RefTables** out);
+int get_coef_tables(int form, int cell, int p, int qdeg, int nf, hipStream_t s, const CoefTables** out);
 int device_cus();
 size_t device_lds_per_cu();
 int set_hip_error(hipError_t e, const char* where);
@@ -132,6 +148,7 @@ size_t quad_lds_bytes(int form, int cell, int ns, int eb, int qc);
 struct Call {
     int form = 0, cell = 0, degree = 1, qdeg = 2;
     int mode = 0;       // FE_MODE_PREEVAL or FE_MODE_QUADRATURE
+    int nf = 0;         // pre-multiplying coefficient functions (mass, Helmholtz)
     int shape[7] = {0, 0, 0, 0, 0, 0, 0};   // caller's launch-shape override (fe_shape_t order)
     int mass_pre = 0;   // Helmholtz quadrature: bit 0 mass monomial pre-evaluated,
                         // bit 1 gradient monomial pre-evaluated

@@ -8,7 +8,9 @@
 //   theta_pre(m) = 2 * rho * iota * (entries): rho pre-evaluable terms per
 //                  entry, each expanded iota times (one multiply-add per term)
 //   iota = C(n + k - 1, k): k coefficient functions in the monomial, n the
-//          basis functions of the coefficient space (Sec. 4.2, Fig. 6).
+//          basis functions of the coefficient space (Sec. 4.2, Fig. 6); the
+//          nf pre-multiplying functions of mass and Helmholtz live in the
+//          test/trial space (n = n_s), the Lame fields of elasticity in P1.
 // theta(m) = theta_pre(m) - theta_se(m); pre-evaluation is profitable iff
 // theta < 0 (the sign convention of Sec. 4.1, which the algorithm's step 1
 // uses).  Step 3 discards a bipartition whose pre-evaluated tables exceed T_H
@@ -34,13 +36,15 @@ static long binom(long n, long k)
 
 using namespace fe;
 
-extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int qdeg, size_t th_bytes, fe_plan_t* plan)
+extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int qdeg, size_t th_bytes,
+                       fe_plan_t* plan)
 {
     if (!plan || (int)form < 0 || (int)form > 3 || (int)cell < 0 || (int)cell > 2 || degree < 1 ||
-        degree > MAX_DEGREE || qdeg > MAX_QDEG)
+        degree > MAX_DEGREE || qdeg > MAX_QDEG || nf < 0 || nf > 3 || (nf > 0 && is_vector_form(form)))
         return FE_EINVAL;
     std::memset(plan, 0, sizeof(*plan));
-    if (qdeg < 0) qdeg = default_qdeg(form, cell, degree);
+    if (qdeg < 0) qdeg = default_qdeg(form, cell, degree, nf);
+    if (qdeg > MAX_QDEG) return FE_EINVAL;
     if (th_bytes == 0) {
         int ndev = 0;
         th_bytes = (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) ? device_lds_per_cu() : 160 * 1024;
@@ -49,6 +53,9 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int qdeg, siz
     const int d = cell_dim(cell), ns = n_scalar(cell, degree), nq = rule_size(cell, qdeg), nc = cell_nv(cell);
     const double pairs = (double)ns * ns;
     const size_t tbl = (size_t)ns * ns * sizeof(double);
+    // nf pre-multiplying coefficient functions in the test/trial space: the
+    // expansion of Sec. 4.2 has iota = C(n_s + nf - 1, nf) distinct tables
+    const int iota_f = (int)binom(ns + nf - 1, nf);
     // table-set ids for the dedup of identical tables
     int table_set[4] = {0, 0, 0, 0};
     int nm = 0;
@@ -57,23 +64,23 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int qdeg, siz
     case FE_MASS:
         nm = 1;
         plan->theta_se[0] = nq * pairs * 2;
-        plan->iota[0] = (int)binom(0, 0);
+        plan->iota[0] = iota_f;
         plan->rho[0] = 1;
-        plan->table_bytes[0] = tbl;
+        plan->table_bytes[0] = (size_t)iota_f * tbl;
         table_set[0] = 1;
         legal[0] = true;
         break;
     case FE_HELMHOLTZ:
         nm = 2;   // grad v . grad u, then v u
         plan->theta_se[0] = nq * pairs * 2 * d;
-        plan->iota[0] = 1;
+        plan->iota[0] = iota_f;
         plan->rho[0] = d * (d + 1) / 2;
-        plan->table_bytes[0] = plan->rho[0] * tbl;
+        plan->table_bytes[0] = (size_t)plan->rho[0] * iota_f * tbl;
         table_set[0] = 2;
         plan->theta_se[1] = nq * pairs * 2;
-        plan->iota[1] = 1;
+        plan->iota[1] = iota_f;
         plan->rho[1] = 1;
-        plan->table_bytes[1] = tbl;
+        plan->table_bytes[1] = (size_t)iota_f * tbl;
         table_set[1] = 1;
         legal[0] = legal[1] = true;
         break;

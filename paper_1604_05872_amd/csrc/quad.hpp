@@ -49,6 +49,8 @@ struct QuadArgs {
     int qc;               // points per LDS chunk
     int nt;               // non-temporal output stores
     double mu, lam;       // hyperelastic constants
+    int nf;               // mass / Helmholtz: pre-multiplying coefficient functions,
+                          // DOFs [E][nf][ns] in coeff (Sec. 7.1)
 };
 
 template <int FORM, int CELL>
@@ -155,7 +157,15 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
                 double* pt = sPt + ((size_t)i * qc_max + qq) * ppt;
                 double* sw = pt + ns * D + (FORM == HYPERELASTIC ? ns * D + 9 : 0);
                 if (FORM == MASS || FORM == HELMHOLTZ) {
-                    sw[0] = w;
+                    // w times prod_i f_i(X_q), f_i = sum_l f_il phi_l
+                    double wf = w;
+                    for (int f = 0; f < a.nf; ++f) {
+                        const double* cf = a.coeff + (e * a.nf + f) * ns;
+                        double fv = 0.0;
+                        for (int l = 0; l < ns; ++l) fv = fma(cf[l], sPhi[qq * ns + l], fv);
+                        wf *= fv;
+                    }
+                    sw[0] = wf;
                 } else if (FORM == ELASTICITY) {
                     const double* ce = a.coeff + e * 2 * NV;
                     if (a.collapse) {

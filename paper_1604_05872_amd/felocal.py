@@ -23,6 +23,12 @@ MODES = {"auto": 0, "preeval": 1, "quadrature": 2}
 GDIM = {"triangle": 2, "tetrahedron": 3, "prism": 3}
 NVERT = {"triangle": 3, "tetrahedron": 4, "prism": 6}
 
+
+def NBASIS(cell: str, p: int) -> int:
+    """Scalar Lagrange P_p basis functions of the cell."""
+    return {"triangle": (p + 1) * (p + 2) // 2, "tetrahedron": (p + 1) * (p + 2) * (p + 3) // 6,
+            "prism": (p + 1) * (p + 2) // 2 * (p + 1)}[cell]
+
 # every function include/felocal.h declares
 EXPORTS = (
     "fe_options_init", "fe_tabulate", "fe_local_dims", "fe_assemble_local", "fe_geometry", "fe_plan",
@@ -53,6 +59,7 @@ class fe_options_t(ctypes.Structure):
         ("th_bytes", ctypes.c_size_t),
         ("validate", ctypes.c_int),
         ("shape", fe_shape_t),
+        ("nf", ctypes.c_int),
     ]
 
 
@@ -104,7 +111,7 @@ def lib():
         L.fe_assemble_local.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, vp, vp, vp,
                                         ctypes.POINTER(fe_options_t)]
         L.fe_geometry.argtypes = [ctypes.c_int, ctypes.c_int64, vp, vp, vp, vp]
-        L.fe_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
+        L.fe_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
                               ctypes.POINTER(fe_plan_t)]
         L.fe_batch_create.argtypes = [ctypes.POINTER(fe_subbatch_t), ctypes.c_int, ctypes.POINTER(fe_options_t),
                                       ctypes.POINTER(vp)]
@@ -159,7 +166,7 @@ def _f64_dev(t, name):
 
 
 def make_options(qdeg=-1, precision="fp64", mode="auto", stream=None, mu=1.0, lam=10.0, status=None,
-                 th_bytes=0, validate=False, need_stream=True, shape=None) -> fe_options_t:
+                 th_bytes=0, validate=False, need_stream=True, shape=None, nf=0) -> fe_options_t:
     o = fe_options_t()
     lib().fe_options_init(ctypes.byref(o))
     o.qdeg = int(qdeg)
@@ -173,6 +180,7 @@ def make_options(qdeg=-1, precision="fp64", mode="auto", stream=None, mu=1.0, la
     o.validate = 1 if validate else 0
     for k, v in (shape or {}).items():
         setattr(o.shape, k, int(v))
+    o.nf = int(nf)
     return o
 
 
@@ -206,11 +214,12 @@ def fe_tabulate(cell: str, degree: int, qdeg: int, rule_only: bool = False):
 def fe_assemble_local(form: str, cell: str, degree: int, coords, coeff, out, qdeg: int = -1,
                       precision: str = "fp64", mode: str = "auto", stream=None, mu: float = 1.0,
                       lam: float = 10.0, status=None, th_bytes: int = 0, validate: bool = False,
-                      shape: dict | None = None):
+                      shape: dict | None = None, nf: int = 0):
     """Element matrices of `form` into `out` [E][n][n] (asynchronous on the stream).
 
     shape: optional launch-shape override, keys of fe_shape_t (kernel: 1 tiled,
-    2 streaming; block, epi, chunk, eb, qc, grid_per_cu)."""
+    2 streaming; block, epi, chunk, eb, qc, grid_per_cu).  nf: mass and
+    Helmholtz pre-multiplied by nf coefficient functions, coeff [E][nf][n_s]."""
     _f64_dev(coords, "coords")
     _f64_dev(coeff, "coeff")
     _f64_dev(out, "out")
@@ -220,9 +229,11 @@ def fe_assemble_local(form: str, cell: str, degree: int, coords, coeff, out, qde
         raise ValueError(f"coords must be [E][{NVERT[cell]}][{GDIM[cell]}]")
     if tuple(out.shape[-2:]) != (n, n) or out.numel() != E * n * n:
         raise ValueError(f"out must be [E][{n}][{n}]")
+    if nf:
+        nc = int(nf) * NBASIS(cell, degree)
     if nc and (coeff is None or coeff.numel() != E * nc):
         raise ValueError(f"coeff must hold {nc} values per element")
-    o = make_options(qdeg, precision, mode, stream, mu, lam, status, th_bytes, validate, shape=shape)
+    o = make_options(qdeg, precision, mode, stream, mu, lam, status, th_bytes, validate, shape=shape, nf=nf)
     _check(lib().fe_assemble_local(FORMS[form], CELLS[cell], int(degree), E, _ptr(coords), _ptr(coeff),
                                    _ptr(out), ctypes.byref(o)), "fe_assemble_local")
     return out
@@ -236,9 +247,9 @@ def fe_geometry(cell: str, coords, det, kinv, stream=None):
                              _stream(stream)), "fe_geometry")
 
 
-def fe_plan(form: str, cell: str, degree: int, qdeg: int = -1, th_bytes: int = 0) -> dict:
+def fe_plan(form: str, cell: str, degree: int, qdeg: int = -1, th_bytes: int = 0, nf: int = 0) -> dict:
     p = fe_plan_t()
-    _check(lib().fe_plan(FORMS[form], CELLS[cell], int(degree), int(qdeg), int(th_bytes), ctypes.byref(p)),
+    _check(lib().fe_plan(FORMS[form], CELLS[cell], int(degree), int(nf), int(qdeg), int(th_bytes), ctypes.byref(p)),
            "fe_plan")
     m = p.n_monomials
     return {
@@ -257,11 +268,11 @@ def fe_plan(form: str, cell: str, degree: int, qdeg: int = -1, th_bytes: int = 0
 
 def fe_autotune(form: str, cell: str, degree: int, coords, coeff, out, qdeg: int = -1,
                 precision: str = "fp64", mode: str = "auto", stream=None, mu: float = 1.0, lam: float = 10.0,
-                return_shape: bool = False):
+                return_shape: bool = False, nf: int = 0):
     """Best time per launch in ms (and, with return_shape, the chosen launch shape as a dict)."""
     _f64_dev(coords, "coords")
     _f64_dev(out, "out")
-    o = make_options(qdeg, precision, mode, stream, mu, lam)
+    o = make_options(qdeg, precision, mode, stream, mu, lam, nf=nf)
     best = ctypes.c_double()
     shape = fe_shape_t()
     _check(lib().fe_autotune(FORMS[form], CELLS[cell], int(degree), int(coords.shape[0]), _ptr(coords),

@@ -247,6 +247,47 @@ def test_fp64_vector_kernels(form, cell, p, kernel):
     assert normwise(A[~bad], B[~bad]).max() <= TOL["fp64"]
 
 
+# Forms pre-multiplied by nf coefficient functions (the sweep of Sec. 7.1):
+# the planner's choice, forced quadrature, and forced pre-evaluation where
+# a 16-element tile of the expanded geometry tensor fits in LDS.
+NF_CASES = [(f, c, p, nf) for f in ("mass", "helmholtz")
+            for (c, p) in [("tetrahedron", 1), ("tetrahedron", 2), ("tetrahedron", 3), ("tetrahedron", 4),
+                           ("triangle", 2), ("prism", 1)] for nf in (1, 2, 3)]
+
+
+def _coef_lds_bytes(form, cell, p, nf):
+    from math import comb
+    ns = oracle.nbasis(cell, p)
+    nr = 1 if form == "mass" else 1 + oracle.TDIM[cell] * (oracle.TDIM[cell] + 1) // 2
+    ntp = (nr * comb(ns + nf - 1, nf) + 7) // 8 * 8
+    return 8 * 16 * (ntp + nr + nf * ns)
+
+
+@pytest.mark.parametrize("mode", ["auto", "quadrature", "preeval"])
+@pytest.mark.parametrize("form,cell,p,nf", NF_CASES)
+def test_coefficient_functions(form, cell, p, nf, mode):
+    ns = oracle.nbasis(cell, p)
+    nq = oracle.rule(cell, oracle.default_qdeg(form, cell, p, nf))[1].size
+    E = int(max(7, min(700, 1.5e9 / (nq * ns * ns * 10))))
+    log(f"coefficient functions {form} {cell} P{p} nf={nf} {mode} E={E}")
+    coords, *_ = mesh(cell, E, seed=40 + p)
+    rng = np.random.default_rng(50 + nf)
+    cf = rng.uniform(0.5, 1.5, size=(E, nf, ns))
+    lds = _coef_lds_bytes(form, cell, p, nf)
+    if mode == "preeval" and lds > 160 * 1024:      # above any LDS per block: rejected up front
+        with pytest.raises(felocal.FeError):
+            gpu_assemble(form, cell, p, coords, cf, nf=nf, mode=mode)
+        return
+    try:
+        A, st = gpu_assemble(form, cell, p, coords, cf, nf=nf, mode=mode)
+    except felocal.FeError:
+        assert mode == "preeval" and lds > 64 * 1024   # only where the device's limit decides
+        return
+    B, fl = oracle.assemble(form, cell, p, coords, cf, nf=nf)
+    assert st == fl == 0
+    assert normwise(A, B).max() <= TOL["fp64"]
+
+
 # Indefinite point weights: a Lame field shifted below zero (lambda or mu),
 # and a negative hyperelastic lambda, through every precision.
 SIGNED_CASES = [("elasticity", "tetrahedron", 2, 0), ("elasticity", "triangle", 3, 0),

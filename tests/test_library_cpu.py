@@ -118,6 +118,32 @@ def test_planner_memory_threshold():
     assert felocal.fe_plan("helmholtz", "tetrahedron", 4)["th_bytes"] >= 160 * 1024
 
 
+def test_planner_coefficient_functions():
+    """nf pre-multiplying functions in the test/trial space: iota =
+    C(n_s + nf - 1, nf) (Sec. 4.2), tables iota * rho * n_s^2 doubles, and
+    Algorithm 3's choices under T_H = 160 KiB follow from theta and T_H."""
+    from math import comb
+    for p, ns in ((1, 4), (2, 10), (3, 20)):
+        for nf in range(4):
+            pl = felocal.fe_plan("mass", "tetrahedron", p, nf=nf, th_bytes=160 * 1024)
+            assert pl["iota"][0] == comb(ns + nf - 1, nf)
+            assert pl["table_bytes"][0] == comb(ns + nf - 1, nf) * ns * ns * 8
+    T = 160 * 1024
+    # mass P2: nf = 2 fits (44 KB) and pays; nf = 3 (176 KB) exceeds T_H
+    assert felocal.fe_plan("mass", "tetrahedron", 2, nf=2, th_bytes=T)["mode"] == "preeval"
+    assert felocal.fe_plan("mass", "tetrahedron", 2, nf=3, th_bytes=T)["mode"] == "quadrature"
+    # Helmholtz P2 nf = 1: all tables (56 KB) fit; P3 nf = 1: only the mass
+    # monomial's (64 KB) fit -> a mixed plan; P4 nf = 1: nothing fits
+    assert felocal.fe_plan("helmholtz", "tetrahedron", 2, nf=1, th_bytes=T)["mode"] == "preeval"
+    assert felocal.fe_plan("helmholtz", "tetrahedron", 3, nf=1, th_bytes=T)["preevaluated"] == [False, True]
+    assert felocal.fe_plan("helmholtz", "tetrahedron", 4, nf=1, th_bytes=T)["preevaluated"] == [False, False]
+    # with T_H relaxed the expansion still pays at P3 (theta < 0)
+    assert felocal.fe_plan("helmholtz", "tetrahedron", 3, nf=1, th_bytes=1 << 30)["mode"] == "preeval"
+    # vector forms take no pre-multiplying functions
+    with pytest.raises(felocal.FeError):
+        felocal.fe_plan("elasticity", "tetrahedron", 2, nf=1)
+
+
 def test_argument_errors_are_synchronous():
     L = felocal.lib()
     o = felocal.fe_options_t()
@@ -138,6 +164,12 @@ def test_argument_errors_are_synchronous():
     o.mode = 0
     assert L.fe_assemble_local(0, 1, 2, 1, 8, None, 8, ctypes.byref(o)) == felocal.FE_EINVAL
     o.qdeg = -1
+    o.nf = 4
+    assert L.fe_assemble_local(0, 1, 2, 1, 8, 8, 8, ctypes.byref(o)) == felocal.FE_EINVAL     # nf in 0..3
+    o.nf = 1
+    assert L.fe_assemble_local(2, 1, 2, 1, 8, 8, 8, ctypes.byref(o)) == felocal.FE_ENOTSUP    # not vector forms
+    assert L.fe_assemble_local(1, 1, 2, 1, 8, None, 8, ctypes.byref(o)) == felocal.FE_EINVAL  # DOFs needed
+    o.nf = 0
     for field, bad in (("kernel", 5), ("kernel", -1), ("block", -64), ("epi", -1), ("chunk", -2), ("eb", -1),
                        ("qc", -3), ("grid_per_cu", -1)):
         setattr(o.shape, field, bad)
