@@ -8,8 +8,10 @@ step.  value = element matrices per second over the timed steps.
 Also measured (fields "workloads"): P1 triangle mass on 4,096 elements,
 vector P2 elasticity on 1,971,054 tetrahedra (float64 and the split-precision
 MFMA variants), the neo-Hookean tangent on 998,250 tetrahedra (P1, P2; float64
-and split), and a 16-sub-batch mixed persistent launch replayed from a HIP
-graph (one persistent work-queue kernel per kernel variant).  Inputs are seeded
+and split), a 16-sub-batch mixed persistent launch replayed from a HIP
+graph (one persistent work-queue kernel per kernel variant), and the
+experiment matrix of Sec. 7.1 (mass and Helmholtz, q = 1..4, nf = 0..3
+coefficient functions) with Algorithm 3's choice against both forced modes.  Inputs are seeded
 synthetic meshes resident in HBM before timing.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -106,7 +108,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the built-in default launch shapes instead of the autotuned ones")
     ap.add_argument("--only-headline", action="store_true")
-    ap.add_argument("--workloads", default="mass,elasticity,hyperelastic,batch",
+    ap.add_argument("--workloads", default="mass,elasticity,hyperelastic,batch,sweep",
                     help="comma list of the extra workloads to time")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a known-size kernel for the HBM counters)")
@@ -381,6 +383,8 @@ def other_workloads(torch, felocal, inputs, stream, ev, reps, which):
         hyperelastic_workload(torch, felocal, inputs, stream, ev, record, reps)
     if "batch" in which:
         res.append(batch_workload(torch, felocal, inputs, stream, ev, reps))
+    if "sweep" in which:
+        res.append(sweep_workload(torch, felocal, inputs, stream, ev, max(2, reps // 3)))
     return res
 
 
@@ -440,6 +444,50 @@ def hyperelastic_workload(torch, felocal, inputs, stream, ev, record, reps):
         del o4, u
         torch.cuda.empty_cache()
     del c4
+
+
+def sweep_workload(torch, felocal, inputs, stream, ev, reps):
+    """The experiment matrix of Sec. 7.1 on one GPU: mass and Helmholtz,
+    degree q = 1..4, nf = 0..3 pre-multiplying coefficient functions of
+    degree q, on 82,944 jittered tetrahedra (24^3 cubes x 6; the paper's mesh
+    has 4,374).  Per case: Algorithm 3's choice (T_H = LDS per CU) and the
+    time of the chosen mode, of forced quadrature and of forced
+    pre-evaluation (where a tile of the expanded tensor fits in LDS)."""
+    log("sweep: mass / helmholtz, q = 1..4, nf = 0..3 on 82,944 tets")
+    cn, V, cells = inputs.tet_workload(24, seed=6)
+    E = cn.shape[0]
+    c = torch.from_numpy(cn).cuda()
+    rng = np.random.default_rng(7)
+    cases = []
+    for form in ("mass", "helmholtz"):
+        for q in (1, 2, 3, 4):
+            ns = n_scalar("tetrahedron", q)
+            out = torch.empty((E, ns, ns), dtype=torch.float64, device="cuda")
+            for nf in (0, 1, 2, 3):
+                cf = torch.from_numpy(rng.uniform(0.5, 1.5, size=(E, nf, ns))).cuda() if nf else None
+                plan = felocal.fe_plan(form, "tetrahedron", q, nf=nf)
+                row = {"form": form, "q": q, "nf": nf, "plan": plan["mode"],
+                       "preevaluated": plan["preevaluated"], "iota": plan["iota"][0]}
+                for mode in ("auto", "quadrature", "preeval"):
+                    try:
+                        ms = time_launch(torch, lambda: felocal.fe_assemble_local(
+                            form, "tetrahedron", q, c, cf, out, nf=nf, mode=mode), stream, ev, reps)
+                        row[f"ms_{mode}"] = round(ms, 4)
+                    except felocal.FeError:
+                        row[f"ms_{mode}"] = None
+                t = [v for k, v in row.items() if k.startswith("ms_") and k != "ms_auto" and v is not None]
+                # within 5% (and 5 us, the launch-to-launch noise) of the faster forced mode
+                row["planner_fastest"] = row["ms_auto"] is not None and row["ms_auto"] <= 1.05 * min(t) + 0.005
+                row["elem_per_s"] = round(E / (row["ms_auto"] * 1e-3), 1)
+                cases.append(row)
+                log(f"  {form} q={q} nf={nf}: plan {plan['mode']} {plan['preevaluated']} auto {row['ms_auto']} "
+                    f"quad {row['ms_quadrature']} pre {row['ms_preeval']} ms")
+                del cf
+            del out
+            torch.cuda.empty_cache()
+    hits = sum(r["planner_fastest"] for r in cases)
+    return {"workload": "nf_sweep_tet_83k", "elements": E, "cases": cases,
+            "planner_fastest_cases": f"{hits}/{len(cases)}"}
 
 
 def batch_workload(torch, felocal, inputs, stream, ev, reps):

@@ -130,8 +130,10 @@ typedef struct {
                                   (degenerate map, non-affine prism, or
                                   det F <= 0 at a point); the element's block
                                   is filled with NaN.  NULL = not counted.    */
-    size_t         th_bytes;   /* T_H (Constraint 2); 0 = LDS capacity of one
-                                  compute unit (160 KiB on gfx950)          */
+    size_t         th_bytes;   /* T_H (Constraint 2); 0 = the device's L2
+                                  capacity (one XCD's 4 MiB on MI355X), the
+                                  cache the pre-evaluated kernels stream
+                                  their tables through                      */
     int            validate;   /* nonzero: synchronously copy coords to the
                                   host and reject non-affine prisms with
                                   FE_ENONAFFINE before launching            */
@@ -210,8 +212,8 @@ typedef struct {
                                   pre-evaluated, else FE_MODE_QUADRATURE     */
 } fe_plan_t;
 
-/* qdeg = -1 for the form default; th_bytes = 0 for the LDS capacity of one
- * compute unit (160 KiB when no device is present); nf as in fe_options_t
+/* qdeg = -1 for the form default; th_bytes = 0 for the device's L2 capacity
+ * (4 MiB when no device is present); nf as in fe_options_t
  * (mass and Helmholtz; iota = C(n_s + nf - 1, nf), Sec. 4.2).  A plan may
  * pre-evaluate only some monomials (Fig. 5): mode is then
  * FE_MODE_QUADRATURE and, with nf = 0, the quadrature kernel adds the

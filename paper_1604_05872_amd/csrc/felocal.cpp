@@ -73,6 +73,21 @@ size_t device_lds_per_cu()
     return lds[d];
 }
 
+// L2 capacity of the current device (one XCD's L2 on MI355X: 4 MiB when the
+// runtime does not report it).
+size_t device_l2_bytes()
+{
+    static size_t l2[64] = {0};
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return 4u << 20;
+    if (l2[d] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeL2CacheSize, d) != hipSuccess || v <= 0) v = 4 << 20;
+        l2[d] = (size_t)v;
+    }
+    return l2[d];
+}
+
 // Builds (once) the rule, the tabulated basis, the P1 coefficient basis and
 // the pre-evaluated tensors of (cell, p, qdeg) on the current device.
 int get_tables(int cell, int p, int qdeg, hipStream_t s, const RefTables** out)
@@ -391,10 +406,10 @@ int fe_resolve_variant(int form, int cell, int degree, int qdeg, const fe_option
     int rc = fe_plan((fe_form_t)form, (fe_cell_t)cell, degree, o->nf, qdeg, o->th_bytes, &plan);
     if (rc) return rc;
     *mode_out = plan.mode;
-    // a mixed Helmholtz plan adds the pre-evaluated monomial's tables in the
-    // quadrature kernel (nf = 0); with coefficient functions it runs as
-    // quadrature throughout
-    if (form == HELMHOLTZ && plan.mode == FE_MODE_QUADRATURE && o->nf == 0)
+    // a mixed Helmholtz plan: with nf = 0 the quadrature kernel adds the
+    // pre-evaluated monomial's tables; with coefficient functions the
+    // coefficient pre-evaluation kernel adds that monomial afterwards
+    if (form == HELMHOLTZ && plan.mode == FE_MODE_QUADRATURE)
         *mass_pre = (plan.preevaluated[1] ? 1 : 0) | (plan.preevaluated[0] ? 2 : 0);
     return FE_OK;
 }
@@ -520,8 +535,9 @@ int launch_call(const Call& c, const Config& cfg)
     a.phi = t->dphi;
     a.dphi = t->ddphi;
     a.psi = t->dpsi;
-    a.mass_table = (c.mass_pre & 1) ? t->dR : nullptr;
-    a.stiff_tables = (c.mass_pre & 2) ? t->dR : nullptr;
+    a.mass_table = (c.nf == 0 && (c.mass_pre & 1)) ? t->dR : nullptr;
+    a.stiff_tables = (c.nf == 0 && (c.mass_pre & 2)) ? t->dR : nullptr;
+    a.skip = c.nf > 0 ? c.mass_pre : 0;
     a.E = c.E;
     a.nq = t->nq;
     a.ns = t->nb;
@@ -537,6 +553,16 @@ int launch_call(const Call& c, const Config& cfg)
     const size_t lds = quad_lds_bytes(c.form, c.cell, t->nb, a.eb, a.qc);
     e = launch_quad(c.form, c.cell, quad_kb(c.cell, c.degree), a, grid, lds, c.stream);
     if (e != hipSuccess) return set_hip_error(e, "quadrature launch");
+    if (c.nf > 0 && c.mass_pre) {
+        // the pre-evaluated monomial of a mixed plan, added to the quadrature part
+        const CoefTables* ct = nullptr;
+        int rc = get_coef_tables(c.form, c.cell, c.degree, c.qdeg, c.nf, c.stream, &ct);
+        if (rc) return rc;
+        const int r_lo = (c.mass_pre & 1) ? 0 : 1, r_hi = (c.mass_pre & 2) ? n_tables(c.form, c.cell) : 1;
+        e = launch_preeval_coef(c.form, c.cell, c.coords, c.coeff, c.out, nullptr,
+                                ct->dR, ct->dCombos, c.E, t->nb, c.nf, ct->iota, 8, cus, c.stream, r_lo, r_hi, 1);
+        if (e != hipSuccess) return set_hip_error(e, "coefficient pre-evaluated launch");
+    }
     return FE_OK;
 }
 

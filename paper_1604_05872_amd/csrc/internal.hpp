@@ -31,9 +31,12 @@ hipError_t launch_preeval_stream(int form, int cell, const PreevalArgs& a, int b
 // preeval_coef.hip: pre-evaluation with nf pre-multiplying coefficient functions
 hipError_t launch_coef_tables(int nq, int nb, int d, int nf, int iota, int nr, const double* W, const double* phi,
                               const double* dphi, const int* combos, double* R, hipStream_t s);
+// geometry-tensor entries [r_lo, r_hi) only (r_hi < 0: all), adding to out
+// when accumulate is set (the pre-evaluated half of a mixed plan)
 hipError_t launch_preeval_coef(int form, int cell, const double* coords, const double* coeff, double* out,
                                int* status, const double* R, const int* combos, int64_t E, int nb, int nf,
-                               int iota, int grid_per_cu, int cus, hipStream_t s);
+                               int iota, int grid_per_cu, int cus, hipStream_t s, int r_lo = 0, int r_hi = -1,
+                               int accumulate = 0);
 size_t preeval_coef_lds_bytes(int form, int cell, int ntp, int nf, int nb);
 hipError_t launch_quad_mass(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_quad_helmholtz(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
@@ -119,6 +122,7 @@ int get_tables(int cell, int p, int qdeg, hipStream_t s, const RefTables** out);
 int get_coef_tables(int form, int cell, int p, int qdeg, int nf, hipStream_t s, const CoefTables** out);
 int device_cus();
 size_t device_lds_per_cu();
+size_t device_l2_bytes();
 int set_hip_error(hipError_t e, const char* where);
 
 // Launch configuration of one variant.

@@ -15,7 +15,8 @@
 // theta < 0 (the sign convention of Sec. 4.1, which the algorithm's step 1
 // uses).  Step 3 discards a bipartition whose pre-evaluated tables exceed T_H
 // (Constraint 2, Sec. 3.4); identical tables are counted once (step 5 note).
-// Argmin ties go to fewer pre-evaluated monomials (less memory).
+// Argmin ties go to a plan with all monomials in one mode (one kernel),
+// then to fewer pre-evaluated monomials (less memory).
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -47,7 +48,7 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int q
     if (qdeg > MAX_QDEG) return FE_EINVAL;
     if (th_bytes == 0) {
         int ndev = 0;
-        th_bytes = (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) ? device_lds_per_cu() : 160 * 1024;
+        th_bytes = (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) ? device_l2_bytes() : (size_t)4 << 20;
     }
     const double inf = std::numeric_limits<double>::infinity();
     const int d = cell_dim(cell), ns = n_scalar(cell, degree), nq = rule_size(cell, qdeg), nc = cell_nv(cell);
@@ -106,6 +107,18 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int q
         legal[0] = false;
         break;
     }
+    // with coefficient functions the pre-evaluated kernel keeps a 16-element
+    // tile of the expanded geometry tensor in LDS: a monomial whose tile
+    // would not fit has no kernel (not legal)
+    if (nf > 0) {
+        int ndev = 0;
+        const size_t lds_block =
+            (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) ? device_lds_per_block() : (size_t)64 << 10;
+        const size_t nr = (size_t)n_tables(form, cell);
+        const size_t tile = 16 * sizeof(double) * ((nr * iota_f + 7) / 8 * 8 + nr + (size_t)nf * ns);
+        if (tile > lds_block)
+            for (int m = 0; m < nm; ++m) legal[m] = false;
+    }
     const double entries = is_vector_form(form) ? pairs * d * d : pairs;
     for (int m = 0; m < nm; ++m)
         plan->theta_pre[m] = plan->iota[m] > 0 ? 2.0 * plan->rho[m] * plan->iota[m] * entries : inf;
@@ -142,7 +155,12 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int q
                 D += plan->theta_se[m];
             }
         }
-        if (D < best || (D == best && cnt < best_count)) {
+        // ties: a plan that keeps every monomial in one mode (one kernel),
+        // then the fewest pre-evaluated monomials (least memory)
+        const bool uniform = (cnt == 0 || cnt == nm);
+        const bool best_uniform = (best_count == 0 || best_count == nm);
+        if (D < best || (D == best && ((uniform && !best_uniform) ||
+                                       (uniform == best_uniform && cnt < best_count)))) {
             best = D;
             best_mask = mask;
             best_count = cnt;

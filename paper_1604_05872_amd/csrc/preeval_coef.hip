@@ -83,6 +83,8 @@ struct CoefArgs {
     const int* combos;     // [iota][nf], sorted multisets
     int64_t E;
     int nb, nn, nf, iota, nt, ntp;   // ntp: nt rounded up to a multiple of 8
+    int r_lo, r_hi;        // geometry-tensor entries (monomials) evaluated here
+    int accumulate;        // add to out instead of overwriting it
 };
 
 template <int FORM, int CELL>
@@ -123,12 +125,13 @@ __global__ __launch_bounds__(64) void k_preeval_coef(CoefArgs a)
         const int ncf = nf * nb;
         for (int i = lane; i < 16 * ncf; i += 64) sCf[i] = i < ne * ncf ? a.coeff[e0 * ncf + i] : 0.0;
         __syncthreads();
-        // A[e][(r, S)] = G'_r(e) C_S(e), zero-padded to ntp columns
+        // A[e][(r, S)] = G'_r(e) C_S(e) for r in [r_lo, r_hi), zero-padded to ntp
         for (int idx = lane; idx < 16 * iota; idx += 64) {
             const int e = idx / iota, c = idx - (idx / iota) * iota;
             const double cs = coef_product(sCf + e * ncf, nb, nf, a.combos + c * nf);
 #pragma unroll
-            for (int r = 0; r < NR; ++r) sA[e * ntp + r * iota + c] = sGeo[e * NR + r] * cs;
+            for (int r = 0; r < NR; ++r)
+                if (r >= a.r_lo && r < a.r_hi) sA[e * ntp + (r - a.r_lo) * iota + c] = sGeo[e * NR + r] * cs;
         }
         for (int idx = lane; idx < 16 * (ntp - a.nt); idx += 64) {
             const int e = idx / (ntp - a.nt);
@@ -143,8 +146,9 @@ __global__ __launch_bounds__(64) void k_preeval_coef(CoefArgs a)
             for (int kb = 0; kb < ntp / 4; kb += 2) {
                 const int k0 = 4 * kb + kq, k1 = k0 + 4;
                 const double a0 = sA[i16 * ntp + k0], a1 = sA[i16 * ntp + k1];
-                const double b0 = (cvalid && k0 < a.nt) ? a.R[(size_t)k0 * nn + col] : 0.0;
-                const double b1 = (cvalid && k1 < a.nt) ? a.R[(size_t)k1 * nn + col] : 0.0;
+                const double* Rr = a.R + (size_t)a.r_lo * iota * nn;   // tables of the evaluated monomials
+                const double b0 = (cvalid && k0 < a.nt) ? Rr[(size_t)k0 * nn + col] : 0.0;
+                const double b1 = (cvalid && k1 < a.nt) ? Rr[(size_t)k1 * nn + col] : 0.0;
                 acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
                 acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
             }
@@ -152,7 +156,12 @@ __global__ __launch_bounds__(64) void k_preeval_coef(CoefArgs a)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = kq + 4 * r;
-                if (row < ne && cvalid) store_out(a.out + (e0 + row) * nn + col, acc0[r] + acc1[r], 0);
+                if (row < ne && cvalid) {
+                    double* o = a.out + (e0 + row) * nn + col;
+                    const double v = acc0[r] + acc1[r];
+                    if (a.accumulate) *o += v;
+                    else store_out(o, v, 0);
+                }
             }
         }
         __syncthreads();
@@ -175,7 +184,7 @@ hipError_t launch_coef_tables(int nq, int nb, int d, int nf, int iota, int nr, c
 
 hipError_t launch_preeval_coef(int form, int cell, const double* coords, const double* coeff, double* out,
                                int* status, const double* R, const int* combos, int64_t E, int nb, int nf,
-                               int iota, int grid_per_cu, int cus, hipStream_t s)
+                               int iota, int grid_per_cu, int cus, hipStream_t s, int r_lo, int r_hi, int accumulate)
 {
     CoefArgs a;
     a.coords = coords;
@@ -189,7 +198,10 @@ hipError_t launch_preeval_coef(int form, int cell, const double* coords, const d
     a.nn = nb * nb;
     a.nf = nf;
     a.iota = iota;
-    a.nt = n_tables(form, cell) * iota;
+    a.r_lo = r_lo;
+    a.r_hi = r_hi < 0 ? n_tables(form, cell) : r_hi;
+    a.accumulate = accumulate;
+    a.nt = (a.r_hi - a.r_lo) * iota;
     a.ntp = (a.nt + 7) / 8 * 8;
     const size_t lds = preeval_coef_lds_bytes(form, cell, a.ntp, nf, nb);
     const int64_t tiles = (E + 15) / 16;

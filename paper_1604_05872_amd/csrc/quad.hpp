@@ -51,6 +51,8 @@ struct QuadArgs {
     double mu, lam;       // hyperelastic constants
     int nf;               // mass / Helmholtz: pre-multiplying coefficient functions,
                           // DOFs [E][nf][ns] in coeff (Sec. 7.1)
+    int skip;             // Helmholtz: bit 0 leaves out the mass term, bit 1 the
+                          // gradient term (added by another kernel afterwards)
 };
 
 template <int FORM, int CELL>
@@ -259,8 +261,8 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
                             if (kk < kn) acc[kk][0] = fma(tj, sPhi[qq * ns + k0 + kk], acc[kk][0]);
                     } else if (FORM == HELMHOLTZ) {
                         const double w = sw[0];
-                        const double tj = a.mass_table ? 0.0 : w * sPhi[qq * ns + uj];
-                        const double wgs = a.stiff_tables ? 0.0 : w;
+                        const double tj = (a.mass_table || (a.skip & 1)) ? 0.0 : w * sPhi[qq * ns + uj];
+                        const double wgs = (a.stiff_tables || (a.skip & 2)) ? 0.0 : w;
                         double wg[D];
 #pragma unroll
                         for (int b = 0; b < D; ++b) wg[b] = wgs * gj[b];

@@ -288,6 +288,28 @@ def test_coefficient_functions(form, cell, p, nf, mode):
     assert normwise(A, B).max() <= TOL["fp64"]
 
 
+# Mixed Helmholtz plans with coefficient functions: the quadrature kernel
+# evaluates one monomial and the coefficient pre-evaluation adds the other.
+MIXED_NF = [("tetrahedron", 3, 1, 160 * 1024), ("tetrahedron", 1, 1, 0), ("tetrahedron", 2, 2, 160 * 1024),
+            ("triangle", 3, 2, 64 * 1024), ("prism", 2, 1, 64 * 1024)]
+
+
+@pytest.mark.parametrize("cell,p,nf,th", MIXED_NF)
+def test_coefficient_mixed_plans(cell, p, nf, th):
+    plan = felocal.fe_plan("helmholtz", cell, p, nf=nf, th_bytes=th)
+    log(f"mixed plan helmholtz {cell} P{p} nf={nf} th={th}: {plan['preevaluated']}")
+    if len(set(plan["preevaluated"])) != 2:
+        pytest.skip(f"plan not mixed on this device: {plan['preevaluated']}")
+    ns = oracle.nbasis(cell, p)
+    E = 300
+    coords, *_ = mesh(cell, E, seed=60 + p)
+    cf = np.random.default_rng(61).uniform(0.5, 1.5, size=(E, nf, ns))
+    A, st = gpu_assemble("helmholtz", cell, p, coords, cf, nf=nf, th_bytes=th)
+    B, fl = oracle.assemble("helmholtz", cell, p, coords, cf, nf=nf)
+    assert st == fl == 0
+    assert normwise(A, B).max() <= TOL["fp64"]
+
+
 # Indefinite point weights: a Lame field shifted below zero (lambda or mu),
 # and a negative hyperelastic lambda, through every precision.
 SIGNED_CASES = [("elasticity", "tetrahedron", 2, 0), ("elasticity", "triangle", 3, 0),
