@@ -6,7 +6,8 @@ import this package.  The GPU library never does, and shares no code with it.
 The compiled part is ``fe_oracle.c`` (plain C, IEEE double, OpenMP over
 elements); this module loads it with ctypes and offers numpy-facing helpers.
 It evaluates Eq. (7) of the paper (quadrature mode, Sec. 2.2) as the naive
-loop nest of Fig. 1.
+loop nest of Fig. 1, and the global assembly of Sec. 2 (element matrices summed
+into the compressed-row matrix of the continuous space, in element order).
 """
 from __future__ import annotations
 
@@ -68,6 +69,9 @@ def lib():
                                        dp, dp, dp, ctypes.c_int]
         L.orc_hyper_min_jf.restype = ctypes.c_int64
         L.orc_max_threads.restype = ctypes.c_int
+        i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+        L.orc_csr_insert.argtypes = [ctypes.c_int64, ctypes.c_int, i32p, ctypes.c_int64, i64p, i32p, dp, dp]
+        L.orc_csr_insert.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -183,6 +187,55 @@ def hyper_min_jf(cell: str, p: int, coords, u, qdeg: int = 4, nthreads: int = 0)
     m = np.zeros(E)
     lib().orc_hyper_min_jf(CELL[cell], p, qdeg, E, _p(coords), _p(u), _p(m), nthreads)
     return m
+
+
+def csr_pattern(dofs, N: int):
+    """Compressed-row pattern of the global matrix (Sec. 2, global assembly):
+    entry (r, c) is stored when some element holds both global DOFs r and c.
+    Columns are sorted within each row.  Returns (row_ptr [N+1] int64,
+    cols [nnz] int32)."""
+    d = np.asarray(dofs, dtype=np.int64)
+    keys = np.unique((d[:, :, None] * N + d[:, None, :]).ravel())
+    rows = keys // N
+    row_ptr = np.zeros(N + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=N), out=row_ptr[1:])
+    return row_ptr, np.ascontiguousarray(keys % N, dtype=np.int32)
+
+
+def csr_insert(dofs, N: int, row_ptr, cols, A):
+    """Values [nnz] of the global matrix: the element matrices A [E][n][n]
+    added at (dofs[e][j], dofs[e][k]) in increasing element order."""
+    d = np.ascontiguousarray(dofs, dtype=np.int32)
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(cols, dtype=np.int32)
+    A = _f64(A)
+    E, n = d.shape
+    if A.shape != (E, n, n) or rp.shape != (N + 1,):
+        raise ValueError("shape mismatch")
+    vals = np.empty(int(rp[N]))
+    i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+    rc = lib().orc_csr_insert(E, n, d.ctypes.data_as(i32p), N, rp.ctypes.data_as(i64p), cl.ctypes.data_as(i32p),
+                              _p(A), _p(vals))
+    if rc != 0:
+        raise ValueError("an element entry is missing from the pattern")
+    return vals
+
+
+def csr_row(dofs, r: int, A_of):
+    """One row of the global matrix, computed on its own: the elements holding
+    DOF r (increasing order), the sorted columns of the row and its values,
+    summed in increasing element order.  A_of(elements) returns the element
+    matrices [len(elements)][n][n] of those elements."""
+    d = np.asarray(dofs)
+    els = np.nonzero((d == r).any(axis=1))[0]
+    cols = np.unique(d[els].ravel()).astype(np.int64)
+    vals = np.zeros(cols.size)
+    A = _f64(A_of(els))
+    for t, e in enumerate(els):
+        j = int(np.nonzero(d[e] == r)[0][0])
+        for k in range(d.shape[1]):
+            vals[np.searchsorted(cols, d[e, k])] += A[t, j, k]
+    return els, cols, vals
 
 
 def max_threads() -> int:

@@ -14,7 +14,9 @@
  *   evaluated as the naive nest of Fig. 1 (element loop, quadrature reduction
  *   loop, then the test and trial loops), with the integrand written out in
  *   full (no factorisation, no hoisting beyond the reference tabulation
- *   Phi_i(X_q) that Eq. (7) itself names).
+ *   Phi_i(X_q) that Eq. (7) itself names);
+ *   and the global assembly of Sec. 2, which sums the element matrices into
+ *   the compressed-row global matrix in element order (orc_csr_insert).
  *
  * Precision: IEEE double throughout; long double only while solving for
  * quadrature nodes.
@@ -629,6 +631,43 @@ int64_t orc_hyper_min_jf(int cell, int p, int qdeg, int64_t E, const double *coo
         minjf[e] = m;
     }
     free(X); free(W); free(PHI); free(DPHI);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Global assembly (Sec. 2): the global matrix A_ij = a(phi_i, phi_j) of the
+ * continuous space is the sum over elements of the element matrices, entry
+ * (j, k) of element e added at (dofs[e][j], dofs[e][k]).  The compressed-row
+ * pattern (row_ptr, cols, columns sorted within a row) is given; each stored
+ * entry is found by bisection and the element contributions are added one
+ * by one in increasing element order (then j, then k), starting from zero.
+ * Returns 0, or -1 if some (row, column) pair is missing from the pattern.
+ * ------------------------------------------------------------------------ */
+int orc_csr_insert(int64_t E, int n, const int32_t *dofs, int64_t N, const int64_t *row_ptr,
+                   const int32_t *cols, const double *A, double *values)
+{
+    for (int64_t i = 0; i < row_ptr[N]; i++) values[i] = 0.0;
+    for (int64_t e = 0; e < E; e++)
+        for (int j = 0; j < n; j++) {
+            int64_t r = dofs[e * n + j];
+            for (int k = 0; k < n; k++) {
+#if ORC_MUTANT == 11
+                if (k == n - 1) continue;
+#endif
+                int32_t c = dofs[e * n + k];
+                int64_t lo = row_ptr[r], hi = row_ptr[r + 1];
+                while (lo < hi) {
+                    int64_t mid = lo + (hi - lo) / 2;
+                    if (cols[mid] < c) lo = mid + 1; else hi = mid;
+                }
+                if (lo == row_ptr[r + 1] || cols[lo] != c) return -1;
+#if ORC_MUTANT == 10
+                values[lo] += A[(e * n + k) * n + j];
+#else
+                values[lo] += A[(e * n + j) * n + k];
+#endif
+            }
+        }
     return 0;
 }
 

@@ -9,6 +9,8 @@ Layouts produced (all float64, C-contiguous, element-major):
   coords  [E][nv][gdim]   nv = 3 (triangle), 4 (tetrahedron), 6 (prism)
   elasticity coefficients [E][2][nc]   Lame lambda DOFs, then mu DOFs, P1 per cell vertex
   hyperelastic displacement [E][gdim * n_s]   component-blocked element-local DOFs
+  global DOF numbers [E][n_s] int32 (global assembly): the node of local DOF j of
+  element e on the refined vertex lattice, shared by every element holding it
 
 Vertex ordering follows the reference cells used throughout the library:
   triangle (0,0),(1,0),(0,1); tetrahedron adds (0,0,1); prism = triangle x [0,1],
@@ -145,6 +147,74 @@ def prism_mesh(n: int, nz: int, seed: int, jitter: float = TRI_JITTER):
     top = bot + nv2
     cells = np.concatenate([bot, top], axis=2).reshape(-1, 6)
     return V, cells
+
+
+def _node_multi_indices(cell: str, p: int) -> np.ndarray:
+    """Lattice multi-indices of the local nodes in the library's node order:
+    triangle (i, j) with i fastest; tetrahedron (i, j, k), loops k, j, i with i
+    fastest; prism (i, j, l) for local index l * n_tri + t, t in triangle order.
+    A node of a simplex sits at v0 + (i (v1 - v0) + j (v2 - v0) [+ k (v3 - v0)]) / p."""
+    if cell == TRI:
+        return np.array([(i, j) for j in range(p + 1) for i in range(p + 1 - j)], dtype=np.int64)
+    if cell == TET:
+        return np.array([(i, j, k) for k in range(p + 1) for j in range(p + 1 - k) for i in range(p + 1 - j - k)],
+                        dtype=np.int64)
+    tri = _node_multi_indices(TRI, p)
+    return np.array([(i, j, l) for l in range(p + 1) for (i, j) in tri], dtype=np.int64)
+
+
+def global_dofs(cell: str, p: int, cells: np.ndarray, n: int, compact: bool = True):
+    """Global numbers of the degree-p Lagrange DOFs of a structured mesh made by
+    triangle_mesh(n, n), tet_mesh(n) or prism_mesh(n, n) (possibly truncated to
+    its first elements).  Every vertex of these meshes is a point of an integer
+    grid (spacing h); the nodes of degree p lie on the grid refined p times, and
+    a node shared by several elements has one refined-grid point, so numbering
+    the refined grid numbers the DOFs of the continuous space.  With compact,
+    the numbers of the nodes in use are renumbered 0..N-1 in increasing order.
+    Returns (dofs [E][n_s] int32, N)."""
+    cells = np.asarray(cells, dtype=np.int64)
+    a = _node_multi_indices(cell, p)
+    m = n * p + 1
+    if cell == TRI:
+        vi = np.stack([cells // (n + 1), cells % (n + 1)], axis=-1)           # [E][3][2]
+        X = p * vi[:, None, 0, :] + a[None, :, 0, None] * (vi[:, None, 1, :] - vi[:, None, 0, :]) \
+            + a[None, :, 1, None] * (vi[:, None, 2, :] - vi[:, None, 0, :])
+        g = X[..., 0] * m + X[..., 1]
+    elif cell == TET:
+        n1 = n + 1
+        vi = np.stack([cells // (n1 * n1), (cells // n1) % n1, cells % n1], axis=-1)   # [E][4][3]
+        X = p * vi[:, None, 0, :]
+        for c in range(3):
+            X = X + a[None, :, c, None] * (vi[:, None, c + 1, :] - vi[:, None, 0, :])
+        g = (X[..., 0] * m + X[..., 1]) * m + X[..., 2]
+    elif cell == PRISM:
+        nv2 = (n + 1) * (n + 1)
+        layer, v2 = cells // nv2, cells % nv2
+        vi = np.stack([v2 // (n + 1), v2 % (n + 1)], axis=-1)                  # [E][6][2]
+        XY = p * vi[:, None, 0, :] + a[None, :, 0, None] * (vi[:, None, 1, :] - vi[:, None, 0, :]) \
+            + a[None, :, 1, None] * (vi[:, None, 2, :] - vi[:, None, 0, :])
+        Z = p * layer[:, None, 0] + a[None, :, 2]
+        g = (XY[..., 0] * m + XY[..., 1]) * m + Z
+    else:
+        raise ValueError(cell)
+    if compact:
+        used, inv = np.unique(g, return_inverse=True)
+        return np.ascontiguousarray(inv.reshape(g.shape), dtype=np.int32), int(used.size)
+    N = m ** (2 if cell == TRI else 3)
+    return np.ascontiguousarray(g, dtype=np.int32), int(N)
+
+
+def vector_dofs(dofs: np.ndarray, N: int, gdim: int) -> np.ndarray:
+    """Global numbers of a component-blocked vector space: local DOF c * n_s + j
+    of an element maps to c * N + dofs[e][j].  Returns [E][gdim * n_s] int32."""
+    return np.ascontiguousarray(np.concatenate([dofs + c * N for c in range(gdim)], axis=1), dtype=np.int32)
+
+
+def random_local_matrices(E: int, n: int, seed: int) -> np.ndarray:
+    """Element matrices [E][n][n] with entries uniform in [-1, 1): synthetic
+    input of the insertion step alone."""
+    (rng,) = _streams(seed, 1)
+    return rng.uniform(-1.0, 1.0, size=(E, n, n))
 
 
 def gather(V: np.ndarray, cells: np.ndarray) -> np.ndarray:

@@ -22,6 +22,8 @@ MUTANTS = {
     7: ("dropped lambda ln J term of the tangent", "hyper"),
     8: ("coefficient function evaluated with a shifted basis index", "coefficients"),
     9: ("only the first pre-multiplying coefficient function applied", "coefficients"),
+    10: ("element matrix inserted transposed", "global assembly"),
+    11: ("last local column dropped from the insertion", "global assembly"),
 }
 
 PINS = {
@@ -34,7 +36,12 @@ PINS = {
     7: "hyper_tangent_is_residual_derivative",
     8: "coefficient_fields_exact_rational",
     9: "coefficient_fields_exact_rational or coefficient_fields_invariants",
+    10: "pattern_and_insert_brute_force",
+    11: "global_quadratic_forms_exact or pattern_and_insert_brute_force",
 }
+
+# pins of the global assembly live in their own module
+PIN_FILE = {10: "test_global_pins.py", 11: "test_global_pins.py"}
 
 
 @pytest.mark.parametrize("k", sorted(MUTANTS))
@@ -43,6 +50,6 @@ def test_pins_catch_planted_mistake(k):
         lib = oracle.build(force=True, out=os.path.join(tmp, f"liboracle_m{k}.so"), defines=[f"ORC_MUTANT={k}"])
         env = dict(os.environ, FE_ORACLE_LIB=lib)
         r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                            os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", PINS[k]],
+                            os.path.join(ROOT, "tests", PIN_FILE.get(k, "test_oracle_pins.py")), "-k", PINS[k]],
                            cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
         assert r.returncode == 1 and "failed" in r.stdout, (MUTANTS[k], r.stdout[-2000:])
