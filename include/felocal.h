@@ -271,6 +271,51 @@ int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems,
                 const double* coords, const double* coeff_dofs, double* out_A,
                 const fe_options_t* opt, double* best_ms, fe_shape_t* best_shape);
 
+/* Global assembly (Sec. 2): the element matrices are coupled by adding them
+ * into the matrix of the continuous space, A_ij = a(phi_i, phi_j), at the
+ * global numbers of their DOFs (Sec. 7.1 times local assembly together with
+ * this insertion).  The global matrix is held in compressed sparse rows with
+ * sorted column indices.
+ *
+ * fe_csr_create builds the pattern on the device from
+ *   cell_dofs  DEVICE int32 [n_elems][n], owned by the caller and read only
+ *              during the call: the global number of local DOF j of element
+ *              e, in the local numbering of the element matrices (vector
+ *              forms: component c of scalar DOF j is local c*n_s + j); every
+ *              number in [0, n_rows), distinct within an element
+ *   n_rows     rows (and columns) of the global matrix; rows no element
+ *              touches are empty
+ * Entry (r, c) is stored when some element holds both r and c.  The call is
+ * synchronous on stream; the handle owns the device memory of the pattern
+ * (about 12 B per stored entry, 2 B per element-matrix entry and 12 B per
+ * row).  Limits: n <= 256, n_elems * n < 2^32, n_rows < 2^31 and, for every
+ * row, (elements holding it) * n <= 8192.
+ * Errors: FE_EINVAL (NULL pointers, negative sizes, a number out of range or
+ * repeated within an element: checked on the device before anything else),
+ * FE_ENOTSUP (a limit exceeded), FE_ENOMEM, FE_EHIP. */
+typedef struct fe_csr fe_csr_t;
+
+int fe_csr_create(int64_t n_elems, int n, const int32_t* cell_dofs, int64_t n_rows, void* stream,
+                  fe_csr_t** csr);
+/* Sizes of the pattern (HOST outputs; any may be NULL): rows, stored entries
+ * and the longest row.  Errors: FE_EINVAL. */
+int fe_csr_info(const fe_csr_t* csr, int64_t* n_rows, int64_t* nnz, int* max_row_len);
+/* Copies the pattern into DEVICE buffers owned by the caller: row_ptr
+ * [n_rows + 1] int64 (row_ptr[0] = 0, row r holds entries row_ptr[r] ..
+ * row_ptr[r+1]-1) and col_idx [nnz] int32.  Asynchronous on stream.
+ * Errors: FE_EINVAL, FE_EHIP. */
+int fe_csr_pattern(const fe_csr_t* csr, int64_t* row_ptr, int32_t* col_idx, void* stream);
+/* values [nnz] (DEVICE float64, overwritten): for every stored (r, c), the sum
+ * of local_A[e][j][k] over the elements e with cell_dofs[e][j] = r and
+ * cell_dofs[e][k] = c, added in increasing e starting from zero, so the
+ * result does not depend on the launch and equals that sequential sum bit
+ * for bit.  local_A is DEVICE [n_elems][n][n] (the out_A layout of
+ * fe_assemble_local) and must not alias values.  Asynchronous on stream.
+ * Errors: FE_EINVAL (NULL pointers), FE_EHIP. */
+int fe_csr_insert(const fe_csr_t* csr, const double* local_A, double* values, void* stream);
+/* Frees the pattern (waits for the device first).  Errors: FE_EINVAL. */
+int fe_csr_destroy(fe_csr_t* csr);
+
 /* Human-readable text for an FE_* code. */
 const char* fe_strerror(int code);
 

@@ -34,6 +34,7 @@ EXPORTS = (
     "fe_options_init", "fe_tabulate", "fe_local_dims", "fe_assemble_local", "fe_geometry", "fe_plan",
     "fe_batch_create", "fe_batch_run", "fe_batch_destroy", "fe_batch_info", "fe_autotune",
     "fe_strerror", "fe_release_caches", "fe_version",
+    "fe_csr_create", "fe_csr_info", "fe_csr_pattern", "fe_csr_insert", "fe_csr_destroy",
 )
 
 
@@ -125,6 +126,12 @@ def lib():
         L.fe_release_caches.argtypes = []
         L.fe_release_caches.restype = None
         L.fe_version.restype = ctypes.c_char_p
+        L.fe_csr_create.argtypes = [ctypes.c_int64, ctypes.c_int, vp, ctypes.c_int64, vp, ctypes.POINTER(vp)]
+        L.fe_csr_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int)]
+        L.fe_csr_pattern.argtypes = [vp, vp, vp, vp]
+        L.fe_csr_insert.argtypes = [vp, vp, vp, vp]
+        L.fe_csr_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -318,6 +325,63 @@ class Batch:
     def close(self):
         if self.handle:
             _check(lib().fe_batch_destroy(self.handle), "fe_batch_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class CsrPattern:
+    """Global assembly (fe_csr_create / fe_csr_info / fe_csr_pattern /
+    fe_csr_insert / fe_csr_destroy).  cell_dofs: int32 tensor [E][n] on the
+    GPU with the global number of every local DOF; n_rows: size of the global
+    matrix."""
+
+    def __init__(self, cell_dofs, n_rows: int, stream=None):
+        import torch
+
+        if not (isinstance(cell_dofs, torch.Tensor) and cell_dofs.is_cuda and cell_dofs.dtype == torch.int32
+                and cell_dofs.is_contiguous() and cell_dofs.dim() == 2):
+            raise ValueError("cell_dofs must be a contiguous int32 [E][n] tensor on the GPU")
+        h = ctypes.c_void_p()
+        self.handle = None
+        _check(lib().fe_csr_create(int(cell_dofs.shape[0]), int(cell_dofs.shape[1]), _ptr(cell_dofs), int(n_rows),
+                                   _stream(stream), ctypes.byref(h)), "fe_csr_create")
+        self.handle = h
+        self.n_elems, self.n = int(cell_dofs.shape[0]), int(cell_dofs.shape[1])
+
+    def info(self):
+        N, nnz, mr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+        _check(lib().fe_csr_info(self.handle, ctypes.byref(N), ctypes.byref(nnz), ctypes.byref(mr)), "fe_csr_info")
+        return {"n_rows": N.value, "nnz": nnz.value, "max_row_len": mr.value}
+
+    def pattern(self, stream=None):
+        """(row_ptr int64 [n_rows+1], col_idx int32 [nnz]) as new GPU tensors."""
+        import torch
+
+        i = self.info()
+        rp = torch.empty(i["n_rows"] + 1, dtype=torch.int64, device="cuda")
+        ci = torch.empty(max(i["nnz"], 1), dtype=torch.int32, device="cuda")
+        _check(lib().fe_csr_pattern(self.handle, _ptr(rp), _ptr(ci), _stream(stream)), "fe_csr_pattern")
+        return rp, ci[: i["nnz"]]
+
+    def insert(self, local_A, values, stream=None):
+        """values [nnz] <- element-order sums of local_A [E][n][n] (asynchronous)."""
+        _f64_dev(local_A, "local_A")
+        _f64_dev(values, "values")
+        if local_A.numel() != self.n_elems * self.n * self.n:
+            raise ValueError(f"local_A must be [{self.n_elems}][{self.n}][{self.n}]")
+        if values.numel() != self.info()["nnz"]:
+            raise ValueError("values must hold nnz entries")
+        _check(lib().fe_csr_insert(self.handle, _ptr(local_A), _ptr(values), _stream(stream)), "fe_csr_insert")
+        return values
+
+    def close(self):
+        if self.handle:
+            _check(lib().fe_csr_destroy(self.handle), "fe_csr_destroy")
             self.handle = None
 
     def __del__(self):

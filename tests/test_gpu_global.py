@@ -1,0 +1,189 @@
+"""Global assembly on the GPU (fe_csr_* through the C ABI) against the oracle.
+
+Pattern and insertion are integer and ordered-sum work: the GPU pattern must
+equal the oracle's exactly, and the GPU insertion of the same element matrices
+must equal the oracle's element-order sum bit for bit.  Local plus global
+assembly is compared with the oracle's local plus global assembly per stored
+entry against the sum of the contributing elements' largest entries, with the
+float64 local bar (1e-12).  Full-size meshes are checked on sampled rows that
+the oracle computes one by one."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_05872_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1604_05872_amd import felocal  # noqa: E402
+
+TOL = 1e-12
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def scalar_case(cell, p, E, seed, vector=False):
+    coords, V, cells, h = inputs.first_elements(cell, E, seed)
+    dofs, N = inputs.global_dofs(cell, p, cells, round(1 / h))
+    if vector:
+        dofs = inputs.vector_dofs(dofs, N, inputs.GDIM[cell])
+        N *= inputs.GDIM[cell]
+    return coords, V, cells, h, dofs, N
+
+
+def gpu_pattern(dofs, N):
+    pat = felocal.CsrPattern(dev(dofs), N)
+    rp, ci = pat.pattern()
+    torch.cuda.synchronize()
+    return pat, rp.cpu().numpy(), ci.cpu().numpy()
+
+
+CASES = [(c, p, False) for c in ("triangle", "tetrahedron", "prism") for p in (1, 2, 3, 4)] + \
+        [("tetrahedron", 2, True), ("prism", 2, True), ("triangle", 2, True), ("tetrahedron", 1, True)]
+
+
+@pytest.mark.parametrize("cell,p,vector", CASES)
+def test_pattern_and_insert_match_oracle(cell, p, vector):
+    """Truncated jittered meshes (short boundary rows) plus three trailing rows
+    that no element touches."""
+    log(f"csr: {cell} P{p} vector={vector}")
+    E = {1: 700, 2: 500, 3: 300, 4: 200}[p]
+    _, _, _, _, dofs, N = scalar_case(cell, p, E, seed=11, vector=vector)
+    N += 3
+    orp, ocl = oracle.csr_pattern(dofs, N)
+    pat, rp, ci = gpu_pattern(dofs, N)
+    info = pat.info()
+    assert info["n_rows"] == N and info["nnz"] == len(ocl)
+    assert info["max_row_len"] == int(np.diff(orp).max())
+    assert np.array_equal(rp, orp) and np.array_equal(ci, ocl)
+    n = dofs.shape[1]
+    A = inputs.random_local_matrices(len(dofs), n, seed=12)
+    vals = torch.full((len(ocl),), float("nan"), dtype=torch.float64, device="cuda")
+    pat.insert(dev(A), vals)
+    torch.cuda.synchronize()
+    assert np.array_equal(vals.cpu().numpy(), oracle.csr_insert(dofs, N, orp, ocl, A))
+    pat.close()
+
+
+LOCAL_CASES = [("mass", "tetrahedron", 3), ("helmholtz", "tetrahedron", 4), ("helmholtz", "triangle", 2),
+               ("helmholtz", "prism", 2), ("mass", "prism", 4), ("elasticity", "tetrahedron", 2),
+               ("elasticity", "prism", 1)]
+
+
+@pytest.mark.parametrize("form,cell,p", LOCAL_CASES)
+def test_local_plus_global_matches_oracle(form, cell, p):
+    log(f"global: {form} {cell} P{p}")
+    vector = form == "elasticity"
+    coords, V, cells, h, dofs, N = scalar_case(cell, p, 240, seed=13, vector=vector)
+    cf = inputs.lame_p1(V.shape[0], cells, 13) if vector else None
+    n, _ = felocal.fe_local_dims(form, cell, p)
+    assert dofs.shape[1] == n
+    local = torch.empty((len(dofs), n, n), dtype=torch.float64, device="cuda")
+    felocal.fe_assemble_local(form, cell, p, dev(coords), dev(cf) if cf is not None else None, local)
+    pat, rp, ci = gpu_pattern(dofs, N)
+    vals = torch.empty(len(ci), dtype=torch.float64, device="cuda")
+    pat.insert(local, vals)
+    torch.cuda.synchronize()
+    B, _ = oracle.assemble(form, cell, p, coords, cf)
+    want = oracle.csr_insert(dofs, N, rp, ci, B)
+    scale = oracle.csr_insert(dofs, N, rp, ci, np.broadcast_to(np.abs(B).max(axis=(1, 2))[:, None, None], B.shape))
+    got = vals.cpu().numpy()
+    assert np.all(np.abs(got - want) <= TOL * scale)
+    pat.close()
+
+
+def test_edge_cases():
+    """No elements, no rows, invalid numbers rejected before any work, one element."""
+    L = felocal.lib()
+    pat = felocal.CsrPattern(torch.zeros((0, 4), dtype=torch.int32, device="cuda"), 5)
+    assert pat.info() == {"n_rows": 5, "nnz": 0, "max_row_len": 0}
+    rp, ci = pat.pattern()
+    assert rp.cpu().tolist() == [0] * 6 and ci.numel() == 0
+    pat.insert(torch.zeros(0, dtype=torch.float64, device="cuda"), torch.zeros(0, dtype=torch.float64, device="cuda"))
+    pat.close()
+    pat = felocal.CsrPattern(torch.zeros((0, 4), dtype=torch.int32, device="cuda"), 0)
+    assert pat.info()["nnz"] == 0
+    pat.close()
+    for bad in ([[0, 1, 2, 9]], [[0, 1, -1, 2]], [[0, 1, 1, 2]]):
+        with pytest.raises(felocal.FeError) as ei:
+            felocal.CsrPattern(torch.tensor(bad, dtype=torch.int32, device="cuda"), 9)
+        assert ei.value.code == felocal.FE_EINVAL
+    with pytest.raises(felocal.FeError) as ei:
+        felocal.CsrPattern(torch.zeros((1, 300), dtype=torch.int32, device="cuda"), 9)
+    assert ei.value.code == felocal.FE_ENOTSUP
+    import ctypes
+    h = ctypes.c_void_p()
+    assert L.fe_csr_create(1, 4, None, 4, None, ctypes.byref(h)) == felocal.FE_EINVAL
+    assert L.fe_csr_info(None, None, None, None) == felocal.FE_EINVAL
+    assert L.fe_csr_destroy(None) == felocal.FE_EINVAL
+    one = torch.tensor([[3, 0, 2]], dtype=torch.int32, device="cuda")
+    pat = felocal.CsrPattern(one, 4)
+    rp, ci = pat.pattern()
+    assert rp.cpu().tolist() == [0, 3, 3, 6, 9] and ci.cpu().tolist() == [0, 2, 3] * 3
+    A = torch.arange(9, dtype=torch.float64, device="cuda").reshape(1, 3, 3)
+    vals = torch.empty(9, dtype=torch.float64, device="cuda")
+    pat.insert(A, vals)
+    torch.cuda.synchronize()
+    # row 0 = local row 1 (columns 0, 2, 3 <- local 1, 2, 0), row 2 = local row 2, row 3 = local row 0
+    assert vals.cpu().tolist() == [4, 5, 3, 7, 8, 6, 1, 2, 0]
+    pat.close()
+
+
+def _sampled_rows(N, k, seed):
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([[0, 1, N // 2, N - 1], rng.integers(0, N, size=k)]))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_full_helmholtz_global_750k(p):
+    """The 750,000-tetrahedron mesh (50^3 cubes): local assembly then global
+    assembly as the benchmark runs them; sampled rows against the oracle, and
+    the insertion of seeded random element matrices bit for bit."""
+    log(f"full global: helmholtz P{p} 750k tets")
+    coords, V, cells = inputs.tet_workload(50, seed=2)
+    dofs, N = inputs.global_dofs("tetrahedron", p, cells, 50)
+    assert N == (50 * p + 1) ** 3
+    n = dofs.shape[1]
+    E = len(dofs)
+    local = torch.empty((E, n, n), dtype=torch.float64, device="cuda")
+    felocal.fe_assemble_local("helmholtz", "tetrahedron", p, dev(coords), None, local)
+    pat = felocal.CsrPattern(dev(dofs), N)
+    info = pat.info()
+    rp_d, ci_d = pat.pattern()
+    vals = torch.empty(info["nnz"], dtype=torch.float64, device="cuda")
+    pat.insert(local, vals)
+    torch.cuda.synchronize()
+    rows = _sampled_rows(N, 24, seed=p)
+    rp = rp_d.cpu().numpy()
+    for r in rows:
+        els, cols, want = oracle.csr_row(dofs, int(r), lambda e: oracle.assemble("helmholtz", "tetrahedron", p,
+                                                                                 coords[e])[0])
+        a, b = int(rp[r]), int(rp[r + 1])
+        assert np.array_equal(ci_d[a:b].cpu().numpy(), cols)
+        got = vals[a:b].cpu().numpy()
+        B = oracle.assemble("helmholtz", "tetrahedron", p, coords[els])[0]
+        scale = np.abs(B).max(axis=(1, 2)).sum()
+        assert np.abs(got - want).max() <= TOL * scale
+    # insertion alone, seeded random element matrices, bit for bit
+    g = torch.Generator(device="cuda")
+    g.manual_seed(100 + p)
+    local.uniform_(-1.0, 1.0, generator=g)
+    pat.insert(local, vals)
+    torch.cuda.synchronize()
+    for r in rows:
+        els, cols, want = oracle.csr_row(dofs, int(r), lambda e: local[torch.from_numpy(e).cuda()].cpu().numpy())
+        a, b = int(rp[r]), int(rp[r + 1])
+        assert np.array_equal(vals[a:b].cpu().numpy(), want)
+    pat.close()
+    del local, vals
+    torch.cuda.empty_cache()
