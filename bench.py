@@ -11,7 +11,9 @@ MFMA variants), the neo-Hookean tangent on 998,250 tetrahedra (P1, P2; float64
 and split), a 16-sub-batch mixed persistent launch replayed from a HIP
 graph (one persistent work-queue kernel per kernel variant), and the
 experiment matrix of Sec. 7.1 (mass and Helmholtz, q = 1..4, nf = 0..3
-coefficient functions) with Algorithm 3's choice against both forced modes.  Inputs are seeded
+coefficient functions) with Algorithm 3's choice against both forced modes,
+and local plus global assembly (insertion into the compressed-row matrix of
+the continuous space) of the headline form and mesh.  Inputs are seeded
 synthetic meshes resident in HBM before timing.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -108,7 +110,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the built-in default launch shapes instead of the autotuned ones")
     ap.add_argument("--only-headline", action="store_true")
-    ap.add_argument("--workloads", default="mass,elasticity,hyperelastic,batch,sweep",
+    ap.add_argument("--workloads", default="mass,elasticity,hyperelastic,batch,sweep,global",
                     help="comma list of the extra workloads to time")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a known-size kernel for the HBM counters)")
@@ -385,6 +387,8 @@ def other_workloads(torch, felocal, inputs, stream, ev, reps, which):
         res.append(batch_workload(torch, felocal, inputs, stream, ev, reps))
     if "sweep" in which:
         res.append(sweep_workload(torch, felocal, inputs, stream, ev, max(2, reps // 3)))
+    if "global" in which:
+        res.append(global_workload(torch, felocal, inputs, stream, ev, reps))
     return res
 
 
@@ -444,6 +448,65 @@ def hyperelastic_workload(torch, felocal, inputs, stream, ev, record, reps):
         del o4, u
         torch.cuda.empty_cache()
     del c4
+
+
+def global_workload(torch, felocal, inputs, stream, ev, reps):
+    """Local plus global assembly (Sec. 2; Sec. 7.1 times the two together) of
+    the Helmholtz form on the 750,000-tetrahedron mesh, P1-P4: the element
+    matrices (pre-evaluated kernel), then their insertion into the
+    compressed-row matrix of the continuous space (fe_csr_insert); and both in
+    one pass (fe_assemble_csr), which forms each entry where it is added.
+    Algorithmic bytes of the insertion: the element matrices read and the
+    stored entries written; the index data it also reads (2 B per
+    element-matrix entry, 4 B per element row, 16 B per global row) is
+    reported beside them.  The one pass moves the stored entries and the
+    index data."""
+    cn, V, cells = inputs.tet_workload(50, seed=2)
+    c = torch.from_numpy(cn).cuda()
+    out = {"workload": "global_helmholtz_tet_750k", "elements": int(cn.shape[0]), "per_degree": {}}
+    for p in (1, 2, 3, 4):
+        log(f"global assembly helmholtz P{p} 750k tets")
+        dofs, N = inputs.global_dofs("tetrahedron", p, cells, 50)
+        E, n = dofs.shape
+        d = torch.from_numpy(dofs).cuda()
+        torch.cuda.synchronize()
+        t0 = time.time()
+        pat = felocal.CsrPattern(d, N)
+        create_s = time.time() - t0
+        info = pat.info()
+        local = torch.empty((E, n, n), dtype=torch.float64, device="cuda")
+        vals = torch.empty(info["nnz"], dtype=torch.float64, device="cuda")
+        ms_local = time_launch(torch, lambda: felocal.fe_assemble_local("helmholtz", "tetrahedron", p, c, None, local),
+                               stream, ev, reps)
+        ms_ins = time_launch(torch, lambda: pat.insert(local, vals), stream, ev, reps)
+
+        def both():
+            felocal.fe_assemble_local("helmholtz", "tetrahedron", p, c, None, local)
+            pat.insert(local, vals)
+        ms_both = time_launch(torch, both, stream, ev, reps)
+        ms_fused = time_launch(torch, lambda: pat.assemble("helmholtz", "tetrahedron", p, c, vals), stream, ev, reps)
+        alg = E * n * n * 8 + info["nnz"] * 8
+        index = E * n * n * 2 + E * n * 4 + 2 * (N + 1) * 8
+        row = {"rows": N, "nnz": info["nnz"], "max_row_len": info["max_row_len"],
+               "pattern_build_s": round(create_s, 3), "local_ms": round(ms_local, 4),
+               "insert_ms": round(ms_ins, 4), "local_plus_insert_ms": round(ms_both, 4),
+               "insert_alg_GBs": round(alg / (ms_ins * 1e-3) / 1e9, 1),
+               "insert_alg_plus_index_GBs": round((alg + index) / (ms_ins * 1e-3) / 1e9, 1),
+               "insert_frac_hbm": round(alg / (ms_ins * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "global_elem_per_s": round(E / (ms_both * 1e-3), 1),
+               "one_pass_ms": round(ms_fused, 4),
+               "one_pass_elem_per_s": round(E / (ms_fused * 1e-3), 1),
+               "one_pass_GBs": round((info["nnz"] * 8 + E * n * n * 2 + E * n * 4 + 2 * (N + 1) * 8)
+                                     / (ms_fused * 1e-3) / 1e9, 1)}
+        out["per_degree"][f"P{p}"] = row
+        log(f"  P{p}: N {N} nnz {info['nnz']} local {ms_local:.4f} ms insert {ms_ins:.4f} ms "
+            f"({row['insert_alg_GBs']} GB/s alg, {row['insert_alg_plus_index_GBs']} with index) "
+            f"both {ms_both:.4f} ms; one pass {ms_fused:.4f} ms; pattern {create_s:.2f} s")
+        pat.close()
+        del local, vals, d
+        torch.cuda.empty_cache()
+    del c
+    return out
 
 
 def sweep_workload(torch, felocal, inputs, stream, ev, reps):

@@ -288,8 +288,10 @@ int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems,
  * Entry (r, c) is stored when some element holds both r and c.  The call is
  * synchronous on stream; the handle owns the device memory of the pattern
  * (about 12 B per stored entry, 2 B per element-matrix entry and 12 B per
- * row).  Limits: n <= 256, n_elems * n < 2^32, n_rows < 2^31 and, for every
- * row, (elements holding it) * n <= 8192.
+ * row).  Limits: n <= 256, n_elems * n < 2^32, n_rows < 2^31; for every
+ * row, (elements holding it) * n <= 8192; and 8 B per entry of the longest
+ * row plus 128 B per element of the row held by the most elements must fit
+ * the LDS of one workgroup (64 KiB at least).
  * Errors: FE_EINVAL (NULL pointers, negative sizes, a number out of range or
  * repeated within an element: checked on the device before anything else),
  * FE_ENOTSUP (a limit exceeded), FE_ENOMEM, FE_EHIP. */
@@ -315,6 +317,28 @@ int fe_csr_pattern(const fe_csr_t* csr, int64_t* row_ptr, int32_t* col_idx, void
 int fe_csr_insert(const fe_csr_t* csr, const double* local_A, double* values, void* stream);
 /* Frees the pattern (waits for the device first).  Errors: FE_EINVAL. */
 int fe_csr_destroy(fe_csr_t* csr);
+
+/* Local and global assembly in one pass for the pre-evaluated forms (Sec. 2
+ * with the pre-evaluated contraction of Sec. 3.3, Algorithm 2): values [nnz]
+ * (DEVICE float64, overwritten) = fe_csr_insert applied to the element
+ * matrices that fe_assemble_local computes for the same arguments, bit for
+ * bit, without storing them: each entry is formed from the element's
+ * geometry tensor and the reference tables where it is added.  csr must come
+ * from fe_csr_create with n_elems elements and n = the element matrix size;
+ * coords as in fe_assemble_local (DEVICE).  Supported: FE_MASS and
+ * FE_HELMHOLTZ in FE_FP64 with nf = 0, in the pre-evaluated mode (what
+ * Algorithm 3 chooses for these forms, or FE_MODE_PREEVAL), with reference
+ * tables of at most 96 KiB (every triangle and tetrahedron degree; prisms up
+ * to P4 for mass and P3 for Helmholtz); other calls return FE_ENOTSUP (use
+ * fe_assemble_local, then fe_csr_insert).  opt->shape is ignored.  The
+ * handle keeps a geometry workspace of 64 B per element, allocated on first
+ * use, so calls on one handle must not overlap.  Asynchronous on
+ * opt->stream; flagged elements are counted through opt->d_status and make
+ * the entries they touch NaN.
+ * Errors: FE_EINVAL (as fe_assemble_local, or csr sized for other
+ * elements), FE_ENOTSUP, FE_ENOMEM, FE_EHIP. */
+int fe_assemble_csr(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
+                    fe_csr_t* csr, double* values, const fe_options_t* opt);
 
 /* Human-readable text for an FE_* code. */
 const char* fe_strerror(int code);

@@ -12,8 +12,10 @@
 //   3. per row, gather the global numbers of its elements, sort them and
 //      drop repeats: the row's columns (one pass for the lengths, a scan,
 //      one pass for the columns);
-//   4. the position table pos[e][j][k]: where column dofs[e][k] sits within
-//      row dofs[e][j].
+//   4. the position table: for the t-th pair (e, j) of the row lists (rows in
+//      order, each row's pairs in increasing element order), pos[t][k] is
+//      where column dofs[e][k] sits within row dofs[e][j].  The insertion
+//      reads it in that order, one contiguous stream.
 // Insertion (fe_csr_insert): one wavefront per row accumulates the row in
 // LDS, adding the contributions of the row's elements in increasing element
 // order, then stores it with contiguous writes.  Each stored value is the
@@ -27,12 +29,12 @@
 #include <vector>
 
 #include "felocal.h"
+#include "csr.hpp"
 #include "internal.hpp"
 
 namespace fe {
 namespace {
 
-constexpr int CSR_WAVE = 64;
 // LDS words (int32) of the per-row candidate list: (elements of the row) * n
 constexpr int CSR_MAX_CANDIDATES = 8192;
 constexpr int CSR_MAX_N = 256;
@@ -167,12 +169,34 @@ __global__ void k_csr_sort_pairs(int64_t N, const int64_t* __restrict__ pair_ptr
     atomicMax(&stats[0], (uint32_t)(b - a));
 }
 
+// LDS sizes of the insertion: for rr = 1, 2, 4, ..., 32 the longest run of
+// rr consecutive rows starting at a multiple of rr (entries), and the most
+// element pairs of a visit of VISIT_ROWS rows.
+__global__ void k_csr_round_stats(int64_t N, const int64_t* __restrict__ row_ptr,
+                                  const int64_t* __restrict__ pair_ptr, int visit_rows,
+                                  uint32_t* __restrict__ stats)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    for (int l = 0; l < CSR_RR_LEVELS; l++) {
+        const int64_t rr = (int64_t)1 << l;
+        if (r % rr == 0) {
+            const int64_t e = r + rr < N ? r + rr : N;
+            atomicMax(&stats[l], (uint32_t)(row_ptr[e] - row_ptr[r]));
+        }
+    }
+    if (r % visit_rows == 0) {
+        const int64_t e = r + visit_rows < N ? r + visit_rows : N;
+        atomicMax(&stats[CSR_RR_LEVELS], (uint32_t)(pair_ptr[e] - pair_ptr[r]));
+    }
+}
+
 // One 64-thread block per row (grid-stride).  The candidate columns of the
 // row (the global numbers of all its elements) are sorted in LDS by a
 // bitonic network; the distinct ones are the row's columns.
 //   WRITE = 0: row_len[r] = number of columns, stats[1] = the largest
-//   WRITE = 1: cols[row_ptr[r] ...] = columns, and pos[e*n + j][k] = index of
-//              column dofs[e][k] within the row, for every pair (e, j) of r
+//   WRITE = 1: cols[row_ptr[r] ...] = columns, and pos[t][k] = index of column
+//              dofs[e][k] within the row, for every pair t = (e, j) of r
 template <int WRITE>
 __global__ __launch_bounds__(CSR_WAVE) void k_csr_rows(int64_t N, int n, const int32_t* __restrict__ dofs,
                                                        const int64_t* __restrict__ pair_ptr,
@@ -245,7 +269,7 @@ __global__ __launch_bounds__(CSR_WAVE) void k_csr_rows(int64_t N, int n, const i
                     const int mid = (lo + hi) >> 1;
                     if (uniq[mid] < c) lo = mid + 1; else hi = mid;
                 }
-                pos[(int64_t)ej * n + k] = (uint16_t)lo;
+                pos[(p0 + s) * n + k] = (uint16_t)lo;
             }
         }
         __syncthreads();
@@ -256,105 +280,139 @@ __global__ __launch_bounds__(CSR_WAVE) void k_csr_rows(int64_t N, int n, const i
 // Insertion
 // ---------------------------------------------------------------------------
 
-constexpr int INSERT_BATCH = 8;      // elements whose loads are in flight together
-constexpr int INSERT_ROWS = 16;      // consecutive rows per visit of a block
 
-// One 64-thread block per visit of INSERT_ROWS consecutive rows.  Blocks are
-// renumbered so that consecutive visits run on one XCD (workgroups are dealt
-// to the 8 XCDs in turn), which keeps the element-matrix lines shared by
-// neighbouring rows in one L2.  KPL = entries of an element row per lane.
-template <int KPL>
-__global__ __launch_bounds__(CSR_WAVE) void k_csr_insert(int64_t N, int n, const int64_t* __restrict__ row_ptr,
+// W lanes per row (a power of two, at least n / KPL; W < 64 puts 64 / W rows
+// side by side in the wavefront), KPL entries of an element row per lane, IL
+// rows interleaved per lane group so that their loads are in flight together,
+// B elements per row per batch of loads.  A round covers RR = (64 / W) * IL
+// consecutive rows, whose values are one contiguous LDS region: zeroed, then
+// accumulated element by element in increasing element order (the rows of a
+// round are disjoint, and a barrier separates two elements of one row), then
+// stored with contiguous writes.  Blocks are renumbered so that consecutive
+// visits run on one XCD (workgroups are dealt to the 8 XCDs in turn), which
+// keeps the element-matrix lines shared by neighbouring rows in one L2.
+template <int W, int KPL, int IL, int B>
+__global__ __launch_bounds__(CSR_WAVE) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_csr_insert(int64_t N, int n, const int64_t* __restrict__ row_ptr,
                                                          const int64_t* __restrict__ pair_ptr,
                                                          const uint32_t* __restrict__ list,
                                                          const uint16_t* __restrict__ pos,
-                                                         const double* __restrict__ A, double* __restrict__ vals)
+                                                         const double* __restrict__ A, double* __restrict__ vals,
+                                                         int round_cap)
 {
-    extern __shared__ double acc[];
+    constexpr int SUB = CSR_WAVE / W;
+    constexpr int RR = SUB * IL;
+    static_assert(VISIT_ROWS % RR == 0, "a visit is whole rounds");
+    extern __shared__ double smem[];
+    double* acc = smem;                                             // [round_cap] values of a round
+    uint32_t* seg = reinterpret_cast<uint32_t*>(smem + round_cap);  // the visit's element lists
     const int t = threadIdx.x;
+    const int g = t / W;
+    const int kl = t % W;
     const int G = gridDim.x;
     const int b = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
-    for (int64_t r0 = (int64_t)b * INSERT_ROWS; r0 < N; r0 += (int64_t)G * INSERT_ROWS) {
-        const int64_t r1 = r0 + INSERT_ROWS < N ? r0 + INSERT_ROWS : N;
-        for (int64_t r = r0; r < r1; r++) {
-            const int64_t rp = row_ptr[r];
-            const int len = (int)(row_ptr[r + 1] - rp);
-            for (int i = t; i < len; i += CSR_WAVE) acc[i] = 0.0;
-            __syncthreads();
-            const int64_t p0 = pair_ptr[r];
-            const int c = (int)(pair_ptr[r + 1] - p0);
-            for (int s0 = 0; s0 < c; s0 += INSERT_BATCH) {
-                double v[INSERT_BATCH][KPL];
-                int q[INSERT_BATCH][KPL];
+    for (int64_t v0 = (int64_t)b * VISIT_ROWS; v0 < N; v0 += (int64_t)G * VISIT_ROWS) {
+        const int nv = (int)(N - v0 < VISIT_ROWS ? N - v0 : VISIT_ROWS);
+        int64_t my_rp = 0, my_pp = 0;
+        if (t <= nv) {
+            my_rp = row_ptr[v0 + t];
+            my_pp = pair_ptr[v0 + t];
+        }
+        const int64_t P0 = __shfl(my_pp, 0);
+        const int np = (int)(__shfl(my_pp, nv) - P0);
+        for (int i = t; i < np; i += CSR_WAVE) seg[i] = list[P0 + i];
+        __syncthreads();
+        for (int r0 = 0; r0 < nv; r0 += RR) {
+            const int nr = nv - r0 < RR ? nv - r0 : RR;
+            const int64_t vb = __shfl(my_rp, r0);
+            const int V = (int)(__shfl(my_rp, r0 + nr) - vb);
+            for (int i = t; i < V; i += CSR_WAVE) acc[i] = 0.0;
+            int off[IL], cnt[IL], lp[IL];
+            int cmax = 0;
 #pragma unroll
-                for (int u = 0; u < INSERT_BATCH; u++) {
-                    if (s0 + u < c) {
-                        const int64_t base = (int64_t)list[p0 + s0 + u] * n;
+            for (int i = 0; i < IL; i++) {
+                const int li = r0 + g * IL + i;   // < VISIT_ROWS
+                const int64_t rp = __shfl(my_rp, li);
+                const int64_t pp = __shfl(my_pp, li);
+                const int64_t pe = __shfl(my_pp, li + 1);
+                const bool ok = g * IL + i < nr;
+                off[i] = ok ? (int)(rp - vb) : 0;
+                cnt[i] = ok ? (int)(pe - pp) : 0;
+                lp[i] = (int)(pp - P0);
+                cmax = cnt[i] > cmax ? cnt[i] : cmax;
+            }
+            for (int o = CSR_WAVE / 2; o > 0; o >>= 1) {
+                const int x = __shfl_xor(cmax, o);
+                cmax = x > cmax ? x : cmax;
+            }
+            __syncthreads();
+            for (int s0 = 0; s0 < cmax; s0 += B) {
+                // Loads are unconditional so that none sits in a branch and
+                // all of them are in flight together: a slot past a row's
+                // last element re-reads that element (a row without elements
+                // reads the visit's first), a lane past n re-reads entry
+                // n - 1, so the extra reads hit lines the wavefront loads anyway.
+                double v[IL][B][KPL];
+                int q[IL][B][KPL];
+#pragma unroll
+                for (int i = 0; i < IL; i++)
+#pragma unroll
+                    for (int u = 0; u < B; u++) {
+                        const int sl = s0 + u < cnt[i] ? lp[i] + s0 + u : cnt[i] > 0 ? lp[i] + cnt[i] - 1 : 0;
+                        const uint32_t ej = np > 0 ? seg[sl] : 0u;
+                        const uint64_t base = (uint64_t)ej * (uint32_t)n;
+                        const uint64_t pbase = (uint64_t)(np > 0 ? P0 + sl : 0) * (uint32_t)n;
 #pragma unroll
                         for (int kk = 0; kk < KPL; kk++) {
-                            const int k = t + CSR_WAVE * kk;
-                            if (k < n) {
-                                v[u][kk] = A[base + k];
-                                q[u][kk] = pos[base + k];
+                            const int k = kl + W * kk < n ? kl + W * kk : n - 1;
+                            v[i][u][kk] = A[base + k];
+                            q[i][u][kk] = pos[pbase + k];
+                        }
+                    }
+#pragma unroll
+                for (int u = 0; u < B; u++) {
+#pragma unroll
+                    for (int i = 0; i < IL; i++)
+                        if (s0 + u < cnt[i]) {
+#pragma unroll
+                            for (int kk = 0; kk < KPL; kk++) {
+                                const int k = kl + W * kk;
+                                if (k < n) acc[off[i] + q[i][u][kk]] += v[i][u][kk];
                             }
                         }
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < INSERT_BATCH; u++) {
-                    if (s0 + u < c) {
-#pragma unroll
-                        for (int kk = 0; kk < KPL; kk++) {
-                            const int k = t + CSR_WAVE * kk;
-                            if (k < n) acc[q[u][kk]] += v[u][kk];
-                        }
-                        // the next element may add to the same entries from other lanes
-                        __syncthreads();
-                    }
+                    // the next element of a row may add to the same entries from other lanes
+                    __syncthreads();
                 }
             }
-            for (int i = t; i < len; i += CSR_WAVE) vals[rp + i] = acc[i];
+            for (int i = t; i < V; i += CSR_WAVE) vals[vb + i] = acc[i];
             __syncthreads();
         }
     }
 }
 
-template <int KPL>
+template <int W, int KPL, int IL, int B>
 hipError_t launch_insert(int64_t N, int n, const int64_t* row_ptr, const int64_t* pair_ptr, const uint32_t* list,
-                         const uint16_t* pos, const double* A, double* vals, size_t lds, hipStream_t s)
+                         const uint16_t* pos, const double* A, double* vals, int round_cap, int visit_pairs,
+                         hipStream_t s)
 {
-    static int per_cu[64] = {0};
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    int occ = dev >= 0 && dev < 64 ? per_cu[dev] : 0;
-    if (occ == 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_csr_insert<KPL>, CSR_WAVE, lds) != hipSuccess ||
-            occ <= 0)
-            occ = 8;
-        if (dev >= 0 && dev < 64) per_cu[dev] = occ;
-    }
-    const int64_t visits = (N + INSERT_ROWS - 1) / INSERT_ROWS;
+    const size_t lds = insert_lds(round_cap, visit_pairs);
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_csr_insert<W, KPL, IL, B>, CSR_WAVE, lds) !=
+            hipSuccess ||
+        occ <= 0)
+        occ = 8;
+    const int64_t visits = (N + VISIT_ROWS - 1) / VISIT_ROWS;
     int64_t grid = (int64_t)device_cus() * occ;
     if (grid > visits) grid = visits;
     if (grid < 1) grid = 1;
-    k_csr_insert<KPL><<<(unsigned)grid, CSR_WAVE, lds, s>>>(N, n, row_ptr, pair_ptr, list, pos, A, vals);
+    k_csr_insert<W, KPL, IL, B><<<(unsigned)grid, CSR_WAVE, lds, s>>>(N, n, row_ptr, pair_ptr, list, pos, A, vals,
+                                                                       round_cap);
     return hipGetLastError();
 }
 
 }  // namespace
 }  // namespace fe
 
-struct fe_csr {
-    int64_t E = 0, N = 0, nnz = 0;
-    int n = 0, max_row = 0, max_pairs = 0;
-    int64_t* row_ptr = nullptr;    // [N + 1]
-    int32_t* cols = nullptr;       // [nnz]
-    int64_t* pair_ptr = nullptr;   // [N + 1]
-    uint32_t* list = nullptr;      // [E * n] pairs e * n + j of each row, increasing
-    uint16_t* pos = nullptr;       // [E * n * n]
-};
-
-static void csr_free(fe_csr* c)
+void fe::csr_free(fe_csr* c)
 {
     if (!c) return;
     (void)hipFree(c->row_ptr);
@@ -362,6 +420,7 @@ static void csr_free(fe_csr* c)
     (void)hipFree(c->pair_ptr);
     (void)hipFree(c->list);
     (void)hipFree(c->pos);
+    (void)hipFree(c->geo);
     delete c;
 }
 
@@ -452,6 +511,26 @@ extern "C" int fe_csr_create(int64_t n_elems, int n, const int32_t* cell_dofs, i
         return hip_fail(e, "csr row lengths");
     c->nnz = nnz;
     c->max_row = (int)h_stats[1];
+    {
+        uint32_t h_round[CSR_RR_LEVELS + 1] = {0};
+        uint32_t* d_round = nullptr;
+        if (hipMalloc(&d_round, sizeof(h_round)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(FE_ENOMEM);
+        }
+        e = hipMemsetAsync(d_round, 0, sizeof(h_round), s);
+        if (e == hipSuccess && n_rows > 0) {
+            k_csr_round_stats<<<rblocks, TB, 0, s>>>(n_rows, c->row_ptr, c->pair_ptr, VISIT_ROWS, d_round);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(h_round, d_round, sizeof(h_round), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipFree(d_round);
+        if (e != hipSuccess) return hip_fail(e, "csr round sizes");
+        for (int l = 0; l < CSR_RR_LEVELS; l++) c->round_len[l] = (int)h_round[l];
+        c->visit_pairs = (int)h_round[CSR_RR_LEVELS];
+    }
+    if (insert_lds(c->round_len[0], c->visit_pairs) > device_lds_per_block()) return fail(FE_ENOTSUP);
     if (hipMalloc(&c->cols, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(FE_ENOMEM);
@@ -495,16 +574,29 @@ extern "C" int fe_csr_insert(const fe_csr_t* c, const double* local_A, double* v
     if (!c || (c->nnz > 0 && (!local_A || !values))) return FE_EINVAL;
     if (c->nnz == 0) return FE_OK;
     hipStream_t s = (hipStream_t)stream;
-    const size_t lds = sizeof(double) * (size_t)(c->max_row > 0 ? c->max_row : 1);
-    const int kpl = (c->n + CSR_WAVE - 1) / CSR_WAVE;
     hipError_t e;
-    switch (kpl) {
-    case 1: e = launch_insert<1>(c->N, c->n, c->row_ptr, c->pair_ptr, c->list, c->pos, local_A, values, lds, s); break;
-    case 2: e = launch_insert<2>(c->N, c->n, c->row_ptr, c->pair_ptr, c->list, c->pos, local_A, values, lds, s); break;
-    default:
-        e = launch_insert<4>(c->N, c->n, c->row_ptr, c->pair_ptr, c->list, c->pos, local_A, values, lds, s);
-        break;
-    }
+    // rows side by side need LDS for each; one row per round always fits (checked at creation)
+    const int W = c->n <= 4 ? 4 : c->n <= 8 ? 8 : c->n <= 16 ? 16 : c->n <= 32 ? 32 : 64;
+    const int IL = c->n <= 16 || c->n > 128 ? 1 : 2;
+    int level = 0;
+    while ((1 << level) < CSR_WAVE / W * IL) level++;
+    const int vp = c->visit_pairs > 0 ? c->visit_pairs : 1;
+    const int cap = c->round_len[level] > 0 ? c->round_len[level] : 1;
+    const int cap1 = c->round_len[0] > 0 ? c->round_len[0] : 1;
+#define FE_INSERT(W, KPL, IL, B, CAP) \
+    launch_insert<W, KPL, IL, B>(c->N, c->n, c->row_ptr, c->pair_ptr, c->list, c->pos, local_A, values, CAP, vp, s)
+    if (insert_lds(cap, vp) > device_lds_per_block()) {
+        if (c->n <= 64) e = FE_INSERT(64, 1, 1, 4, cap1);
+        else if (c->n <= 128) e = FE_INSERT(64, 2, 1, 4, cap1);
+        else e = FE_INSERT(64, 4, 1, 4, cap1);
+    } else if (c->n <= 4) e = FE_INSERT(4, 1, 1, 8, cap);
+    else if (c->n <= 8) e = FE_INSERT(8, 1, 1, 8, cap);
+    else if (c->n <= 16) e = FE_INSERT(16, 1, 1, 8, cap);
+    else if (c->n <= 32) e = FE_INSERT(32, 1, 2, 4, cap);
+    else if (c->n <= 64) e = FE_INSERT(64, 1, 2, 4, cap);
+    else if (c->n <= 128) e = FE_INSERT(64, 2, 2, 4, cap);
+    else e = FE_INSERT(64, 4, 1, 4, cap);
+#undef FE_INSERT
     return e == hipSuccess ? FE_OK : set_hip_error(e, "fe_csr_insert");
 }
 
@@ -512,6 +604,6 @@ extern "C" int fe_csr_destroy(fe_csr_t* c)
 {
     if (!c) return FE_EINVAL;
     (void)hipDeviceSynchronize();
-    csr_free(c);
+    fe::csr_free(c);
     return FE_OK;
 }

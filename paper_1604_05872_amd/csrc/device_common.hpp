@@ -18,6 +18,9 @@ template <int CELL>
 __device__ __forceinline__ int affine_map(const double* __restrict__ v, double (&K)[3][3], double& adet,
                                           double* det_out = nullptr)
 {
+    // every product rounded on its own: the same geometry bit for bit in
+    // every kernel that inlines this
+#pragma clang fp contract(off)
     constexpr int D = cell_dim(CELL);
     double J[3][3];
 #pragma unroll

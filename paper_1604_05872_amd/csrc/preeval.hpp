@@ -42,6 +42,8 @@ constexpr int preeval_nt() { return n_tables(FORM, CELL); }
 template <int FORM, int CELL>
 __device__ __forceinline__ int preeval_coeffs(const double* __restrict__ vsrc, double* c)
 {
+    // no contraction, so that every kernel computes the same tensor bit for bit
+#pragma clang fp contract(off)
     constexpr int D = cell_dim(CELL), NV = cell_nv(CELL);
     double v[NV * D];
 #pragma unroll

@@ -34,7 +34,7 @@ EXPORTS = (
     "fe_options_init", "fe_tabulate", "fe_local_dims", "fe_assemble_local", "fe_geometry", "fe_plan",
     "fe_batch_create", "fe_batch_run", "fe_batch_destroy", "fe_batch_info", "fe_autotune",
     "fe_strerror", "fe_release_caches", "fe_version",
-    "fe_csr_create", "fe_csr_info", "fe_csr_pattern", "fe_csr_insert", "fe_csr_destroy",
+    "fe_csr_create", "fe_csr_info", "fe_csr_pattern", "fe_csr_insert", "fe_csr_destroy", "fe_assemble_csr",
 )
 
 
@@ -132,6 +132,8 @@ def lib():
         L.fe_csr_pattern.argtypes = [vp, vp, vp, vp]
         L.fe_csr_insert.argtypes = [vp, vp, vp, vp]
         L.fe_csr_destroy.argtypes = [vp]
+        L.fe_assemble_csr.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, vp, vp, vp,
+                                      ctypes.POINTER(fe_options_t)]
         _lib = L
     return _lib
 
@@ -377,6 +379,18 @@ class CsrPattern:
         if values.numel() != self.info()["nnz"]:
             raise ValueError("values must hold nnz entries")
         _check(lib().fe_csr_insert(self.handle, _ptr(local_A), _ptr(values), _stream(stream)), "fe_csr_insert")
+        return values
+
+    def assemble(self, form: str, cell: str, degree: int, coords, values, qdeg: int = -1, mode: str = "auto",
+                 stream=None, status=None, validate: bool = False):
+        """values [nnz] <- local and global assembly in one pass (fe_assemble_csr)."""
+        _f64_dev(coords, "coords")
+        _f64_dev(values, "values")
+        if values.numel() != self.info()["nnz"]:
+            raise ValueError("values must hold nnz entries")
+        o = make_options(qdeg, "fp64", mode, stream, status=status, validate=validate)
+        _check(lib().fe_assemble_csr(FORMS[form], CELLS[cell], int(degree), int(coords.shape[0]), _ptr(coords),
+                                     self.handle, _ptr(values), ctypes.byref(o)), "fe_assemble_csr")
         return values
 
     def close(self):

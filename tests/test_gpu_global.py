@@ -187,3 +187,127 @@ def test_full_helmholtz_global_750k(p):
     pat.close()
     del local, vals
     torch.cuda.empty_cache()
+
+
+# --------------------------------------------------------------------------
+# Local and global assembly in one pass (fe_assemble_csr)
+# --------------------------------------------------------------------------
+
+def _table_bytes(form, cell, p):
+    nt = 1 if form == "mass" else (4 if cell == "triangle" else 7)
+    n = inputs.n_scalar_dofs(cell, p)
+    return nt * n * n * 8
+
+
+FUSED_CASES = [(f, c, p) for f in ("mass", "helmholtz") for c in ("triangle", "tetrahedron", "prism")
+               for p in (1, 2, 3, 4)]
+
+
+def _as_bits(t):
+    return t.view(torch.int64)
+
+
+@pytest.mark.parametrize("form,cell,p", FUSED_CASES)
+def test_fused_equals_local_then_insert(form, cell, p):
+    """Bit for bit equal to fe_assemble_local followed by fe_csr_insert, and
+    within the float64 bar of the oracle; unsupported sizes are refused."""
+    log(f"fused: {form} {cell} P{p}")
+    coords, V, cells, h, dofs, N = scalar_case(cell, p, {1: 900, 2: 600, 3: 300, 4: 150}[p], seed=17)
+    n = dofs.shape[1]
+    dc = dev(coords)
+    pat, rp, ci = gpu_pattern(dofs, N)
+    vals = torch.full((len(ci),), float("nan"), dtype=torch.float64, device="cuda")
+    plan = felocal.fe_plan(form, cell, p)
+    if plan["mode"] != "preeval" or _table_bytes(form, cell, p) > 96 * 1024:
+        with pytest.raises(felocal.FeError) as ei:
+            pat.assemble(form, cell, p, dc, vals)
+        assert ei.value.code == felocal.FE_ENOTSUP
+        pat.close()
+        return
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pat.assemble(form, cell, p, dc, vals, status=st)
+    local = torch.empty((len(dofs), n, n), dtype=torch.float64, device="cuda")
+    felocal.fe_assemble_local(form, cell, p, dc, None, local)
+    ref = torch.empty_like(vals)
+    pat.insert(local, ref)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert torch.equal(_as_bits(vals), _as_bits(ref))
+    B, _ = oracle.assemble(form, cell, p, coords)
+    want = oracle.csr_insert(dofs, N, rp, ci, B)
+    scale = oracle.csr_insert(dofs, N, rp, ci, np.broadcast_to(np.abs(B).max(axis=(1, 2))[:, None, None], B.shape))
+    assert np.all(np.abs(vals.cpu().numpy() - want) <= TOL * scale)
+    pat.close()
+
+
+def test_fused_flagged_and_refused():
+    """A degenerate element is counted once and poisons exactly the entries it
+    touches, as in the two-step path; other forms and mismatched patterns are
+    refused before any launch."""
+    coords, V, cells, h, dofs, N = scalar_case("tetrahedron", 2, 300, seed=19)
+    coords = coords.copy()
+    coords[123, 3] = coords[123, 0]          # collapse one tetrahedron
+    dc = dev(coords)
+    pat, rp, ci = gpu_pattern(dofs, N)
+    vals = torch.empty(len(ci), dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pat.assemble("helmholtz", "tetrahedron", 2, dc, vals, status=st)
+    local = torch.empty((len(dofs), 10, 10), dtype=torch.float64, device="cuda")
+    felocal.fe_assemble_local("helmholtz", "tetrahedron", 2, dc, None, local)
+    ref = torch.empty_like(vals)
+    pat.insert(local, ref)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 1
+    assert torch.equal(_as_bits(vals), _as_bits(ref))
+    rows = np.repeat(np.arange(N), np.diff(rp))
+    touched = np.isin(rows, dofs[123]) & np.isin(ci, dofs[123])
+    assert np.array_equal(np.isnan(vals.cpu().numpy()), touched)
+    for form in ("elasticity", "hyperelastic"):
+        with pytest.raises(felocal.FeError) as ei:
+            felocal.lib()
+            o = felocal.make_options()
+            rc = felocal.lib().fe_assemble_csr(felocal.FORMS[form], 1, 2, len(dofs), felocal._ptr(dc), pat.handle,
+                                               felocal._ptr(vals), felocal.ctypes.byref(o))
+            felocal._check(rc, "fe_assemble_csr")
+        assert ei.value.code in (felocal.FE_ENOTSUP, felocal.FE_EINVAL)
+    with pytest.raises(felocal.FeError) as ei:
+        pat.assemble("helmholtz", "tetrahedron", 2, dc[:200].contiguous(), vals)
+    assert ei.value.code == felocal.FE_EINVAL
+    with pytest.raises(felocal.FeError) as ei:
+        pat.assemble("helmholtz", "tetrahedron", 3, dc, vals)
+    assert ei.value.code == felocal.FE_EINVAL
+    pat.close()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_full_fused_helmholtz_750k(p):
+    """The 750,000-tetrahedron mesh as the benchmark runs it: the one-pass
+    result equals local assembly then insertion bit for bit on every stored
+    entry, and the oracle on sampled rows."""
+    log(f"full fused: helmholtz P{p} 750k tets")
+    coords, V, cells = inputs.tet_workload(50, seed=2)
+    dofs, N = inputs.global_dofs("tetrahedron", p, cells, 50)
+    n = dofs.shape[1]
+    dc = dev(coords)
+    pat = felocal.CsrPattern(dev(dofs), N)
+    nnz = pat.info()["nnz"]
+    vals = torch.empty(nnz, dtype=torch.float64, device="cuda")
+    pat.assemble("helmholtz", "tetrahedron", p, dc, vals)
+    local = torch.empty((len(dofs), n, n), dtype=torch.float64, device="cuda")
+    felocal.fe_assemble_local("helmholtz", "tetrahedron", p, dc, None, local)
+    ref = torch.empty_like(vals)
+    pat.insert(local, ref)
+    torch.cuda.synchronize()
+    assert torch.equal(_as_bits(vals), _as_bits(ref))
+    del local, ref
+    rp_d, ci_d = pat.pattern()
+    rp = rp_d.cpu().numpy()
+    for r in _sampled_rows(N, 12, seed=10 + p):
+        els, cols, want = oracle.csr_row(dofs, int(r), lambda e: oracle.assemble("helmholtz", "tetrahedron", p,
+                                                                                 coords[e])[0])
+        a, b = int(rp[r]), int(rp[r + 1])
+        B = oracle.assemble("helmholtz", "tetrahedron", p, coords[els])[0]
+        assert np.abs(vals[a:b].cpu().numpy() - want).max() <= TOL * np.abs(B).max(axis=(1, 2)).sum()
+    pat.close()
+    del vals
+    torch.cuda.empty_cache()
