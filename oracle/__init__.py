@@ -69,6 +69,9 @@ def lib():
                                        dp, dp, dp, ctypes.c_int]
         L.orc_hyper_min_jf.restype = ctypes.c_int64
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_assemble_pointgeo.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, dp, dp,
+                                            ctypes.c_double, ctypes.c_double, dp, ctypes.c_int]
+        L.orc_assemble_pointgeo.restype = ctypes.c_int64
         i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
         L.orc_csr_insert.argtypes = [ctypes.c_int64, ctypes.c_int, i32p, ctypes.c_int64, i64p, i32p, dp, dp]
         L.orc_csr_insert.restype = ctypes.c_int
@@ -170,6 +173,34 @@ def assemble(form: str, cell: str, p: int, coords, coeff=None, qdeg=None,
     if flagged < 0:
         raise ValueError("oracle rejected arguments")
     return out, int(flagged)
+
+
+def assemble_pointgeo(form: str, p: int, coords, coeff=None, qdeg=None, mu: float = 1.0, lam: float = 10.0,
+                      nthreads: int = 0):
+    """Prism element matrices without the affine assumption: the P1 x P1
+    vertex map's J, det J and J^{-1} at every quadrature point.  The default
+    rule adds one degree to the affine default (det J varies over the
+    element).  Returns (out [E][n][n], flagged)."""
+    coords = _f64(coords)
+    E = coords.shape[0]
+    n = local_dim(form, "prism", p)
+    if qdeg is None:
+        qdeg = default_qdeg_pointgeo(form, p)
+    out = np.empty((E, n, n))
+    cf = _f64(coeff) if coeff is not None else None
+    if form in ("elasticity", "hyperelastic") and cf is None:
+        raise ValueError("coefficients required")
+    flagged = lib().orc_assemble_pointgeo(FORM[form], p, qdeg, E, _p(coords), _p(cf), mu, lam, _p(out), nthreads)
+    if flagged < 0:
+        raise ValueError("oracle rejected arguments")
+    return out, int(flagged)
+
+
+def default_qdeg_pointgeo(form: str, p: int) -> int:
+    """Rule degree for non-affine prisms: the affine default plus one, the
+    degree det J adds when only the vertex heights vary (det J is then
+    linear in X, Y and constant in Z)."""
+    return default_qdeg(form, "prism", p) + 1
 
 
 def hyper_residual(cell: str, p: int, coords, u, qdeg: int = 4, mu: float = 1.0, lam: float = 10.0):

@@ -273,11 +273,42 @@ int orc_basis(int cell, int p, const double *X, double *phi, double *dphi)
     return nb;
 }
 
-/* P1 (prism: P1 x P1) basis used for the Lame coefficient fields. */
+/* P1 (prism: P1 x P1) basis used for the Lame coefficient fields and, with
+ * its gradients, for the vertex map of a non-affine prism. */
 static int p1_basis(int cell, const double *X, double *psi)
 {
     double dpsi[3 * 6];
     return orc_basis(cell, 1, X, psi, dpsi);
+}
+
+static int p1_basis_grad(int cell, const double *X, double *psi, double *dpsi)
+{
+    return orc_basis(cell, 1, X, psi, dpsi);
+}
+
+/* det and inverse K = J^{-1} of a d x d Jacobian (row-major J[r][a] = dx_r/dX_a). */
+static double jac_inverse(int d, const double *J, double *K)
+{
+    double det;
+    if (d == 2) {
+        det = J[0] * J[3] - J[1] * J[2];
+        K[0] = J[3] / det; K[1] = -J[1] / det; K[2] = -J[2] / det; K[3] = J[0] / det;
+        return det;
+    }
+    double c00 = J[4] * J[8] - J[5] * J[7];
+    double c01 = J[5] * J[6] - J[3] * J[8];
+    double c02 = J[3] * J[7] - J[4] * J[6];
+    det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+    K[0] = c00 / det;
+    K[1] = (J[2] * J[7] - J[1] * J[8]) / det;
+    K[2] = (J[1] * J[5] - J[2] * J[4]) / det;
+    K[3] = c01 / det;
+    K[4] = (J[0] * J[8] - J[2] * J[6]) / det;
+    K[5] = (J[2] * J[3] - J[0] * J[5]) / det;
+    K[6] = c02 / det;
+    K[7] = (J[1] * J[6] - J[0] * J[7]) / det;
+    K[8] = (J[0] * J[4] - J[1] * J[3]) / det;
+    return det;
 }
 
 /* ------------------------------------------------------------------------ *
@@ -400,7 +431,7 @@ static void neo_hookean(int d, const double *F, double mu, double lam, double *P
  * Returns the number of elements flagged (degenerate map, non-affine prism,
  * or J_F <= 0 for the hyperelastic form); their blocks are filled with NaN.
  * ------------------------------------------------------------------------ */
-static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int64_t E,
+static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int pointgeo, int64_t E,
                              const double *coords, const double *coeff,
                              double mu_c, double lam_c, double *out, int nthreads);
 
@@ -408,7 +439,18 @@ int64_t orc_assemble(int form, int cell, int p, int qdeg, int64_t E,
                      const double *coords, const double *coeff,
                      double mu_c, double lam_c, double *out, int nthreads)
 {
-    return assemble_nest(form, cell, p, qdeg, 0, E, coords, coeff, mu_c, lam_c, out, nthreads);
+    return assemble_nest(form, cell, p, qdeg, 0, 0, E, coords, coeff, mu_c, lam_c, out, nthreads);
+}
+
+/* Prisms without the affine assumption of Sec. 2.2: F_K is the vertex map
+ * x(X) = sum_v psi_v(X) v with the P1 x P1 basis psi, so J, det J and
+ * J^{-1} are evaluated at every quadrature point (J(X_q) = sum_v v (x)
+ * grad psi_v(X_q)) instead of once per element.  An element is flagged when
+ * det J is zero, not finite, or changes sign between points. */
+int64_t orc_assemble_pointgeo(int form, int p, int qdeg, int64_t E, const double *coords,
+                              const double *coeff, double mu_c, double lam_c, double *out, int nthreads)
+{
+    return assemble_nest(form, 2, p, qdeg, 0, 1, E, coords, coeff, mu_c, lam_c, out, nthreads);
 }
 
 /* Mass and Helmholtz pre-multiplied by nf coefficient functions (the
@@ -419,10 +461,10 @@ int64_t orc_assemble_coef(int form, int cell, int p, int qdeg, int nf, int64_t E
                           const double *coords, const double *coeff, double *out, int nthreads)
 {
     if (form < 0 || form > 1 || nf < 0 || nf > 3 || (nf > 0 && !coeff)) return -1;
-    return assemble_nest(form, cell, p, qdeg, nf, E, coords, coeff, 1.0, 10.0, out, nthreads);
+    return assemble_nest(form, cell, p, qdeg, nf, 0, E, coords, coeff, 1.0, 10.0, out, nthreads);
 }
 
-static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int64_t E,
+static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int pointgeo, int64_t E,
                              const double *coords, const double *coeff,
                              double mu_c, double lam_c, double *out, int nthreads)
 {
@@ -438,11 +480,22 @@ static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int64_
     double *PHI = (double *)malloc(sizeof(double) * nq * ns);
     double *DPHI = (double *)malloc(sizeof(double) * nq * ns * 3);
     double *PSI = (double *)malloc(sizeof(double) * nq * 6);
+    double *DPSI = (double *)malloc(sizeof(double) * (nq + 1) * 18);
     orc_rule(cell, qdeg, X, W);
     /* reference tabulation Phi_i(X_q), dPhi_i/dX_a(X_q): the tables of Eq. (7) */
     for (int q = 0; q < nq; ++q) {
         orc_basis(cell, p, X + q * d, PHI + q * ns, DPHI + q * ns * d);
         p1_basis(cell, X + q * d, PSI + q * 6);
+        if (pointgeo) {
+            double ps[6];
+#if ORC_MUTANT == 12
+            /* planted mistake: the vertex map's gradient at the centroid for every point */
+            const double Xc[3] = {1.0 / 3.0, 1.0 / 3.0, 0.5};
+            p1_basis_grad(cell, Xc, ps, DPSI + q * 18);
+#else
+            p1_basis_grad(cell, X + q * d, ps, DPSI + q * 18);
+#endif
+        }
     }
     int64_t flagged = 0;
 #ifdef _OPENMP
@@ -452,13 +505,28 @@ static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int64_
     for (int64_t e = 0; e < E; ++e) {
         double *A = out + (size_t)e * n * n;
         const double *v = coords + (size_t)e * nv * d;
-        double J[9], K[9], detJ;
-        int bad = orc_geometry(cell, v, J, &detJ, K);
-        if (!(detJ != 0.0) || !isfinite(detJ)) bad = 1;
+        double J[9], K[9], detJ, det0 = 0.0;
+        int bad = 0;
+        if (!pointgeo) {
+            bad = orc_geometry(cell, v, J, &detJ, K);
+            if (!(detJ != 0.0) || !isfinite(detJ)) bad = 1;
+        }
         for (int k = 0; k < n * n; ++k) A[k] = 0.0;
         double g[ORC_MAXNB * 3];
         for (int q = 0; q < nq && !bad; ++q) {
             const double *phi = PHI + q * ns, *dphi = DPHI + q * ns * d;
+            if (pointgeo) {
+                /* J(X_q)[r][a] = sum_v v_r dpsi_v/dX_a(X_q) */
+                for (int r = 0; r < d; ++r)
+                    for (int a = 0; a < d; ++a) {
+                        double s = 0.0;
+                        for (int l = 0; l < nv; ++l) s += v[l * d + r] * DPSI[q * 18 + l * d + a];
+                        J[r * d + a] = s;
+                    }
+                detJ = jac_inverse(d, J, K);
+                if (q == 0) det0 = detJ;
+                if (!(detJ != 0.0) || !isfinite(detJ) || (detJ > 0.0) != (det0 > 0.0)) { bad = 1; break; }
+            }
             double dx = W[q] * fabs(detJ);
             /* pre-multiplying coefficient functions f_i(X_q) = sum_l f_il Phi_l(X_q) */
             for (int f = 0; f < nf; ++f) {
@@ -525,7 +593,7 @@ static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int64_
             flagged += 1;
         }
     }
-    free(X); free(W); free(PHI); free(DPHI); free(PSI);
+    free(X); free(W); free(PHI); free(DPHI); free(PSI); free(DPSI);
     return flagged;
 }
 

@@ -23,7 +23,9 @@ perturbations is attained at a box corner; the corners were enumerated):
   * Kuhn tetrahedra, +-0.15 h per axis: worst volume ratio 0.10
     (+-0.2 h can invert a Kuhn tetrahedron);
   * prisms: the triangle jitter in x, y only, layers of equal height, so every
-    prism is an exact translate-extrusion (affine).
+    prism is an exact translate-extrusion (affine); optionally each interior
+    layer's vertices also move in z by less than half a layer (non-affine
+    prisms with positive height everywhere).
 """
 from __future__ import annotations
 
@@ -131,10 +133,14 @@ def tet_mesh(n: int, seed: int, jitter: float = TET_JITTER):
     return V, cells.reshape(-1, 4)
 
 
-def prism_mesh(n: int, nz: int, seed: int, jitter: float = TRI_JITTER):
+def prism_mesh(n: int, nz: int, seed: int, jitter: float = TRI_JITTER, zjitter: float = 0.0):
     """Extruded triangle mesh: n*n*2 triangles (jittered in x, y) times nz
     layers of height 1/nz.  Prism vertices are the bottom triangle then the
-    same triangle one layer up, so every prism is affine.  Returns
+    same triangle one layer up, so every prism is affine -- unless zjitter > 0:
+    then every vertex of an interior layer moves in z by up to zjitter/nz
+    (uniform, per vertex), so a prism's top face is no longer a translate of
+    its bottom face (a non-affine prism; its height stays above
+    (1 - 2 zjitter)/nz at every point for zjitter < 0.5).  Returns
     (vertices[NV][3], cells[E][6]) with E = 2*n*n*nz."""
     V2, tris = triangle_mesh(n, n, seed, jitter)
     nv2 = V2.shape[0]
@@ -142,6 +148,14 @@ def prism_mesh(n: int, nz: int, seed: int, jitter: float = TRI_JITTER):
     V = np.concatenate(
         [np.concatenate([V2, np.full((nv2, 1), zl)], axis=1) for zl in z], axis=0
     )
+    if zjitter > 0:
+        if not zjitter < 0.5:
+            raise ValueError("zjitter must be below 0.5")
+        (rz,) = _streams(seed + 7919, 1)
+        dz = rz.uniform(-zjitter / nz, zjitter / nz, size=(nz + 1, nv2))
+        dz[0, :] = 0.0
+        dz[-1, :] = 0.0
+        V[:, 2] += dz.ravel()
     layers = np.arange(nz)
     bot = tris[None, :, :] + (layers * nv2)[:, None, None]
     top = bot + nv2
@@ -276,15 +290,16 @@ def grid_for_count(cell: str, E: int) -> int:
     return n
 
 
-def first_elements(cell: str, E: int, seed: int):
+def first_elements(cell: str, E: int, seed: int, zjitter: float = 0.0):
     """The first E elements of the smallest jittered structured grid with at
-    least E cells.  Returns (coords, vertices, cells[:E], h)."""
+    least E cells (prisms: non-affine with zjitter > 0, see prism_mesh).
+    Returns (coords, vertices, cells[:E], h)."""
     n = grid_for_count(cell, E)
     if cell == TRI:
         V, cells = triangle_mesh(n, n, seed)
     elif cell == TET:
         V, cells = tet_mesh(n, seed)
     else:
-        V, cells = prism_mesh(n, n, seed)
+        V, cells = prism_mesh(n, n, seed, zjitter=zjitter)
     cells = cells[:E]
     return gather(V, cells), V, cells, 1.0 / n

@@ -24,6 +24,7 @@ MUTANTS = {
     9: ("only the first pre-multiplying coefficient function applied", "coefficients"),
     10: ("element matrix inserted transposed", "global assembly"),
     11: ("last local column dropped from the insertion", "global assembly"),
+    12: ("non-affine prism geometry taken at the centroid for every point", "non-affine geometry"),
 }
 
 PINS = {
@@ -38,10 +39,11 @@ PINS = {
     9: "coefficient_fields_exact_rational or coefficient_fields_invariants",
     10: "pattern_and_insert_brute_force",
     11: "global_quadratic_forms_exact or pattern_and_insert_brute_force",
+    12: "zjittered_box_quadratic_forms",
 }
 
 # pins of the global assembly live in their own module
-PIN_FILE = {10: "test_global_pins.py", 11: "test_global_pins.py"}
+PIN_FILE = {10: "test_global_pins.py", 11: "test_global_pins.py", 12: "test_nonaffine_pins.py"}
 
 
 @pytest.mark.parametrize("k", sorted(MUTANTS))
