@@ -145,6 +145,23 @@ typedef struct {
                                   experiment matrix of Sec. 7.1); coeff_dofs
                                   is then [E][nf][n_s] and the default rule
                                   exact degree (2 + nf) * degree.  Default 0 */
+    int            pointgeo;   /* prisms: nonzero lifts the affine assumption
+                                  of Sec. 2.2.  The element map is the vertex
+                                  map x(X) = sum_v psi_v(X) v (P1 x P1 basis
+                                  psi), and J, det J and J^{-1} are evaluated
+                                  at every quadrature point, so prisms need
+                                  not be affine.  The geometry then varies
+                                  over the element, which makes pre-
+                                  evaluation illegal (Sec. 3.3): every
+                                  monomial is evaluated by the float64 VALU
+                                  quadrature kernel (FE_MODE_PREEVAL, nf > 0
+                                  and the split precisions are FE_ENOTSUP;
+                                  fe_autotune and batches refuse it), and the
+                                  default rule gains one degree.  An element
+                                  whose det J is zero, not finite, or changes
+                                  sign between points is flagged.  No effect
+                                  on triangles and tetrahedra (their vertex
+                                  map is affine).  Default 0 */
 } fe_options_t;
 
 /* Fills *opt with the defaults listed above. */

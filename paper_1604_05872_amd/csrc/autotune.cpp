@@ -68,7 +68,7 @@ Config default_for(const Call& c)
         x.variant = 1;
         return x;
     }
-    return default_quad_config(c.form, c.cell, c.degree, c.tables->nq);
+    return default_quad_config(c.form, c.cell, c.degree, c.tables->nq, c.pointgeo);
 }
 
 std::vector<Config> candidates(const Call& c)
@@ -137,7 +137,7 @@ std::vector<Config> candidates(const Call& c)
             x.grid_per_cu = g;
             out.push_back(x);
         }
-    const Config vb = default_quad_config(c.form, c.cell, c.degree, c.tables->nq);
+    const Config vb = default_quad_config(c.form, c.cell, c.degree, c.tables->nq, c.pointgeo);
     for (int div : {1, 2, 4}) {
         for (int g : {4, 8}) {
             Config x = vb;
@@ -157,7 +157,7 @@ std::vector<Config> candidates(const Call& c)
 
 void lookup_config(const Call& c, Config* cfg)
 {
-    {
+    if (!c.pointgeo) {
         std::lock_guard<std::mutex> lk(g_tmu);
         load_file_locked();
         auto it = g_tuned.find(key_of(c));
@@ -184,6 +184,7 @@ extern "C" int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n
     Call c;
     int rc = resolve_call(form, cell, degree, n_elems, coords, coeff_dofs, out_A, opt, &c);
     if (rc) return rc;
+    if (c.pointgeo) return FE_ENOTSUP;   // per-point prism maps use the built-in shape
     std::vector<Config> cands;
     for (const Config& x : candidates(c))
         if (check_config(c, x) == FE_OK) cands.push_back(x);

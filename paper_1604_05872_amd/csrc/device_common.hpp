@@ -77,6 +77,25 @@ __device__ __forceinline__ int affine_map(const double* __restrict__ v, double (
     return bad;
 }
 
+// Jacobian of the vertex map x(X) = sum_v psi_v(X) v at one point:
+// J[r][a] = sum_v v_r dpsi_v/dX_a, with dpsi [NV][D] the vertex basis
+// gradients at that point.
+template <int NV, int D>
+__device__ __forceinline__ void vertex_map_jacobian(const double* __restrict__ v, const double* __restrict__ dpsi,
+                                                    double (&J)[3][3])
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) J[r][c] = 0.0;
+#pragma unroll
+    for (int l = 0; l < NV; ++l)
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) J[r][c] = fma(v[l * D + r], dpsi[l * D + c], J[r][c]);
+}
+
 // 3x3 (or 2x2) inverse and determinant, row-major in a 3x3 array.
 template <int D>
 __device__ __forceinline__ double inverse_small(const double (&F)[3][3], double (&Fi)[3][3])

@@ -123,17 +123,15 @@ int get_tables(int cell, int p, int qdeg, hipStream_t s, const RefTables** out)
     M(&t->ddphi, (size_t)nq * nb * d);
     M(&t->dpsi, (size_t)nq * t->nv);
     M(&t->dR, (size_t)nt * nb * nb);
-    double* tmp = nullptr;
-    M(&tmp, (size_t)nq * t->nv * d);
+    M(&t->ddpsi, (size_t)nq * t->nv * d);
     if (e == hipSuccess) e = hipMemcpyAsync(t->dX, t->X.data(), sizeof(double) * nq * d, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(t->dW, t->W.data(), sizeof(double) * nq, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_tabulate(cell, p, nq, t->dX, t->dphi, t->ddphi, s);
-    if (e == hipSuccess) e = launch_tabulate(cell, 1, nq, t->dX, t->dpsi, tmp, s);
+    if (e == hipSuccess) e = launch_tabulate(cell, 1, nq, t->dX, t->dpsi, t->ddpsi, s);
     if (e == hipSuccess) e = launch_preeval_tables(nq, nb, d, t->dW, t->dphi, t->ddphi, t->dR, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (tmp) (void)hipFree(tmp);
     if (e != hipSuccess) {
-        for (double* p_ : {t->dX, t->dW, t->dphi, t->ddphi, t->dpsi, t->dR})
+        for (double* p_ : {t->dX, t->dW, t->dphi, t->ddphi, t->dpsi, t->ddpsi, t->dR})
             if (p_) (void)hipFree(p_);
         delete t;
         return set_hip_error(e, "building reference tables");
@@ -244,7 +242,7 @@ Config default_preeval_config(int form, int nn)
     return default_preeval_tiled_config(nn, preeval_mm(form));
 }
 
-Config default_quad_config(int form, int cell, int p, int nq)
+Config default_quad_config(int form, int cell, int p, int nq, int pointgeo)
 {
     Config c;
     c.block = QUAD_BLOCK;
@@ -253,7 +251,7 @@ Config default_quad_config(int form, int cell, int p, int nq)
     const int units = ns * ((ns + kb - 1) / kb);
     c.eb = std::max(1, QUAD_BLOCK / units);
     const int D = cell_dim(cell);
-    const int ppt = ns * D + (form == HYPERELASTIC ? ns * D + 9 : 0) + 3;
+    const int ppt = ns * D + (form == HYPERELASTIC ? ns * D + 9 : 0) + 3 + (pointgeo ? 10 : 0);
     const size_t fixed = (size_t)c.eb * 12 * 8;
     const size_t per_q = ((size_t)ns + (size_t)c.eb * ppt) * 8;
     int qc = (int)((QUAD_LDS_BUDGET - fixed) / per_q);
@@ -261,10 +259,10 @@ Config default_quad_config(int form, int cell, int p, int nq)
     return c;
 }
 
-size_t quad_lds_bytes(int form, int cell, int ns, int eb, int qc)
+size_t quad_lds_bytes(int form, int cell, int ns, int eb, int qc, int pointgeo)
 {
     const int D = cell_dim(cell);
-    const int ppt = ns * D + (form == HYPERELASTIC ? ns * D + 9 : 0) + 3;
+    const int ppt = ns * D + (form == HYPERELASTIC ? ns * D + 9 : 0) + 3 + (pointgeo ? 10 : 0);
     return ((size_t)eb * 12 + (size_t)qc * ns + (size_t)eb * qc * ppt) * 8;
 }
 
@@ -439,6 +437,7 @@ bool q_invariant(const Call& c)
 
 bool gram64_eligible(const Call& c)
 {
+    if (c.pointgeo) return false;   // the matrix-core kernels take one map per element
     if (!is_vector_form(c.form) || n_rows(c.form, c.cell, c.degree) > 32) return false;
     if (n_scalar(c.cell, c.degree) > 16) return false;
     const int nq = q_invariant(c) ? 1 : c.tables->nq;
@@ -548,9 +547,11 @@ int launch_call(const Call& c, const Config& cfg)
     a.mu = c.mu;
     a.lam = c.lam;
     a.nf = c.nf;
+    a.pointgeo = c.pointgeo;
+    a.dpsi_grad = t->ddpsi;
     const int64_t tiles = (c.E + a.eb - 1) / a.eb;
     const int grid = (int)std::min<int64_t>(tiles, (int64_t)cus * cfg.grid_per_cu);
-    const size_t lds = quad_lds_bytes(c.form, c.cell, t->nb, a.eb, a.qc);
+    const size_t lds = quad_lds_bytes(c.form, c.cell, t->nb, a.eb, a.qc, c.pointgeo);
     e = launch_quad(c.form, c.cell, quad_kb(c.cell, c.degree), a, grid, lds, c.stream);
     if (e != hipSuccess) return set_hip_error(e, "quadrature launch");
     if (c.nf > 0 && c.mass_pre) {
@@ -614,7 +615,7 @@ int check_config(const Call& c, const Config& cfg)
         return gram64_lds_bytes(c.form, c.cell, gram64_nqp(nq), t->nq, t->nb) <= max_lds ? FE_OK : FE_EINVAL;
     }
     if (cfg.eb < 1 || cfg.qc < 1 || cfg.qc > t->nq) return FE_EINVAL;
-    return quad_lds_bytes(c.form, c.cell, t->nb, cfg.eb, cfg.qc) <= max_lds ? FE_OK : FE_EINVAL;
+    return quad_lds_bytes(c.form, c.cell, t->nb, cfg.eb, cfg.qc, c.pointgeo) <= max_lds ? FE_OK : FE_EINVAL;
 }
 
 int final_config(const Call& c, Config* cfg)
@@ -629,7 +630,7 @@ int final_config(const Call& c, Config* cfg)
         if (c.prec == FE_FP64) {
             const int v = (s[0] == 2 || s[0] == 4) ? 1 : 0;
             if (!pre && v != autocfg.variant) {
-                *cfg = v ? Config() : default_quad_config(c.form, c.cell, c.degree, c.tables->nq);
+                *cfg = v ? Config() : default_quad_config(c.form, c.cell, c.degree, c.tables->nq, c.pointgeo);
                 cfg->variant = v;
             }
             cfg->variant = v;
@@ -659,9 +660,13 @@ int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, co
     if ((int)o.precision < 0 || (int)o.precision > 2 || (int)o.mode < 0 || (int)o.mode > 2) return FE_EINVAL;
     if (o.nf < 0 || o.nf > 3) return FE_EINVAL;
     if (o.nf > 0 && (is_vector_form(form) || o.precision != FE_FP64)) return FE_ENOTSUP;
-    const int qdeg = o.qdeg < 0 ? default_qdeg(form, cell, degree, o.nf) : o.qdeg;
+    // the vertex map of a simplex is affine: per-point geometry only changes prisms
+    const int pg = (o.pointgeo && cell == PRISM) ? 1 : 0;
+    if (pg && (o.nf > 0 || o.precision != FE_FP64 || o.mode == FE_MODE_PREEVAL)) return FE_ENOTSUP;
+    const int qdeg = o.qdeg < 0 ? default_qdeg(form, cell, degree, o.nf) + pg : o.qdeg;
     if (qdeg > MAX_QDEG) return FE_EINVAL;
     c->nf = o.nf;
+    c->pointgeo = pg;
     c->form = form;
     c->cell = cell;
     c->degree = degree;
@@ -685,9 +690,18 @@ int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, co
     if (!coords || !out_A) return FE_EINVAL;
     if ((is_vector_form(form) || o.nf > 0) && !coeff_dofs) return FE_EINVAL;
     if (form == HYPERELASTIC && !(std::isfinite(o.mu) && std::isfinite(o.lambda))) return FE_EINVAL;
-    int rc = fe_resolve_variant(form, cell, degree, qdeg, &o, &c->mode, &c->mass_pre);
-    if (rc) return rc;
-    if (o.validate && cell == PRISM) {
+    int rc = FE_OK;
+    if (pg) {
+        // pre-evaluation needs a geometry tensor that is constant over the
+        // element (Sec. 3.3); with per-point maps every monomial is evaluated
+        // by quadrature
+        c->mode = FE_MODE_QUADRATURE;
+        c->mass_pre = 0;
+    } else {
+        rc = fe_resolve_variant(form, cell, degree, qdeg, &o, &c->mode, &c->mass_pre);
+        if (rc) return rc;
+    }
+    if (o.validate && cell == PRISM && !pg) {
         rc = validate_prisms(n_elems, coords, c->stream);
         if (rc) return rc;
     }
@@ -715,7 +729,7 @@ void fe_release_caches(void)
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& kv : g_tables) {
         RefTables* t = kv.second;
-        for (double* p_ : {t->dX, t->dW, t->dphi, t->ddphi, t->dpsi, t->dR})
+        for (double* p_ : {t->dX, t->dW, t->dphi, t->ddphi, t->dpsi, t->ddpsi, t->dR})
             if (p_) (void)hipFree(p_);
         delete t;
     }

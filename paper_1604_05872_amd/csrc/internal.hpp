@@ -106,6 +106,7 @@ struct RefTables {
     double* dphi = nullptr;            // [nq][nb]
     double* ddphi = nullptr;           // [nq][nb][d]
     double* dpsi = nullptr;            // [nq][nv] P1 (prism P1 x P1) basis
+    double* ddpsi = nullptr;           // [nq][nv][d] its gradients (the vertex map's)
     double* dR = nullptr;              // [1 + d(d+1)/2][nb][nb] pre-evaluated tensors
 };
 
@@ -145,14 +146,15 @@ inline size_t preeval_lds_bytes(int form, int cell, int chunk)
 {
     return (size_t)chunk * (n_tables(form, cell) + cell_nv(cell) * cell_dim(cell)) * sizeof(double);
 }
-Config default_quad_config(int form, int cell, int p, int nq);
-size_t quad_lds_bytes(int form, int cell, int ns, int eb, int qc);
+Config default_quad_config(int form, int cell, int p, int nq, int pointgeo = 0);
+size_t quad_lds_bytes(int form, int cell, int ns, int eb, int qc, int pointgeo = 0);
 
 // One resolved assembly call.
 struct Call {
     int form = 0, cell = 0, degree = 1, qdeg = 2;
     int mode = 0;       // FE_MODE_PREEVAL or FE_MODE_QUADRATURE
     int nf = 0;         // pre-multiplying coefficient functions (mass, Helmholtz)
+    int pointgeo = 0;   // prisms: the vertex map evaluated at every point (non-affine)
     int shape[7] = {0, 0, 0, 0, 0, 0, 0};   // caller's launch-shape override (fe_shape_t order)
     int mass_pre = 0;   // Helmholtz quadrature: bit 0 mass monomial pre-evaluated,
                         // bit 1 gradient monomial pre-evaluated

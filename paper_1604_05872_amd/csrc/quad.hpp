@@ -53,23 +53,26 @@ struct QuadArgs {
                           // DOFs [E][nf][ns] in coeff (Sec. 7.1)
     int skip;             // Helmholtz: bit 0 leaves out the mass term, bit 1 the
                           // gradient term (added by another kernel afterwards)
+    int pointgeo = 0;     // prisms: J, det J, J^{-1} of the vertex map at every point
+    const double* dpsi_grad = nullptr;   // [nq][nv][d] gradients of the vertex basis (pointgeo)
 };
 
 template <int FORM, int CELL>
 struct QuadLayout {
     static constexpr int D = cell_dim(CELL);
     static constexpr int VEC = is_vector_form(FORM) ? 1 : 0;
-    // per (element, point): g [ns][D], s [ns][D] (hyperelastic), 3 scaled weights,
-    // F^{-1} (hyperelastic, 9)
-    __host__ __device__ static int per_point(int ns)
+    // per (element, point): g [ns][D], s [ns][D] (hyperelastic), F^{-1}
+    // (hyperelastic, 9), 3 scaled weights, then with per-point geometry the
+    // point's K (9) and |det J| (1)
+    __host__ __device__ static int per_point(int ns, int pg = 0)
     {
-        return ns * D + (FORM == HYPERELASTIC ? ns * D + 9 : 0) + 3;
+        return ns * D + (FORM == HYPERELASTIC ? ns * D + 9 : 0) + 3 + (pg ? 10 : 0);
     }
-    // per element: K (9), |det J|, flag
+    // per element: K (9), |det J|, flag, det J at the first point (per-point geometry)
     static constexpr int PER_ELEM = 12;
-    __host__ __device__ static size_t lds_doubles(int ns, int eb, int qc)
+    __host__ __device__ static size_t lds_doubles(int ns, int eb, int qc, int pg = 0)
     {
-        return (size_t)eb * PER_ELEM + (size_t)qc * ns + (size_t)eb * qc * per_point(ns);
+        return (size_t)eb * PER_ELEM + (size_t)qc * ns + (size_t)eb * qc * per_point(ns, pg);
     }
 };
 
@@ -83,21 +86,34 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
     const int ns = a.ns, nq = a.nq, qc_max = a.qc;
     const int64_t rem = a.E - e_begin;
     const int eb = rem < a.eb ? (int)rem : a.eb;
-    const int ppt = L::per_point(ns);
+    // per-point geometry applies to prisms only (a simplex's vertex map is affine)
+    const int pg = CELL == PRISM ? a.pointgeo : 0;
+    const int ppt = L::per_point(ns, pg);
 
     double* sEl = lds;                                  // [eb][12]
     double* sPhi = lds + (size_t)a.eb * L::PER_ELEM;    // [qc][ns]
     double* sPt = sPhi + (size_t)qc_max * ns;           // [eb][qc][ppt]
 
-    // element geometry
+    // element geometry (per-point geometry: only the sign of det J at the
+    // first point, which every point must share)
     for (int i = tid; i < eb; i += B) {
         const int64_t e = e_begin + i;
         double v[NV * D];
 #pragma unroll
         for (int k = 0; k < NV * D; ++k) v[k] = a.coords[e * (NV * D) + k];
+        double* s = sEl + i * L::PER_ELEM;
+        if (CELL == PRISM && pg) {
+            double J[3][3], Kq[3][3];
+            vertex_map_jacobian<NV, D>(v, a.dpsi_grad, J);
+            const double det = inverse_small<D>(J, Kq);
+#pragma unroll
+            for (int r = 0; r < 10; ++r) s[r] = 0.0;
+            s[10] = (det != 0.0 && isfinite(det)) ? 0.0 : 1.0;
+            s[11] = det;
+            continue;
+        }
         double K[3][3], adet;
         const int bad = affine_map<CELL>(v, K, adet);
-        double* s = sEl + i * L::PER_ELEM;
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -131,11 +147,35 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
             const int qc = min(qc_max, nq_loop - q0);
             // --- stage per-point data -------------------------------------
             for (int idx = tid; idx < qc * ns; idx += B) sPhi[idx] = a.phi[q0 * ns + idx];
+            if (CELL == PRISM && pg) {
+                // J(X_q) = sum_v v (x) grad psi_v(X_q), its inverse and |det J|
+                for (int idx = tid; idx < eb * qc; idx += B) {
+                    const int i = idx / qc, qq = idx - i * qc;
+                    const int64_t e = e_begin + i;
+                    double v[NV * D];
+#pragma unroll
+                    for (int k = 0; k < NV * D; ++k) v[k] = a.coords[e * (NV * D) + k];
+                    double J[3][3], Kq[3][3];
+                    vertex_map_jacobian<NV, D>(v, a.dpsi_grad + (size_t)(q0 + qq) * NV * D, J);
+                    const double det = inverse_small<D>(J, Kq);
+                    double* gq = sPt + ((size_t)i * qc_max + qq) * ppt + ppt - 10;
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) gq[r * 3 + c] = Kq[r][c];
+                    gq[9] = fabs(det);
+                    const double det0 = sEl[i * L::PER_ELEM + 11];
+                    if (!(det != 0.0 && isfinite(det)) || ((det > 0.0) != (det0 > 0.0)))
+                        sEl[i * L::PER_ELEM + 10] = 1.0;
+                }
+                __syncthreads();
+            }
             for (int idx = tid; idx < eb * qc * ns; idx += B) {
                 const int i = idx / (qc * ns);
                 const int r = idx - i * qc * ns;
                 const int qq = r / ns, j = r - qq * ns;
-                const double* K = sEl + i * L::PER_ELEM;
+                const double* K = (CELL == PRISM && pg) ? sPt + ((size_t)i * qc_max + qq) * ppt + ppt - 10
+                                                        : sEl + i * L::PER_ELEM;
                 const double* gh = a.dphi + ((size_t)(q0 + qq) * ns + j) * D;
                 double* g = sPt + ((size_t)i * qc_max + qq) * ppt + j * D;
 #pragma unroll
@@ -155,8 +195,8 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
                     wsum = 0.0;
                     for (int q = 0; q < nq; ++q) wsum += a.W[q];
                 }
-                const double w = wsum * sEl[i * L::PER_ELEM + 9];
                 double* pt = sPt + ((size_t)i * qc_max + qq) * ppt;
+                const double w = wsum * ((CELL == PRISM && pg) ? pt[ppt - 1] : sEl[i * L::PER_ELEM + 9]);
                 double* sw = pt + ns * D + (FORM == HYPERELASTIC ? ns * D + 9 : 0);
                 if (FORM == MASS || FORM == HELMHOLTZ) {
                     // w times prod_i f_i(X_q), f_i = sum_l f_il phi_l

@@ -61,6 +61,7 @@ class fe_options_t(ctypes.Structure):
         ("validate", ctypes.c_int),
         ("shape", fe_shape_t),
         ("nf", ctypes.c_int),
+        ("pointgeo", ctypes.c_int),
     ]
 
 
@@ -175,7 +176,7 @@ def _f64_dev(t, name):
 
 
 def make_options(qdeg=-1, precision="fp64", mode="auto", stream=None, mu=1.0, lam=10.0, status=None,
-                 th_bytes=0, validate=False, need_stream=True, shape=None, nf=0) -> fe_options_t:
+                 th_bytes=0, validate=False, need_stream=True, shape=None, nf=0, pointgeo=False) -> fe_options_t:
     o = fe_options_t()
     lib().fe_options_init(ctypes.byref(o))
     o.qdeg = int(qdeg)
@@ -190,6 +191,7 @@ def make_options(qdeg=-1, precision="fp64", mode="auto", stream=None, mu=1.0, la
     for k, v in (shape or {}).items():
         setattr(o.shape, k, int(v))
     o.nf = int(nf)
+    o.pointgeo = 1 if pointgeo else 0
     return o
 
 
@@ -223,12 +225,13 @@ def fe_tabulate(cell: str, degree: int, qdeg: int, rule_only: bool = False):
 def fe_assemble_local(form: str, cell: str, degree: int, coords, coeff, out, qdeg: int = -1,
                       precision: str = "fp64", mode: str = "auto", stream=None, mu: float = 1.0,
                       lam: float = 10.0, status=None, th_bytes: int = 0, validate: bool = False,
-                      shape: dict | None = None, nf: int = 0):
+                      shape: dict | None = None, nf: int = 0, pointgeo: bool = False):
     """Element matrices of `form` into `out` [E][n][n] (asynchronous on the stream).
 
     shape: optional launch-shape override, keys of fe_shape_t (kernel: 1 tiled,
     2 streaming; block, epi, chunk, eb, qc, grid_per_cu).  nf: mass and
-    Helmholtz pre-multiplied by nf coefficient functions, coeff [E][nf][n_s]."""
+    Helmholtz pre-multiplied by nf coefficient functions, coeff [E][nf][n_s].
+    pointgeo: prisms need not be affine (the vertex map at every point)."""
     _f64_dev(coords, "coords")
     _f64_dev(coeff, "coeff")
     _f64_dev(out, "out")
@@ -242,7 +245,8 @@ def fe_assemble_local(form: str, cell: str, degree: int, coords, coeff, out, qde
         nc = int(nf) * NBASIS(cell, degree)
     if nc and (coeff is None or coeff.numel() != E * nc):
         raise ValueError(f"coeff must hold {nc} values per element")
-    o = make_options(qdeg, precision, mode, stream, mu, lam, status, th_bytes, validate, shape=shape, nf=nf)
+    o = make_options(qdeg, precision, mode, stream, mu, lam, status, th_bytes, validate, shape=shape, nf=nf,
+                     pointgeo=pointgeo)
     _check(lib().fe_assemble_local(FORMS[form], CELLS[cell], int(degree), E, _ptr(coords), _ptr(coeff),
                                    _ptr(out), ctypes.byref(o)), "fe_assemble_local")
     return out

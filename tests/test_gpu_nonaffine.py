@@ -1,0 +1,154 @@
+"""Prisms without the affine assumption (fe_options_t.pointgeo) on the GPU,
+through the C ABI, against the oracle's per-point geometry.
+
+Metric as in test_gpu_parity.py: per element max |A_gpu - A_oracle| /
+max |A_oracle| <= 1e-12 (float64).  The meshes are z-jittered prism grids:
+every interior layer's vertices move in z, so no prism is affine."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_05872_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1604_05872_amd import felocal  # noqa: E402
+
+TOL = 1e-12
+ZJ = 0.3
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def normwise(A, B):
+    return np.max(np.abs(A - B), axis=(1, 2)) / np.max(np.abs(B), axis=(1, 2))
+
+
+def case(form, p, E, seed):
+    coords, V, cells, h = inputs.first_elements("prism", E, seed, zjitter=ZJ)
+    if form == "elasticity":
+        cf = inputs.lame_p1(V.shape[0], cells, seed)
+    elif form == "hyperelastic":
+        cf = inputs.displacement_dofs(len(coords), 3, oracle.nbasis("prism", p), h, p, seed)
+    else:
+        cf = None
+    return coords, cf
+
+
+def gpu(form, p, coords, cf, **kw):
+    n, _ = felocal.fe_local_dims(form, "prism", p)
+    out = torch.full((len(coords), n, n), float("nan"), dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    felocal.fe_assemble_local(form, "prism", p, dev(coords), dev(cf) if cf is not None else None, out,
+                              status=st, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), int(st.item())
+
+
+CASES = [("mass", p) for p in (1, 2, 3, 4)] + [("helmholtz", p) for p in (1, 2, 3, 4)] + \
+        [("elasticity", 1), ("elasticity", 2), ("hyperelastic", 1), ("hyperelastic", 2)]
+
+
+@pytest.mark.parametrize("form,p", CASES)
+def test_pointgeo_matches_oracle(form, p):
+    """Several tiles and a ragged tail; the rule is the library's default
+    (the affine default plus one degree) on both sides."""
+    log(f"pointgeo: {form} prism P{p}")
+    E = {1: 777, 2: 333, 3: 121, 4: 61}[p]
+    coords, cf = case(form, p, E, seed=21)
+    A, st = gpu(form, p, coords, cf, pointgeo=True)
+    B, fl = oracle.assemble_pointgeo(form, p, coords, cf)
+    assert st == fl
+    ok = ~np.isnan(B[:, 0, 0])
+    assert np.array_equal(np.isnan(A[:, 0, 0]), ~ok)
+    assert normwise(A[ok], B[ok]).max() <= TOL
+    # without the option these prisms are rejected element by element
+    if form in ("mass", "helmholtz"):
+        _, st_aff = gpu(form, p, coords, cf)
+        assert st_aff == len(coords)
+
+
+@pytest.mark.parametrize("form,p", [("mass", 2), ("helmholtz", 3), ("elasticity", 2)])
+def test_pointgeo_on_affine_prisms_equals_affine_path(form, p):
+    coords, V, cells, h = inputs.first_elements("prism", 200, 22)
+    cf = inputs.lame_p1(V.shape[0], cells, 22) if form == "elasticity" else None
+    q = oracle.default_qdeg_pointgeo(form, p)
+    A, st = gpu(form, p, coords, cf, pointgeo=True)
+    B, st2 = gpu(form, p, coords, cf, qdeg=q, mode="quadrature")
+    assert st == 0 and st2 == 0
+    assert normwise(A, B).max() <= 1e-13
+
+
+def test_pointgeo_flags_and_refusals():
+    coords, cf = case("helmholtz", 2, 50, seed=23)
+    coords = coords.copy()
+    coords[7, 5, 2] = coords[7, 2, 2] - 0.5 * (coords[7, 3, 2] - coords[7, 0, 2])   # top vertex below the bottom face
+    A, st = gpu("helmholtz", 2, coords, None, pointgeo=True)
+    B, fl = oracle.assemble_pointgeo("helmholtz", 2, coords)
+    assert fl == 1 and st == 1
+    assert np.isnan(A[7]).all() and not np.isnan(np.delete(A, 7, axis=0)).any()
+    n, _ = felocal.fe_local_dims("helmholtz", "prism", 2)
+    out = torch.empty((len(coords), n, n), dtype=torch.float64, device="cuda")
+    dc = dev(coords)
+    for kw in ({"mode": "preeval"}, {"nf": 1}):
+        with pytest.raises(felocal.FeError) as ei:
+            felocal.fe_assemble_local("helmholtz", "prism", 2, dc,
+                                      dev(np.ones((len(coords), 18))) if "nf" in kw else None, out,
+                                      pointgeo=True, **kw)
+        assert ei.value.code == felocal.FE_ENOTSUP
+    cfe, _ = case("elasticity", 1, 50, seed=23)
+    lame = dev(np.ones((len(cfe), 2, 6)))
+    out3 = torch.empty((len(cfe), 18, 18), dtype=torch.float64, device="cuda")
+    for prec in ("fp32", "bf16x3"):
+        with pytest.raises(felocal.FeError) as ei:
+            felocal.fe_assemble_local("elasticity", "prism", 1, dev(cfe), lame, out3, precision=prec, pointgeo=True)
+        assert ei.value.code == felocal.FE_ENOTSUP
+    o = felocal.make_options(pointgeo=True)
+    best = felocal.ctypes.c_double()
+    rc = felocal.lib().fe_autotune(felocal.FORMS["helmholtz"], felocal.CELLS["prism"], 2, len(coords),
+                                   felocal._ptr(dc), None, felocal._ptr(out), felocal.ctypes.byref(o),
+                                   felocal.ctypes.byref(best), None)
+    assert rc == felocal.FE_ENOTSUP
+    # simplices: the option changes nothing
+    tc, _, _, _ = inputs.first_elements("tetrahedron", 100, 24)
+    n4, _ = felocal.fe_local_dims("helmholtz", "tetrahedron", 2)
+    o1 = torch.empty((100, n4, n4), dtype=torch.float64, device="cuda")
+    o2 = torch.empty_like(o1)
+    felocal.fe_assemble_local("helmholtz", "tetrahedron", 2, dev(tc), None, o1)
+    felocal.fe_assemble_local("helmholtz", "tetrahedron", 2, dev(tc), None, o2, pointgeo=True)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_full_pointgeo_helmholtz_prisms(p):
+    """The z-jittered prism workload the benchmark times (2 x 63^3 = 500,094
+    prisms), sampled elements."""
+    log(f"full pointgeo: helmholtz prism P{p} 500k")
+    V, cells = inputs.prism_mesh(63, 63, 25, zjitter=ZJ)
+    coords = inputs.gather(V, cells)
+    E = len(coords)
+    n, _ = felocal.fe_local_dims("helmholtz", "prism", p)
+    out = torch.empty((E, n, n), dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    felocal.fe_assemble_local("helmholtz", "prism", p, dev(coords), None, out, status=st, pointgeo=True)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    rng = np.random.default_rng(p)
+    idx = np.unique(np.concatenate([[0, 1, E - 1], rng.integers(0, E, size=48)]))
+    B, fl = oracle.assemble_pointgeo("helmholtz", p, coords[idx])
+    assert fl == 0
+    A = out[torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert normwise(A, B).max() <= TOL
+    del out
+    torch.cuda.empty_cache()
