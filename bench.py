@@ -12,8 +12,9 @@ and split), a 16-sub-batch mixed persistent launch replayed from a HIP
 graph (one persistent work-queue kernel per kernel variant), and the
 experiment matrix of Sec. 7.1 (mass and Helmholtz, q = 1..4, nf = 0..3
 coefficient functions) with Algorithm 3's choice against both forced modes,
-and local plus global assembly (insertion into the compressed-row matrix of
-the continuous space) of the headline form and mesh.  Inputs are seeded
+local plus global assembly (insertion into the compressed-row matrix of
+the continuous space) of the headline form and mesh, and Helmholtz on
+non-affine (z-jittered) prisms with per-point geometry.  Inputs are seeded
 synthetic meshes resident in HBM before timing.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -110,7 +111,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the built-in default launch shapes instead of the autotuned ones")
     ap.add_argument("--only-headline", action="store_true")
-    ap.add_argument("--workloads", default="mass,elasticity,hyperelastic,batch,sweep,global",
+    ap.add_argument("--workloads", default="mass,elasticity,hyperelastic,batch,sweep,global,nonaffine",
                     help="comma list of the extra workloads to time")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a known-size kernel for the HBM counters)")
@@ -389,7 +390,45 @@ def other_workloads(torch, felocal, inputs, stream, ev, reps, which):
         res.append(sweep_workload(torch, felocal, inputs, stream, ev, max(2, reps // 3)))
     if "global" in which:
         res.append(global_workload(torch, felocal, inputs, stream, ev, reps))
+    if "nonaffine" in which:
+        res.append(nonaffine_workload(torch, felocal, inputs, stream, ev, reps))
     return res
+
+
+def nonaffine_workload(torch, felocal, inputs, stream, ev, reps):
+    """Prisms without the affine assumption: Helmholtz P1-P3 on 2 x 63^3 =
+    500,094 prisms.  On the affine mesh: the planner's choice (pre-evaluated)
+    and forced quadrature; on the same mesh with every interior layer
+    z-jittered (no prism affine): quadrature with the vertex map's geometry
+    at every point (fe_options_t.pointgeo), the only legal mode there."""
+    out = {"workload": "nonaffine_helmholtz_prism_500k", "per_degree": {}}
+    Va, cells = inputs.prism_mesh(63, 63, 25)
+    Vj, _ = inputs.prism_mesh(63, 63, 25, zjitter=0.3)
+    ca = torch.from_numpy(inputs.gather(Va, cells)).cuda()
+    cj = torch.from_numpy(inputs.gather(Vj, cells)).cuda()
+    E = int(ca.shape[0])
+    out["elements"] = E
+    for p in (1, 2, 3):
+        log(f"non-affine prisms: helmholtz P{p}")
+        n, _ = felocal.fe_local_dims("helmholtz", "prism", p)
+        o = torch.empty((E, n, n), dtype=torch.float64, device="cuda")
+        ms_pre = time_launch(torch, lambda: felocal.fe_assemble_local("helmholtz", "prism", p, ca, None, o),
+                             stream, ev, reps)
+        ms_quad = time_launch(torch, lambda: felocal.fe_assemble_local("helmholtz", "prism", p, ca, None, o,
+                                                                       mode="quadrature"), stream, ev, reps)
+        ms_pg = time_launch(torch, lambda: felocal.fe_assemble_local("helmholtz", "prism", p, cj, None, o,
+                                                                     pointgeo=True), stream, ev, reps)
+        B = E * n * n * 8
+        row = {"affine_planner_ms": round(ms_pre, 4), "affine_quadrature_ms": round(ms_quad, 4),
+               "pointgeo_ms": round(ms_pg, 4), "pointgeo_elem_per_s": round(E / (ms_pg * 1e-3), 1),
+               "pointgeo_store_GBs": round(B / (ms_pg * 1e-3) / 1e9, 1)}
+        out["per_degree"][f"P{p}"] = row
+        log(f"  P{p}: affine planner {ms_pre:.4f} ms, affine quadrature {ms_quad:.4f} ms, "
+            f"non-affine per-point geometry {ms_pg:.4f} ms")
+        del o
+        torch.cuda.empty_cache()
+    del ca, cj
+    return out
 
 
 def mass_workload(torch, felocal, inputs, stream, ev, record):
