@@ -101,9 +101,10 @@ enum {
  *                the mass form; visits of `chunk` consecutive elements);
  *                quadrature mode: 3 = VALU kernel (any size), 4 = matrix-
  *                core Gram kernel (vector forms with n <= 32, n_s <= 16 and
- *                at most 32 points; the only kernel of the split
- *                precisions).  A kernel that does not serve the call's mode
- *                and precision is rejected.
+ *                at most 32 points, the only kernel of the split
+ *                precisions; mass and Helmholtz with n <= 48 except a mixed
+ *                plan without coefficient functions).  A kernel that does
+ *                not serve the call's mode and precision is rejected.
  *   block        threads of the pre-evaluated kernels (multiple of 64, <= 512)
  *   epi          pre-evaluated: elements per step (1 <= epi <= block)
  *   chunk        pre-evaluated: elements per tile or visit, a multiple of
@@ -153,7 +154,7 @@ typedef struct {
                                   not be affine.  The geometry then varies
                                   over the element, which makes pre-
                                   evaluation illegal (Sec. 3.3): every
-                                  monomial is evaluated by the float64 VALU
+                                  monomial is evaluated by a float64
                                   quadrature kernel (FE_MODE_PREEVAL, nf > 0
                                   and the split precisions are FE_ENOTSUP;
                                   fe_autotune and batches refuse it), and the

@@ -62,8 +62,16 @@ Config default_for(const Call& c)
     if (c.mode == FE_MODE_PREEVAL && c.nf > 0) return Config();
     if (c.mode == FE_MODE_PREEVAL) return default_preeval_config(c.form, c.tables->nb * c.tables->nb);
     // float64 matrix-core Gram kernel where the point loop is not hoisted
-    // (with one point per element the VALU kernel is faster)
-    if (gram64_eligible(c) && !q_invariant(c)) {
+    // (with one point per element the VALU kernel is faster).  For the scalar
+    // forms it wins where its tiles are well filled (measured on MI355X over
+    // every cell, degree and nf = 0..2): mass from n = 10, Helmholtz (four
+    // rows per point) with three tiles or one nearly full tile.
+    bool gram = gram64_eligible(c) && !q_invariant(c);
+    if (gram && !is_vector_form(c.form)) {
+        const int ns = c.tables->nb;
+        gram = c.form == MASS ? ns >= 10 : (ns > 32 || (ns >= 13 && ns <= 16));
+    }
+    if (gram) {
         Config x;
         x.variant = 1;
         return x;

@@ -437,8 +437,16 @@ bool q_invariant(const Call& c)
 
 bool gram64_eligible(const Call& c)
 {
-    if (c.pointgeo) return false;   // the matrix-core kernels take one map per element
-    if (!is_vector_form(c.form) || n_rows(c.form, c.cell, c.degree) > 32) return false;
+    if (!is_vector_form(c.form)) {
+        // scalar Gram kernel: element matrices up to 48 x 48, any rule, per-point
+        // prism geometry and coefficient functions; a mixed plan without
+        // coefficient functions adds its pre-evaluated tables in the VALU kernel
+        if (c.prec != FE_FP64 || c.mode != FE_MODE_QUADRATURE) return false;
+        if (n_scalar(c.cell, c.degree) > 48) return false;
+        return !(c.nf == 0 && c.mass_pre != 0);
+    }
+    if (c.pointgeo) return false;   // the vector matrix-core kernels take one map per element
+    if (n_rows(c.form, c.cell, c.degree) > 32) return false;
     if (n_scalar(c.cell, c.degree) > 16) return false;
     const int nq = q_invariant(c) ? 1 : c.tables->nq;
     return nq <= 32;
@@ -453,7 +461,7 @@ int launch_call(const Call& c, const Config& cfg)
     const RefTables* t = c.tables;
     const int cus = device_cus();
     hipError_t e;
-    if (c.prec != FE_FP64 || (c.mode == FE_MODE_QUADRATURE && cfg.variant)) {
+    if (c.prec != FE_FP64 || (c.mode == FE_MODE_QUADRATURE && cfg.variant && is_vector_form(c.form))) {
         SplitArgs a;
         a.coords = c.coords;
         a.coeff = c.coeff;
@@ -525,6 +533,30 @@ int launch_call(const Call& c, const Config& cfg)
         if (e != hipSuccess) return set_hip_error(e, "pre-evaluated launch");
         return FE_OK;
     }
+    if (cfg.variant) {
+        // mass and Helmholtz on the float64 matrix cores
+        if (!gram64_eligible(c)) return FE_EINVAL;
+        GramScalarArgs g;
+        g.coords = c.coords;
+        g.coeff = c.coeff;
+        g.out = c.out;
+        g.status = c.status;
+        g.W = t->dW;
+        g.phi = t->dphi;
+        g.dphi = t->ddphi;
+        g.dpsi_grad = t->ddpsi;
+        g.E = c.E;
+        g.nq = t->nq;
+        g.nf = c.nf;
+        g.skip = c.nf > 0 ? c.mass_pre : 0;
+        g.pointgeo = c.pointgeo;
+        g.nt = store_mode();
+        const int64_t blocks = (c.E + gram64_scalar_elems_per_block() - 1) / gram64_scalar_elems_per_block();
+        const int grid = (int)std::min<int64_t>(blocks, (int64_t)cus * cfg.grid_per_cu);
+        e = launch_gram64_scalar(c.form, c.cell, c.degree, g, grid, c.stream);
+        if (e != hipSuccess) return set_hip_error(e, "float64 matrix-core launch");
+        return add_coef_monomial(c, cfg);
+    }
     QuadArgs a;
     a.coords = c.coords;
     a.coeff = c.coeff;
@@ -554,16 +586,23 @@ int launch_call(const Call& c, const Config& cfg)
     const size_t lds = quad_lds_bytes(c.form, c.cell, t->nb, a.eb, a.qc, c.pointgeo);
     e = launch_quad(c.form, c.cell, quad_kb(c.cell, c.degree), a, grid, lds, c.stream);
     if (e != hipSuccess) return set_hip_error(e, "quadrature launch");
-    if (c.nf > 0 && c.mass_pre) {
-        // the pre-evaluated monomial of a mixed plan, added to the quadrature part
-        const CoefTables* ct = nullptr;
-        int rc = get_coef_tables(c.form, c.cell, c.degree, c.qdeg, c.nf, c.stream, &ct);
-        if (rc) return rc;
-        const int r_lo = (c.mass_pre & 1) ? 0 : 1, r_hi = (c.mass_pre & 2) ? n_tables(c.form, c.cell) : 1;
-        e = launch_preeval_coef(c.form, c.cell, c.coords, c.coeff, c.out, nullptr,
-                                ct->dR, ct->dCombos, c.E, t->nb, c.nf, ct->iota, 8, cus, c.stream, r_lo, r_hi, 1);
-        if (e != hipSuccess) return set_hip_error(e, "coefficient pre-evaluated launch");
-    }
+    return add_coef_monomial(c, cfg);
+}
+
+// A mixed plan with coefficient functions: the pre-evaluated monomial is
+// added to the quadrature part by the coefficient pre-evaluation kernel.
+int add_coef_monomial(const Call& c, const Config& cfg)
+{
+    (void)cfg;
+    if (!(c.nf > 0 && c.mass_pre)) return FE_OK;
+    const RefTables* t = c.tables;
+    const CoefTables* ct = nullptr;
+    int rc = get_coef_tables(c.form, c.cell, c.degree, c.qdeg, c.nf, c.stream, &ct);
+    if (rc) return rc;
+    const int r_lo = (c.mass_pre & 1) ? 0 : 1, r_hi = (c.mass_pre & 2) ? n_tables(c.form, c.cell) : 1;
+    hipError_t e = launch_preeval_coef(c.form, c.cell, c.coords, c.coeff, c.out, nullptr, ct->dR, ct->dCombos, c.E,
+                                       t->nb, c.nf, ct->iota, 8, device_cus(), c.stream, r_lo, r_hi, 1);
+    if (e != hipSuccess) return set_hip_error(e, "coefficient pre-evaluated launch");
     return FE_OK;
 }
 
@@ -611,6 +650,8 @@ int check_config(const Call& c, const Config& cfg)
     }
     if (cfg.variant) {
         if (!gram64_eligible(c)) return FE_EINVAL;
+        if (cfg.grid_per_cu < 1) return FE_EINVAL;
+        if (!is_vector_form(c.form)) return gram64_scalar_lds_bytes(c.cell, c.degree) <= max_lds ? FE_OK : FE_EINVAL;
         const int nq = q_invariant(c) ? 1 : t->nq;
         return gram64_lds_bytes(c.form, c.cell, gram64_nqp(nq), t->nq, t->nb) <= max_lds ? FE_OK : FE_EINVAL;
     }

@@ -63,6 +63,25 @@ hipError_t launch_gram64_elasticity(int cell, int p, int nqp, const SplitArgs& a
                                     hipStream_t s);
 hipError_t launch_gram64_hyperelastic(int cell, int p, int nqp, const SplitArgs& a, int grid, size_t lds,
                                       hipStream_t s);
+// assemble_gram64_scalar.hip: float64 matrix-core quadrature of mass and Helmholtz
+struct GramScalarArgs {
+    const double* coords;
+    const double* coeff;        // nf coefficient functions [E][nf][ns]
+    double* out;
+    int* status;
+    const double* W;            // [nq]
+    const double* phi;          // [nq][ns]
+    const double* dphi;         // [nq][ns][d]
+    const double* dpsi_grad;    // [nq][nv][d] (per-point prism geometry)
+    int64_t E;
+    int nq, nf;
+    int skip;                   // bit 0: no value rows, bit 1: no gradient rows
+    int pointgeo;
+    int nt;
+};
+hipError_t launch_gram64_scalar(int form, int cell, int p, const GramScalarArgs& a, int grid, hipStream_t s);
+size_t gram64_scalar_lds_bytes(int cell, int p);
+int gram64_scalar_elems_per_block();
 // prec: 1 = fp32 operands, 2 = bf16 hi/lo split
 inline hipError_t launch_split(int form, int cell, int p, int prec, int nqp, const SplitArgs& a, int grid,
                                size_t lds, hipStream_t s)
@@ -170,6 +189,7 @@ struct Call {
 };
 
 int launch_call(const Call& c, const Config& cfg);
+int add_coef_monomial(const Call& c, const Config& cfg);
 int store_mode();
 // configuration from the autotune cache, else the built-in default
 void lookup_config(const Call& c, Config* cfg);

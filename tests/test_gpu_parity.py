@@ -208,6 +208,7 @@ BAD_SHAPES = [
     ("elasticity", "tetrahedron", 3, "quadrature", dict(kernel=4)),                 # n = 60 > 32
     ("elasticity", "tetrahedron", 2, "quadrature", dict(kernel=2)),                 # a pre-evaluated kernel
     ("helmholtz", "tetrahedron", 2, "preeval", dict(kernel=4)),                     # a quadrature kernel
+    ("helmholtz", "prism", 4, "quadrature", dict(kernel=4)),                        # n = 75 > 48
 ]
 
 
