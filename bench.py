@@ -284,10 +284,12 @@ def _short(name):
 
 def summarize_trace(db_dir, out, title, command, only=""):
     """Per-kernel duration statistics of a --kernel-trace run, one row per
-    (kernel, block, grid, LDS); `only` keeps kernels whose name contains it."""
+    (kernel, block, grid, LDS); `only` (comma-separated) keeps kernels whose
+    name contains one of its parts."""
     cur = _rocpd(db_dir).cursor()
+    parts = only.split(",")
     rows = [r for r in cur.execute("select name, workgroup_x, grid_x, lds_size, duration from kernels").fetchall()
-            if only in r[0]]
+            if any(f in r[0] for f in parts)]
     agg = {}
     for name, wg, grid, lds, dur in rows:
         agg.setdefault((_short(name), wg, grid // max(1, wg), lds), []).append(dur)
