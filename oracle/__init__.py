@@ -69,6 +69,10 @@ def lib():
                                        dp, dp, dp, ctypes.c_int]
         L.orc_hyper_min_jf.restype = ctypes.c_int64
         L.orc_max_threads.restype = ctypes.c_int
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.orc_assemble_spec.argtypes = [ctypes.c_int, ip, ip, ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int64, dp, dp, dp, ctypes.c_int]
+        L.orc_assemble_spec.restype = ctypes.c_int64
         L.orc_assemble_pointgeo.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, dp, dp,
                                             ctypes.c_double, ctypes.c_double, dp, ctypes.c_int]
         L.orc_assemble_pointgeo.restype = ctypes.c_int64
@@ -172,6 +176,37 @@ def assemble(form: str, cell: str, p: int, coords, coeff=None, qdeg=None,
                                  mu, lam, _p(out), nthreads)
     if flagged < 0:
         raise ValueError("oracle rejected arguments")
+    return out, int(flagged)
+
+
+SYMBOLS = {"value": 0, "dx": 1, "dy": 2, "dz": 3}
+
+
+def assemble_spec(terms, cell: str, p: int, coords, fields=None, qdeg=None, nthreads: int = 0):
+    """Element matrices of a generic scalar bilinear form.  terms: list of
+    (test_symbol, trial_symbol, field, scale) with symbols from SYMBOLS (or
+    their integer codes) and field -1 (constant) or the index of a P1 field
+    whose vertex values are fields [E][n_fields][nv].  qdeg defaults to 2p
+    plus one per field-weighted term (exact for affine elements)."""
+    coords = _f64(coords)
+    E = coords.shape[0]
+    ns = nbasis(cell, p)
+    code = lambda s: SYMBOLS[s] if isinstance(s, str) else int(s)  # noqa: E731
+    te = (ctypes.c_int * len(terms))(*[code(t[0]) for t in terms])
+    tr = (ctypes.c_int * len(terms))(*[code(t[1]) for t in terms])
+    fl = (ctypes.c_int * len(terms))(*[int(t[2]) for t in terms])
+    sc = np.array([float(t[3]) for t in terms])
+    nfld = 0 if fields is None else np.asarray(fields).shape[1]
+    if qdeg is None:
+        qdeg = 2 * p + (1 if any(int(t[2]) >= 0 for t in terms) else 0)
+        if cell == "prism" and any(int(t[2]) >= 0 for t in terms):
+            qdeg = 2 * p + 1
+    fd = _f64(fields) if fields is not None else None
+    out = np.empty((E, ns, ns))
+    flagged = lib().orc_assemble_spec(len(terms), te, tr, fl, _p(sc), nfld, CELL[cell], p, qdeg, E, _p(coords),
+                                      _p(fd), _p(out), nthreads)
+    if flagged < 0:
+        raise ValueError("oracle rejected the form")
     return out, int(flagged)
 
 

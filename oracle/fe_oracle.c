@@ -703,6 +703,89 @@ int64_t orc_hyper_min_jf(int cell, int p, int qdeg, int64_t E, const double *coo
 }
 
 /* ------------------------------------------------------------------------
+ * Generic scalar bilinear forms: the integrand is a sum of terms
+ *     scale_t * c_t(x) * s_test_t(phi_j) * s_trial_t(phi_k),
+ * each symbol s being phi itself (0) or a physical derivative d/dx_b (1 + b),
+ * and c_t = 1 (field < 0) or a P1 field interpolated from its vertex values
+ * fields[e][field][v] -- the multilinear operands sharing elimination
+ * (Sec. 3.2, Algorithm 1) works on.  Evaluated as the naive nest of Fig. 1
+ * for Eq. (7): element, point, then every (j, k) pair with every term.
+ * ------------------------------------------------------------------------ */
+int64_t orc_assemble_spec(int n_terms, const int *test, const int *trial, const int *field, const double *scale,
+                          int n_fields, int cell, int p, int qdeg, int64_t E, const double *coords,
+                          const double *fields, double *out, int nthreads)
+{
+    int d = tdim_of(cell), nv = nvert_of(cell);
+    int ns = orc_nbasis(cell, p);
+    int nq = orc_rule_size(cell, qdeg);
+    if (ns < 0 || nq < 0 || n_terms < 0) return -1;
+    for (int t = 0; t < n_terms; ++t)
+        if (test[t] < 0 || test[t] > d || trial[t] < 0 || trial[t] > d || field[t] >= n_fields ||
+            (field[t] >= 0 && !fields))
+            return -1;
+    double *X = (double *)malloc(sizeof(double) * nq * 3);
+    double *W = (double *)malloc(sizeof(double) * nq);
+    double *PHI = (double *)malloc(sizeof(double) * nq * ns);
+    double *DPHI = (double *)malloc(sizeof(double) * nq * ns * 3);
+    double *PSI = (double *)malloc(sizeof(double) * nq * 6);
+    orc_rule(cell, qdeg, X, W);
+    for (int q = 0; q < nq; ++q) {
+        orc_basis(cell, p, X + q * d, PHI + q * ns, DPHI + q * ns * d);
+        p1_basis(cell, X + q * d, PSI + q * 6);
+    }
+    int64_t flagged = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static) reduction(+ : flagged)
+#endif
+    for (int64_t e = 0; e < E; ++e) {
+        double *A = out + (size_t)e * ns * ns;
+        const double *v = coords + (size_t)e * nv * d;
+        double J[9], K[9], detJ;
+        int bad = orc_geometry(cell, v, J, &detJ, K);
+        if (!(detJ != 0.0) || !isfinite(detJ)) bad = 1;
+        for (int k = 0; k < ns * ns; ++k) A[k] = bad ? NAN : 0.0;
+        if (bad) { flagged += 1; continue; }
+        double sym[ORC_MAXNB * 4];
+        for (int q = 0; q < nq; ++q) {
+            const double *phi = PHI + q * ns, *dphi = DPHI + q * ns * d;
+            double dx = W[q] * fabs(detJ);
+            for (int i = 0; i < ns; ++i) {
+                sym[i * 4] = phi[i];
+                for (int b = 0; b < d; ++b) {
+                    double s = 0.0;
+                    for (int a = 0; a < d; ++a) s += K[a * d + b] * dphi[i * d + a];
+                    sym[i * 4 + 1 + b] = s;
+                }
+            }
+            double c[32];
+            for (int t = 0; t < n_terms; ++t) {
+                double ct = scale[t];
+                if (field[t] >= 0) {
+                    double f = 0.0;
+                    for (int l = 0; l < nv; ++l) f += fields[((size_t)e * n_fields + field[t]) * nv + l] * PSI[q * 6 + l];
+                    ct *= f;
+                }
+                c[t] = ct;
+            }
+            for (int j = 0; j < ns; ++j)
+                for (int k = 0; k < ns; ++k) {
+                    double s = 0.0;
+                    for (int t = 0; t < n_terms; ++t)
+#if ORC_MUTANT == 13
+                        s += c[t] * sym[k * 4 + test[t]] * sym[j * 4 + trial[t]];
+#else
+                        s += c[t] * sym[j * 4 + test[t]] * sym[k * 4 + trial[t]];
+#endif
+                    A[j * ns + k] += dx * s;
+                }
+        }
+    }
+    free(X); free(W); free(PHI); free(DPHI); free(PSI);
+    return flagged;
+}
+
+/* ------------------------------------------------------------------------
  * Global assembly (Sec. 2): the global matrix A_ij = a(phi_i, phi_j) of the
  * continuous space is the sum over elements of the element matrices, entry
  * (j, k) of element e added at (dofs[e][j], dofs[e][k]).  The compressed-row

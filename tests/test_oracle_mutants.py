@@ -25,6 +25,7 @@ MUTANTS = {
     10: ("element matrix inserted transposed", "global assembly"),
     11: ("last local column dropped from the insertion", "global assembly"),
     12: ("non-affine prism geometry taken at the centroid for every point", "non-affine geometry"),
+    13: ("test and trial basis indices swapped in a generic term", "generic forms"),
 }
 
 PINS = {
@@ -40,10 +41,12 @@ PINS = {
     10: "pattern_and_insert_brute_force",
     11: "global_quadratic_forms_exact or pattern_and_insert_brute_force",
     12: "zjittered_box_quadratic_forms",
+    13: "spec_constant_terms_exact",
 }
 
 # pins of the global assembly live in their own module
-PIN_FILE = {10: "test_global_pins.py", 11: "test_global_pins.py", 12: "test_nonaffine_pins.py"}
+PIN_FILE = {10: "test_global_pins.py", 11: "test_global_pins.py", 12: "test_nonaffine_pins.py",
+            13: "test_form_spec_pins.py"}
 
 
 @pytest.mark.parametrize("k", sorted(MUTANTS))
