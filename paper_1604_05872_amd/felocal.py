@@ -35,6 +35,7 @@ EXPORTS = (
     "fe_batch_create", "fe_batch_run", "fe_batch_destroy", "fe_batch_info", "fe_autotune",
     "fe_strerror", "fe_release_caches", "fe_version",
     "fe_csr_create", "fe_csr_info", "fe_csr_pattern", "fe_csr_insert", "fe_csr_destroy", "fe_assemble_csr",
+    "fe_sharing_plan", "fe_form_source", "fe_assemble_form",
 )
 
 
@@ -78,6 +79,45 @@ class fe_plan_t(ctypes.Structure):
         ("cost", ctypes.c_double),
         ("mode", ctypes.c_int),
     ]
+
+
+SYMBOLS = {"value": 0, "dx": 1, "dy": 2, "dz": 3}
+MAX_TERMS, MAX_FIELDS = 16, 4
+
+
+class fe_term_t(ctypes.Structure):
+    _fields_ = [("test", ctypes.c_int), ("trial", ctypes.c_int), ("field", ctypes.c_int), ("scale", ctypes.c_double)]
+
+
+class fe_form_spec_t(ctypes.Structure):
+    _fields_ = [("n_terms", ctypes.c_int), ("terms", fe_term_t * MAX_TERMS), ("n_fields", ctypes.c_int)]
+
+
+class fe_sharing_t(ctypes.Structure):
+    _fields_ = [
+        ("n_vertices", ctypes.c_int),
+        ("vertex_side", ctypes.c_int * 8),
+        ("vertex_symbol", ctypes.c_int * 8),
+        ("factorized", ctypes.c_int * 8),
+        ("n_edges", ctypes.c_int),
+        ("edge_test", ctypes.c_int * MAX_TERMS),
+        ("edge_trial", ctypes.c_int * MAX_TERMS),
+        ("edge_owner", ctypes.c_int * MAX_TERMS),
+        ("theta_expanded", ctypes.c_double),
+        ("theta_se", ctypes.c_double),
+    ]
+
+
+def form_spec(terms, n_fields: int = 0) -> fe_form_spec_t:
+    """terms: list of (test_symbol, trial_symbol, field, scale); symbols are
+    names from SYMBOLS or their codes, field -1 for a constant term."""
+    sp = fe_form_spec_t()
+    sp.n_terms = len(terms)
+    sp.n_fields = int(n_fields)
+    code = lambda x: SYMBOLS[x] if isinstance(x, str) else int(x)  # noqa: E731
+    for i, (te, tr, f, sc) in enumerate(terms):
+        sp.terms[i].test, sp.terms[i].trial, sp.terms[i].field, sp.terms[i].scale = code(te), code(tr), int(f), float(sc)
+    return sp
 
 
 class fe_subbatch_t(ctypes.Structure):
@@ -133,6 +173,12 @@ def lib():
         L.fe_csr_pattern.argtypes = [vp, vp, vp, vp]
         L.fe_csr_insert.argtypes = [vp, vp, vp, vp]
         L.fe_csr_destroy.argtypes = [vp]
+        L.fe_sharing_plan.argtypes = [ctypes.POINTER(fe_form_spec_t), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(fe_sharing_t)]
+        L.fe_form_source.argtypes = [ctypes.POINTER(fe_form_spec_t), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_char_p, ctypes.POINTER(ctypes.c_size_t)]
+        L.fe_assemble_form.argtypes = [ctypes.POINTER(fe_form_spec_t), ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                       vp, vp, vp, ctypes.POINTER(fe_options_t)]
         L.fe_assemble_csr.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, vp, vp, vp,
                                       ctypes.POINTER(fe_options_t)]
         _lib = L
@@ -407,6 +453,48 @@ class CsrPattern:
             self.close()
         except Exception:
             pass
+
+
+def fe_sharing_plan(terms, cell: str, degree: int, qdeg: int = -1, n_fields: int = 0) -> dict:
+    """Algorithm 1 (Sec. 3.2) for a generic scalar form: the factorised
+    symbols and operation counts (host only)."""
+    sp = form_spec(terms, n_fields)
+    pl = fe_sharing_t()
+    _check(lib().fe_sharing_plan(ctypes.byref(sp), CELLS[cell], int(degree), int(qdeg), ctypes.byref(pl)),
+           "fe_sharing_plan")
+    nv, ne = pl.n_vertices, pl.n_edges
+    return {
+        "vertices": [(pl.vertex_side[i], pl.vertex_symbol[i]) for i in range(nv)],
+        "factorized": [bool(pl.factorized[i]) for i in range(nv)],
+        "edges": [(pl.edge_test[e], pl.edge_trial[e]) for e in range(ne)],
+        "owner": [pl.edge_owner[e] for e in range(ne)],
+        "theta_expanded": pl.theta_expanded,
+        "theta_se": pl.theta_se,
+    }
+
+
+def fe_form_source(terms, cell: str, degree: int, expanded: bool = False, n_fields: int = 0) -> str:
+    sp = form_spec(terms, n_fields)
+    n = ctypes.c_size_t(0)
+    _check(lib().fe_form_source(ctypes.byref(sp), CELLS[cell], int(degree), int(expanded), None, ctypes.byref(n)),
+           "fe_form_source")
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().fe_form_source(ctypes.byref(sp), CELLS[cell], int(degree), int(expanded), buf, ctypes.byref(n)),
+           "fe_form_source")
+    return buf.value.decode()
+
+
+def fe_assemble_form(terms, cell: str, degree: int, coords, fields, out, n_fields: int = 0, qdeg: int = -1,
+                     expanded: bool = False, stream=None, status=None):
+    """Element matrices of a generic scalar form by the generated kernel."""
+    _f64_dev(coords, "coords")
+    _f64_dev(fields, "fields")
+    _f64_dev(out, "out")
+    sp = form_spec(terms, n_fields)
+    o = make_options(qdeg, stream=stream, status=status, shape={"kernel": 5} if expanded else None)
+    _check(lib().fe_assemble_form(ctypes.byref(sp), CELLS[cell], int(degree), int(coords.shape[0]), _ptr(coords),
+                                  _ptr(fields), _ptr(out), ctypes.byref(o)), "fe_assemble_form")
+    return out
 
 
 def fe_release_caches():
