@@ -13,8 +13,10 @@ graph (one persistent work-queue kernel per kernel variant), and the
 experiment matrix of Sec. 7.1 (mass and Helmholtz, q = 1..4, nf = 0..3
 coefficient functions) with Algorithm 3's choice against both forced modes,
 local plus global assembly (insertion into the compressed-row matrix of
-the continuous space) of the headline form and mesh, and Helmholtz on
-non-affine (z-jittered) prisms with per-point geometry.  Inputs are seeded
+the continuous space) of the headline form and mesh, Helmholtz on
+non-affine (z-jittered) prisms with per-point geometry, and a full-tensor
+diffusion form through automatically sharing-eliminated generated kernels.
+Inputs are seeded
 synthetic meshes resident in HBM before timing.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -111,7 +113,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the built-in default launch shapes instead of the autotuned ones")
     ap.add_argument("--only-headline", action="store_true")
-    ap.add_argument("--workloads", default="mass,elasticity,hyperelastic,batch,sweep,global,nonaffine",
+    ap.add_argument("--workloads", default="mass,elasticity,hyperelastic,batch,sweep,global,nonaffine,forms",
                     help="comma list of the extra workloads to time")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a known-size kernel for the HBM counters)")
@@ -394,7 +396,38 @@ def other_workloads(torch, felocal, inputs, stream, ev, reps, which):
         res.append(global_workload(torch, felocal, inputs, stream, ev, reps))
     if "nonaffine" in which:
         res.append(nonaffine_workload(torch, felocal, inputs, stream, ev, reps))
+    if "forms" in which:
+        res.append(forms_workload(torch, felocal, inputs, stream, ev, reps))
     return res
+
+
+def forms_workload(torch, felocal, inputs, stream, ev, reps):
+    """Automatic sharing elimination (Sec. 3.2, Algorithm 1) on a form no
+    hand-written kernel covers: full-tensor diffusion sum_ab K_ab d_a u d_b v
+    (9 products between 3 test and 3 trial symbols; the ILP factorises the 3
+    test gradients) on 82,944 tetrahedra, P2-P4, with the generated
+    sharing-eliminated nest against the generated expanded nest."""
+    import itertools
+    terms = [(a, b, -1, 1.0 + 0.25 * i) for i, (a, b) in enumerate(itertools.product(("dx", "dy", "dz"), repeat=2))]
+    coords, V, cells, h = inputs.first_elements("tetrahedron", 82944, 46)
+    c = torch.from_numpy(coords).cuda()
+    out = {"workload": "sharing_elimination_full_tensor_tet_83k", "elements": int(c.shape[0]), "per_degree": {}}
+    for p in (2, 3, 4):
+        n = felocal.NBASIS("tetrahedron", p)
+        o = torch.empty((int(c.shape[0]), n, n), dtype=torch.float64, device="cuda")
+        pl = felocal.fe_sharing_plan(terms, "tetrahedron", p)
+        ms = {}
+        for ex in (False, True):
+            ms[ex] = time_launch(torch, lambda: felocal.fe_assemble_form(terms, "tetrahedron", p, c, None, o,
+                                                                         expanded=ex), stream, ev, reps)
+        out["per_degree"][f"P{p}"] = {"factorised_ms": round(ms[False], 4), "expanded_ms": round(ms[True], 4),
+                                      "theta_se": pl["theta_se"], "theta_expanded": pl["theta_expanded"],
+                                      "factorised_symbols": int(sum(pl["factorized"]))}
+        log(f"  sharing elimination P{p}: factorised {ms[False]:.4f} ms, expanded {ms[True]:.4f} ms")
+        del o
+    del c
+    torch.cuda.empty_cache()
+    return out
 
 
 def nonaffine_workload(torch, felocal, inputs, stream, ev, reps):
