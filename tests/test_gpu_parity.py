@@ -305,10 +305,12 @@ def test_coefficient_mixed_plans(cell, p, nf, th):
     E = 300
     coords, *_ = mesh(cell, E, seed=60 + p)
     cf = np.random.default_rng(61).uniform(0.5, 1.5, size=(E, nf, ns))
-    A, st = gpu_assemble("helmholtz", cell, p, coords, cf, nf=nf, th_bytes=th)
     B, fl = oracle.assemble("helmholtz", cell, p, coords, cf, nf=nf)
-    assert st == fl == 0
-    assert normwise(A, B).max() <= TOL["fp64"]
+    # the quadrature part on both quadrature kernels (VALU, matrix core)
+    for kernel in (3, 4):
+        A, st = gpu_assemble("helmholtz", cell, p, coords, cf, nf=nf, th_bytes=th, shape={"kernel": kernel})
+        assert st == fl == 0
+        assert normwise(A, B).max() <= TOL["fp64"]
 
 
 # Indefinite point weights: a Lame field shifted below zero (lambda or mu),
