@@ -10,13 +10,14 @@ namespace fe {
 
 // Geometry of the affine map F_K (Sec. 2.2): J has the edge vectors
 // v_{a+1} - v_0 as columns (prism: v1-v0, v2-v0, v3-v0).  Produces
-// K = J^{-1} (K[a][b] = dX_a/dx_b, the factors of Eq. (7)) and |det J|.
+// K = J^{-1} (K[a][b] = dX_a/dx_b, the factors of Eq. (7)) and |det J|, and
+// optionally det J and J itself (row-major 3x3, zero-padded).
 // Returns nonzero when the map is unusable: |det J| not above
 // 1e-13 * (max |J entry|)^d (degenerate, or NaN input), or a prism whose top
 // face is not the bottom face translated (relative tolerance 1e-12).
 template <int CELL>
 __device__ __forceinline__ int affine_map(const double* __restrict__ v, double (&K)[3][3], double& adet,
-                                          double* det_out = nullptr)
+                                          double* det_out = nullptr, double* J_out = nullptr)
 {
     // every product rounded on its own: the same geometry bit for bit in
     // every kernel that inlines this
@@ -56,6 +57,11 @@ __device__ __forceinline__ int affine_map(const double* __restrict__ v, double (
         K[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
     }
     if (det_out) *det_out = det;
+    if (J_out)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) J_out[r * 3 + a] = (r < D && a < D) ? J[r][a] : 0.0;
     adet = fabs(det);
     double scale = jmax;
 #pragma unroll

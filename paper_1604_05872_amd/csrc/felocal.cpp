@@ -491,9 +491,10 @@ int launch_call(const Call& c, const Config& cfg)
             return FE_OK;
         }
         const int nqp = split_nqp(nq_eff);
-        const int64_t steps = (c.E + SPLIT_WAVES * SPLIT_EB - 1) / (SPLIT_WAVES * SPLIT_EB);
+        const int per_block = SPLIT_WAVES * split_eb(c.form);
+        const int64_t steps = (c.E + per_block - 1) / per_block;
         const int grid = (int)std::min<int64_t>(steps, (int64_t)cus * cfg.grid_per_cu);
-        const size_t lds = split_lds_bytes(c.cell, t->nq, t->nb);
+        const size_t lds = split_lds_bytes(c.form, c.cell, t->nq, t->nb);
         e = launch_split(c.form, c.cell, c.degree, c.prec == FE_SPLIT_FP32 ? SPLIT_FP32 : SPLIT_BF16X3, nqp, a, grid,
                          lds, c.stream);
         if (e != hipSuccess) return set_hip_error(e, "split-precision launch");

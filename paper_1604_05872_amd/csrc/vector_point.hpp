@@ -112,6 +112,48 @@ __device__ __forceinline__ int vector_point_data(const double* __restrict__ in, 
     return bad;
 }
 
+// Hyperelastic point data from the gradient of the deformed map,
+// A = dx/dX + du/dX = J + H.  Since F = A K, J_F = det A / det J and
+// M = K F^{-1} = A^{-1}: the same quantities as vector_point_data without
+// forming F, F^{-1} or K F^{-1}.  Jm is J (row-major, zero-padded), det its
+// determinant.
+template <int CELL, int NS>
+__device__ __forceinline__ int hyper_point_from_gradient(const double* __restrict__ in, const double (&Jm)[9],
+                                                         double det, double adet, int q, const PointTables& t,
+                                                         double& w0, double& w1, double (&M)[3][3])
+{
+    constexpr int D = cell_dim(CELL), NV = cell_nv(CELL), NVD = NV * D;
+    const double w = (t.collapse ? t.wsum : t.W[q]) * adet;
+    const double* ue = in + NVD;
+    double A[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) A[r][c] = Jm[r * 3 + c];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const double* dg = t.dphi + (q * NS + k) * D;
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            const double ur = ue[r * NS + k];
+#pragma unroll
+            for (int c = 0; c < D; ++c) A[r][c] = fma(ur, dg[c], A[r][c]);
+        }
+    }
+    const double da = inverse_small<D>(A, M);
+    const double jf = da / det;
+    const int bad = !(jf > 0.0);
+    const double lnj = log(jf);
+    w0 = w * t.lam;
+    w1 = w * (t.mu - t.lam * lnj);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (r >= D || c >= D) M[r][c] = 0.0;
+    return bad;
+}
+
 // Signed square root: the weighted product sum_q w_q x_q x_q^T is the Gram
 // matrix Z^T diag(sign w) Z of z_q = sqrt|w_q| x_q; the root carries the
 // sign of w.
