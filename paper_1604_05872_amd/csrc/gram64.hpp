@@ -9,10 +9,12 @@
 // x = g (elasticity) or s = F^{-T} g (hyperelastic).  P_lam (t = 0) and P_2
 // (t = 1) are symmetric, so the 16x16 tiles 00, 01 and 11 of the padded
 // 32x32 matrix cover them, one v_mfma_f64_16x16x4_f64 per tile and 4 points.
-// The trace term D[j][k] = sum_b P_g[(b,j),(b,k)] of the hyperelastic form
-// is one 16x16 Gram matrix over the stacked index (q, b):
-//     D = Y^T diag(sign r_2) Y,   Y[(q,b)][j] = |r_2(q)| g_{q,j,b};
-// for elasticity P_g = P_2 and D is read from the P_2 tile.  Then
+// The trace term D[j][k] = sum_q mu'_q g_{q,j} . g_{q,k}: for elasticity
+// (mu varies over the element) it is the block trace of the P_2 tile; for
+// the hyperelastic form mu is a constant, so D is pre-evaluated (Sec. 3.3) as
+//     D[j][k] = mu |det J| sum_{a<=b} (K K^T)_ab S_ab[j][k]
+// from tables S_ab formed once per workgroup (the same split of the form as
+// in split.hpp), all in float64.  Then
 //     A[(c,j),(e,k)] = P_lam[(c,j),(e,k)] + P_2[(e,j),(c,k)] + delta_ce D[j][k].
 //
 // Instruction layout (16x16x4, f64): lane l supplies A[l % 16][l / 16] and
@@ -46,9 +48,11 @@ __host__ __device__ constexpr int g64_off_geo(int form, int nqp)
 {
     return g64_off_m(form, nqp) + (form == HYPERELASTIC ? g64_eb(form) * nqp * 9 * 8 : 0);
 }
+// hyperelastic: trace coefficients mu |det J| (K K^T)_ab [eb][8] f64
+__host__ __device__ constexpr int g64_off_dco(int form, int nqp) { return g64_off_geo(form, nqp) + g64_eb(form) * 10 * 8; }
 __host__ __device__ constexpr int g64_off_flag(int form, int nqp)
 {
-    return g64_off_geo(form, nqp) + g64_eb(form) * 10 * 8;
+    return g64_off_dco(form, nqp) + (form == HYPERELASTIC ? g64_eb(form) * 8 * 8 : 0);
 }
 __host__ __device__ constexpr int g64_off_t(int form, int nqp) { return g64_off_flag(form, nqp) + 16; }
 __host__ __device__ constexpr int g64_off_d(int form, int nqp) { return g64_off_t(form, nqp) + 32 * G64_TLD * 8; }
@@ -56,11 +60,13 @@ __host__ __device__ constexpr int g64_wave_bytes(int form, int nqp)
 {
     return g64_off_d(form, nqp) + (form == HYPERELASTIC ? 16 * 17 * 8 : 0);
 }
-// block LDS: the wave areas, then W [nq], psi [nq][nv], dphi [nq][ns][d] (f64)
+// block LDS: the wave areas, then W [nq], psi [nq][nv] (elasticity), dphi
+// [nq][ns][d] and (hyperelastic) the trace tables [ntr][ns][ns], all f64
 __host__ __device__ constexpr size_t gram64_lds_bytes(int form, int cell, int nqp, int nq, int ns)
 {
     return (size_t)G64_WAVES * g64_wave_bytes(form, nqp) +
-           ((size_t)nq + (size_t)nq * cell_nv(cell) + (size_t)nq * ns * cell_dim(cell)) * 8;
+           ((size_t)nq + (form == HYPERELASTIC ? 0 : (size_t)nq * cell_nv(cell)) + (size_t)nq * ns * cell_dim(cell) +
+            (size_t)split_trace_tables(form, cell) * ns * ns) * 8;
 }
 
 template <int FORM, int CELL, int P, int NQP>
@@ -83,15 +89,19 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
     double* sRw = (double*)(wl + g64_off_rw(FORM));
     double* sM = (double*)(wl + g64_off_m(FORM, NQP));
     double* sGeo = (double*)(wl + g64_off_geo(FORM, NQP));
+    double* sDco = (double*)(wl + g64_off_dco(FORM, NQP));
+    constexpr int NTR = split_trace_tables(FORM, CELL);
     int* sFlag = (int*)(wl + g64_off_flag(FORM, NQP));
     double* sT = (double*)(wl + g64_off_t(FORM, NQP));
     double* sD = (double*)(wl + g64_off_d(FORM, NQP));
     double* gW = (double*)(lds + G64_WAVES * g64_wave_bytes(FORM, NQP));
     double* gPsi = gW + nq_all;
-    double* gTab = gPsi + nq_all * NV;
+    double* gTab = gPsi + (HYP ? 0 : nq_all * NV);   // the hyperelastic form has no Lame field
+    double* gTr = gTab + nq_all * ns * D;             // [NTR][ns][ns]
 
     for (int i = tid; i < nq_all; i += blockDim.x) gW[i] = a.W[i];
-    for (int i = tid; i < nq_all * NV; i += blockDim.x) gPsi[i] = a.psi[i];
+    if (!HYP)
+        for (int i = tid; i < nq_all * NV; i += blockDim.x) gPsi[i] = a.psi[i];
     for (int i = tid; i < nq_all * ns * D; i += blockDim.x) gTab[i] = a.dphi[i];
     // padding points q >= nq carry zero weights and zero matrices
     for (int i = lane; i < EB * NQP * 3; i += 64)
@@ -103,6 +113,23 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
     for (int q = 0; q < nq_all; ++q) wsum += a.W[q];
     const PointTables pt{gW, gPsi, gTab, nq_all, a.collapse, wsum, a.mu, a.lam};
     __syncthreads();
+    if (NTR > 0) {
+        // trace tables S_ab over the whole rule (pairs a <= b in row order)
+        for (int i = tid; i < NTR * ns * ns; i += blockDim.x) {
+            const int r = i / (ns * ns), jk = i - r * ns * ns, j = jk / ns, k = jk - j * ns;
+            const int ta = D == 3 ? (r < 3 ? 0 : r < 5 ? 1 : 2) : (r < 2 ? 0 : 1);
+            const int tb = D == 3 ? (r < 3 ? r : r < 5 ? r - 2 : 2) : (r < 2 ? r : 1);
+            double x = 0.0;
+            for (int q = 0; q < nq_all; ++q) {
+                const double* gq = gTab + q * ns * D;
+                double t = gq[j * D + ta] * gq[k * D + tb];
+                if (ta != tb) t += gq[j * D + tb] * gq[k * D + ta];
+                x = fma(gW[q], t, x);
+            }
+            gTr[i] = x;
+        }
+        __syncthreads();
+    }
 
     const int64_t stride = (int64_t)gridDim.x * G64_WAVES * EB;
     constexpr int nbatch_in = EB * nin;
@@ -130,7 +157,6 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
         ccol[h] = col < n ? col / ns : 0;     // columns >= n feed entries that are never stored
         jcol[h] = col < n ? col - (col / ns) * ns : 0;
     }
-    const int jd = i16 < ns ? i16 : 0;        // column of the trace Gram matrix
 
     for (; b0 < a.E; b0 += stride) {
         // --- A: inputs of this batch to LDS; loads of the next batch ----------
@@ -155,6 +181,18 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) sGeo[lane * 10 + r * 3 + c] = (r < D && c < D) ? K[r][c] : 0.0;
             sGeo[lane * 10 + 9] = adet;
+            if (HYP) {
+                const double sc = a.mu * adet;
+#pragma unroll
+                for (int r = 0; r < NTR; ++r) {
+                    const int ta = D == 3 ? (r < 3 ? 0 : r < 5 ? 1 : 2) : (r < 2 ? 0 : 1);
+                    const int tb = D == 3 ? (r < 3 ? r : r < 5 ? r - 2 : 2) : (r < 2 ? r : 1);
+                    double g = 0.0;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) g = fma(K[ta][c], K[tb][c], g);
+                    sDco[lane * 8 + r] = sc * g;
+                }
+            }
             if (bad) sFlag[lane] = 1;
         }
         wave_sync();
@@ -170,12 +208,12 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) K[r][c] = sGeo[ib * 10 + r * 3 + c];
             double w0, w1, w2, M[3][3];
-            const int bad = vector_point_data<FORM, CELL, ns>(sIn + ib * SPLIT_MAX_IN, K, sGeo[ib * 10 + 9], q, pt,
+            const int bad = vector_point_data<FORM, CELL, ns>(sIn + ib * SPLIT_MAX_IN + NVD, K, sGeo[ib * 10 + 9], q, pt,
                                                               w0, w1, w2, M);
             double* rw = sRw + (ib * NQP + q) * 3;
             rw[0] = signed_root(w0);
             rw[1] = signed_root(w1);
-            rw[2] = signed_root(w2);
+            (void)w2;
             if (HYP) {
                 double* mt = sM + (ib * NQP + q) * 9;     // [c][a] = M[a][c]
 #pragma unroll
@@ -201,7 +239,7 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
 #pragma unroll
                 for (int b = 0; b < 3; ++b) kc[h][b] = ge[b * 3 + ccol[h]];
 
-            v4d aL[3], a2[3], aD[4];
+            v4d aL[3], a2[3];
 #pragma unroll
             for (int t = 0; t < 3; ++t)
 #pragma unroll
@@ -209,10 +247,6 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
                     aL[t][r] = 0.0;
                     a2[t][r] = 0.0;
                 }
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) aD[t][r] = 0.0;
 
             // column value x_q[(c,j)] of the operand
             auto colx = [&](int q, int h) -> double {
@@ -248,33 +282,6 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
                     a2[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(m1, r1 * x1, a2[2], 0, 0, 0);
                 }
             }
-            if (HYP) {
-                // D = Y^T diag(sign r_2) Y over the stacked (point, component)
-                // index, on four independent accumulators
-                const int nrow = nq * D;
-                constexpr int NKD = (NQP * D + 15) / 16;
-#pragma unroll 1
-                for (int kd = 0; kd < NKD; ++kd) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int rr = 16 * kd + 4 * u + kq;
-                        const int q = rr / D, b = rr - (rr / D) * D;
-                        double y = 0.0, r2 = 0.0;
-                        if (rr < nrow) {
-                            const double* gh = gTab + (q * ns + jd) * D;
-                            double g = ge[0 * 3 + b] * gh[0];
-#pragma unroll
-                            for (int c = 1; c < D; ++c) g = fma(ge[c * 3 + b], gh[c], g);
-                            r2 = rwe[q * 3 + 2];
-                            y = fabs(r2) * g;
-                        }
-                        aD[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(y, r2 < 0.0 ? -y : y, aD[u], 0, 0, 0);
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) aD[0][r] += aD[1][r] + aD[2][r] + aD[3][r];
-            }
-
             // --- epilogue -----------------------------------------------------
             // P_2 (both triangles) and D to LDS; each lane then combines and
             // stores the entries its P_lam tiles hold (rows of 16 consecutive
@@ -289,9 +296,20 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
                     if (I != J) sT[col * G64_TLD + row] = a2[t][r];
                 }
             }
-            if (HYP)
+            if (HYP) {
+                // pre-evaluated trace term, entries e = lane + 64 s
+                const double* dco = sDco + ib * 8;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) sD[(kq + 4 * r) * 17 + i16] = aD[0][r];
+                for (int s2 = 0; s2 < (ns * ns + 63) / 64; ++s2) {
+                    const int ee = lane + 64 * s2;
+                    if (ee < ns * ns) {
+                        double dv = 0.0;
+#pragma unroll
+                        for (int t = 0; t < NTR; ++t) dv = fma(dco[t], gTr[t * ns * ns + ee], dv);
+                        sD[(ee / ns) * 17 + ee % ns] = dv;
+                    }
+                }
+            }
             wave_sync();
             const bool bad = sFlag[ib] != 0;
             const double nanv = __builtin_nan("");

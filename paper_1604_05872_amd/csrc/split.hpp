@@ -38,17 +38,18 @@
 // Each wavefront owns its LDS area and walks its own elements; no block-wide
 // barrier is taken after the tables are staged, so wavefronts of a block
 // overlap their VALU, matrix-core and store phases.  Per element:
-//   A. (once per batch of EB elements) the batch's coordinates and
-//      coefficients, loaded into registers during the previous batch, go to
-//      LDS, and the loads of the next batch are issued, so one global round
-//      trip is hidden behind a whole batch;
-//   B. one lane per (element, quadrature point) of the batch computes the
-//      float64 point data for the whole batch;
+//   A. (once per batch of EB elements) the batch's inputs are already in
+//      LDS: they were loaded into registers two batches ahead and staged
+//      right after the previous batch's point phase;
+//   B. one lane per (element, quadrature point) of the batch maps its element
+//      and computes the float64 point data for the whole batch; then the next
+//      batch's inputs go to LDS and the loads of the one after are issued;
 //   C. every lane builds exactly the operand entries the instruction layout
 //      assigns to it (column (c,j) = lane % 32) and runs the MFMAs;
 //   D. the block-transposed and trace terms are exchanged through LDS and the
 //      element matrix is stored row by row.
 #pragma once
+#include <type_traits>
 #include "device_common.hpp"
 #include "vector_point.hpp"
 
@@ -92,7 +93,7 @@ __host__ __device__ constexpr int split_trace_tables(int form, int cell)
 
 // per-wave LDS (bytes), for a batch of eb elements
 struct SplitLayout {
-    int in;     // inputs [eb][48] f64
+    int in;     // inputs: coordinates [eb][nv d], then coefficients [eb][ncf] (f64, at most eb x 48)
     int w;      // signed weight roots [eb][32][2] f32
     int m;      // M^T [eb][32][3][3] f32
     int flag;   // flags [eb] (+pad)
@@ -208,34 +209,40 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
         __syncthreads();
     }
 
-    // the lane's entries e = lane + 64 s of the trace tables, held in registers
-    constexpr int S2 = (ns * ns + 63) / 64;
-    float trR[S2][NTR > 0 ? NTR : 1];
-#pragma unroll
-    for (int s2 = 0; s2 < S2; ++s2)
-#pragma unroll
-        for (int t = 0; t < NTR; ++t) {
-            const int e = lane + 64 * s2;
-            trR[s2][t] = e < ns * ns ? gTr[t * ns * ns + e] : 0.f;
-        }
+    constexpr int S2 = (ns * ns + 63) / 64;   // trace entries per lane: e = lane + 64 s
 
     const int64_t stride = (int64_t)gridDim.x * SPLIT_WAVES * EB;
     constexpr int nbatch_in = EB * nin;
-    constexpr int NPRE = (EB * SPLIT_MAX_IN + 63) / 64;   // prefetch registers per lane
+    constexpr int NPRE = (nbatch_in + 63) / 64;   // prefetch registers per lane
+    // a batch's inputs are two contiguous ranges: coordinates [EB][NVD], then
+    // coefficients [EB][ncf]; sBuf keeps that layout
     double pre[NPRE];
     auto fetch = [&](int64_t first) {
 #pragma unroll
         for (int k = 0; k < NPRE; ++k) {
             const int t = lane + 64 * k;
-            const int i = t / nin, x = t - (t / nin) * nin;
-            const int64_t ee = first + i;
             pre[k] = 0.0;
-            if (t < nbatch_in && ee < a.E)
-                pre[k] = x < NVD ? a.coords[ee * NVD + x] : a.coeff[ee * ncf + (x - NVD)];
+            if (t < EB * NVD) {
+                if (first * NVD + t < a.E * NVD) pre[k] = a.coords[first * NVD + t];
+            } else if (t < nbatch_in) {
+                if (first * ncf + (t - EB * NVD) < a.E * ncf) pre[k] = a.coeff[first * ncf + (t - EB * NVD)];
+            }
         }
     };
     int64_t b0 = ((int64_t)blockIdx.x * SPLIT_WAVES + wave) * EB;
+    // inputs of a batch go to LDS right after the previous batch's point
+    // phase (the only reader of sBuf), so the wait for their loads never
+    // also waits for the output stores of the batch before
+    auto stage = [&]() {
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k) {
+            const int t = lane + 64 * k;
+            if (t < nbatch_in) sBuf[t] = pre[k];
+        }
+    };
     fetch(b0);
+    stage();
+    fetch(b0 + stride);
 
     const int col = lane & 31, half = lane >> 5;
     // columns >= n only feed rows/columns of the 32x32 tile that are never
@@ -246,17 +253,8 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
     static_assert(n <= 32 && nin <= SPLIT_MAX_IN, "element matrix must fit one 32x32 tile");
 
     for (; b0 < a.E; b0 += stride) {
-        // --- A: this batch's inputs to LDS; loads of the next batch ----------
-#pragma unroll
-        for (int k = 0; k < NPRE; ++k) {
-            const int t = lane + 64 * k;
-            if (t < nbatch_in) {
-                const int i = t / nin;
-                sBuf[i * SPLIT_MAX_IN + (t - i * nin)] = pre[k];
-            }
-        }
+        // --- A: flags of this batch (its inputs are in LDS) --------------------
         if (lane < EB) sFlag[lane] = 0;
-        fetch(b0 + stride);
         wave_sync();
 
         // --- B: float64 point data, one lane per (element, point); every lane
@@ -265,8 +263,10 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
         for (int t = lane; t < EB * nq; t += 64) {
             const int ib = t / nq, q = t - ib * nq;
             if (b0 + ib >= a.E) continue;
+            const double* xe = sBuf + ib * NVD;                 // coordinates
+            const double* ce = sBuf + EB * NVD + ib * ncf;      // coefficients
             double K[3][3], adet, det, Jm[9];
-            const int bad_geo = affine_map<CELL>(sBuf + ib * SPLIT_MAX_IN, K, adet, &det, Jm);
+            const int bad_geo = affine_map<CELL>(xe, K, adet, &det, Jm);
 #pragma unroll
             for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -275,10 +275,10 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
             double w0, w1, M[3][3];
             int bad;
             if (HYP) {
-                bad = hyper_point_from_gradient<CELL, ns>(sBuf + ib * SPLIT_MAX_IN, Jm, det, adet, q, pt, w0, w1, M);
+                bad = hyper_point_from_gradient<CELL, ns>(ce, Jm, det, adet, q, pt, w0, w1, M);
             } else {
                 double w2;
-                bad = vector_point_data<FORM, CELL, ns>(sBuf + ib * SPLIT_MAX_IN, K, adet, q, pt, w0, w1, w2, M);
+                bad = vector_point_data<FORM, CELL, ns>(ce, K, adet, q, pt, w0, w1, w2, M);
             }
             // signed square roots of the two product weights (the operands
             // are fp32, so the root is taken in fp32); bit t + 1 of the
@@ -309,6 +309,9 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
             }
         }
         wave_sync();
+        // the next batch's inputs (loaded during this batch's point phase)
+        stage();
+        fetch(b0 + 2 * stride);
 
         // --- C, D: per element of the batch ------------------------------------
 #pragma unroll 1
@@ -345,7 +348,9 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                 // r_t of the weights, z = |r_t| x enters as the A operand and
                 // sign(r_t) z as the B operand (an exact sign-bit flip); z is
                 // split into bf16 hi + lo and hi*hi + hi*lo + lo*hi accumulated
-                auto product = [&](const float* x, int q0, int t, v16f acc) -> v16f {
+                // SG: the product's weights may be negative (a branch on the
+                // element's flag word, taken once per element)
+                auto product = [&](auto sg, const float* x, int q0, int t, v16f acc) -> v16f {
                     typedef float v2f __attribute__((ext_vector_type(2)));
                     typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
                     vu hu, lu;
@@ -361,7 +366,7 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                         lu[i] = __builtin_bit_cast(unsigned, __builtin_convertvector((v2f){z0 - h0, z1 - h1}, v2bf));
                     }
                     const vbf h = __builtin_bit_cast(vbf, hu), l = __builtin_bit_cast(vbf, lu);
-                    if (negw & (2 << t)) {   // uniform over the wavefront (one element)
+                    if constexpr (decltype(sg)::value) {
                         vu sm;
 #pragma unroll
                         for (int i = 0; i < KW / 2; ++i)
@@ -371,23 +376,35 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                         acc = mma(l, hb, acc);
                         acc = mma(h, lb, acc);
                         return mma(h, hb, acc);
+                    } else {
+                        acc = mma(l, h, acc);
+                        acc = mma(h, l, acc);
+                        return mma(h, h, acc);
                     }
-                    acc = mma(l, h, acc);
-                    acc = mma(h, l, acc);
-                    return mma(h, h, acc);
                 };
-                const v16f zero = {};
-                accL = zero;
-                acc2 = zero;
+                // both point blocks' columns first, then the products, with no
+                // branch in between
+                auto run = [&](auto s0, auto s1) {
+                    constexpr int NKB = NQP / (2 * KW);
+                    float x[NKB][KW];
 #pragma unroll
-                for (int kb = 0; kb < NQP / (2 * KW); ++kb) {
-                    const int q0 = 2 * KW * kb + KW * half;
-                    float x[KW];
+                    for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
-                    for (int i = 0; i < KW; ++i) x[i] = colx(q0 + i);
-                    accL = product(x, q0, 0, accL);
-                    acc2 = product(x, q0, 1, acc2);
-                }
+                        for (int i = 0; i < KW; ++i) x[kb][i] = colx(2 * KW * kb + KW * half + i);
+                    const v16f zero = {};
+                    accL = zero;
+                    acc2 = zero;
+#pragma unroll
+                    for (int kb = 0; kb < NKB; ++kb) {
+                        const int q0 = 2 * KW * kb + KW * half;
+                        accL = product(s0, x[kb], q0, 0, accL);
+                        acc2 = product(s1, x[kb], q0, 1, acc2);
+                    }
+                };
+                typedef std::integral_constant<bool, true> Neg;
+                typedef std::integral_constant<bool, false> Pos;
+                if (negw & 6) run(Neg(), Neg());
+                else run(Pos(), Pos());
             } else {
                 const v16f zero = {};
                 accL = zero;
@@ -420,7 +437,7 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                     if (ee < ns * ns) {
                         float dv = 0.f;
 #pragma unroll
-                        for (int t = 0; t < NTR; ++t) dv = fmaf(dco[t], trR[s2][t], dv);
+                        for (int t = 0; t < NTR; ++t) dv = fmaf(dco[t], gTr[t * ns * ns + ee], dv);
                         sDtr[(ee / ns) * 16 + ee % ns] = dv;
                     }
                 }

@@ -28,18 +28,18 @@ struct PointTables {
     double mu, lam;       // hyperelastic constants
 };
 
-// in: the element's coordinates followed by its coefficients (Lame nodal
-// values [2][nv], or displacement DOFs [d][ns]).  Returns nonzero when the
-// element must be flagged.
+// coef: the element's coefficients (Lame nodal values [2][nv], or
+// displacement DOFs [d][ns]).  Returns nonzero when the element must be
+// flagged.
 template <int FORM, int CELL, int NS>
-__device__ __forceinline__ int vector_point_data(const double* __restrict__ in, const double (&K)[3][3], double adet,
+__device__ __forceinline__ int vector_point_data(const double* __restrict__ coef, const double (&K)[3][3], double adet,
                                                  int q, const PointTables& t, double& w0, double& w1, double& w2,
                                                  double (&M)[3][3])
 {
-    constexpr int D = cell_dim(CELL), NV = cell_nv(CELL), NVD = NV * D;
+    constexpr int D = cell_dim(CELL), NV = cell_nv(CELL);
     const double w = (t.collapse ? t.wsum : t.W[q]) * adet;
     if (FORM != HYPERELASTIC) {
-        const double* ce = in + NVD;
+        const double* ce = coef;
         double lam = 0.0, mu = 0.0;
         if (t.collapse) {
             for (int qq = 0; qq < t.nq; ++qq) {
@@ -71,7 +71,7 @@ __device__ __forceinline__ int vector_point_data(const double* __restrict__ in, 
         return 0;
     }
     // H = sum_k u_k (x) grad_X phi_k ; F = I + H K
-    const double* ue = in + NVD;
+    const double* ue = coef;
     double H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
@@ -115,16 +115,15 @@ __device__ __forceinline__ int vector_point_data(const double* __restrict__ in, 
 // Hyperelastic point data from the gradient of the deformed map,
 // A = dx/dX + du/dX = J + H.  Since F = A K, J_F = det A / det J and
 // M = K F^{-1} = A^{-1}: the same quantities as vector_point_data without
-// forming F, F^{-1} or K F^{-1}.  Jm is J (row-major, zero-padded), det its
-// determinant.
+// forming F, F^{-1} or K F^{-1}.  ue: displacement DOFs [d][ns]; Jm is J
+// (row-major, zero-padded), det its determinant.
 template <int CELL, int NS>
-__device__ __forceinline__ int hyper_point_from_gradient(const double* __restrict__ in, const double (&Jm)[9],
+__device__ __forceinline__ int hyper_point_from_gradient(const double* __restrict__ ue, const double (&Jm)[9],
                                                          double det, double adet, int q, const PointTables& t,
                                                          double& w0, double& w1, double (&M)[3][3])
 {
-    constexpr int D = cell_dim(CELL), NV = cell_nv(CELL), NVD = NV * D;
+    constexpr int D = cell_dim(CELL);
     const double w = (t.collapse ? t.wsum : t.W[q]) * adet;
-    const double* ue = in + NVD;
     double A[3][3];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
