@@ -97,6 +97,10 @@ def alg_flops(form, cell, p, collapsed=True):
     nq = rule_size(cell, default_qdeg(form, cell, p))
     nqi = 1 if (collapsed and p == 1 and cell != "prism") else nq   # q-invariant P1 gradients
     inner = nqi * ns * ns * (4 * d * d + 3 * d)
+    if form == "hyperelastic" and nqi > 1:
+        # the plan pre-evaluates the trace monomial mu |det J| g_j . g_k:
+        # rho = d(d+1)/2 tables per pair, then d diagonal-block additions
+        inner = nqi * ns * ns * 4 * d * d + ns * ns * (d * (d + 1) + d)
     if form == "elasticity":
         return inner + nq * (ns * d * (2 * d - 1) + 4 * NV[cell] + 4) + geo
     return inner + nq * (2 * ns * d * (2 * d - 1) + 2 * d * d * ns + 60) + geo

@@ -236,7 +236,10 @@ typedef struct {
  * pre-evaluate only some monomials (Fig. 5): mode is then
  * FE_MODE_QUADRATURE and, with nf = 0, the quadrature kernel adds the
  * pre-evaluated monomials' tables; with nf > 0 such a mixed plan is executed
- * in quadrature mode.
+ * in quadrature mode.  The hyperelastic form has two monomials: the terms in
+ * F (never pre-evaluable) and the trace term mu |det J| g_j . g_k (constant
+ * coefficient); its matrix-core kernels (split precisions, float64 shape
+ * kernel 1) pre-evaluate the trace term, the VALU kernel integrates both.
  * Errors: FE_EINVAL. */
 int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int qdeg, size_t th_bytes,
             fe_plan_t* plan);

@@ -99,12 +99,24 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int q
         legal[0] = legal[1] = false;   // no pre-evaluated kernel for vector forms
         break;
     default:
-        nm = 1;   // non-polynomial sigma: pre-evaluation is not legal
-        plan->theta_se[0] = nq * pairs * (4.0 * d * d + 3.0 * d);
+        // hyperelastic tangent: the terms in F (lambda' s_j,c s_k,e and
+        // alpha' s_j,e s_k,c, 2 d^2 entries of two operations each per pair
+        // and point) have a non-polynomial coefficient, so pre-evaluation is
+        // not legal for them; the trace term mu |det J| g_j . g_k has a
+        // constant coefficient (g_j . g_k: d products, d - 1 sums, then d
+        // diagonal-block additions)
+        nm = 2;
+        plan->theta_se[0] = nq * pairs * 4.0 * d * d;
         plan->iota[0] = 0;
         plan->rho[0] = 0;
         plan->table_bytes[0] = 0;
         legal[0] = false;
+        plan->theta_se[1] = nq * pairs * 3.0 * d;
+        plan->iota[1] = 1;
+        plan->rho[1] = d * (d + 1) / 2;   // tables S_ab, a <= b
+        plan->table_bytes[1] = (size_t)plan->rho[1] * tbl;
+        table_set[1] = 2;
+        legal[1] = true;
         break;
     }
     // with coefficient functions the pre-evaluated kernel keeps a 16-element
@@ -122,7 +134,11 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int q
     const double entries = is_vector_form(form) ? pairs * d * d : pairs;
     for (int m = 0; m < nm; ++m)
         plan->theta_pre[m] = plan->iota[m] > 0 ? 2.0 * plan->rho[m] * plan->iota[m] * entries : inf;
-    if (form == FE_HYPERELASTIC) plan->theta_pre[0] = inf;
+    if (form == FE_HYPERELASTIC) {
+        plan->theta_pre[0] = inf;
+        // the trace matrix is n_s x n_s, then added to the d diagonal blocks
+        plan->theta_pre[1] = (2.0 * plan->rho[1] + d) * pairs;
+    }
     plan->n_monomials = nm;
     plan->th_bytes = th_bytes;
 

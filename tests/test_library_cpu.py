@@ -99,6 +99,14 @@ def test_planner_decisions(cell, p):
         assert all(tp > ts for tp, ts in zip(pe["theta_pre"], pe["theta_se"]))
     phy = felocal.fe_plan("hyperelastic", cell, p, th_bytes=big)
     assert phy["mode"] == "quadrature" and math.isinf(phy["theta_pre"][0])
+    # the trace monomial (constant coefficient) is pre-evaluated: with at least
+    # two points its (2 rho + d) ops per pair beat nq * 3d
+    d, ns = (2 if cell == "triangle" else 3), oracle.nbasis(cell, p)
+    nq = oracle.rule(cell, oracle.default_qdeg("hyperelastic", cell, p))[1].size
+    assert phy["n_monomials"] == 2 and phy["preevaluated"] == [False, nq * 3 * d > d * (d + 1) + d]
+    assert phy["rho"][1] == d * (d + 1) // 2 and phy["iota"][1] == 1
+    assert phy["theta_se"][0] + phy["theta_se"][1] == nq * ns * ns * (4 * d * d + 3 * d)
+    assert phy["table_bytes"][1] == d * (d + 1) // 2 * ns * ns * 8
 
 
 def test_planner_memory_threshold():
