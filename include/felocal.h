@@ -103,8 +103,12 @@ enum {
  *                core Gram kernel (vector forms with n <= 32, n_s <= 16 and
  *                at most 32 points, the only kernel of the split
  *                precisions; mass and Helmholtz with n <= 48 except a mixed
- *                plan without coefficient functions).  A kernel that does
- *                not serve the call's mode and precision is rejected.
+ *                plan without coefficient functions), 5 = the hoisted
+ *                degree-1 kernel (elasticity and hyperelastic at degree 1 on
+ *                triangles and tetrahedra, float64: every gradient is
+ *                constant, one record per element, rows stored whole; the
+ *                default there).  A kernel that does not serve the call's
+ *                mode and precision is rejected.
  *   block        threads of the pre-evaluated kernels (multiple of 64, <= 512)
  *   epi          pre-evaluated: elements per step (1 <= epi <= block)
  *   chunk        pre-evaluated: elements per tile or visit, a multiple of

@@ -51,14 +51,6 @@ __global__ void k_csr_geometry(int64_t E, const double* __restrict__ coords, dou
     for (int r = 0; r < GEO_STRIDE; ++r) geo[e * GEO_STRIDE + r] = r < NT ? c[r] : 0.0;
 }
 
-// Orders one wavefront's LDS accesses across the barrier for the compiler;
-// LDS operations of a wavefront are performed in issue order.
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Workgroups of `waves` independent wavefronts that share the tables in LDS.
 // Wavefront w of workgroup b takes visits of VISIT_ROWS rows, W lanes per

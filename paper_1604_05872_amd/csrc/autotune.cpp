@@ -66,6 +66,15 @@ Config default_for(const Call& c)
     // forms it wins where its tiles are well filled (measured on MI355X over
     // every cell, degree and nf = 0..2): mass from n = 10, Helmholtz (four
     // rows per point) with three tiles or one nearly full tile.
+    if (vec_p1_eligible(c)) {
+        // degree 1 on a simplex: the hoisted streaming kernel; two resident
+        // blocks per CU measured fastest on MI355X (the grid's store window
+        // stays small)
+        Config x;
+        x.variant = 2;
+        x.grid_per_cu = 2;
+        return x;
+    }
     bool gram = gram64_eligible(c) && !q_invariant(c);
     if (gram && !is_vector_form(c.form)) {
         const int ns = c.tables->nb;
@@ -138,6 +147,13 @@ std::vector<Config> candidates(const Call& c)
         if (out.empty()) out.push_back(base);
         return out;
     }
+    if (vec_p1_eligible(c))
+        for (int g : {2, 4, 8}) {
+            Config x;
+            x.variant = 2;
+            x.grid_per_cu = g;
+            out.push_back(x);
+        }
     if (gram64_eligible(c))
         for (int g : {2, 4, 8}) {
             Config x;
@@ -247,7 +263,7 @@ extern "C" int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n
         best_shape->kernel = c.prec != FE_FP64                  ? 4
                              : c.mode == FE_MODE_PREEVAL && c.nf ? 0   // a single kernel
                              : c.mode == FE_MODE_PREEVAL         ? (best_cfg.variant ? 2 : 1)
-                                                                 : (best_cfg.variant ? 4 : 3);
+                                                                 : (best_cfg.variant == 2 ? 5 : best_cfg.variant ? 4 : 3);
         best_shape->block = best_cfg.block;
         best_shape->epi = best_cfg.epi;
         best_shape->chunk = best_cfg.chunk;

@@ -132,6 +132,15 @@ __device__ __forceinline__ double inverse_small(const double (&F)[3][3], double 
     return det;
 }
 
+// LDS ordering between the lanes of one wavefront (for an LDS area that
+// only this wavefront uses)
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Output store.  nt = 1 marks the store non-temporal (streaming); nt = 0 is an
 // ordinary store, which lets L2 merge the partial lines that scattered row
 // segments produce before they reach HBM.

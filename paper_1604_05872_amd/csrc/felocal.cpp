@@ -435,6 +435,13 @@ bool q_invariant(const Call& c)
     return is_vector_form(c.form) && c.degree == 1 && c.cell != PRISM;
 }
 
+// the hoisted degree-1 kernel: float64 quadrature mode, vector forms on
+// simplices
+bool vec_p1_eligible(const Call& c)
+{
+    return c.prec == FE_FP64 && c.mode == FE_MODE_QUADRATURE && q_invariant(c) && !c.pointgeo;
+}
+
 bool gram64_eligible(const Call& c)
 {
     if (!is_vector_form(c.form)) {
@@ -461,7 +468,29 @@ int launch_call(const Call& c, const Config& cfg)
     const RefTables* t = c.tables;
     const int cus = device_cus();
     hipError_t e;
-    if (c.prec != FE_FP64 || (c.mode == FE_MODE_QUADRATURE && cfg.variant && is_vector_form(c.form))) {
+    if (c.prec == FE_FP64 && c.mode == FE_MODE_QUADRATURE && cfg.variant == 2) {
+        // degree 1 on a simplex: the hoisted streaming kernel
+        if (!vec_p1_eligible(c)) return FE_EINVAL;
+        VecP1Args v;
+        v.coords = c.coords;
+        v.coeff = c.coeff;
+        v.out = c.out;
+        v.status = c.status;
+        v.W = t->dW;
+        v.psi = t->dpsi;
+        v.dphi = t->ddphi;
+        v.E = c.E;
+        v.nq = t->nq;
+        v.nt = store_mode();
+        v.mu = c.mu;
+        v.lam = c.lam;
+        const int64_t tiles = (c.E + vec_p1_elems_per_block() - 1) / vec_p1_elems_per_block();
+        const int grid = (int)std::min<int64_t>(tiles, (int64_t)cus * cfg.grid_per_cu);
+        e = launch_vec_p1(c.form, c.cell, v, grid, c.stream);
+        if (e != hipSuccess) return set_hip_error(e, "degree-1 vector launch");
+        return FE_OK;
+    }
+    if (c.prec != FE_FP64 || (c.mode == FE_MODE_QUADRATURE && cfg.variant == 1 && is_vector_form(c.form))) {
         SplitArgs a;
         a.coords = c.coords;
         a.coeff = c.coeff;
@@ -534,7 +563,7 @@ int launch_call(const Call& c, const Config& cfg)
         if (e != hipSuccess) return set_hip_error(e, "pre-evaluated launch");
         return FE_OK;
     }
-    if (cfg.variant) {
+    if (cfg.variant == 1) {
         // mass and Helmholtz on the float64 matrix cores
         if (!gram64_eligible(c)) return FE_EINVAL;
         GramScalarArgs g;
@@ -649,6 +678,8 @@ int check_config(const Call& c, const Config& cfg)
         if (cfg.chunk == 0) return FE_EINVAL;
         return preeval_lds_bytes(c.form, c.cell, cfg.chunk) <= max_lds ? FE_OK : FE_EINVAL;
     }
+    if (cfg.variant == 2)
+        return vec_p1_eligible(c) && vec_p1_lds_bytes(c.cell) <= max_lds ? FE_OK : FE_EINVAL;
     if (cfg.variant) {
         if (!gram64_eligible(c)) return FE_EINVAL;
         if (cfg.grid_per_cu < 1) return FE_EINVAL;
@@ -666,11 +697,12 @@ int final_config(const Call& c, Config* cfg)
     const int* s = c.shape;   // kernel, block, epi, chunk, eb, qc, grid_per_cu
     const Config autocfg = *cfg;
     if (s[0]) {
-        // 1, 2: tiled or streaming pre-evaluated kernel; 3, 4: VALU or matrix-core quadrature
+        // 1, 2: tiled or streaming pre-evaluated kernel; 3, 4: VALU or matrix-core
+        // quadrature; 5: the hoisted degree-1 vector kernel
         const bool pre = c.mode == FE_MODE_PREEVAL && c.prec == FE_FP64;
         if (pre != (s[0] <= 2) || (c.prec != FE_FP64 && s[0] != 4)) return FE_EINVAL;
         if (c.prec == FE_FP64) {
-            const int v = (s[0] == 2 || s[0] == 4) ? 1 : 0;
+            const int v = s[0] == 5 ? 2 : (s[0] == 2 || s[0] == 4) ? 1 : 0;
             if (!pre && v != autocfg.variant) {
                 *cfg = v ? Config() : default_quad_config(c.form, c.cell, c.degree, c.tables->nq, c.pointgeo);
                 cfg->variant = v;
@@ -725,7 +757,7 @@ int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, co
     const int sh[7] = {o.shape.kernel, o.shape.block, o.shape.epi, o.shape.chunk,
                        o.shape.eb,     o.shape.qc,    o.shape.grid_per_cu};
     for (int i = 0; i < 7; ++i) {
-        if (sh[i] < 0 || (i == 0 && sh[i] > 4)) return FE_EINVAL;
+        if (sh[i] < 0 || (i == 0 && sh[i] > 5)) return FE_EINVAL;
         c->shape[i] = sh[i];
     }
     if (n_elems == 0) return FE_OK;

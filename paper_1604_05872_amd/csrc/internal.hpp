@@ -82,6 +82,24 @@ struct GramScalarArgs {
 hipError_t launch_gram64_scalar(int form, int cell, int p, const GramScalarArgs& a, int grid, hipStream_t s);
 size_t gram64_scalar_lds_bytes(int cell, int p);
 int gram64_scalar_elems_per_block();
+// assemble_vec_p1.hip: the vector forms at degree 1 on simplices (every
+// gradient constant, the point loop hoisted), float64
+struct VecP1Args {
+    const double* coords;
+    const double* coeff;
+    double* out;
+    int* status;
+    const double* W;            // [nq]
+    const double* psi;          // [nq][nv] P1 basis at the points
+    const double* dphi;         // [nq][ns][d] (the first point's gradients are used)
+    int64_t E;
+    int nq;
+    int nt;
+    double mu, lam;
+};
+hipError_t launch_vec_p1(int form, int cell, const VecP1Args& a, int grid, hipStream_t s);
+size_t vec_p1_lds_bytes(int cell);
+int vec_p1_elems_per_block();
 // prec: 1 = fp32 operands, 2 = bf16 hi/lo split
 inline hipError_t launch_split(int form, int cell, int p, int prec, int nqp, const SplitArgs& a, int grid,
                                size_t lds, hipStream_t s)
@@ -196,6 +214,9 @@ void lookup_config(const Call& c, Config* cfg);
 // the float64 matrix-core kernel serves this call (vector form, n <= 32,
 // at most 32 contraction points)
 bool gram64_eligible(const Call& c);
+// the hoisted degree-1 vector kernel serves this call (float64 quadrature,
+// vector form at degree 1 on a simplex)
+bool vec_p1_eligible(const Call& c);
 // P1 vector form on a simplex: every gradient is constant over the element,
 // so the point loop is hoisted (generalised code motion, Sec. 3.2)
 bool q_invariant(const Call& c);

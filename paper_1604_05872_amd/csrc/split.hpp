@@ -132,14 +132,6 @@ __host__ __device__ constexpr int split_coeffs_per_elem(int ns)
     return FORM == HYPERELASTIC ? cell_dim(CELL) * ns : 2 * cell_nv(CELL);
 }
 
-// LDS ordering between the lanes of one wavefront (its LDS area is private)
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // P: polynomial degree (the scalar space size is then a compile-time
 // constant); NQP: padded point count (8, 16 or 32).  Every thread of the
 // block runs it.

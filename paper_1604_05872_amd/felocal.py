@@ -275,7 +275,8 @@ def fe_assemble_local(form: str, cell: str, degree: int, coords, coeff, out, qde
     """Element matrices of `form` into `out` [E][n][n] (asynchronous on the stream).
 
     shape: optional launch-shape override, keys of fe_shape_t (kernel: 1 tiled,
-    2 streaming; block, epi, chunk, eb, qc, grid_per_cu).  nf: mass and
+    2 streaming pre-evaluated, 3 VALU, 4 matrix-core quadrature, 5 hoisted
+    degree-1 vector kernel; block, epi, chunk, eb, qc, grid_per_cu).  nf: mass and
     Helmholtz pre-multiplied by nf coefficient functions, coeff [E][nf][n_s].
     pointgeo: prisms need not be affine (the vertex map at every point)."""
     _f64_dev(coords, "coords")

@@ -169,7 +169,7 @@ def test_preeval_shapes(form, cell, p, shape, E):
 
 
 AUTOTUNE_CASES = [("helmholtz", "tetrahedron", 3, 4001), ("mass", "prism", 2, 3001), ("helmholtz", "prism", 4, 301),
-                  ("elasticity", "tetrahedron", 2, 1201)]
+                  ("elasticity", "tetrahedron", 2, 1201), ("hyperelastic", "tetrahedron", 1, 2001)]
 
 
 @pytest.mark.parametrize("form,cell,p,E", AUTOTUNE_CASES)
@@ -185,7 +185,7 @@ def test_autotune_shape_roundtrip(form, cell, p, E):
                                     return_shape=True)
     assert ms > 0
     preeval = form in ("mass", "helmholtz") and felocal.fe_plan(form, cell, p)["mode"] == "preeval"
-    assert (shape["kernel"] in (1, 2)) if preeval else shape["kernel"] in (3, 4)
+    assert (shape["kernel"] in (1, 2)) if preeval else shape["kernel"] in (3, 4, 5)
     B, _ = oracle.assemble(form, cell, p, coords, cf)
     A1, st1 = gpu_assemble(form, cell, p, coords, cf)
     shape = {k: v for k, v in shape.items() if v}
@@ -246,6 +246,49 @@ def test_fp64_vector_kernels(form, cell, p, kernel):
     assert st == fl == bad.sum()
     assert (np.isnan(A[:, 0, 0]) == bad).all() and np.isfinite(A[~bad]).all()
     assert normwise(A[~bad], B[~bad]).max() <= TOL["fp64"]
+
+
+# The hoisted degree-1 kernel (shape kernel 5, the default there): several
+# 128-element tiles and a ragged tail, degenerate and inverted elements.
+@pytest.mark.parametrize("form", ["elasticity", "hyperelastic"])
+@pytest.mark.parametrize("cell", ["triangle", "tetrahedron"])
+def test_degree1_vector_kernel(form, cell):
+    E = 1000
+    log(f"degree-1 vector kernel {form} {cell} E={E}")
+    coords, V, cells, h = mesh(cell, E, seed=71)
+    coords = coords.copy()
+    coords[5, 1] = coords[5, 0]                      # degenerate map
+    cf = coefficients(form, cell, 1, E, V, cells, h, seed=72)
+    if form == "hyperelastic":
+        cf = cf.copy()
+        cf[[17, 300, 999]] *= 60.0                   # large displacements: inverted F somewhere
+    B, fl = oracle.assemble(form, cell, 1, coords, cf)
+    bad = np.isnan(B[:, 0, 0])
+    assert bad[5] and fl == bad.sum()
+    for kw in ({}, {"shape": {"kernel": 5}}, {"shape": {"kernel": 5, "grid_per_cu": 1}}):
+        A, st = gpu_assemble(form, cell, 1, coords, cf, **kw)
+        assert st == fl
+        assert (np.isnan(A[:, 0, 0]) == bad).all() and np.isnan(A[bad]).all() and np.isfinite(A[~bad]).all()
+        assert normwise(A[~bad], B[~bad]).max() <= TOL["fp64"]
+    # the VALU kernel agrees element by element
+    A3, _ = gpu_assemble(form, cell, 1, coords, cf, shape={"kernel": 3})
+    assert normwise(A3[~bad], A[~bad]).max() <= 1e-13
+    # one element, and the last tile holding a single element
+    for n1 in (1, 129):
+        A1, st1 = gpu_assemble(form, cell, 1, coords[:n1], cf[:n1], shape={"kernel": 5})
+        assert st1 == bad[:n1].sum() and normwise(A1[~bad[:n1]], B[:n1][~bad[:n1]]).max() <= TOL["fp64"]
+
+
+def test_degree1_vector_kernel_refusals():
+    coords, V, cells, h = mesh("tetrahedron", 50, seed=73)
+    for form, cell, p, kw in (("elasticity", "tetrahedron", 2, {}), ("hyperelastic", "prism", 1, {}),
+                              ("mass", "tetrahedron", 1, {"mode": "quadrature"}),
+                              ("hyperelastic", "tetrahedron", 1, {"precision": "bf16x3"})):
+        c2, V2, cells2, h2 = mesh(cell, 50, seed=73)
+        cf = coefficients(form, cell, p, 50, V2, cells2, h2, seed=74)
+        with pytest.raises(felocal.FeError) as ei:
+            gpu_assemble(form, cell, p, c2, cf, shape={"kernel": 5}, **kw)
+        assert ei.value.code == felocal.FE_EINVAL
 
 
 # Forms pre-multiplied by nf coefficient functions (the sweep of Sec. 7.1):
