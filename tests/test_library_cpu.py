@@ -178,7 +178,7 @@ def test_argument_errors_are_synchronous():
     assert L.fe_assemble_local(2, 1, 2, 1, 8, 8, 8, ctypes.byref(o)) == felocal.FE_ENOTSUP    # not vector forms
     assert L.fe_assemble_local(1, 1, 2, 1, 8, None, 8, ctypes.byref(o)) == felocal.FE_EINVAL  # DOFs needed
     o.nf = 0
-    for field, bad in (("kernel", 5), ("kernel", -1), ("block", -64), ("epi", -1), ("chunk", -2), ("eb", -1),
+    for field, bad in (("kernel", 6), ("kernel", -1), ("block", -64), ("epi", -1), ("chunk", -2), ("eb", -1),
                        ("qc", -3), ("grid_per_cu", -1)):
         setattr(o.shape, field, bad)
         assert L.fe_assemble_local(0, 1, 2, 0, None, None, None, ctypes.byref(o)) == felocal.FE_EINVAL
