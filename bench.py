@@ -480,15 +480,17 @@ def mass_workload(torch, felocal, inputs, stream, ev, record):
 
 
 # float64 through the VALU quadrature kernel (launch-shape kernel 3) and the
-# matrix-core Gram kernel (kernel 4; the default except for hoisted P1), then
-# the two split precisions
+# matrix-core Gram kernel (kernel 4; the default except at degree 1), then
+# the two split precisions; at degree 1 also the hoisted kernel (kernel 5,
+# the default there)
 FP64_AND_SPLIT = [("fp64", {"kernel": 3}), ("fp64", {"kernel": 4}), ("fp32", None), ("bf16x3", None)]
+FP64_P1 = [("fp64", {"kernel": 5})]
 
 
 def kernel_name(prec, shape):
     if prec != "fp64":
         return f"k_split {prec} MFMA"
-    return "k_quad (VALU)" if shape["kernel"] == 3 else "k_gram64 (f64 MFMA)"
+    return {3: "k_quad (VALU)", 4: "k_gram64 (f64 MFMA)", 5: "k_vec_p1 (hoisted degree 1)"}[shape["kernel"]]
 
 
 def elasticity_workload(torch, felocal, inputs, stream, ev, record, reps):
@@ -516,7 +518,7 @@ def hyperelastic_workload(torch, felocal, inputs, stream, ev, record, reps):
         u = torch.from_numpy(inputs.displacement_dofs(E4, 3, ns, 1.0 / 55, p, seed=40 + p)).cuda()
         o4 = torch.empty((E4, 3 * ns, 3 * ns), dtype=torch.float64, device="cuda")
         st = torch.zeros(1, dtype=torch.int32, device="cuda")
-        for prec, kern in FP64_AND_SPLIT:
+        for prec, kern in (FP64_P1 if p == 1 else []) + FP64_AND_SPLIT:
             st.zero_()
             ms = time_launch(torch, lambda: felocal.fe_assemble_local("hyperelastic", "tetrahedron", p, c4, u, o4,
                                                                       precision=prec, status=st, shape=kern),
