@@ -354,8 +354,10 @@ int fe_csr_destroy(fe_csr_t* csr);
  * FE_HELMHOLTZ in FE_FP64 with nf = 0, in the pre-evaluated mode (what
  * Algorithm 3 chooses for these forms, or FE_MODE_PREEVAL), with reference
  * tables of at most 96 KiB (every triangle and tetrahedron degree; prisms up
- * to P4 for mass and P3 for Helmholtz); other calls return FE_ENOTSUP (use
- * fe_assemble_local, then fe_csr_insert).  opt->shape is ignored.  The
+ * to P4 for mass and P3 for Helmholtz); other calls, and meshes where one
+ * row's entries and the tables together exceed a workgroup's LDS, return
+ * FE_ENOTSUP (use fe_assemble_local, then fe_csr_insert).  opt->shape is
+ * ignored.  The
  * handle keeps a geometry workspace of 64 B per element, allocated on first
  * use, so calls on one handle must not overlap.  Asynchronous on
  * opt->stream; flagged elements are counted through opt->d_status and make

@@ -195,20 +195,41 @@ hipError_t launch_fused(const fe_csr* c, const double* tables, double* vals, int
 // rows side by side in a wavefront, so that more rows have their loads in
 // flight at once (each row's chain of dependent loads is what bounds the pass).
 template <int FORM, int CELL>
+hipError_t fused_shape(const fe_csr* c, const double* tables, double* vals, hipStream_t s);
+
+// The measured shape first; where its rounds do not fit in LDS beside the
+// tables (rows shared by very many elements), one row per round (the
+// smallest round).  hipErrorInvalidConfiguration when even that does not fit.
+template <int FORM, int CELL>
 hipError_t fused_for_n(const fe_csr* c, const double* tables, double* vals, hipStream_t s)
 {
+    const hipError_t e = fused_shape<FORM, CELL>(c, tables, vals, s);
+    if (e != hipErrorInvalidConfiguration) return e;
+    const int cap0 = c->round_len[0] > 0 ? c->round_len[0] : 1;
+    if (c->n <= 64) return launch_fused<FORM, CELL, 64, 1, 2>(c, tables, vals, cap0, s);
+    return launch_fused<FORM, CELL, 64, 2, 2>(c, tables, vals, cap0, s);
+}
+
+template <int FORM, int CELL>
+hipError_t fused_shape(const fe_csr* c, const double* tables, double* vals, hipStream_t s)
+{
     const int n = c->n;
-    const int W = n <= 4 ? 4 : n <= 8 ? 8 : n <= 64 ? 16 : n <= 96 ? 32 : 64;
+    // lanes per row: 8 up to n = 32 (eight rows side by side; measured on
+    // MI355X, Helmholtz tet P2 0.59 -> 0.38 ms and P3 1.75 -> 1.10 ms against
+    // 16 lanes), then 16, 32, 64
+    const int W = n <= 4 ? 4 : n <= 32 ? 8 : n <= 64 ? 16 : n <= 96 ? 32 : 64;
     int level = 0;
     while ((1 << level) < CSR_WAVE / W) level++;
     const int cap = c->round_len[level] > 0 ? c->round_len[level] : 1;
     // the geometry tensors of B elements sit in registers: fewer per batch
     // for the seven-term Helmholtz tensors
     constexpr int BS = n_tables(FORM, CELL) > 1 ? 4 : 8;
+    constexpr int B8 = BS / 2;
     if (n <= 4) return launch_fused<FORM, CELL, 4, 1, BS>(c, tables, vals, cap, s);
     if (n <= 8) return launch_fused<FORM, CELL, 8, 1, BS>(c, tables, vals, cap, s);
-    if (n <= 16) return launch_fused<FORM, CELL, 16, 1, BS>(c, tables, vals, cap, s);
-    if (n <= 32) return launch_fused<FORM, CELL, 16, 2, 4>(c, tables, vals, cap, s);
+    if (n <= 16) return launch_fused<FORM, CELL, 8, 2, B8>(c, tables, vals, cap, s);
+    if (n <= 24) return launch_fused<FORM, CELL, 8, 3, B8>(c, tables, vals, cap, s);
+    if (n <= 32) return launch_fused<FORM, CELL, 8, 4, B8>(c, tables, vals, cap, s);
     if (n <= 48) return launch_fused<FORM, CELL, 16, 3, BS == 4 ? 3 : 4>(c, tables, vals, cap, s);
     if (n <= 64) return launch_fused<FORM, CELL, 16, 4, BS == 4 ? 2 : 4>(c, tables, vals, cap, s);
     if (n <= 96) return launch_fused<FORM, CELL, 32, 3, 2>(c, tables, vals, cap, s);
@@ -262,5 +283,6 @@ extern "C" int fe_assemble_csr(fe_form_t form, fe_cell_t cell, int degree, int64
             : cell == FE_TETRAHEDRON ? run_fused<HELMHOLTZ, TET>(csr, coords, R, values, c.status, c.stream)
                                      : run_fused<HELMHOLTZ, PRISM>(csr, coords, R, values, c.status, c.stream);
     }
+    if (e == hipErrorInvalidConfiguration) return FE_ENOTSUP;   // one row and the tables exceed the LDS
     return e == hipSuccess ? FE_OK : set_hip_error(e, "fe_assemble_csr");
 }

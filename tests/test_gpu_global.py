@@ -240,6 +240,52 @@ def test_fused_equals_local_then_insert(form, cell, p):
     pat.close()
 
 
+def test_fused_rows_shared_by_many_elements():
+    """Sixteen hub vertices with consecutive numbers, each in 600 tetrahedra
+    whose other vertices are their own: a round of sixteen hub rows
+    (3 x 600 + 1 entries each) no longer fits in LDS, so the one pass falls
+    back to one row per round; it still equals local assembly plus insertion
+    bit for bit."""
+    rng = np.random.default_rng(81)
+    hubs, m = 16, 600
+    E = hubs * m
+    cells = np.empty((E, 4), np.int32)
+    V = [rng.uniform(0.0, 1.0, 3) for _ in range(hubs)]
+    for h in range(hubs):
+        for t in range(m):
+            e = h * m + t
+            base = len(V)
+            while True:
+                d = rng.normal(size=(3, 3))
+                if abs(np.linalg.det(d)) > 0.05:
+                    break
+            V.extend(V[h] + 0.1 * d[i] for i in range(3))
+            cells[e] = (h, base, base + 1, base + 2)
+    V = np.array(V)
+    coords = V[cells]
+    N = len(V)
+    entries_16 = 16 * (3 * m + 1) * 8
+    assert entries_16 > 160 * 1024   # the sixteen-row round exceeds any workgroup's LDS
+    log(f"fused fallback: {E} tets, {N} rows")
+    for form in ("mass", "helmholtz"):
+        pat, rp, ci = gpu_pattern(cells, N)
+        assert rp[1] - rp[0] == 3 * m + 1
+        dc = dev(coords)
+        vals = torch.full((len(ci),), float("nan"), dtype=torch.float64, device="cuda")
+        pat.assemble(form, "tetrahedron", 1, dc, vals)
+        local = torch.empty((E, 4, 4), dtype=torch.float64, device="cuda")
+        felocal.fe_assemble_local(form, "tetrahedron", 1, dc, None, local)
+        ref = torch.empty_like(vals)
+        pat.insert(local, ref)
+        torch.cuda.synchronize()
+        assert torch.equal(_as_bits(vals), _as_bits(ref))
+        B, _ = oracle.assemble(form, "tetrahedron", 1, coords)
+        want = oracle.csr_insert(cells, N, rp, ci, B)
+        scale = oracle.csr_insert(cells, N, rp, ci, np.broadcast_to(np.abs(B).max(axis=(1, 2))[:, None, None], B.shape))
+        assert np.all(np.abs(vals.cpu().numpy() - want) <= TOL * scale)
+        pat.close()
+
+
 def test_fused_flagged_and_refused():
     """A degenerate element is counted once and poisons exactly the entries it
     touches, as in the two-step path; other forms and mismatched patterns are
