@@ -74,7 +74,10 @@ typedef enum { FE_MASS = 0, FE_HELMHOLTZ = 1, FE_ELASTICITY = 2, FE_HYPERELASTIC
  * FE_SPLIT_FP32 <= 2e-6; FE_FP64 agrees with the float64 oracle to 1e-12. */
 typedef enum { FE_FP64 = 0, FE_SPLIT_FP32 = 1, FE_SPLIT_BF16X3 = 2 } fe_precision_t;
 
-/* Contraction mode (Sec. 4.1, Algorithm 3 chooses it when FE_MODE_AUTO). */
+/* Contraction mode (Sec. 4.1, Algorithm 3 chooses it when FE_MODE_AUTO).
+ * FE_MODE_PREEVAL serves mass, Helmholtz and elasticity (its P1 Lame fields
+ * expanded out of the reduction, FE_FP64 only); the hyperelastic form's
+ * coefficient is not a polynomial, so it is FE_ENOTSUP there. */
 typedef enum {
     FE_MODE_AUTO = 0,      /* planner decides from theta and T_H           */
     FE_MODE_PREEVAL = 1,   /* pre-evaluated reference tensors (Alg. 2)     */
@@ -240,7 +243,11 @@ typedef struct {
  * pre-evaluate only some monomials (Fig. 5): mode is then
  * FE_MODE_QUADRATURE and, with nf = 0, the quadrature kernel adds the
  * pre-evaluated monomials' tables; with nf > 0 such a mixed plan is executed
- * in quadrature mode.  The hyperelastic form has two monomials: the terms in
+ * in quadrature mode.  Elasticity (P1 Lame fields, iota = n_c) has two
+ * monomials that share one set of tables T_{l,a,b}[j][k] =
+ * sum_q W_q psi_l dphi_{j,a} dphi_{k,b}; its pre-evaluated kernel takes both,
+ * so its plans are both-or-neither (each must have theta <= 0 and the
+ * tables must fit T_H).  The hyperelastic form has two monomials: the terms in
  * F (never pre-evaluable) and the trace term mu |det J| g_j . g_k (constant
  * coefficient); its matrix-core kernels (split precisions, float64 shape
  * kernel 1) pre-evaluate the trace term, the VALU kernel integrates both.
@@ -256,7 +263,9 @@ int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int qdeg, size_t
  * All sub-batch pointers are DEVICE pointers owned by the caller and must
  * stay valid until fe_batch_destroy.  Every sub-batch uses FE_FP64 and the
  * mode Algorithm 3 chooses for it (tiled pre-evaluated or VALU quadrature
- * tiles); tile sizes come from the autotune cache (fe_autotune) when
+ * tiles; elasticity sub-batches that it pre-evaluates run the pre-evaluated
+ * elasticity kernel, one launch each, on one more branch of the graph);
+ * tile sizes come from the autotune cache (fe_autotune) when
  * present, else from built-in defaults.  Sub-batches with no elements are
  * allowed and do nothing.  Replays on one stream are ordered; replays of
  * one batch on different streams at once race on its work queues.

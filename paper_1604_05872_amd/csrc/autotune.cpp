@@ -59,7 +59,7 @@ void load_file_locked()
 Config default_for(const Call& c)
 {
     if (c.prec != FE_FP64) return Config();
-    if (c.mode == FE_MODE_PREEVAL && c.nf > 0) return Config();
+    if (c.mode == FE_MODE_PREEVAL && (c.nf > 0 || c.form == ELASTICITY)) return Config();
     if (c.mode == FE_MODE_PREEVAL) return default_preeval_config(c.form, c.tables->nb * c.tables->nb);
     // float64 matrix-core Gram kernel where the point loop is not hoisted
     // (with one point per element the VALU kernel is faster).  For the scalar
@@ -100,7 +100,7 @@ std::vector<Config> candidates(const Call& c)
         }
         return out;
     }
-    if (c.mode == FE_MODE_PREEVAL && c.nf > 0) {
+    if (c.mode == FE_MODE_PREEVAL && (c.nf > 0 || c.form == ELASTICITY)) {
         for (int g : {2, 4, 8, 16}) {
             Config x;
             x.grid_per_cu = g;
@@ -261,7 +261,7 @@ extern "C" int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n
     if (best_ms) *best_ms = best;
     if (best_shape) {
         best_shape->kernel = c.prec != FE_FP64                  ? 4
-                             : c.mode == FE_MODE_PREEVAL && c.nf ? 0   // a single kernel
+                             : c.mode == FE_MODE_PREEVAL && (c.nf || c.form == ELASTICITY) ? 0   // a single kernel
                              : c.mode == FE_MODE_PREEVAL         ? (best_cfg.variant ? 2 : 1)
                                                                  : (best_cfg.variant == 2 ? 5 : best_cfg.variant ? 4 : 3);
         best_shape->block = best_cfg.block;

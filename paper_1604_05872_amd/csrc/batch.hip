@@ -113,6 +113,17 @@ struct fe_batch {
         SubDesc* d_subs = nullptr;
     };
     std::vector<Group> groups;
+    // elasticity sub-batches that Algorithm 3 pre-evaluates: the pre-evaluated
+    // elasticity kernel, one launch each, on a branch of their own
+    struct ElastSub {
+        int cell = 0, ns = 0;
+        const double* coords = nullptr;
+        const double* coeff = nullptr;
+        double* out = nullptr;
+        const double* T = nullptr;
+        int64_t E = 0;
+    };
+    std::vector<ElastSub> elast;
     unsigned long long* d_counters = nullptr;
     int64_t total = 0;
     int grid = 0;
@@ -176,6 +187,7 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
     hipStream_t s = (hipStream_t)o.stream;
     std::vector<std::vector<SubDesc>> by_vid(N_VARIANTS);
     std::vector<size_t> lds_vid(N_VARIANTS, 0);
+    std::vector<fe_batch::ElastSub> elast;
     for (int i = 0; i < n_subs; ++i) {
         const fe_subbatch_t& sb = subs[i];
         if ((int)sb.form < 0 || (int)sb.form > 2 || (int)sb.cell < 0 || (int)sb.cell > 2 || sb.degree < 1 ||
@@ -200,6 +212,21 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
         rc = get_tables(sb.cell, sb.degree, qdeg, s, &c.tables);
         if (rc) return rc;
         const RefTables* t = c.tables;
+        if (sb.form == FE_ELASTICITY && c.mode == FE_MODE_PREEVAL) {
+            const CoefTables* ct = nullptr;
+            rc = get_coef_tables(ELASTICITY, sb.cell, sb.degree, qdeg, 0, s, &ct);
+            if (rc) return rc;
+            fe_batch::ElastSub es;
+            es.cell = sb.cell;
+            es.ns = t->nb;
+            es.coords = sb.coords;
+            es.coeff = sb.coeff_dofs;
+            es.out = sb.out_A;
+            es.T = ct->dR;
+            es.E = sb.n_elems;
+            elast.push_back(es);
+            continue;
+        }
         Config cfg;
         lookup_config(c, &cfg);
         SubDesc d;
@@ -251,6 +278,7 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
         lds_vid[vid] = std::max(lds_vid[vid], lds);
     }
     fe_batch* b = new fe_batch();
+    b->elast = elast;
     hipError_t e = hipSuccess;
     const int cus = device_cus();
     for (int v = 0; v < N_VARIANTS && e == hipSuccess; ++v) {
@@ -272,19 +300,20 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
         b->groups.push_back(g);
     }
     const int ng = (int)b->groups.size();
+    const int nbr = ng + (b->elast.empty() ? 0 : 1);   // parallel branches of the graph
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_counters, sizeof(unsigned long long) * std::max(1, ng));
     if (e != hipSuccess) {
         destroy(b);
         return set_hip_error(e, "fe_batch_create setup");
     }
     // capture: counter reset, then the group kernels on parallel branches
-    std::vector<hipStream_t> br(ng, nullptr);
-    std::vector<hipEvent_t> done(ng, nullptr);
+    std::vector<hipStream_t> br(nbr, nullptr);
+    std::vector<hipEvent_t> done(nbr, nullptr);
     hipStream_t cs = nullptr;
     hipEvent_t start = nullptr;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&start, hipEventDisableTiming);
-    for (int i = 0; i < ng && e == hipSuccess; ++i) {
+    for (int i = 0; i < nbr && e == hipSuccess; ++i) {
         e = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&done[i], hipEventDisableTiming);
     }
@@ -306,12 +335,22 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
         if (e == hipSuccess) e = hipEventRecord(done[i], br[i]);
         if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[i], 0);
     }
+    if (nbr > ng && e == hipSuccess) {
+        e = hipStreamWaitEvent(br[ng], start, 0);
+        for (size_t k = 0; k < b->elast.size() && e == hipSuccess; ++k) {
+            const fe_batch::ElastSub& es = b->elast[k];
+            e = launch_preeval_elast(es.cell, es.coords, es.coeff, es.out, o.d_status, es.T, es.E, es.ns, 8, cus,
+                                     br[ng]);
+        }
+        if (e == hipSuccess) e = hipEventRecord(done[ng], br[ng]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[ng], 0);
+    }
     if (capturing) {
         const hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
         if (e == hipSuccess) e = e2;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-    for (int i = 0; i < ng; ++i) {
+    for (int i = 0; i < nbr; ++i) {
         if (done[i]) (void)hipEventDestroy(done[i]);
         if (br[i]) (void)hipStreamDestroy(br[i]);
     }

@@ -156,6 +156,23 @@ int get_coef_tables(int form, int cell, int p, int qdeg, int nf, hipStream_t s, 
         return FE_OK;
     }
     const int nb = rt->nb;
+    if (form == ELASTICITY) {
+        // T[(l, a, b)][j][k] = sum_q W_q psi_l dphi_{j,a} dphi_{k,b}
+        CoefTables* t = new CoefTables();
+        t->iota = rt->nv;
+        t->nt = rt->nv * rt->d * rt->d;
+        hipError_t e = hipMalloc((void**)&t->dR, (size_t)t->nt * nb * nb * sizeof(double));
+        if (e == hipSuccess) e = launch_elast_tables(rt->nq, nb, rt->d, rt->nv, rt->dW, rt->dpsi, rt->ddphi, t->dR, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            if (t->dR) (void)hipFree(t->dR);
+            delete t;
+            return set_hip_error(e, "building elasticity tables");
+        }
+        g_coef[key] = t;
+        *out = t;
+        return FE_OK;
+    }
     // sorted multisets l_1 <= ... <= l_nf, lexicographic
     std::vector<int> combos;
     std::vector<int> cur(nf, 0);
@@ -392,7 +409,7 @@ int fe_resolve_variant(int form, int cell, int degree, int qdeg, const fe_option
         return FE_OK;
     }
     if (o->mode == FE_MODE_PREEVAL) {
-        if (is_vector_form(form)) return FE_ENOTSUP;
+        if (form == HYPERELASTIC) return FE_ENOTSUP;   // a non-polynomial coefficient
         *mode_out = FE_MODE_PREEVAL;
         return FE_OK;
     }
@@ -529,6 +546,16 @@ int launch_call(const Call& c, const Config& cfg)
         if (e != hipSuccess) return set_hip_error(e, "split-precision launch");
         return FE_OK;
     }
+    if (c.mode == FE_MODE_PREEVAL && c.form == ELASTICITY) {
+        // the P1 Lame fields expanded out of the reduction (iota = n_c)
+        const CoefTables* ct = nullptr;
+        int rc = get_coef_tables(c.form, c.cell, c.degree, c.qdeg, 0, c.stream, &ct);
+        if (rc) return rc;
+        e = launch_preeval_elast(c.cell, c.coords, c.coeff, c.out, c.status, ct->dR, c.E, t->nb, cfg.grid_per_cu, cus,
+                                 c.stream);
+        if (e != hipSuccess) return set_hip_error(e, "pre-evaluated elasticity launch");
+        return FE_OK;
+    }
     if (c.mode == FE_MODE_PREEVAL && c.nf > 0) {
         const CoefTables* ct = nullptr;
         int rc = get_coef_tables(c.form, c.cell, c.degree, c.qdeg, c.nf, c.stream, &ct);
@@ -656,6 +683,7 @@ int check_config(const Call& c, const Config& cfg)
     if (c.prec != FE_FP64) return FE_OK;
     const RefTables* t = c.tables;
     const size_t max_lds = device_lds_per_block();
+    if (c.mode == FE_MODE_PREEVAL && c.form == ELASTICITY) return FE_OK;   // static LDS, grid only
     if (c.mode == FE_MODE_PREEVAL && c.nf > 0) {
         // one wavefront per block; the element rows of a 16-element tile
         // (n_tables * iota of them) sit in LDS

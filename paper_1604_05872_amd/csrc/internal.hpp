@@ -38,6 +38,11 @@ hipError_t launch_preeval_coef(int form, int cell, const double* coords, const d
                                int iota, int grid_per_cu, int cus, hipStream_t s, int r_lo = 0, int r_hi = -1,
                                int accumulate = 0);
 size_t preeval_coef_lds_bytes(int form, int cell, int ntp, int nf, int nb);
+// preeval_elast.hip: pre-evaluated linear elasticity with P1 Lame fields
+hipError_t launch_elast_tables(int nq, int ns, int d, int nc, const double* W, const double* psi, const double* dphi,
+                               double* T, hipStream_t s);
+hipError_t launch_preeval_elast(int cell, const double* coords, const double* coeff, double* out, int* status,
+                                const double* T, int64_t E, int ns, int grid_per_cu, int cus, hipStream_t s);
 hipError_t launch_quad_mass(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_quad_helmholtz(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_quad_elasticity(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
@@ -149,6 +154,8 @@ struct RefTables {
 
 // Tables of the pre-evaluation with nf coefficient functions: the sorted
 // multisets S of nf basis indices and R[(r, S)][j][k], device resident.
+// For elasticity (nf = 0, the P1 Lame fields): iota = n_c, no multisets,
+// and R = T[(l, a, b)][j][k].
 struct CoefTables {
     int iota = 0, nt = 0;
     int* dCombos = nullptr;   // [iota][nf]

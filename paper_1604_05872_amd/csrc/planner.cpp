@@ -96,7 +96,9 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int q
         }
         plan->rho[0] = d * d;
         plan->rho[1] = 2 * d * d;
-        legal[0] = legal[1] = false;   // no pre-evaluated kernel for vector forms
+        // the pre-evaluated kernel takes both monomials together (one set of
+        // tables): a plan that splits them has no kernel (see below)
+        legal[0] = legal[1] = true;
         break;
     default:
         // hyperelastic tangent: the terms in F (lambda' s_j,c s_k,e and
@@ -153,6 +155,8 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int q
         for (int m = 0; m < nm; ++m)
             if ((mask >> m & 1) && !inP[m]) ok = false;
         if (!ok) continue;
+        // elasticity: both monomials in one mode
+        if (form == FE_ELASTICITY && mask != 0 && mask != (1 << nm) - 1) continue;
         size_t mem = 0;
         int seen = 0;
         for (int m = 0; m < nm; ++m)

@@ -240,12 +240,51 @@ def test_fp64_vector_kernels(form, cell, p, kernel):
     log(f"fp64 vector kernel {kernel} {form} {cell} P{p} E={E}")
     coords, V, cells, h = mesh(cell, E, seed=300 + p)
     cf = coefficients(form, cell, p, E, V, cells, h, seed=400 + p)
-    A, st = gpu_assemble(form, cell, p, coords, cf, shape=dict(kernel=kernel))
+    A, st = gpu_assemble(form, cell, p, coords, cf, shape=dict(kernel=kernel), mode="quadrature")
     B, fl = oracle.assemble(form, cell, p, coords, cf)
     bad = np.isnan(B[:, 0, 0])
     assert st == fl == bad.sum()
     assert (np.isnan(A[:, 0, 0]) == bad).all() and np.isfinite(A[~bad]).all()
     assert normwise(A[~bad], B[~bad]).max() <= TOL["fp64"]
+
+
+# Pre-evaluated elasticity (the P1 Lame fields expanded, iota = n_c): every
+# cell and degree forced into the mode, several 16-element tiles, a
+# degenerate element; where Algorithm 3 chooses it the default is the same.
+ELAST_PRE = [(c, p) for c in CELLS for p in (1, 2, 3, 4)]
+
+
+@pytest.mark.parametrize("cell,p", ELAST_PRE)
+def test_elasticity_preevaluated(cell, p):
+    E = max(5, min(70, case_size("elasticity", cell, p, cap=70)))
+    log(f"elasticity pre-evaluated {cell} P{p} E={E}")
+    coords, V, cells, h = mesh(cell, E, seed=500 + p)
+    coords = coords.copy()
+    coords[E // 2, 2] = coords[E // 2, 0]            # degenerate map
+    cf = coefficients("elasticity", cell, p, E, V, cells, h, seed=510 + p)
+    B, fl = oracle.assemble("elasticity", cell, p, coords, cf)
+    bad = np.isnan(B[:, 0, 0])
+    assert bad[E // 2] and fl == bad.sum()
+    A, st = gpu_assemble("elasticity", cell, p, coords, cf, mode="preeval")
+    assert st == fl
+    assert (np.isnan(A[:, 0, 0]) == bad).all() and np.isnan(A[bad]).all() and np.isfinite(A[~bad]).all()
+    assert normwise(A[~bad], B[~bad]).max() <= TOL["fp64"]
+    if felocal.fe_plan("elasticity", cell, p)["mode"] == "preeval":
+        A2, _ = gpu_assemble("elasticity", cell, p, coords, cf)
+        assert np.array_equal(A2[~bad], A[~bad])
+
+
+def test_elasticity_preevaluated_refusals():
+    coords, V, cells, h = mesh("tetrahedron", 20, seed=520)
+    u = coefficients("hyperelastic", "tetrahedron", 2, 20, V, cells, h, seed=521)
+    with pytest.raises(felocal.FeError) as ei:
+        gpu_assemble("hyperelastic", "tetrahedron", 2, coords, u, mode="preeval")
+    assert ei.value.code == felocal.FE_ENOTSUP
+    cf = coefficients("elasticity", "tetrahedron", 2, 20, V, cells, h, seed=522)
+    for prec in ("fp32", "bf16x3"):
+        with pytest.raises(felocal.FeError) as ei:
+            gpu_assemble("elasticity", "tetrahedron", 2, coords, cf, mode="preeval", precision=prec)
+        assert ei.value.code == felocal.FE_ENOTSUP
 
 
 # The hoisted degree-1 kernel (shape kernel 5, the default there): several
@@ -475,7 +514,7 @@ def test_batch_bitwise_equal_to_separate_calls():
     specs = [("mass", "triangle", 1, 3000), ("helmholtz", "tetrahedron", 3, 1500), ("elasticity", "prism", 2, 200),
              ("helmholtz", "prism", 4, 60), ("elasticity", "tetrahedron", 2, 999), ("mass", "prism", 3, 0),
              ("helmholtz", "triangle", 4, 777), ("helmholtz", "tetrahedron", 2, 2500), ("mass", "triangle", 2, 1234),
-             ("elasticity", "tetrahedron", 2, 321)]
+             ("elasticity", "tetrahedron", 2, 321), ("elasticity", "tetrahedron", 4, 45), ("elasticity", "prism", 4, 9)]
     subs, refs = [], []
     for i, (form, cell, p, E) in enumerate(specs):
         coords, V, cells, h = mesh(cell, max(E, 1), seed=20 + i)
@@ -486,8 +525,10 @@ def test_batch_bitwise_equal_to_separate_calls():
         subs.append(dict(form=form, cell=cell, degree=p, coords=dev(coords),
                          coeff=dev(cf) if cf is not None else None, out=out))
         if E:
-            # the batch runs the VALU quadrature tiles for the vector forms
-            kw = dict(shape=dict(kernel=3)) if form == "elasticity" else {}
+            # the batch runs the VALU quadrature tiles for the vector forms,
+            # or the pre-evaluated elasticity kernel where Algorithm 3 chooses it
+            quad = form == "elasticity" and felocal.fe_plan(form, cell, p)["mode"] == "quadrature"
+            kw = dict(shape=dict(kernel=3)) if quad else {}
             ref = gpu_assemble(form, cell, p, coords, cf, **kw)[0]
             assert normwise(ref, oracle.assemble(form, cell, p, coords, cf)[0]).max() <= TOL["fp64"]
             refs.append(ref)

@@ -92,11 +92,20 @@ def test_planner_decisions(cell, p):
     # with no memory bound, the scalar forms pre-evaluate every monomial
     assert felocal.fe_plan("mass", cell, p, th_bytes=big)["mode"] == "preeval"
     assert felocal.fe_plan("helmholtz", cell, p, th_bytes=big)["mode"] == "preeval"
-    # elasticity with P1 Lame fields and the hyperelastic form use quadrature
+    # elasticity with P1 Lame fields: iota = n_c, rho = d^2 and 2 d^2, one
+    # set of tables; pre-evaluated when theta <= 0 for both monomials
     pe = felocal.fe_plan("elasticity", cell, p, th_bytes=big)
-    assert pe["mode"] == "quadrature" and not any(pe["preevaluated"])
+    d, nc = (2, 3) if cell == "triangle" else (3, 4) if cell == "tetrahedron" else (3, 6)
+    assert pe["iota"] == [nc, nc] and pe["rho"] == [d * d, 2 * d * d]
+    both = all(tp <= ts for tp, ts in zip(pe["theta_pre"], pe["theta_se"]))
+    assert pe["preevaluated"] == [both, both] and pe["mode"] == ("preeval" if both else "quadrature")
     if (cell, p) == ("tetrahedron", 2):   # the elasticity workload: theta > 0 for both monomials
         assert all(tp > ts for tp, ts in zip(pe["theta_pre"], pe["theta_se"]))
+    if (cell, p) == ("tetrahedron", 4):   # 64 points: pre-evaluation pays for both
+        assert pe["mode"] == "preeval"
+    # tables over T_H: quadrature
+    small = felocal.fe_plan("elasticity", cell, p, th_bytes=1024)
+    assert small["mode"] == "quadrature" and not any(small["preevaluated"])
     phy = felocal.fe_plan("hyperelastic", cell, p, th_bytes=big)
     assert phy["mode"] == "quadrature" and math.isinf(phy["theta_pre"][0])
     # the trace monomial (constant coefficient) is pre-evaluated: with at least
@@ -167,7 +176,7 @@ def test_argument_errors_are_synchronous():
     assert L.fe_assemble_local(2, 1, 3, 1, 8, 8, 8, ctypes.byref(o)) == felocal.FE_ENOTSUP      # n = 60 > 32
     o.precision = 0
     o.mode = 1
-    assert L.fe_assemble_local(2, 1, 2, 1, 8, 8, 8, ctypes.byref(o)) == felocal.FE_ENOTSUP      # no vector pre-evaluation
+    assert L.fe_assemble_local(3, 1, 2, 1, 8, 8, 8, ctypes.byref(o)) == felocal.FE_ENOTSUP      # hyperelastic: no pre-evaluation
     o.qdeg = 99
     o.mode = 0
     assert L.fe_assemble_local(0, 1, 2, 1, 8, None, 8, ctypes.byref(o)) == felocal.FE_EINVAL
