@@ -59,7 +59,15 @@ void load_file_locked()
 Config default_for(const Call& c)
 {
     if (c.prec != FE_FP64) return Config();
-    if (c.mode == FE_MODE_PREEVAL && (c.nf > 0 || c.form == ELASTICITY)) return Config();
+    if (c.mode == FE_MODE_PREEVAL && c.form == ELASTICITY) {
+        // two resident workgroups per CU: fewer tiles write partial lines at
+        // once, so the L2 merges them (measured on MI355X; one is better for
+        // some shapes, which the autotuner finds)
+        Config x;
+        x.grid_per_cu = 2;
+        return x;
+    }
+    if (c.mode == FE_MODE_PREEVAL && c.nf > 0) return Config();
     if (c.mode == FE_MODE_PREEVAL) return default_preeval_config(c.form, c.tables->nb * c.tables->nb);
     // float64 matrix-core Gram kernel where the point loop is not hoisted
     // (with one point per element the VALU kernel is faster).  For the scalar
@@ -101,7 +109,7 @@ std::vector<Config> candidates(const Call& c)
         return out;
     }
     if (c.mode == FE_MODE_PREEVAL && (c.nf > 0 || c.form == ELASTICITY)) {
-        for (int g : {2, 4, 8, 16}) {
+        for (int g : {1, 2, 4, 8, 16}) {
             Config x;
             x.grid_per_cu = g;
             out.push_back(x);

@@ -339,7 +339,7 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
         e = hipStreamWaitEvent(br[ng], start, 0);
         for (size_t k = 0; k < b->elast.size() && e == hipSuccess; ++k) {
             const fe_batch::ElastSub& es = b->elast[k];
-            e = launch_preeval_elast(es.cell, es.coords, es.coeff, es.out, o.d_status, es.T, es.E, es.ns, 8, cus,
+            e = launch_preeval_elast(es.cell, es.coords, es.coeff, es.out, o.d_status, es.T, es.E, es.ns, 2, cus,
                                      br[ng]);
         }
         if (e == hipSuccess) e = hipEventRecord(done[ng], br[ng]);

@@ -11,10 +11,11 @@
 //                               + delta_ce mu_l (K K^T)_ab):
 // one dense product of a (16 elements) x (n_c d^2) coefficient matrix with
 // the table matrix per block, on the FP64 matrix cores
-// (v_mfma_f64_16x16x4_f64).  The unit of work is (16-element tile, block):
-// a wavefront forms the tile's coefficients of its block in its own LDS area
-// and sweeps the block's 16-entry column groups; the tables are read
-// through the L2 (the planner admits them only when they fit T_H).
+// (v_mfma_f64_16x16x4_f64).  A workgroup takes a 16-element tile: it forms
+// the coefficient rows of all d^2 blocks in LDS, then its wavefronts split
+// the 16-entry column groups, each group's table values (read through the
+// L2; the planner admits the tables only when they fit T_H) feeding the
+// d^2 blocks as independent accumulator chains.
 #include <algorithm>
 
 #include "device_common.hpp"
@@ -23,6 +24,11 @@
 namespace fe {
 
 typedef double v4d_e __attribute__((ext_vector_type(4)));
+typedef unsigned u2_e __attribute__((ext_vector_type(2)));
+// buffer resource word 3 on gfx950: a raw (stride 0) byte buffer whose
+// accesses are range-checked against num_records; stores beyond it are
+// dropped
+constexpr int BUFFER_WORD3 = 0x00020000;
 
 namespace {
 
@@ -51,65 +57,69 @@ struct ElastArgs {
     const double* T;       // [nt][ns * ns]
     int64_t E;
     int ns;
+    int parts;             // column-group ranges per tile (units = tiles x parts)
 };
 
 template <int CELL>
-__global__ __launch_bounds__(64 * PE_WAVES) void k_preeval_elast(ElastArgs a)
+__global__ __launch_bounds__(64 * PE_WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_preeval_elast(ElastArgs a)
 {
     constexpr int D = cell_dim(CELL), NC = cell_nv(CELL), NVD = NC * D;
-    constexpr int NT = NC * D * D, NTP = (NT + 7) / 8 * 8, NB = D * D;
-    __shared__ double sA[PE_WAVES][16 * NTP];       // the unit's coefficient rows
-    __shared__ double sG[PE_WAVES][16 * 12];        // K [9], |det J|, flag
-    __shared__ double sL[PE_WAVES][16 * 2 * NC];    // Lame nodal values
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int NT = NC * D * D, NTP = (NT + 7) / 8 * 8, NB = D * D, NK = NTP / 4;
+    // coefficient rows [block][element][(l, a, b)], rows NTP + 1 doubles apart
+    // so that the 16 rows of an operand read fall in distinct LDS banks
+    constexpr int LDA = NTP + 1;
+    __shared__ double sA[NB * 16 * LDA];
+    __shared__ double sG[16 * 12];           // K [9], |det J|, flag
+    __shared__ double sL[16 * 2 * NC];       // Lame nodal values
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int i16 = lane & 15, kq = lane >> 4;
     const int ns = a.ns, nn = ns * ns, n = D * ns;
     const int64_t ntiles = (a.E + 15) / 16;
-    const int64_t units = ntiles * NB;
     const int ncb = (nn + 15) / 16;
-    double* A = sA[w];
-    double* G = sG[w];
-    double* L = sL[w];
-    for (int64_t u = (int64_t)blockIdx.x * PE_WAVES + w; u < units; u += (int64_t)gridDim.x * PE_WAVES) {
-        const int64_t tile = u / NB;
-        const int blk = (int)(u - tile * NB), c = blk / D, e2 = blk - c * D;
+    const int parts = a.parts;                 // column-group ranges per tile
+    const int64_t units = ntiles * parts;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t tile = u / parts;
+        const int part = (int)(u - tile * parts);
         const int64_t e0 = tile * 16;
         const int ne = a.E - e0 < 16 ? (int)(a.E - e0) : 16;
         // geometry and Lame values of the tile's elements
-        if (lane < 16) {
+        if (tid < 16) {
             double K[3][3], adet;
             int bad = 0;
-            if (lane < ne) {
+            if (tid < ne) {
                 double v[NVD];
 #pragma unroll
-                for (int i = 0; i < NVD; ++i) v[i] = a.coords[(e0 + lane) * NVD + i];
+                for (int i = 0; i < NVD; ++i) v[i] = a.coords[(e0 + tid) * NVD + i];
                 bad = affine_map<CELL>(v, K, adet);
             } else {
 #pragma unroll
                 for (int r = 0; r < 3; ++r)
 #pragma unroll
-                    for (int s = 0; s < 3; ++s) K[r][s] = 0.0;
+                    for (int q = 0; q < 3; ++q) K[r][q] = 0.0;
                 adet = 0.0;
             }
 #pragma unroll
             for (int r = 0; r < D; ++r)
 #pragma unroll
-                for (int s = 0; s < D; ++s) G[lane * 12 + r * 3 + s] = K[r][s];
-            G[lane * 12 + 9] = adet;
-            G[lane * 12 + 10] = bad ? 1.0 : 0.0;
-            // one unit per tile reports flagged elements
-            if (bad && blk == 0 && a.status) atomicAdd(a.status, 1);
+                for (int q = 0; q < D; ++q) sG[tid * 12 + r * 3 + q] = K[r][q];
+            sG[tid * 12 + 9] = adet;
+            sG[tid * 12 + 10] = bad ? 1.0 : 0.0;
+            // the tile's first unit reports flagged elements
+            if (bad && part == 0 && a.status) atomicAdd(a.status, 1);
         }
-        for (int i = lane; i < 16 * 2 * NC; i += 64) L[i] = i < ne * 2 * NC ? a.coeff[e0 * 2 * NC + i] : 0.0;
-        wave_sync();
-        // coefficient rows C^{c e2}[e][(l, a, b)], zero-padded to NTP
-        for (int i = lane; i < 16 * NTP; i += 64) {
-            const int e = i / NTP, t = i - e * NTP;
+        for (int i = tid; i < 16 * 2 * NC; i += blockDim.x) sL[i] = i < ne * 2 * NC ? a.coeff[e0 * 2 * NC + i] : 0.0;
+        __syncthreads();
+        // coefficient rows C^{c e2}[e][(l, a, b)] of every block, zero-padded to NTP
+        for (int i = tid; i < NB * 16 * NTP; i += blockDim.x) {
+            const int blk = i / (16 * NTP), r = i - blk * 16 * NTP, e = r / NTP, t = r - e * NTP;
+            const int at = (blk * 16 + e) * LDA + t;
+            const int c = blk / D, e2 = blk - c * D;
             double x = 0.0;
             if (t < NT) {
                 const int l = t / (D * D), aa = (t / D) % D, b = t % D;
-                const double* K = G + e * 12;
-                const double lam = L[e * 2 * NC + l], mu = L[e * 2 * NC + NC + l];
+                const double* K = sG + e * 12;
+                const double lam = sL[e * 2 * NC + l], mu = sL[e * 2 * NC + NC + l];
                 x = lam * (K[aa * 3 + c] * K[b * 3 + e2]) + mu * (K[aa * 3 + e2] * K[b * 3 + c]);
                 if (c == e2) {
                     double g = 0.0;
@@ -119,68 +129,67 @@ __global__ __launch_bounds__(64 * PE_WAVES) void k_preeval_elast(ElastArgs a)
                 }
                 x *= K[9];
             }
-            A[i] = x;
+            sA[at] = x;
         }
-        wave_sync();
-        const bool bad_row[4] = {G[(kq + 0) * 12 + 10] != 0.0, G[(kq + 4) * 12 + 10] != 0.0,
-                                 G[(kq + 8) * 12 + 10] != 0.0, G[(kq + 12) * 12 + 10] != 0.0};
-        // the block's entries in 16-entry column groups, NG at a time (2 NG
-        // independent accumulator chains; prisms, whose coefficient rows are
-        // longer, take one group to keep two wavefronts per SIMD); a step's
-        // table values are loaded together, one step ahead of its products
-        constexpr int NK = NTP / 4, NG = CELL == PRISM ? 1 : 2;
-        double bv[NG][NK];
+        __syncthreads();
+        // the tile's output as a buffer of ne element matrices (byte records)
+        const int nn_e = n * n;
+        const __amdgpu_buffer_rsrc_t out_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            a.out + e0 * (int64_t)nn_e, 0, (int)((unsigned)ne * (unsigned)nn_e * 8u), BUFFER_WORD3);
+        bool bad_row[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bad_row[r] = sG[(kq + 4 * r) * 12 + 10] != 0.0;
+        // this unit's column groups, wavefront w taking every PE_WAVES-th; a
+        // group's table values feed all NB blocks, loaded one group ahead
+        const int cb_lo = (int)((int64_t)ncb * part / parts), cb_hi = (int)((int64_t)ncb * (part + 1) / parts);
+        double bv[NK];
         auto load_b = [&](int cb) {
+            const int col = 16 * cb + i16;
+            const int colc = col < nn ? col : nn - 1;   // in-range table column for padding lanes
 #pragma unroll
-            for (int h = 0; h < NG; ++h) {
-                const int col = 16 * (cb + h) + i16;
-                const int colc = col < nn ? col : nn - 1;   // in-range table column for padding lanes
-#pragma unroll
-                for (int kk = 0; kk < NK; ++kk) {
-                    const int k = 4 * kk + kq;
-                    bv[h][kk] = k < NT ? a.T[(size_t)k * nn + colc] : 0.0;
-                }
+            for (int kk = 0; kk < NK; ++kk) {
+                const int k = 4 * kk + kq;
+                bv[kk] = k < NT ? a.T[(size_t)k * nn + colc] : 0.0;
             }
         };
-        auto store_group = [&](int col, const v4d_e& x0, const v4d_e& x1) {
-            // lane holds elements kq + 4 r, entry col = (j, k) of block (c, e2)
-            if (col < nn) {
-                const int j = col / ns, k = col - (col / ns) * ns;
-                const int64_t off = (int64_t)(c * ns + j) * n + e2 * ns + k;
+        if (cb_lo + w < cb_hi) load_b(cb_lo + w);
+        for (int cb = cb_lo + w; cb < cb_hi; cb += PE_WAVES) {
+            double bc[NK];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = kq + 4 * r;
-                    if (row < ne) {
-                        const double v = bad_row[r] ? __builtin_nan("") : x0[r] + x1[r];
-                        store_out(a.out + (e0 + row) * (int64_t)(n * n) + off, v, 0);
+            for (int kk = 0; kk < NK; ++kk) bc[kk] = bv[kk];
+            if (cb + PE_WAVES < cb_hi) load_b(cb + PE_WAVES);
+            // blocks in groups of D (D independent accumulator chains per
+            // group, few registers live), each group stored before the next
+            const int col = 16 * cb + i16;
+            const int j = col < nn ? col / ns : 0, k = col < nn ? col - (col / ns) * ns : 0;
+#pragma unroll 1
+            for (int c = 0; c < D; ++c) {
+                v4d_e acc[D];
+#pragma unroll
+                for (int e2 = 0; e2 < D; ++e2) acc[e2] = (v4d_e){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < NK; ++kk)
+#pragma unroll
+                    for (int e2 = 0; e2 < D; ++e2)
+                        acc[e2] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            sA[((c * D + e2) * 16 + i16) * LDA + 4 * kk + kq], bc[kk], acc[e2], 0, 0, 0);
+                // lane holds elements kq + 4 r, entry col = (j, k) of blocks
+                // (c, e2).  Every store is issued: a lane past the block or an
+                // element past the tile addresses beyond the tile's records,
+                // and the buffer unit drops it
+#pragma unroll
+                for (int e2 = 0; e2 < D; ++e2) {
+                    const unsigned off = (unsigned)((c * ns + j) * n + e2 * ns + k);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const unsigned byte = col < nn ? (unsigned)((kq + 4 * r) * nn_e + off) * 8u : 0x80000000u;
+                        const double v = bad_row[r] ? __builtin_nan("") : acc[e2][r];
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_e, v), out_rsrc, byte, 0, 0);
                     }
                 }
             }
-        };
-        load_b(0);
-        for (int cb = 0; cb < ncb; cb += NG) {
-            double bc[NG][NK];
-#pragma unroll
-            for (int h = 0; h < NG; ++h)
-#pragma unroll
-                for (int kk = 0; kk < NK; ++kk) bc[h][kk] = bv[h][kk];
-            if (cb + NG < ncb) load_b(cb + NG);
-            v4d_e acc[2 * NG];
-#pragma unroll
-            for (int i = 0; i < 2 * NG; ++i) acc[i] = (v4d_e){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int kk = 0; kk < NK; ++kk) {
-                const double av = A[i16 * NTP + 4 * kk + kq];
-#pragma unroll
-                for (int h = 0; h < NG; ++h)
-                    acc[2 * h + (kk & 1)] =
-                        __builtin_amdgcn_mfma_f64_16x16x4f64(av, bc[h][kk], acc[2 * h + (kk & 1)], 0, 0, 0);
-            }
-#pragma unroll
-            for (int h = 0; h < NG; ++h)   // a group past the block stores nothing
-                store_group(16 * (cb + h) + i16, acc[2 * h], acc[2 * h + 1]);
         }
-        wave_sync();
+        __syncthreads();
     }
 }
 
@@ -206,10 +215,13 @@ hipError_t launch_preeval_elast(int cell, const double* coords, const double* co
     a.T = T;
     a.E = E;
     a.ns = ns;
-    const int d = cell_dim(cell);
-    const int64_t units = (E + 15) / 16 * d * d;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((units + PE_WAVES - 1) / PE_WAVES,
-                                                                 (int64_t)cus * grid_per_cu));
+    // a workgroup per (tile, column-group range): ranges split a tile only
+    // when there are too few tiles to give every CU two units
+    const int64_t tiles = (E + 15) / 16;
+    const int64_t want = (int64_t)cus * 2;
+    a.parts = (int)std::max<int64_t>(1, std::min<int64_t>(4, (want + tiles - 1) / tiles));
+    const int64_t units = tiles * a.parts;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(units, (int64_t)cus * grid_per_cu));
     if (cell == TRI) hipLaunchKernelGGL((k_preeval_elast<TRI>), dim3(grid), dim3(64 * PE_WAVES), 0, s, a);
     else if (cell == TET) hipLaunchKernelGGL((k_preeval_elast<TET>), dim3(grid), dim3(64 * PE_WAVES), 0, s, a);
     else hipLaunchKernelGGL((k_preeval_elast<PRISM>), dim3(grid), dim3(64 * PE_WAVES), 0, s, a);
