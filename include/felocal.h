@@ -305,6 +305,10 @@ int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems,
                 const double* coords, const double* coeff_dofs, double* out_A,
                 const fe_options_t* opt, double* best_ms, fe_shape_t* best_shape);
 
+/* Empties the in-memory autotune cache (the JSON file is left as it is; it
+ * is not read again in this process).  Host-only, thread-safe. */
+void fe_autotune_clear(void);
+
 /* Global assembly (Sec. 2): the element matrices are coupled by adding them
  * into the matrix of the continuous space, A_ij = a(phi_i, phi_j), at the
  * global numbers of their DOFs (Sec. 7.1 times local assembly together with
@@ -444,7 +448,8 @@ int fe_assemble_form(const fe_form_spec_t* spec, fe_cell_t cell, int degree, int
 /* Human-readable text for an FE_* code. */
 const char* fe_strerror(int code);
 
-/* Frees the reference-table and autotune caches (device memory included). */
+/* Frees the reference-table, coefficient-table and autotune caches (device
+ * memory included).  No call may be in flight. */
 void fe_release_caches(void);
 
 /* Library version string. */

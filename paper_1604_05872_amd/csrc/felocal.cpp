@@ -826,8 +826,11 @@ int fe_assemble_local(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elem
     return launch_call(c, cfg);
 }
 
+void fe_autotune_clear(void);
+
 void fe_release_caches(void)
 {
+    fe_autotune_clear();
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& kv : g_tables) {
         RefTables* t = kv.second;
@@ -836,6 +839,13 @@ void fe_release_caches(void)
         delete t;
     }
     g_tables.clear();
+    for (auto& kv : g_coef) {
+        CoefTables* t = kv.second;
+        if (t->dCombos) (void)hipFree(t->dCombos);
+        if (t->dR) (void)hipFree(t->dR);
+        delete t;
+    }
+    g_coef.clear();
 }
 
 }  // extern "C"

@@ -32,7 +32,7 @@ def NBASIS(cell: str, p: int) -> int:
 # every function include/felocal.h declares
 EXPORTS = (
     "fe_options_init", "fe_tabulate", "fe_local_dims", "fe_assemble_local", "fe_geometry", "fe_plan",
-    "fe_batch_create", "fe_batch_run", "fe_batch_destroy", "fe_batch_info", "fe_autotune",
+    "fe_batch_create", "fe_batch_run", "fe_batch_destroy", "fe_batch_info", "fe_autotune", "fe_autotune_clear",
     "fe_strerror", "fe_release_caches", "fe_version",
     "fe_csr_create", "fe_csr_info", "fe_csr_pattern", "fe_csr_insert", "fe_csr_destroy", "fe_assemble_csr",
     "fe_sharing_plan", "fe_form_source", "fe_assemble_form",
@@ -166,6 +166,8 @@ def lib():
         L.fe_strerror.restype = ctypes.c_char_p
         L.fe_release_caches.argtypes = []
         L.fe_release_caches.restype = None
+        L.fe_autotune_clear.argtypes = []
+        L.fe_autotune_clear.restype = None
         L.fe_version.restype = ctypes.c_char_p
         L.fe_csr_create.argtypes = [ctypes.c_int64, ctypes.c_int, vp, ctypes.c_int64, vp, ctypes.POINTER(vp)]
         L.fe_csr_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
