@@ -274,6 +274,28 @@ def test_elasticity_preevaluated(cell, p):
         assert np.array_equal(A2[~bad], A[~bad])
 
 
+def test_release_caches_then_rebuild():
+    """Releasing every cache between calls (reference, coefficient and
+    elasticity tables, autotune entries) rebuilds them on the next call with
+    the same results."""
+    cases = [("helmholtz", "tetrahedron", 2, {}), ("mass", "tetrahedron", 2, {"nf": 1}),
+             ("elasticity", "tetrahedron", 4, {"mode": "preeval"}), ("hyperelastic", "tetrahedron", 1, {})]
+    runs = []
+    for form, cell, p, kw in cases:
+        coords, V, cells, h = mesh(cell, 40, seed=530)
+        if kw.get("nf"):
+            cf = np.random.default_rng(531).uniform(0.5, 1.5, size=(40, 1, oracle.nbasis(cell, p)))
+        else:
+            cf = coefficients(form, cell, p, 40, V, cells, h, seed=532)
+        runs.append((form, cell, p, kw, coords, cf))
+    first = [gpu_assemble(form, cell, p, coords, cf, **kw)[0] for form, cell, p, kw, coords, cf in runs]
+    torch.cuda.synchronize()
+    felocal.lib().fe_release_caches()
+    second = [gpu_assemble(form, cell, p, coords, cf, **kw)[0] for form, cell, p, kw, coords, cf in runs]
+    for a, b in zip(first, second):
+        assert np.array_equal(a, b)
+
+
 def test_elasticity_preevaluated_refusals():
     coords, V, cells, h = mesh("tetrahedron", 20, seed=520)
     u = coefficients("hyperelastic", "tetrahedron", 2, 20, V, cells, h, seed=521)
