@@ -114,7 +114,7 @@ struct fe_batch {
     };
     std::vector<Group> groups;
     // elasticity sub-batches that Algorithm 3 pre-evaluates: the pre-evaluated
-    // elasticity kernel, one launch each, on a branch of their own
+    // elasticity kernel, one launch each, each on a branch of its own
     struct ElastSub {
         int cell = 0, ns = 0;
         const double* coords = nullptr;
@@ -300,7 +300,7 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
         b->groups.push_back(g);
     }
     const int ng = (int)b->groups.size();
-    const int nbr = ng + (b->elast.empty() ? 0 : 1);   // parallel branches of the graph
+    const int nbr = ng + (int)b->elast.size();   // parallel branches of the graph
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_counters, sizeof(unsigned long long) * std::max(1, ng));
     if (e != hipSuccess) {
         destroy(b);
@@ -335,15 +335,13 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
         if (e == hipSuccess) e = hipEventRecord(done[i], br[i]);
         if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[i], 0);
     }
-    if (nbr > ng && e == hipSuccess) {
-        e = hipStreamWaitEvent(br[ng], start, 0);
-        for (size_t k = 0; k < b->elast.size() && e == hipSuccess; ++k) {
-            const fe_batch::ElastSub& es = b->elast[k];
-            e = launch_preeval_elast(es.cell, es.coords, es.coeff, es.out, o.d_status, es.T, es.E, es.ns, 2, cus,
-                                     br[ng]);
-        }
-        if (e == hipSuccess) e = hipEventRecord(done[ng], br[ng]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[ng], 0);
+    for (int i = ng; i < nbr && e == hipSuccess; ++i) {
+        const fe_batch::ElastSub& es = b->elast[i - ng];
+        e = hipStreamWaitEvent(br[i], start, 0);
+        if (e == hipSuccess)
+            e = launch_preeval_elast(es.cell, es.coords, es.coeff, es.out, o.d_status, es.T, es.E, es.ns, 2, cus, br[i]);
+        if (e == hipSuccess) e = hipEventRecord(done[i], br[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[i], 0);
     }
     if (capturing) {
         const hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
