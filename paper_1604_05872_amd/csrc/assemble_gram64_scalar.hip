@@ -31,7 +31,11 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int GS_WAVES = 4;
+// wavefronts (elements) per block: the point chunks' tables are staged once
+// per block, so prisms (the largest tables) share them among 8; 4 elsewhere
+// (measured on MI355X: non-affine Helmholtz prism P3 20.8 -> 13.3 ms with 8,
+// tetrahedra with large rules a few per cent slower with 8)
+__host__ __device__ constexpr int gs_waves(int cell) { return cell == PRISM ? 8 : 4; }
 constexpr int GS_QC = 32;                       // points per staged chunk
 constexpr int GS_PT = 12;                       // doubles per staged point: root, K (9), pad
 constexpr int GS_TILE_LD = 17;
@@ -90,8 +94,9 @@ __device__ __forceinline__ void gs_operands(int R0, int nrows, int NC, int c_fir
 }
 
 template <int FORM, int CELL, int P>
-__global__ __launch_bounds__(GS_WAVES * 64) void k_gram64_scalar(GramScalarArgs a)
+__global__ __launch_bounds__(gs_waves(CELL) * 64) void k_gram64_scalar(GramScalarArgs a)
 {
+    constexpr int GS_WAVES = gs_waves(CELL);
     constexpr int D = cell_dim(CELL), NV = cell_nv(CELL), NVD = NV * D;
     constexpr int NS = n_scalar(CELL, P);
     constexpr int T = (NS + 15) / 16;
@@ -240,12 +245,12 @@ template <int FORM, int CELL>
 hipError_t launch_p(int p, const GramScalarArgs& a, int grid, size_t lds, hipStream_t s)
 {
     switch (p) {
-    case 1: k_gram64_scalar<FORM, CELL, 1><<<grid, GS_WAVES * 64, lds, s>>>(a); break;
-    case 2: k_gram64_scalar<FORM, CELL, 2><<<grid, GS_WAVES * 64, lds, s>>>(a); break;
-    case 3: k_gram64_scalar<FORM, CELL, 3><<<grid, GS_WAVES * 64, lds, s>>>(a); break;
+    case 1: k_gram64_scalar<FORM, CELL, 1><<<grid, gs_waves(CELL) * 64, lds, s>>>(a); break;
+    case 2: k_gram64_scalar<FORM, CELL, 2><<<grid, gs_waves(CELL) * 64, lds, s>>>(a); break;
+    case 3: k_gram64_scalar<FORM, CELL, 3><<<grid, gs_waves(CELL) * 64, lds, s>>>(a); break;
     default:
         if constexpr (CELL != PRISM) {
-            k_gram64_scalar<FORM, CELL, 4><<<grid, GS_WAVES * 64, lds, s>>>(a);
+            k_gram64_scalar<FORM, CELL, 4><<<grid, gs_waves(CELL) * 64, lds, s>>>(a);
             break;
         }
         return hipErrorInvalidValue;
@@ -258,9 +263,9 @@ hipError_t launch_p(int p, const GramScalarArgs& a, int grid, size_t lds, hipStr
 size_t gram64_scalar_lds_bytes(int cell, int p)
 {
     const int ns = n_scalar(cell, p);
-    return sizeof(double) * ((size_t)GS_WAVES * GS_WAVE_DOUBLES + (size_t)GS_QC * ns * (1 + cell_dim(cell)));
+    return sizeof(double) * ((size_t)gs_waves(cell) * GS_WAVE_DOUBLES + (size_t)GS_QC * ns * (1 + cell_dim(cell)));
 }
-int gram64_scalar_elems_per_block() { return GS_WAVES; }
+int gram64_scalar_elems_per_block(int cell) { return gs_waves(cell); }
 
 hipError_t launch_gram64_scalar(int form, int cell, int p, const GramScalarArgs& a, int grid, hipStream_t s)
 {

@@ -608,7 +608,8 @@ int launch_call(const Call& c, const Config& cfg)
         g.skip = c.nf > 0 ? c.mass_pre : 0;
         g.pointgeo = c.pointgeo;
         g.nt = store_mode();
-        const int64_t blocks = (c.E + gram64_scalar_elems_per_block() - 1) / gram64_scalar_elems_per_block();
+        const int64_t blocks =
+            (c.E + gram64_scalar_elems_per_block(c.cell) - 1) / gram64_scalar_elems_per_block(c.cell);
         const int grid = (int)std::min<int64_t>(blocks, (int64_t)cus * cfg.grid_per_cu);
         e = launch_gram64_scalar(c.form, c.cell, c.degree, g, grid, c.stream);
         if (e != hipSuccess) return set_hip_error(e, "float64 matrix-core launch");

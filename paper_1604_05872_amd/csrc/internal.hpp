@@ -86,7 +86,7 @@ struct GramScalarArgs {
 };
 hipError_t launch_gram64_scalar(int form, int cell, int p, const GramScalarArgs& a, int grid, hipStream_t s);
 size_t gram64_scalar_lds_bytes(int cell, int p);
-int gram64_scalar_elems_per_block();
+int gram64_scalar_elems_per_block(int cell);
 // assemble_vec_p1.hip: the vector forms at degree 1 on simplices (every
 // gradient constant, the point loop hoisted), float64
 struct VecP1Args {
