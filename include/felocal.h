@@ -264,7 +264,7 @@ int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int qdeg, size_t
  * stay valid until fe_batch_destroy.  Every sub-batch uses FE_FP64 and the
  * mode Algorithm 3 chooses for it (tiled pre-evaluated or VALU quadrature
  * tiles; elasticity sub-batches that it pre-evaluates run the pre-evaluated
- * elasticity kernel, one launch each on a branch of its own);
+ * elasticity kernel, one launch each, in sequence after the groups);
  * tile sizes come from the autotune cache (fe_autotune) when
  * present, else from built-in defaults.  Sub-batches with no elements are
  * allowed and do nothing.  Replays on one stream are ordered; replays of

@@ -60,11 +60,11 @@ Config default_for(const Call& c)
 {
     if (c.prec != FE_FP64) return Config();
     if (c.mode == FE_MODE_PREEVAL && c.form == ELASTICITY) {
-        // two resident workgroups per CU: fewer tiles write partial lines at
-        // once, so the L2 merges them (measured on MI355X; one is better for
-        // some shapes, which the autotuner finds)
+        // resident workgroups per CU by matrix width: the fewer tiles write
+        // partial lines at once, the more of them the L2 merges (measured on
+        // MI355X; the autotuner may find a better count for a given shape)
         Config x;
-        x.grid_per_cu = 2;
+        x.grid_per_cu = preeval_elast_grid_per_cu(c.tables->nb);
         return x;
     }
     if (c.mode == FE_MODE_PREEVAL && c.nf > 0) return Config();
