@@ -274,6 +274,24 @@ def test_elasticity_preevaluated(cell, p):
         assert np.array_equal(A2[~bad], A[~bad])
 
 
+@pytest.mark.parametrize("cell,p,E", [("tetrahedron", 4, 2100), ("prism", 4, 1210)])
+def test_elasticity_preevaluated_many_units(cell, p, E):
+    """More (tile, column-range) units than workgroups, so every workgroup
+    takes several, and a ragged last tile: sampled elements (every 17th and
+    the last 20) against the oracle, at one and two workgroups per CU."""
+    log(f"elasticity pre-evaluated, many units: {cell} P{p} E={E}")
+    coords, V, cells, h = mesh(cell, E, seed=540)
+    cf = coefficients("elasticity", cell, p, E, V, cells, h, seed=541)
+    idx = np.unique(np.r_[np.arange(0, E, 17), np.arange(E - 20, E)])
+    B, fl = oracle.assemble("elasticity", cell, p, coords[idx], cf[idx])
+    assert fl == 0
+    for g in (1, 2):
+        A, st = gpu_assemble("elasticity", cell, p, coords, cf, mode="preeval", shape={"grid_per_cu": g})
+        assert st == 0
+        assert np.isfinite(A).all()
+        assert normwise(A[idx], B).max() <= TOL["fp64"]
+
+
 def test_release_caches_then_rebuild():
     """Releasing every cache between calls (reference, coefficient and
     elasticity tables, autotune entries) rebuilds them on the next call with
