@@ -18,7 +18,8 @@
 //   * Step 6 emits the loop nest: per point, each factorised test symbol u
 //     gets a hoisted temporary h_u(k) = sum over its products of c s_trial(k)
 //     (Strategy 2), each factorised trial symbol v a temporary h_v(j); the
-//     innermost (j, k) body has one multiply-add per factorised symbol.
+//     innermost (j, k) body has one multiply-add per factorised symbol,
+//     accumulated in per-lane register tiles of the element matrix.
 // The kernel is written out as HIP source for the form, the cell and the
 // degree, compiled at run time with hipRTC for the current device, and
 // cached.  fe_options_t.shape.kernel = 5 selects the expanded loop nest
@@ -26,6 +27,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -152,8 +154,42 @@ int default_form_qdeg(const fe_form_spec_t* s, int p)
 
 const char* SYMNAME[4] = {"s0", "s1", "s2", "s3"};
 
-// HIP source of the quadrature kernel of one form (one wavefront per
-// element, lane j < NS owns row j of the element matrix).
+// Register tile of the generated nest.  Each lane owns a TR x TC block of
+// the element matrix, so one K step costs TR + TC LDS reads and TR * TC
+// multiply-adds per lane.  The tile minimises the larger of the two per K
+// step: the VALU time (4 cycles per wavefront float64 multiply-add) and the
+// LDS time (a wavefront read of one double returns 512 bytes, at 128 bytes
+// per clock shared by the four SIMDs of a CU: 16 cycles).
+void pick_tile(int ns, int* tr, int* tc)
+{
+    *tr = *tc = 8;
+    double best = 1e30;
+    for (int lim : {40, 64}) {
+        bool found = false;
+        for (int a = 1; a <= 8; ++a)
+            for (int b = 1; b <= 8; ++b) {
+                const int rt = (ns + a - 1) / a, ct = (ns + b - 1) / b;
+                if (a * b > lim || rt * ct > 64 || rt * a > 64 || ct * b > 64) continue;
+                const double cost = std::max(4.0 * a * b, 16.0 * (a + b));
+                if (cost < best || (cost == best && a * b < *tr * *tc)) {
+                    best = cost;
+                    *tr = a;
+                    *tc = b;
+                    found = true;
+                }
+            }
+        if (found) return;
+    }
+}
+
+// HIP source of the quadrature kernel of one form: one wavefront per
+// element.  Per point, lane i computes the symbols of basis function i and
+// from them the row factor X_f(i) and the column factor Y_f(i) of every K
+// step f; the element matrix is the sum over points and K steps of
+// X_f Y_f^T, accumulated in register tiles.  Sharing-eliminated: one K step
+// per factorised symbol (test symbol u: X = w s_u, Y = h_u, the hoisted sum
+// of c_e s_trial over its products; trial symbol v: X = w h_v, Y = s_v).
+// Expanded: one K step per product (X = w c_e s_test, Y = s_trial).
 std::string generate(const fe_form_spec_t* s, const Graph& g, const int* x, const int* owner, int cell, int p,
                      bool expanded)
 {
@@ -161,12 +197,47 @@ std::string generate(const fe_form_spec_t* s, const Graph& g, const int* x, cons
     for (int i = 0; i < g.nv; ++i) any |= x[i] != 0;
     expanded = expanded || !any;
     const int d = cell_dim(cell), nv = cell_nv(cell), ns = n_scalar(cell, p);
+    // the K steps: (row factor, column factor) expressions in the symbols of
+    // the lane's own basis function
+    std::vector<std::string> xs, ys;
+    auto coef_sum = [&](int i, bool test_side) {
+        std::string t = "(0.0";
+        for (int e = 0; e < g.ne; ++e)
+            if (owner[e] == i) t += std::string(" + c") + std::to_string(e) + " * " + SYMNAME[g.sym[test_side ? g.et[e] : g.er[e]]];
+        return t + ")";
+    };
+    if (expanded) {
+        for (int e = 0; e < g.ne; ++e) {
+            xs.push_back(std::string("wq * c") + std::to_string(e) + " * " + SYMNAME[g.sym[g.et[e]]]);
+            ys.push_back(SYMNAME[g.sym[g.er[e]]]);
+        }
+    } else {
+        for (int i = 0; i < g.nv; ++i) {
+            if (!x[i]) continue;
+            if (g.side[i] == 0) {
+                xs.push_back(std::string("wq * ") + SYMNAME[g.sym[i]]);
+                ys.push_back(coef_sum(i, false));
+            } else {
+                xs.push_back("wq * " + coef_sum(i, true));
+                ys.push_back(SYMNAME[g.sym[i]]);
+            }
+        }
+    }
+    const int nk = (int)xs.size();
+    int tr = 1, tc = 1;
+    pick_tile(ns, &tr, &tc);
+    const int rt = (ns + tr - 1) / tr, ct = (ns + tc - 1) / tc;
+    // two buffers of factors per wavefront (one wave_sync per point) when
+    // they fit in 48 KiB per block
+    const int nbuf = 2 * 4 * nk * (rt * tr + ct * tc) * 8 <= 48 * 1024 ? 2 : 1;
     std::ostringstream o;
     o.precision(17);
     o << "// generated: scalar bilinear form, cell " << cell << ", degree " << p
       << (expanded ? ", expanded products\n" : ", sharing-eliminated\n");
     o << "#define NS " << ns << "\n#define D " << d << "\n#define NV " << nv << "\n#define NF " << s->n_fields
-      << "\n";
+      << "\n#define NK " << nk << "\n#define TR " << tr << "\n#define TC " << tc << "\n#define RT " << rt
+      << "\n#define CT " << ct << "\n#define NXP " << rt * tr << "\n#define NYP " << ct * tc << "\n#define NBUF "
+      << nbuf << "\n";
     o << R"(
 __device__ static inline void wave_sync()
 {
@@ -180,12 +251,12 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
     int* __restrict__ status, const double* __restrict__ W, const double* __restrict__ phi,
     const double* __restrict__ dphi, const double* __restrict__ psi, long long E, int nq)
 {
-    __shared__ double sS[4][4][NS];    // symbols of the current point, per wavefront
-)";
-    int nht = 0;   // factorised test symbols: temporaries over k in LDS
-    for (int i = 0; i < g.nv; ++i) nht += (!expanded && x[i] && g.side[i] == 0);
-    if (nht) o << "    __shared__ double sH[4][" << nht << "][NS];\n";
-    o << R"(    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // row and column factors of the current point, per wavefront
+    __shared__ double sX[4][NBUF][NK][NXP];
+    __shared__ double sY[4][NBUF][NK][NYP];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int rt = lane / CT, ct = lane - (lane / CT) * CT;
+    const bool act = lane < RT * CT;
     for (long long e = (long long)blockIdx.x * 4 + wv; e < E; e += (long long)gridDim.x * 4) {
         double v[NV * D];
         for (int i = 0; i < NV * D; ++i) v[i] = coords[e * NV * D + i];
@@ -223,23 +294,34 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
                     if (__builtin_fabs((v[(t + 3) * 3 + r] - v[t * 3 + r]) - (v[9 + r] - v[r])) > 1e-12 * (vmax > 0 ? vmax : 1.0))
                         bad = 1;
         }
-        double acc[NS];
+        double acc[TR][TC];
 #pragma unroll
-        for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+        for (int r = 0; r < TR; ++r)
+#pragma unroll
+            for (int c = 0; c < TC; ++c) acc[r][c] = 0.0;
+        // reference value and gradient of basis function `lane`, one point
+        // ahead (zero for lanes past the basis, whose factors are then zero)
+        double np = 0.0, ng0 = 0.0, ng1 = 0.0, ng2 = 0.0;
+        if (lane < NS) {
+            np = phi[lane];
+            ng0 = dphi[lane * D];
+            ng1 = dphi[lane * D + 1];
+            if (D == 3) ng2 = dphi[lane * D + D - 1];
+        }
         for (int q = 0; q < nq; ++q) {
-            // symbols of basis function `lane` at the point
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            if (lane < NS) {
-                s0 = phi[q * NS + lane];
-                const double* gh = dphi + (q * NS + lane) * D;
-                s1 = K[0][0] * gh[0] + K[1][0] * gh[1] + (D == 3 ? K[2][0] * gh[D - 1] : 0.0);
-                s2 = K[0][1] * gh[0] + K[1][1] * gh[1] + (D == 3 ? K[2][1] * gh[D - 1] : 0.0);
-                s3 = D == 3 ? K[0][2] * gh[0] + K[1][2] * gh[1] + K[2][2] * gh[D - 1] : 0.0;
-                sS[wv][0][lane] = s0;
-                sS[wv][1][lane] = s1;
-                sS[wv][2][lane] = s2;
-                sS[wv][3][lane] = s3;
+            const double h0 = ng0, h1 = ng1, h2 = ng2;
+            const double s0 = np;
+            if (lane < NS && q + 1 < nq) {
+                np = phi[(q + 1) * NS + lane];
+                ng0 = dphi[((q + 1) * NS + lane) * D];
+                ng1 = dphi[((q + 1) * NS + lane) * D + 1];
+                if (D == 3) ng2 = dphi[((q + 1) * NS + lane) * D + D - 1];
             }
+            // symbols of basis function `lane` at the point
+            const double s1 = K[0][0] * h0 + K[1][0] * h1 + (D == 3 ? K[2][0] * h2 : 0.0);
+            const double s2 = K[0][1] * h0 + K[1][1] * h1 + (D == 3 ? K[2][1] * h2 : 0.0);
+            const double s3 = D == 3 ? K[0][2] * h0 + K[1][2] * h1 + K[2][2] * h2 : 0.0;
+            (void)s0; (void)s1; (void)s2; (void)s3;
             // the coefficient of every product at the point
             double f[NF > 0 ? NF : 1];
             for (int i = 0; i < NF; ++i) {
@@ -249,7 +331,6 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
             }
             (void)f;
 )";
-    // coefficient of each product: sum of its terms
     for (int e = 0; e < g.ne; ++e) {
         o << "            const double c" << e << " = 0.0";
         for (int t : g.terms_of[e]) {
@@ -259,55 +340,44 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
         o << ";\n";
     }
     o << "            const double wq = W[q] * adet;\n";
-    if (expanded) {
-        o << "            wave_sync();\n            if (lane < NS) {\n";
-        for (int e = 0; e < g.ne; ++e)
-            o << "                const double a" << e << " = wq * c" << e << " * " << SYMNAME[g.sym[g.et[e]]] << ";\n";
-        o << "#pragma unroll\n                for (int k = 0; k < NS; ++k) {\n                    double t = acc[k];\n";
-        for (int e = 0; e < g.ne; ++e) o << "                    t += a" << e << " * sS[wv][" << g.sym[g.er[e]] << "][k];\n";
-        o << "                    acc[k] = t;\n                }\n            }\n";
-    } else {
-        // temporaries of factorised test symbols: h_u(k) over the products grouped under u
-        int h = 0;
-        for (int i = 0; i < g.nv; ++i) {
-            if (!(x[i] && g.side[i] == 0)) continue;
-            o << "            if (lane < NS) sH[wv][" << h << "][lane] = 0.0";
-            for (int e = 0; e < g.ne; ++e)
-                if (owner[e] == i) o << " + c" << e << " * " << SYMNAME[g.sym[g.er[e]]];
-            o << ";\n";
-            ++h;
-        }
-        o << "            wave_sync();\n            if (lane < NS) {\n";
-        // per-row factors: w s_u(j) for factorised test symbols, w h_v(j) for trial ones
-        h = 0;
-        for (int i = 0; i < g.nv; ++i) {
-            if (!x[i]) continue;
-            if (g.side[i] == 0) {
-                o << "                const double a" << i << " = wq * " << SYMNAME[g.sym[i]] << ";\n";
-            } else {
-                o << "                const double a" << i << " = wq * (0.0";
-                for (int e = 0; e < g.ne; ++e)
-                    if (owner[e] == i) o << " + c" << e << " * " << SYMNAME[g.sym[g.et[e]]];
-                o << ");\n";
-            }
-        }
-        o << "#pragma unroll\n                for (int k = 0; k < NS; ++k) {\n                    double t = acc[k];\n";
-        h = 0;
-        for (int i = 0; i < g.nv; ++i) {
-            if (!x[i]) continue;
-            if (g.side[i] == 0) o << "                    t += a" << i << " * sH[wv][" << h++ << "][k];\n";
-            else o << "                    t += a" << i << " * sS[wv][" << g.sym[i] << "][k];\n";
-        }
-        o << "                    acc[k] = t;\n                }\n            }\n";
+    o << "            const int b = NBUF == 2 ? (q & 1) : 0;\n";
+    for (int k = 0; k < nk; ++k) {
+        o << "            if (lane < NXP) sX[wv][b][" << k << "][lane] = " << xs[k] << ";\n";
+        o << "            if (lane < NYP) sY[wv][b][" << k << "][lane] = " << ys[k] << ";\n";
     }
     o << R"(            wave_sync();
-        }
-        if (lane < NS) {
-            double* row = out + (e * NS + lane) * NS;
+            if (act) {
 #pragma unroll
-            for (int k = 0; k < NS; ++k) row[k] = bad ? __builtin_nan("") : acc[k];
+                for (int f = 0; f < NK; ++f) {
+                    double xr[TR], yc[TC];
+#pragma unroll
+                    for (int r = 0; r < TR; ++r) xr[r] = sX[wv][b][f][rt * TR + r];
+#pragma unroll
+                    for (int c = 0; c < TC; ++c) yc[c] = sY[wv][b][f][ct * TC + c];
+#pragma unroll
+                    for (int r = 0; r < TR; ++r)
+#pragma unroll
+                        for (int c = 0; c < TC; ++c) acc[r][c] = __builtin_fma(xr[r], yc[c], acc[r][c]);
+                }
+            }
+            if (NBUF == 1) wave_sync();
+        }
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < TR; ++r) {
+                const int j = rt * TR + r;
+                if (j < NS) {
+                    double* row = out + (e * NS + j) * NS;
+#pragma unroll
+                    for (int c = 0; c < TC; ++c) {
+                        const int k = ct * TC + c;
+                        if (k < NS) row[k] = bad ? __builtin_nan("") : acc[r][c];
+                    }
+                }
+            }
         }
         if (bad && lane == 0 && status) atomicAdd(status, 1);
+        wave_sync();
     }
 }
 )";

@@ -53,7 +53,10 @@ def run(terms, cell, p, coords, fields, nf, expanded=False):
     return out.cpu().numpy(), int(st.item())
 
 
-CASES = [(f, c, p) for f in sorted(FORMS) for c in ("triangle", "tetrahedron", "prism") for p in (1, 2, 3)]
+# degrees 1-4 (prisms 1-3: P4 has more than 64 basis functions); P4 on
+# tetrahedra (35 rows) pads the register tiles past the last row
+CASES = [(f, c, p) for f in sorted(FORMS) for c in ("triangle", "tetrahedron", "prism")
+         for p in ((1, 2, 3) if c == "prism" else (1, 2, 3, 4))]
 
 
 @pytest.mark.parametrize("expanded", [False, True])
