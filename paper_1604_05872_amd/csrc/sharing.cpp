@@ -154,36 +154,44 @@ int default_form_qdeg(const fe_form_spec_t* s, int p)
 
 const char* SYMNAME[4] = {"s0", "s1", "s2", "s3"};
 
-// Register tile of the generated nest.  Each lane owns a TR x TC block of
-// the element matrix, so one K step costs TR + TC LDS reads and TR * TC
-// multiply-adds per lane.  The tile minimises the larger of the two per K
+// Layout of the generated nest.  A wavefront holds EPW elements, LPE =
+// 64 / EPW lanes each, and each lane owns a TR x TC block of its element's
+// matrix, so one K step costs TR + TC LDS reads and TR * TC multiply-adds per
+// lane.  The layout minimises, per element, the larger of the two per K
 // step: the VALU time (4 cycles per wavefront float64 multiply-add) and the
 // LDS time (a wavefront read of one double returns 512 bytes, at 128 bytes
-// per clock shared by the four SIMDs of a CU: 16 cycles).
-void pick_tile(int ns, int* tr, int* tc)
+// per clock shared by the four SIMDs of a CU: 16 cycles), both shared by the
+// EPW elements of the wavefront.
+void pick_layout(int ns, int* epw, int* tr, int* tc)
 {
+    *epw = 1;
     *tr = *tc = 8;
     double best = 1e30;
     for (int lim : {40, 64}) {
         bool found = false;
-        for (int a = 1; a <= 8; ++a)
-            for (int b = 1; b <= 8; ++b) {
-                const int rt = (ns + a - 1) / a, ct = (ns + b - 1) / b;
-                if (a * b > lim || rt * ct > 64 || rt * a > 64 || ct * b > 64) continue;
-                const double cost = std::max(4.0 * a * b, 16.0 * (a + b));
-                if (cost < best || (cost == best && a * b < *tr * *tc)) {
-                    best = cost;
-                    *tr = a;
-                    *tc = b;
-                    found = true;
+        for (int w = 1; w <= 8; w *= 2) {
+            const int lpe = 64 / w;
+            if (ns > lpe) continue;
+            for (int a = 1; a <= 8; ++a)
+                for (int b = 1; b <= 8; ++b) {
+                    const int rt = (ns + a - 1) / a, ct = (ns + b - 1) / b;
+                    if (a * b > lim || rt * ct > lpe || rt * a > lpe || ct * b > lpe) continue;
+                    const double cost = std::max(4.0 * a * b, 16.0 * (a + b)) / w;
+                    if (cost < best || (cost == best && a * b < *tr * *tc)) {
+                        best = cost;
+                        *epw = w;
+                        *tr = a;
+                        *tc = b;
+                        found = true;
+                    }
                 }
-            }
+        }
         if (found) return;
     }
 }
 
-// HIP source of the quadrature kernel of one form: one wavefront per
-// element.  Per point, lane i computes the symbols of basis function i and
+// HIP source of the quadrature kernel of one form: EPW elements per
+// wavefront.  Per point, lane i of an element computes the symbols of basis function i and
 // from them the row factor X_f(i) and the column factor Y_f(i) of every K
 // step f; the element matrix is the sum over points and K steps of
 // X_f Y_f^T, accumulated in register tiles.  Sharing-eliminated: one K step
@@ -224,12 +232,12 @@ std::string generate(const fe_form_spec_t* s, const Graph& g, const int* x, cons
         }
     }
     const int nk = (int)xs.size();
-    int tr = 1, tc = 1;
-    pick_tile(ns, &tr, &tc);
+    int epw = 1, tr = 1, tc = 1;
+    pick_layout(ns, &epw, &tr, &tc);
     const int rt = (ns + tr - 1) / tr, ct = (ns + tc - 1) / tc;
     // two buffers of factors per wavefront (one wave_sync per point) when
     // they fit in 48 KiB per block
-    const int nbuf = 2 * 4 * nk * (rt * tr + ct * tc) * 8 <= 48 * 1024 ? 2 : 1;
+    const int nbuf = 2 * 4 * epw * nk * (rt * tr + ct * tc) * 8 <= 48 * 1024 ? 2 : 1;
     std::ostringstream o;
     o.precision(17);
     o << "// generated: scalar bilinear form, cell " << cell << ", degree " << p
@@ -237,7 +245,7 @@ std::string generate(const fe_form_spec_t* s, const Graph& g, const int* x, cons
     o << "#define NS " << ns << "\n#define D " << d << "\n#define NV " << nv << "\n#define NF " << s->n_fields
       << "\n#define NK " << nk << "\n#define TR " << tr << "\n#define TC " << tc << "\n#define RT " << rt
       << "\n#define CT " << ct << "\n#define NXP " << rt * tr << "\n#define NYP " << ct * tc << "\n#define NBUF "
-      << nbuf << "\n";
+      << nbuf << "\n#define EPW " << epw << "\n#define LPE " << 64 / epw << "\n";
     o << R"(
 __device__ static inline void wave_sync()
 {
@@ -252,12 +260,16 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
     const double* __restrict__ dphi, const double* __restrict__ psi, long long E, int nq)
 {
     // row and column factors of the current point, per wavefront
-    __shared__ double sX[4][NBUF][NK][NXP];
-    __shared__ double sY[4][NBUF][NK][NYP];
+    __shared__ double sX[4][NBUF][EPW][NK][NXP];
+    __shared__ double sY[4][NBUF][EPW][NK][NYP];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int rt = lane / CT, ct = lane - (lane / CT) * CT;
-    const bool act = lane < RT * CT;
-    for (long long e = (long long)blockIdx.x * 4 + wv; e < E; e += (long long)gridDim.x * 4) {
+    const int sub = lane / LPE, li = lane - sub * LPE;     // element of the wavefront, lane within it
+    const int rt = li / CT, ct = li - (li / CT) * CT;
+    const bool act = li < RT * CT;
+    for (long long e0 = ((long long)blockIdx.x * 4 + wv) * EPW; e0 < E; e0 += (long long)gridDim.x * 4 * EPW) {
+        // lanes of an element past the end work on the last one and store nothing
+        const bool valid = e0 + sub < E;
+        const long long e = valid ? e0 + sub : E - 1;
         double v[NV * D];
         for (int i = 0; i < NV * D; ++i) v[i] = coords[e * NV * D + i];
         double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, K[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -299,25 +311,25 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
         for (int r = 0; r < TR; ++r)
 #pragma unroll
             for (int c = 0; c < TC; ++c) acc[r][c] = 0.0;
-        // reference value and gradient of basis function `lane`, one point
+        // reference value and gradient of basis function `li`, one point
         // ahead (zero for lanes past the basis, whose factors are then zero)
         double np = 0.0, ng0 = 0.0, ng1 = 0.0, ng2 = 0.0;
-        if (lane < NS) {
-            np = phi[lane];
-            ng0 = dphi[lane * D];
-            ng1 = dphi[lane * D + 1];
-            if (D == 3) ng2 = dphi[lane * D + D - 1];
+        if (li < NS) {
+            np = phi[li];
+            ng0 = dphi[li * D];
+            ng1 = dphi[li * D + 1];
+            if (D == 3) ng2 = dphi[li * D + D - 1];
         }
         for (int q = 0; q < nq; ++q) {
             const double h0 = ng0, h1 = ng1, h2 = ng2;
             const double s0 = np;
-            if (lane < NS && q + 1 < nq) {
-                np = phi[(q + 1) * NS + lane];
-                ng0 = dphi[((q + 1) * NS + lane) * D];
-                ng1 = dphi[((q + 1) * NS + lane) * D + 1];
-                if (D == 3) ng2 = dphi[((q + 1) * NS + lane) * D + D - 1];
+            if (li < NS && q + 1 < nq) {
+                np = phi[(q + 1) * NS + li];
+                ng0 = dphi[((q + 1) * NS + li) * D];
+                ng1 = dphi[((q + 1) * NS + li) * D + 1];
+                if (D == 3) ng2 = dphi[((q + 1) * NS + li) * D + D - 1];
             }
-            // symbols of basis function `lane` at the point
+            // symbols of basis function `li` at the point
             const double s1 = K[0][0] * h0 + K[1][0] * h1 + (D == 3 ? K[2][0] * h2 : 0.0);
             const double s2 = K[0][1] * h0 + K[1][1] * h1 + (D == 3 ? K[2][1] * h2 : 0.0);
             const double s3 = D == 3 ? K[0][2] * h0 + K[1][2] * h1 + K[2][2] * h2 : 0.0;
@@ -342,8 +354,8 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
     o << "            const double wq = W[q] * adet;\n";
     o << "            const int b = NBUF == 2 ? (q & 1) : 0;\n";
     for (int k = 0; k < nk; ++k) {
-        o << "            if (lane < NXP) sX[wv][b][" << k << "][lane] = " << xs[k] << ";\n";
-        o << "            if (lane < NYP) sY[wv][b][" << k << "][lane] = " << ys[k] << ";\n";
+        o << "            if (li < NXP) sX[wv][b][sub][" << k << "][li] = " << xs[k] << ";\n";
+        o << "            if (li < NYP) sY[wv][b][sub][" << k << "][li] = " << ys[k] << ";\n";
     }
     o << R"(            wave_sync();
             if (act) {
@@ -351,9 +363,9 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
                 for (int f = 0; f < NK; ++f) {
                     double xr[TR], yc[TC];
 #pragma unroll
-                    for (int r = 0; r < TR; ++r) xr[r] = sX[wv][b][f][rt * TR + r];
+                    for (int r = 0; r < TR; ++r) xr[r] = sX[wv][b][sub][f][rt * TR + r];
 #pragma unroll
-                    for (int c = 0; c < TC; ++c) yc[c] = sY[wv][b][f][ct * TC + c];
+                    for (int c = 0; c < TC; ++c) yc[c] = sY[wv][b][sub][f][ct * TC + c];
 #pragma unroll
                     for (int r = 0; r < TR; ++r)
 #pragma unroll
@@ -362,7 +374,7 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
             }
             if (NBUF == 1) wave_sync();
         }
-        if (act) {
+        if (act && valid) {
 #pragma unroll
             for (int r = 0; r < TR; ++r) {
                 const int j = rt * TR + r;
@@ -376,7 +388,7 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
                 }
             }
         }
-        if (bad && lane == 0 && status) atomicAdd(status, 1);
+        if (bad && valid && li == 0 && status) atomicAdd(status, 1);
         wave_sync();
     }
 }
