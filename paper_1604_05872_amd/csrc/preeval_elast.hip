@@ -32,7 +32,10 @@ constexpr int BUFFER_WORD3 = 0x00020000;
 
 namespace {
 
-constexpr int PE_WAVES = 4;
+// wavefronts per workgroup: eight on prisms, whose coefficient rows are the
+// largest to form and whose units hold the most column groups (prism P4
+// 1.79 -> 1.65 ms on MI355X), four elsewhere (eight are slower there)
+__host__ __device__ constexpr int pe_waves(int cell) { return cell == PRISM ? 8 : 4; }
 
 // T[((l * d + a) * d + b)][j * ns + k]
 __global__ void k_elast_tables(int nq, int ns, int d, int nc, const double* __restrict__ W,
@@ -61,8 +64,9 @@ struct ElastArgs {
 };
 
 template <int CELL>
-__global__ __launch_bounds__(64 * PE_WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_preeval_elast(ElastArgs a)
+__global__ __launch_bounds__(64 * pe_waves(CELL)) __attribute__((amdgpu_waves_per_eu(2))) void k_preeval_elast(ElastArgs a)
 {
+    constexpr int PE_WAVES = pe_waves(CELL);
     constexpr int D = cell_dim(CELL), NC = cell_nv(CELL), NVD = NC * D;
     constexpr int NT = NC * D * D, NTP = (NT + 7) / 8 * 8, NB = D * D, NK = NTP / 4;
     // coefficient rows [block][element][(l, a, b)], rows NTP + 1 doubles apart
@@ -230,9 +234,9 @@ hipError_t launch_preeval_elast(int cell, const double* coords, const double* co
     a.parts = std::max(1, std::min(ncb, std::max(by_width, by_count)));
     const int64_t units = tiles * a.parts;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(units, (int64_t)cus * grid_per_cu));
-    if (cell == TRI) hipLaunchKernelGGL((k_preeval_elast<TRI>), dim3(grid), dim3(64 * PE_WAVES), 0, s, a);
-    else if (cell == TET) hipLaunchKernelGGL((k_preeval_elast<TET>), dim3(grid), dim3(64 * PE_WAVES), 0, s, a);
-    else hipLaunchKernelGGL((k_preeval_elast<PRISM>), dim3(grid), dim3(64 * PE_WAVES), 0, s, a);
+    if (cell == TRI) hipLaunchKernelGGL((k_preeval_elast<TRI>), dim3(grid), dim3(64 * pe_waves(TRI)), 0, s, a);
+    else if (cell == TET) hipLaunchKernelGGL((k_preeval_elast<TET>), dim3(grid), dim3(64 * pe_waves(TET)), 0, s, a);
+    else hipLaunchKernelGGL((k_preeval_elast<PRISM>), dim3(grid), dim3(64 * pe_waves(PRISM)), 0, s, a);
     return hipGetLastError();
 }
 
