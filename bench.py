@@ -213,8 +213,15 @@ def main():
     roofline.update(profiled_traffic(kname, dom_shape))
     step_bytes = sum(alg_bytes("helmholtz", "tetrahedron", p) for p in (1, 2, 3, 4)) * E
     step_flops = sum(alg_flops("helmholtz", "tetrahedron", p) for p in (1, 2, 3, 4)) * E
-    del outs
-    torch.cuda.empty_cache()
+    # the last timed step's matrices, kept for the element-by-element check of
+    # the CPU-baseline leg: only the first elements (the oracle's sample) go
+    # to the host
+    headline_out = None
+    if not args.no_cpu_baseline:
+        headline_out = outs
+    else:
+        del outs
+        torch.cuda.empty_cache()
 
     result = {
         "metric": "element matrices/s", "value": round(value, 1), "unit": "element matrices/s",
@@ -238,7 +245,9 @@ def main():
 
     # ------------------------------------------------------------------ CPU baseline (oracle)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(coords_np)
+        result["cpu_baseline"], result["parity"] = cpu_baseline(coords_np, headline_out)
+        result["max_err"] = result["parity"]["max_err"]
+        del headline_out
     print(json.dumps(result), flush=True)
 
 
@@ -515,7 +524,7 @@ def hyperelastic_workload(torch, felocal, inputs, stream, ev, record, reps):
     for p in (1, 2):
         log(f"hyperelastic P{p} on 998k tets")
         ns = n_scalar("tetrahedron", p)
-        u = torch.from_numpy(inputs.displacement_dofs(E4, 3, ns, 1.0 / 55, p, seed=40 + p)).cuda()
+        u = torch.from_numpy(inputs.displacement_dofs(E4, 3, ns, 1.0 / 55, seed=40 + p)).cuda()
         o4 = torch.empty((E4, 3 * ns, 3 * ns), dtype=torch.float64, device="cuda")
         st = torch.zeros(1, dtype=torch.int32, device="cuda")
         for prec, kern in (FP64_P1 if p == 1 else []) + FP64_AND_SPLIT:
@@ -671,31 +680,69 @@ def batch_workload(torch, felocal, inputs, stream, ev, reps):
     return row
 
 
-def cpu_baseline(coords_np):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_leg(oracle, coords_np, nthreads, t_target, n_cap):
+    """For each degree, the first n elements (n grown until the degree takes
+    t_target seconds, at most n_cap): seconds per element and the matrices."""
+    t_per, sample, mats = {}, {}, {}
+    for p in (1, 2, 3, 4):
+        n = 64
+        while True:
+            t = time.perf_counter()
+            A, _ = oracle.assemble("helmholtz", "tetrahedron", p, coords_np[:n], nthreads=nthreads)
+            dt = time.perf_counter() - t
+            if dt >= t_target or n >= n_cap:
+                break
+            n = min(n_cap, n * 4 if dt < t_target / 5 else n * 2)
+        t_per[p], sample[p], mats[p] = dt / n, n, A
+        log(f"cpu oracle P{p}: {n} elements in {dt:.2f} s on {nthreads} thread(s)")
+    return t_per, sample, mats
+
+
+def cpu_baseline(coords_np, gpu_out=None):
     """The float64 oracle (naive Eq. (7) nest, OpenMP over elements) on a
-    bounded sample of the headline workload: for each degree, the first n
-    elements with n grown until that degree takes >= 2.5 s."""
+    bounded sample of the headline workload, on all host threads (for each
+    degree the first n elements, n grown until that degree takes >= 2.5 s)
+    and on one thread (the paper's single-core setting of Sec. 7.1; the
+    first elements, at most 16,384, per degree, extrapolated per element).
+    With gpu_out (the headline's device outputs per degree), every matrix the
+    all-threads leg computed is compared with the GPU's, element by element:
+    max over elements of max|A_gpu - A_oracle| / max|A_oracle|."""
     import oracle
 
     cores = oracle.max_threads()
-    t_per = {}
-    sample = {}
-    for p in (1, 2, 3, 4):
-        n = 256
-        while True:
-            t = time.perf_counter()
-            oracle.assemble("helmholtz", "tetrahedron", p, coords_np[:n], nthreads=cores)
-            dt = time.perf_counter() - t
-            if dt >= 2.5 or n >= coords_np.shape[0]:
-                break
-            n = min(coords_np.shape[0], n * 4 if dt < 0.5 else n * 2)
-        t_per[p] = dt / n
-        sample[p] = n
-        log(f"cpu oracle P{p}: {n} elements in {dt:.2f} s on {cores} threads")
+    t_per, sample, mats = _oracle_leg(oracle, coords_np, cores, 2.5, coords_np.shape[0])
+    t1, sample1, _ = _oracle_leg(oracle, coords_np, 1, 2.5, 16384)
     per_step = sum(t_per.values())
-    return {"value": round(4.0 / per_step, 1), "unit": "element matrices/s", "cores": cores, "kind": "oracle",
+    base = {"value": round(4.0 / per_step, 1), "unit": "element matrices/s", "cores": cores, "kind": "oracle",
             "sample": "helmholtz tet P1-P4, first " + ", ".join(f"P{p}:{sample[p]}" for p in sample)
-                      + " elements of the 750k mesh; rate = 4 / sum_p(seconds per element)"}
+                      + " elements of the 750k mesh; rate = 4 / sum_p(seconds per element)",
+            "cpu_model": cpu_model(),
+            "one_core": {"value": round(4.0 / sum(t1.values()), 1), "unit": "element matrices/s", "cores": 1,
+                         "sample": "first " + ", ".join(f"P{p}:{sample1[p]}" for p in sample1)
+                                   + " elements, extrapolated per element"}}
+    parity = None
+    if gpu_out is not None:
+        per = {}
+        for p in (1, 2, 3, 4):
+            B = mats[p]
+            A = gpu_out[p][:B.shape[0]].cpu().numpy()
+            err = np.max(np.abs(A - B), axis=(1, 2)) / np.max(np.abs(B), axis=(1, 2))
+            per[f"P{p}"] = {"elements": int(B.shape[0]), "max_err": float(err.max())}
+            log(f"parity P{p}: {B.shape[0]} elements, max normwise error {err.max():.3e}")
+        parity = {"metric": "max_e max|A_gpu - A_oracle| / max|A_oracle|", "bar": 1e-12,
+                  "max_err": max(v["max_err"] for v in per.values()), "per_degree": per}
+    return base, parity
 
 
 if __name__ == "__main__":

@@ -63,10 +63,13 @@ typedef enum { FE_MASS = 0, FE_HELMHOLTZ = 1, FE_ELASTICITY = 2, FE_HYPERELASTIC
  * per-point kinematics always run in float64.
  *   FE_FP64          float64 everywhere (all forms)
  *   FE_SPLIT_FP32    contraction on MFMA with float32 operands and float32
- *                    accumulation, final combination in float64
+ *                    accumulation; the three terms of an entry (the two
+ *                    products and the trace term) are added in float32 and
+ *                    the sum is stored as float64
  *   FE_SPLIT_BF16X3  contraction on MFMA with each operand split into a
  *                    bf16 high and low part (three products hi*hi + hi*lo +
- *                    lo*hi), float32 accumulation, float64 combination
+ *                    lo*hi), float32 accumulation, the same float32
+ *                    three-term combination, stored as float64
  * The split precisions apply to FE_ELASTICITY and FE_HYPERELASTIC when the
  * element matrix fits one 32x32 tile (gdim*n_s <= 32) and the rule has at most
  * 32 points; otherwise FE_ENOTSUP.  Stated error bounds (normwise per element,
@@ -192,9 +195,12 @@ int fe_tabulate(fe_cell_t cell, int degree, int qdeg,
                 double* points, double* weights, double* phi, double* dphi,
                 int* info);
 
-/* n (rows of the element matrix) and the number of coefficient DOFs per
- * element for (form, cell, degree).  Host pointers; either may be NULL.
- * Errors: FE_EINVAL. */
+/* Sizes of the element tensor A^K of Sec. 2 (one row and one column per
+ * local basis function of the test and trial space, Sec. 2.2) and of the
+ * coefficient DOFs each element carries (the local DOFs of the coefficient
+ * functions of Eq. (7)) for (form, cell, degree): n (rows) and the
+ * coefficient DOFs per element (0 for mass and Helmholtz without nf).
+ * Host pointers; either may be NULL.  Errors: FE_EINVAL. */
 int fe_local_dims(fe_form_t form, fe_cell_t cell, int degree, int* n_rows, int* n_coeff);
 
 /* Local assembly (Sec. 2: element tensor A^K of Eq. (7); evaluated in the

@@ -249,14 +249,13 @@ def lame_p1(nverts: int, cells: np.ndarray, seed: int, lo: float = 0.5, hi: floa
     return np.ascontiguousarray(np.stack([lam[cells], mu[cells]], axis=1))
 
 
-def displacement_dofs(E: int, gdim: int, n_s: int, h: float, p: int, seed: int,
+def displacement_dofs(E: int, gdim: int, n_s: int, h: float, seed: int,
                       rel: float = 0.05, clip: float = 3.0) -> np.ndarray:
     """Element-local displacement DOFs [E][gdim*n_s], component-blocked,
-    i.i.d. normal with standard deviation rel*h/p (h/p is the spacing of the
-    degree-p DOF lattice along a mesh edge), redrawn where beyond clip
-    standard deviations."""
+    i.i.d. normal with standard deviation rel*h (h the mesh spacing), redrawn
+    where beyond clip standard deviations."""
     (rng,) = _streams(seed, 1)
-    sig = rel * h / p
+    sig = rel * h
     u = rng.standard_normal(size=(E, gdim * n_s))
     bad = np.abs(u) > clip
     while bad.any():

@@ -39,7 +39,7 @@ def case(form, p, E, seed):
     if form == "elasticity":
         cf = inputs.lame_p1(V.shape[0], cells, seed)
     elif form == "hyperelastic":
-        cf = inputs.displacement_dofs(len(coords), 3, oracle.nbasis("prism", p), h, p, seed)
+        cf = inputs.displacement_dofs(len(coords), 3, oracle.nbasis("prism", p), h, seed, rel=0.05 / p)
     else:
         cf = None
     return coords, cf
