@@ -60,11 +60,14 @@ def lib():
                                    dp, ctypes.c_int]
         L.orc_assemble.restype = ctypes.c_int64
         L.orc_assemble_coef.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                        ctypes.c_int64, dp, dp, dp, ctypes.c_int]
+                                        ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int]
         L.orc_assemble_coef.restype = ctypes.c_int64
         L.orc_hyper_residual.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                          dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
         L.orc_hyper_residual.restype = ctypes.c_int64
+        L.orc_hyper_residual_coef.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                              dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.orc_hyper_residual_coef.restype = ctypes.c_int64
         L.orc_hyper_min_jf.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                        dp, dp, dp, ctypes.c_int]
         L.orc_hyper_min_jf.restype = ctypes.c_int64
@@ -99,14 +102,21 @@ def nbasis(cell: str, p: int) -> int:
 
 def default_qdeg(form: str, cell: str, p: int, nf: int = 0) -> int:
     """Exact quadrature degree for each form (Sec. 7.1 uses exact quadrature):
-    mass and Helmholtz 2p, plus p per pre-multiplying coefficient function;
-    elasticity with P1 Lame fields 2(p-1)+1 on simplices and 2p+1 on prisms
-    (tensor-product degree); hyperelastic 4."""
+    mass and Helmholtz 2p; elasticity with P1 Lame fields 2(p-1)+1 on
+    simplices and 2p+1 on prisms (tensor-product degree); hyperelastic 4 (its
+    integrand is not a polynomial); plus p per pre-multiplying coefficient
+    function of degree p."""
     if form in ("mass", "helmholtz"):
         return (2 + nf) * p
     if form == "elasticity":
-        return 2 * p + 1 if cell == "prism" else 2 * p - 1
-    return 4
+        return (2 * p + 1 if cell == "prism" else 2 * p - 1) + nf * p
+    return 4 + nf * p
+
+
+def own_coeff(form: str, cell: str, p: int) -> int:
+    """The form's own coefficient DOFs per element (before any nf functions)."""
+    return {"mass": 0, "helmholtz": 0, "elasticity": 2 * NVERT[cell],
+            "hyperelastic": TDIM[cell] * nbasis(cell, p)}[form]
 
 
 def rule(cell: str, qdeg: int):
@@ -163,10 +173,10 @@ def assemble(form: str, cell: str, p: int, coords, coeff=None, qdeg=None,
     out = np.empty((E, n, n))
     cf = _f64(coeff) if coeff is not None else None
     if nf:
-        if form not in ("mass", "helmholtz") or cf is None or cf.size != E * nf * nbasis(cell, p):
-            raise ValueError("nf coefficient functions need mass/helmholtz and coeff [E][nf][n_s]")
+        if cf is None or cf.size != E * (own_coeff(form, cell, p) + nf * nbasis(cell, p)):
+            raise ValueError("nf coefficient functions need coeff [E][own + nf * n_s]")
         flagged = lib().orc_assemble_coef(FORM[form], CELL[cell], p, qdeg, nf, E, _p(coords), _p(cf),
-                                          _p(out), nthreads)
+                                          mu, lam, _p(out), nthreads)
         if flagged < 0:
             raise ValueError("oracle rejected arguments")
         return out, int(flagged)
@@ -238,12 +248,14 @@ def default_qdeg_pointgeo(form: str, p: int) -> int:
     return default_qdeg(form, "prism", p) + 1
 
 
-def hyper_residual(cell: str, p: int, coords, u, qdeg: int = 4, mu: float = 1.0, lam: float = 10.0):
+def hyper_residual(cell: str, p: int, coords, u, qdeg: int = 4, mu: float = 1.0, lam: float = 10.0, nf: int = 0):
+    """Residual [E][d n_s] and strain energy [E]; with nf > 0, u holds the
+    displacement DOFs then the nf pre-multiplying functions' DOFs per element."""
     coords, u = _f64(coords), _f64(u)
     E = coords.shape[0]
     R = np.zeros((E, TDIM[cell] * nbasis(cell, p)))
     en = np.zeros(E)
-    lib().orc_hyper_residual(CELL[cell], p, qdeg, E, _p(coords), _p(u), mu, lam, _p(R), _p(en))
+    lib().orc_hyper_residual_coef(CELL[cell], p, qdeg, nf, E, _p(coords), _p(u), mu, lam, _p(R), _p(en))
     return R, en
 
 

@@ -453,15 +453,19 @@ int64_t orc_assemble_pointgeo(int form, int p, int qdeg, int64_t E, const double
     return assemble_nest(form, 2, p, qdeg, 0, 1, E, coords, coeff, mu_c, lam_c, out, nthreads);
 }
 
-/* Mass and Helmholtz pre-multiplied by nf coefficient functions (the
- * experiment matrix of Sec. 7.1): the integrand is multiplied by
- * prod_{i<nf} f_i(X_q), each f_i in the same Lagrange space as the test and
- * trial functions, given by its element-local DOFs coeff[E][nf][n_s]. */
+/* A form pre-multiplied by nf coefficient functions (the experiment matrix
+ * of Sec. 7.1, which pre-multiplies each of its forms): the integrand is
+ * multiplied by prod_{i<nf} f_i(X_q), each f_i in the same Lagrange space as
+ * the test and trial functions.  Per element the coefficient record is the
+ * form's own coefficients (elasticity: the Lame DOFs [2][nv]; hyperelastic:
+ * the displacement DOFs [d][n_s]; none for mass and Helmholtz) followed by
+ * the DOFs of the functions [nf][n_s]. */
 int64_t orc_assemble_coef(int form, int cell, int p, int qdeg, int nf, int64_t E,
-                          const double *coords, const double *coeff, double *out, int nthreads)
+                          const double *coords, const double *coeff, double mu_c, double lam_c,
+                          double *out, int nthreads)
 {
-    if (form < 0 || form > 1 || nf < 0 || nf > 3 || (nf > 0 && !coeff)) return -1;
-    return assemble_nest(form, cell, p, qdeg, nf, 0, E, coords, coeff, 1.0, 10.0, out, nthreads);
+    if (form < 0 || form > 3 || nf < 0 || nf > 3 || (nf > 0 && !coeff)) return -1;
+    return assemble_nest(form, cell, p, qdeg, nf, 0, E, coords, coeff, mu_c, lam_c, out, nthreads);
 }
 
 static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int pointgeo, int64_t E,
@@ -475,6 +479,9 @@ static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int po
     int n = vec ? d * ns : ns;
     int nq = orc_rule_size(cell, qdeg);
     if (nq < 0) return -1;
+    /* per-element coefficient record: the form's own DOFs, then nf functions */
+    const int own = form == 2 ? 2 * nv : (form == 3 ? d * ns : 0);
+    const int cstride = own + nf * ns;
     double *X = (double *)malloc(sizeof(double) * nq * 3);
     double *W = (double *)malloc(sizeof(double) * nq);
     double *PHI = (double *)malloc(sizeof(double) * nq * ns);
@@ -530,7 +537,7 @@ static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int po
             double dx = W[q] * fabs(detJ);
             /* pre-multiplying coefficient functions f_i(X_q) = sum_l f_il Phi_l(X_q) */
             for (int f = 0; f < nf; ++f) {
-                const double *cf = coeff + ((size_t)e * nf + f) * ns;
+                const double *cf = coeff + (size_t)e * cstride + own + (size_t)f * ns;
                 double fv = 0.0;
                 for (int l = 0; l < ns; ++l) fv += cf[l] * phi[ORC_MUTANT == 8 ? (l + 1) % ns : l];
                 if (!(ORC_MUTANT == 9 && f > 0)) dx *= fv;
@@ -553,7 +560,7 @@ static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int po
                         A[i * n + j] += dx * (gg + phi[i] * phi[j]);
                     }
             } else if (form == 2) {
-                const double *ce = coeff + (size_t)e * 2 * nv;
+                const double *ce = coeff + (size_t)e * cstride;
                 double lam = 0.0, mu = 0.0;
                 for (int l = 0; l < nv; ++l) {
                     lam += ce[l] * PSI[q * 6 + l];
@@ -566,7 +573,7 @@ static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int po
                                 A[(c * ns + i) * n + f * ns + j] +=
                                     dx * elasticity_pair(d, c, f, g + i * d, g + j * d, lam, mu);
             } else {
-                const double *u = coeff + (size_t)e * d * ns;
+                const double *u = coeff + (size_t)e * cstride;
                 double F[9], P[9], AA[81], JF;
                 for (int a = 0; a < d; ++a)
                     for (int b = 0; b < d; ++b) {
@@ -597,12 +604,25 @@ static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int po
     return flagged;
 }
 
-/* Hyperelastic residual R_(c,i) = sum_q W_q |det J| sum_b P_cb g_i[b]
+/* Hyperelastic residual R_(c,i) = sum_q W_q |det J| w(X_q) sum_b P_cb g_i[b]
  * (the form whose derivative the tangent above is); also the strain energy
- * Psi = sum_q W_q |det J| psi(F), psi = mu/2 (tr F^T F - d) - mu ln J + lam/2 ln^2 J. */
+ * Psi = sum_q W_q |det J| w(X_q) psi(F), psi = mu/2 (tr F^T F - d) - mu ln J
+ * + lam/2 ln^2 J.  w = prod_{i<nf} f_i, the pre-multiplying functions laid
+ * out after the displacement DOFs as in orc_assemble_coef (w = 1 for nf = 0). */
+int64_t orc_hyper_residual_coef(int cell, int p, int qdeg, int nf, int64_t E, const double *coords,
+                                const double *coeff, double mu_c, double lam_c,
+                                double *R, double *energy);
+
 int64_t orc_hyper_residual(int cell, int p, int qdeg, int64_t E, const double *coords,
                            const double *coeff, double mu_c, double lam_c,
                            double *R, double *energy)
+{
+    return orc_hyper_residual_coef(cell, p, qdeg, 0, E, coords, coeff, mu_c, lam_c, R, energy);
+}
+
+int64_t orc_hyper_residual_coef(int cell, int p, int qdeg, int nf, int64_t E, const double *coords,
+                                const double *coeff, double mu_c, double lam_c,
+                                double *R, double *energy)
 {
     int d = tdim_of(cell), nv = nvert_of(cell);
     int ns = orc_nbasis(cell, p);
@@ -620,10 +640,16 @@ int64_t orc_hyper_residual(int cell, int p, int qdeg, int64_t E, const double *c
         double J[9], K[9], detJ, psi_sum = 0.0;
         for (int k = 0; k < d * ns; ++k) r[k] = 0.0;
         if (orc_geometry(cell, coords + (size_t)e * nv * d, J, &detJ, K)) { flagged++; continue; }
-        const double *u = coeff + (size_t)e * d * ns;
+        const double *u = coeff + (size_t)e * (d + nf) * ns;
         for (int q = 0; q < nq; ++q) {
             double g[ORC_MAXNB * 3], F[9], P[9], JF;
             const double *dphi = DPHI + q * ns * d;
+            double wf = 1.0;
+            for (int f = 0; f < nf; ++f) {
+                double fv = 0.0;
+                for (int l = 0; l < ns; ++l) fv += u[(d + f) * ns + l] * PHI[q * ns + l];
+                wf *= fv;
+            }
             for (int i = 0; i < ns; ++i)
                 for (int b = 0; b < d; ++b) {
                     double s = 0.0;
@@ -637,7 +663,7 @@ int64_t orc_hyper_residual(int cell, int p, int qdeg, int64_t E, const double *c
                     F[a * d + b] = s;
                 }
             neo_hookean(d, F, mu_c, lam_c, P, NULL, &JF);
-            double dx = W[q] * fabs(detJ);
+            double dx = W[q] * fabs(detJ) * wf;
             for (int c = 0; c < d; ++c)
                 for (int i = 0; i < ns; ++i) {
                     double s = 0.0;

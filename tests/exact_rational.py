@@ -272,13 +272,22 @@ def helmholtz(cell, p, verts):
     return [[M[j][k] + S[j][k] for k in range(len(M))] for j in range(len(M))]
 
 
-def elasticity(cell, p, verts, lam_dofs, mu_dofs):
-    """Exact element matrix of int 2 mu eps(u):eps(v) + lam div u div v with
-    P1 (prism: P1 x P1) Lame fields, from
-        mu (delta_cd g_j.g_k + g_jd g_kc) + lam g_jc g_kd,  g = K^T grad_X."""
+def elasticity(cell, p, verts, lam_dofs, mu_dofs, fields=()):
+    """Exact element matrix of int w (2 mu eps(u):eps(v) + lam div u div v)
+    with P1 (prism: P1 x P1) Lame fields, from
+        mu (delta_cd g_j.g_k + g_jd g_kc) + lam g_jc g_kd,  g = K^T grad_X,
+    and w = prod_i f_i of degree-p functions with DOFs `fields` (w = 1 when
+    there are none)."""
     d = TDIM[cell]
     _, adet, K = affine(cell, verts)
-    T = reference_weighted_stiffness(cell, p)
+    if fields:
+        ex, C = lagrange(cell, p)
+        D = [_deriv_coeffs(ex, C, a) for a in range(d)]
+        cw = coefficient_weight(cell, p, fields)
+        T = [[[_bilinear(cell, D[a], D[b], weight=_poly_mul(w, cw)) for b in range(d)] for a in range(d)]
+             for w in _p1_weights(cell)]
+    else:
+        T = reference_weighted_stiffness(cell, p)
     ns = len(T[0][0][0])
     lam = [Fr(x) for x in lam_dofs]
     mu = [Fr(x) for x in mu_dofs]
