@@ -149,13 +149,26 @@ typedef struct {
                                   host and reject non-affine prisms with
                                   FE_ENONAFFINE before launching            */
     fe_shape_t     shape;      /* launch shape override; zero = automatic   */
-    int            nf;         /* mass and Helmholtz only: the form is pre-
-                                  multiplied by nf (0..3) coefficient
-                                  functions f_i of the same Lagrange degree
-                                  as the test and trial functions (the
-                                  experiment matrix of Sec. 7.1); coeff_dofs
-                                  is then [E][nf][n_s] and the default rule
-                                  exact degree (2 + nf) * degree.  Default 0 */
+    int            nf;         /* the form is pre-multiplied by nf (0..3)
+                                  coefficient functions f_i of the same
+                                  Lagrange degree as the test and trial
+                                  functions (the experiment matrix of
+                                  Sec. 7.1, every form).  An element's
+                                  coeff_dofs record is then the form's own
+                                  DOFs (none for mass and Helmholtz, the Lame
+                                  DOFs [2][nc] for elasticity, the
+                                  displacement DOFs [gdim][n_s] for the
+                                  hyperelastic form) followed by the
+                                  functions' DOFs [nf][n_s]; the default rule
+                                  gains nf * degree (mass and Helmholtz
+                                  (2 + nf) * degree).  FE_FP64 only; the
+                                  vector forms then run the VALU quadrature
+                                  kernel (shape kernel 3) and, where
+                                  Algorithm 3 pre-evaluates, the coefficient-
+                                  expanded pre-evaluated kernels (elasticity;
+                                  the hyperelastic trace monomial is added to
+                                  the diagonal blocks after the quadrature
+                                  kernel).  Default 0 */
     int            pointgeo;   /* prisms: nonzero lifts the affine assumption
                                   of Sec. 2.2.  The element map is the vertex
                                   map x(X) = sum_v psi_v(X) v (P1 x P1 basis
@@ -245,7 +258,8 @@ typedef struct {
 
 /* qdeg = -1 for the form default; th_bytes = 0 for the device's L2 capacity
  * (4 MiB when no device is present); nf as in fe_options_t
- * (mass and Helmholtz; iota = C(n_s + nf - 1, nf), Sec. 4.2).  A plan may
+ * (iota = C(n_s + nf - 1, nf), Sec. 4.2; times n_c for elasticity, whose
+ * P1 Lame fields are expanded as well).  A plan may
  * pre-evaluate only some monomials (Fig. 5): mode is then
  * FE_MODE_QUADRATURE and, with nf = 0, the quadrature kernel adds the
  * pre-evaluated monomials' tables; with nf > 0 such a mixed plan is executed
@@ -256,7 +270,10 @@ typedef struct {
  * tables must fit T_H).  The hyperelastic form has two monomials: the terms in
  * F (never pre-evaluable) and the trace term mu |det J| g_j . g_k (constant
  * coefficient); its matrix-core kernels (split precisions, float64 shape
- * kernel 1) pre-evaluate the trace term, the VALU kernel integrates both.
+ * kernel 4) pre-evaluate the trace term, the VALU kernel integrates both.
+ * With nf > 0 the trace term's coefficient is mu prod_i f_i (iota =
+ * C(n_s + nf - 1, nf)); where the plan pre-evaluates it, the VALU kernel
+ * integrates the terms in F and the coefficient kernel adds the trace term.
  * Errors: FE_EINVAL. */
 int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int qdeg, size_t th_bytes,
             fe_plan_t* plan);

@@ -55,13 +55,22 @@ FE_HD constexpr int rule_size(int cell, int qdeg)
                          : (qdeg <= 2 ? 3 : rule_m(qdeg) * rule_m(qdeg)) * rule_m(qdeg);
 }
 
-// exact degree; mass and Helmholtz gain p per pre-multiplying coefficient
-// function (nf, Sec. 7.1)
+// exact degree (the hyperelastic integrand is not a polynomial: degree 4);
+// every form gains p per pre-multiplying coefficient function of degree p
+// (nf, Sec. 7.1)
 FE_HD constexpr int default_qdeg(int form, int cell, int p, int nf = 0)
 {
     return (form == MASS || form == HELMHOLTZ) ? (2 + nf) * p
-         : form == ELASTICITY ? (cell == PRISM ? 2 * p + 1 : 2 * p - 1)
-                              : 4;
+         : form == ELASTICITY ? (cell == PRISM ? 2 * p + 1 : 2 * p - 1) + nf * p
+                              : 4 + nf * p;
+}
+
+// the form's own coefficient DOFs per element (elasticity: the Lame DOFs
+// [2][nv]; hyperelastic: the displacement DOFs [d][n_s]); nf pre-multiplying
+// functions follow them in the element's record, [nf][n_s]
+FE_HD constexpr int own_coeff(int form, int cell, int p)
+{
+    return form == ELASTICITY ? 2 * cell_nv(cell) : form == HYPERELASTIC ? cell_dim(cell) * n_scalar(cell, p) : 0;
 }
 
 constexpr int MAX_DEGREE = 4;

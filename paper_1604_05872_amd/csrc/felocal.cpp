@@ -156,7 +156,7 @@ int get_coef_tables(int form, int cell, int p, int qdeg, int nf, hipStream_t s, 
         return FE_OK;
     }
     const int nb = rt->nb;
-    if (form == ELASTICITY) {
+    if (form == ELASTICITY && nf == 0) {
         // T[(l, a, b)][j][k] = sum_q W_q psi_l dphi_{j,a} dphi_{k,b}
         CoefTables* t = new CoefTables();
         t->iota = rt->nv;
@@ -186,13 +186,18 @@ int get_coef_tables(int form, int cell, int p, int qdeg, int nf, hipStream_t s, 
     }
     CoefTables* t = new CoefTables();
     t->iota = (int)(combos.size() / nf);
-    const int nr = n_tables(form, cell);
+    // elasticity: T[((l * iota + S) * d + a) * d + b] for the P1 Lame basis
+    // psi_l and the multisets S; the scalar forms: R[(r, S)]
+    const int nr = form == ELASTICITY ? rt->nv * rt->d * rt->d : n_tables(form, cell);
     t->nt = nr * t->iota;
     hipError_t e = hipMalloc((void**)&t->dCombos, combos.size() * sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void**)&t->dR, (size_t)t->nt * nb * nb * sizeof(double));
     if (e == hipSuccess)
         e = hipMemcpyAsync(t->dCombos, combos.data(), combos.size() * sizeof(int), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
+    if (e == hipSuccess && form == ELASTICITY)
+        e = launch_elast_coef_tables(rt->nq, nb, rt->d, rt->nv, nf, t->iota, rt->dW, rt->dphi, rt->dpsi, rt->ddphi,
+                                     t->dCombos, t->dR, s);
+    else if (e == hipSuccess)
         e = launch_coef_tables(rt->nq, nb, rt->d, nf, t->iota, nr, rt->dW, rt->dphi, rt->ddphi, t->dCombos, t->dR, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -426,6 +431,11 @@ int fe_resolve_variant(int form, int cell, int degree, int qdeg, const fe_option
     // coefficient pre-evaluation kernel adds that monomial afterwards
     if (form == HELMHOLTZ && plan.mode == FE_MODE_QUADRATURE)
         *mass_pre = (plan.preevaluated[1] ? 1 : 0) | (plan.preevaluated[0] ? 2 : 0);
+    // the hyperelastic trace monomial mu |det J| w g_j . g_k with nf > 0
+    // pre-multiplying functions w: pre-evaluated by the coefficient kernel,
+    // added to the diagonal blocks after the quadrature kernel (with nf = 0
+    // the matrix-core kernels pre-evaluate it themselves)
+    if (form == HYPERELASTIC && o->nf > 0 && plan.preevaluated[1]) *mass_pre = 2;
     return FE_OK;
 }
 
@@ -449,7 +459,8 @@ int store_mode()
 // the point loop and integrate the remaining scalar weights only.
 bool q_invariant(const Call& c)
 {
-    return is_vector_form(c.form) && c.degree == 1 && c.cell != PRISM;
+    // (pre-multiplying functions vary over the element)
+    return is_vector_form(c.form) && c.degree == 1 && c.cell != PRISM && c.nf == 0;
 }
 
 // the hoisted degree-1 kernel: float64 quadrature mode, vector forms on
@@ -470,6 +481,7 @@ bool gram64_eligible(const Call& c)
         return !(c.nf == 0 && c.mass_pre != 0);
     }
     if (c.pointgeo) return false;   // the vector matrix-core kernels take one map per element
+    if (c.nf > 0) return false;      // and no pre-multiplying functions
     if (n_rows(c.form, c.cell, c.degree) > 32) return false;
     if (n_scalar(c.cell, c.degree) > 16) return false;
     const int nq = q_invariant(c) ? 1 : c.tables->nq;
@@ -544,6 +556,16 @@ int launch_call(const Call& c, const Config& cfg)
         e = launch_split(c.form, c.cell, c.degree, c.prec == FE_SPLIT_FP32 ? SPLIT_FP32 : SPLIT_BF16X3, nqp, a, grid,
                          lds, c.stream);
         if (e != hipSuccess) return set_hip_error(e, "split-precision launch");
+        return FE_OK;
+    }
+    if (c.mode == FE_MODE_PREEVAL && c.form == ELASTICITY && c.nf > 0) {
+        // the P1 Lame fields and the nf functions expanded (iota = n_c C(n_s + nf - 1, nf))
+        const CoefTables* ct = nullptr;
+        int rc = get_coef_tables(c.form, c.cell, c.degree, c.qdeg, c.nf, c.stream, &ct);
+        if (rc) return rc;
+        e = launch_preeval_elast_coef(c.cell, c.coords, c.coeff, c.out, c.status, ct->dR, ct->dCombos, c.E, t->nb,
+                                      c.nf, ct->iota, cfg.grid_per_cu, cus, c.stream);
+        if (e != hipSuccess) return set_hip_error(e, "pre-evaluated elasticity launch");
         return FE_OK;
     }
     if (c.mode == FE_MODE_PREEVAL && c.form == ELASTICITY) {
@@ -655,11 +677,21 @@ int add_coef_monomial(const Call& c, const Config& cfg)
     if (!(c.nf > 0 && c.mass_pre)) return FE_OK;
     const RefTables* t = c.tables;
     const CoefTables* ct = nullptr;
-    int rc = get_coef_tables(c.form, c.cell, c.degree, c.qdeg, c.nf, c.stream, &ct);
+    // the hyperelastic trace monomial is the Helmholtz gradient monomial with
+    // the constant mu, on each of the d diagonal blocks: Helmholtz's tables
+    const int tform = c.form == HYPERELASTIC ? HELMHOLTZ : c.form;
+    int rc = get_coef_tables(tform, c.cell, c.degree, c.qdeg, c.nf, c.stream, &ct);
     if (rc) return rc;
-    const int r_lo = (c.mass_pre & 1) ? 0 : 1, r_hi = (c.mass_pre & 2) ? n_tables(c.form, c.cell) : 1;
-    hipError_t e = launch_preeval_coef(c.form, c.cell, c.coords, c.coeff, c.out, nullptr, ct->dR, ct->dCombos, c.E,
-                                       t->nb, c.nf, ct->iota, 8, device_cus(), c.stream, r_lo, r_hi, 1);
+    const int r_lo = (c.mass_pre & 1) ? 0 : 1, r_hi = (c.mass_pre & 2) ? n_tables(tform, c.cell) : 1;
+    CoefOut o;
+    if (c.form == HYPERELASTIC) {
+        o.vec_d = cell_dim(c.cell);
+        o.scale = c.mu;
+        o.cstride = own_coeff(c.form, c.cell, c.degree) + c.nf * t->nb;
+        o.coff = own_coeff(c.form, c.cell, c.degree);
+    }
+    hipError_t e = launch_preeval_coef(tform, c.cell, c.coords, c.coeff, c.out, nullptr, ct->dR, ct->dCombos, c.E,
+                                       t->nb, c.nf, ct->iota, 8, device_cus(), c.stream, r_lo, r_hi, 1, o);
     if (e != hipSuccess) return set_hip_error(e, "coefficient pre-evaluated launch");
     return FE_OK;
 }
@@ -684,6 +716,15 @@ int check_config(const Call& c, const Config& cfg)
     if (c.prec != FE_FP64) return FE_OK;
     const RefTables* t = c.tables;
     const size_t max_lds = device_lds_per_block();
+    if (c.mode == FE_MODE_PREEVAL && c.form == ELASTICITY && c.nf > 0) {
+        // one wavefront per 16-element tile; one block's coefficient rows in LDS
+        long iota = 1;
+        for (int i = 1; i <= c.nf; ++i) iota = iota * (t->nb + i - 1) / i;
+        const long nt = (long)cell_nv(c.cell) * iota * cell_dim(c.cell) * cell_dim(c.cell);
+        return preeval_elast_coef_lds_bytes(c.cell, (int)std::min<long>(nt, 1L << 30), c.nf, t->nb) <= max_lds
+                   ? FE_OK
+                   : FE_EINVAL;
+    }
     if (c.mode == FE_MODE_PREEVAL && c.form == ELASTICITY) return FE_OK;   // static LDS, grid only
     if (c.mode == FE_MODE_PREEVAL && c.nf > 0) {
         // one wavefront per block; the element rows of a 16-element tile
@@ -762,7 +803,7 @@ int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, co
         return FE_EINVAL;
     if ((int)o.precision < 0 || (int)o.precision > 2 || (int)o.mode < 0 || (int)o.mode > 2) return FE_EINVAL;
     if (o.nf < 0 || o.nf > 3) return FE_EINVAL;
-    if (o.nf > 0 && (is_vector_form(form) || o.precision != FE_FP64)) return FE_ENOTSUP;
+    if (o.nf > 0 && o.precision != FE_FP64) return FE_ENOTSUP;
     // the vertex map of a simplex is affine: per-point geometry only changes prisms
     const int pg = (o.pointgeo && cell == PRISM) ? 1 : 0;
     if (pg && (o.nf > 0 || o.precision != FE_FP64 || o.mode == FE_MODE_PREEVAL)) return FE_ENOTSUP;

@@ -31,13 +31,33 @@ hipError_t launch_preeval_stream(int form, int cell, const PreevalArgs& a, int b
 // preeval_coef.hip: pre-evaluation with nf pre-multiplying coefficient functions
 hipError_t launch_coef_tables(int nq, int nb, int d, int nf, int iota, int nr, const double* W, const double* phi,
                               const double* dphi, const int* combos, double* R, hipStream_t s);
+// Output and coefficient layout of the coefficient pre-evaluation: scalar
+// forms write [E][nb][nb] with the functions' DOFs [E][nf][nb]; for the
+// hyperelastic trace monomial each entry, times `scale` (mu), goes to the
+// vec_d diagonal blocks of [E][vec_d nb][vec_d nb], and an element's record
+// is `cstride` doubles with the functions' DOFs from `coff`.
+struct CoefOut {
+    int vec_d = 0;
+    double scale = 1.0;
+    int cstride = 0;   // 0: nf * nb
+    int coff = 0;
+};
 // geometry-tensor entries [r_lo, r_hi) only (r_hi < 0: all), adding to out
 // when accumulate is set (the pre-evaluated half of a mixed plan)
 hipError_t launch_preeval_coef(int form, int cell, const double* coords, const double* coeff, double* out,
                                int* status, const double* R, const int* combos, int64_t E, int nb, int nf,
                                int iota, int grid_per_cu, int cus, hipStream_t s, int r_lo = 0, int r_hi = -1,
-                               int accumulate = 0);
+                               int accumulate = 0, const CoefOut& o = CoefOut());
 size_t preeval_coef_lds_bytes(int form, int cell, int ntp, int nf, int nb);
+// elasticity pre-evaluated with its P1 Lame fields and nf functions expanded:
+// tables T[((l * iota + S) * d + a) * d + b][j][k] and the kernel
+hipError_t launch_elast_coef_tables(int nq, int nb, int d, int nc, int nf, int iota, const double* W,
+                                    const double* phi, const double* psi, const double* dphi, const int* combos,
+                                    double* T, hipStream_t s);
+hipError_t launch_preeval_elast_coef(int cell, const double* coords, const double* coeff, double* out, int* status,
+                                     const double* T, const int* combos, int64_t E, int nb, int nf, int iota,
+                                     int grid_per_cu, int cus, hipStream_t s);
+size_t preeval_elast_coef_lds_bytes(int cell, int nt, int nf, int nb);
 // preeval_elast.hip: pre-evaluated linear elasticity with P1 Lame fields
 hipError_t launch_elast_tables(int nq, int ns, int d, int nc, const double* W, const double* psi, const double* dphi,
                                double* T, hipStream_t s);
@@ -199,11 +219,12 @@ size_t quad_lds_bytes(int form, int cell, int ns, int eb, int qc, int pointgeo =
 struct Call {
     int form = 0, cell = 0, degree = 1, qdeg = 2;
     int mode = 0;       // FE_MODE_PREEVAL or FE_MODE_QUADRATURE
-    int nf = 0;         // pre-multiplying coefficient functions (mass, Helmholtz)
+    int nf = 0;         // pre-multiplying coefficient functions
     int pointgeo = 0;   // prisms: the vertex map evaluated at every point (non-affine)
     int shape[7] = {0, 0, 0, 0, 0, 0, 0};   // caller's launch-shape override (fe_shape_t order)
     int mass_pre = 0;   // Helmholtz quadrature: bit 0 mass monomial pre-evaluated,
-                        // bit 1 gradient monomial pre-evaluated
+                        // bit 1 gradient monomial pre-evaluated; hyperelastic
+                        // with nf > 0: bit 1 the trace monomial pre-evaluated
     int prec = 0;       // fe_precision_t
     int64_t E = 0;
     const double* coords = nullptr;

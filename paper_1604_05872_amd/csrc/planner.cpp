@@ -41,7 +41,7 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int q
                        fe_plan_t* plan)
 {
     if (!plan || (int)form < 0 || (int)form > 3 || (int)cell < 0 || (int)cell > 2 || degree < 1 ||
-        degree > MAX_DEGREE || qdeg > MAX_QDEG || nf < 0 || nf > 3 || (nf > 0 && is_vector_form(form)))
+        degree > MAX_DEGREE || qdeg > MAX_QDEG || nf < 0 || nf > 3)
         return FE_EINVAL;
     std::memset(plan, 0, sizeof(*plan));
     if (qdeg < 0) qdeg = default_qdeg(form, cell, degree, nf);
@@ -90,8 +90,11 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int q
         plan->theta_se[0] = nq * pairs * 2.0 * d * d;
         plan->theta_se[1] = nq * pairs * (2.0 * d * d + 3.0 * d);
         for (int m = 0; m < 2; ++m) {
-            plan->iota[m] = (int)binom(nc + 1 - 1, 1);
-            plan->table_bytes[m] = (size_t)nc * d * d * tbl;   // int psi_l dphi_j/dX_a dphi_k/dX_b
+            // the P1 Lame field (n_c functions) times the nf pre-multiplying
+            // functions: iota = n_c C(n_s + nf - 1, nf) distinct tables per term
+            plan->iota[m] = (int)binom(nc + 1 - 1, 1) * iota_f;
+            // int psi_l prod_S phi dphi_j/dX_a dphi_k/dX_b
+            plan->table_bytes[m] = (size_t)nc * iota_f * d * d * tbl;
             table_set[m] = 3;                                   // the same tables serve both
         }
         plan->rho[0] = d * d;
@@ -114,9 +117,9 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int q
         plan->table_bytes[0] = 0;
         legal[0] = false;
         plan->theta_se[1] = nq * pairs * 3.0 * d;
-        plan->iota[1] = 1;
+        plan->iota[1] = iota_f;            // 1 without pre-multiplying functions
         plan->rho[1] = d * (d + 1) / 2;   // tables S_ab, a <= b
-        plan->table_bytes[1] = (size_t)plan->rho[1] * tbl;
+        plan->table_bytes[1] = (size_t)plan->rho[1] * iota_f * tbl;
         table_set[1] = 2;
         legal[1] = true;
         break;
@@ -128,10 +131,21 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int q
         int ndev = 0;
         const size_t lds_block =
             (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) ? device_lds_per_block() : (size_t)64 << 10;
-        const size_t nr = (size_t)n_tables(form, cell);
-        const size_t tile = 16 * sizeof(double) * ((nr * iota_f + 7) / 8 * 8 + nr + (size_t)nf * ns);
-        if (tile > lds_block)
-            for (int m = 0; m < nm; ++m) legal[m] = false;
+        if (form == FE_ELASTICITY) {
+            // one block's coefficient rows (the n_c iota_f d^2 tables) per tile
+            if (preeval_elast_coef_lds_bytes(cell, nc * iota_f * d * d, nf, ns) > lds_block)
+                legal[0] = legal[1] = false;
+        } else if (form == FE_HYPERELASTIC) {
+            // the trace term: the Helmholtz gradient tables with the functions
+            const size_t nr = (size_t)n_tables(FE_HELMHOLTZ, cell), rho = (size_t)d * (d + 1) / 2;
+            const size_t tile = 16 * sizeof(double) * ((rho * iota_f + 7) / 8 * 8 + nr + (size_t)nf * ns);
+            if (tile > lds_block) legal[1] = false;
+        } else {
+            const size_t nr = (size_t)n_tables(form, cell);
+            const size_t tile = 16 * sizeof(double) * ((nr * iota_f + 7) / 8 * 8 + nr + (size_t)nf * ns);
+            if (tile > lds_block)
+                for (int m = 0; m < nm; ++m) legal[m] = false;
+        }
     }
     const double entries = is_vector_form(form) ? pairs * d * d : pairs;
     for (int m = 0; m < nm; ++m)
@@ -139,7 +153,7 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int q
     if (form == FE_HYPERELASTIC) {
         plan->theta_pre[0] = inf;
         // the trace matrix is n_s x n_s, then added to the d diagonal blocks
-        plan->theta_pre[1] = (2.0 * plan->rho[1] + d) * pairs;
+        plan->theta_pre[1] = (2.0 * plan->rho[1] * plan->iota[1] + d) * pairs;
     }
     plan->n_monomials = nm;
     plan->th_bytes = th_bytes;

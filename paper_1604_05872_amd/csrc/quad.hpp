@@ -49,10 +49,12 @@ struct QuadArgs {
     int qc;               // points per LDS chunk
     int nt;               // non-temporal output stores
     double mu, lam;       // hyperelastic constants
-    int nf;               // mass / Helmholtz: pre-multiplying coefficient functions,
-                          // DOFs [E][nf][ns] in coeff (Sec. 7.1)
+    int nf;               // pre-multiplying coefficient functions (Sec. 7.1): an
+                          // element's coeff record is the form's own DOFs
+                          // (own_coeff) followed by the functions' [nf][ns]
     int skip;             // Helmholtz: bit 0 leaves out the mass term, bit 1 the
-                          // gradient term (added by another kernel afterwards)
+                          // gradient term; hyperelastic: bit 1 leaves out the
+                          // trace term (each added by another kernel afterwards)
     int pointgeo = 0;     // prisms: J, det J, J^{-1} of the vertex map at every point
     const double* dpsi_grad = nullptr;   // [nq][nv][d] gradients of the vertex basis (pointgeo)
 };
@@ -89,6 +91,9 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
     // per-point geometry applies to prisms only (a simplex's vertex map is affine)
     const int pg = CELL == PRISM ? a.pointgeo : 0;
     const int ppt = L::per_point(ns, pg);
+    // an element's coefficient record: the form's own DOFs, then nf functions
+    const int own = FORM == ELASTICITY ? 2 * NV : FORM == HYPERELASTIC ? D * ns : 0;
+    const int cst = own + a.nf * ns;
 
     double* sEl = lds;                                  // [eb][12]
     double* sPhi = lds + (size_t)a.eb * L::PER_ELEM;    // [qc][ns]
@@ -198,18 +203,19 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
                 double* pt = sPt + ((size_t)i * qc_max + qq) * ppt;
                 const double w = wsum * ((CELL == PRISM && pg) ? pt[ppt - 1] : sEl[i * L::PER_ELEM + 9]);
                 double* sw = pt + ns * D + (FORM == HYPERELASTIC ? ns * D + 9 : 0);
+                // w times prod_i f_i(X_q), f_i = sum_l f_il phi_l (collapse
+                // only without functions)
+                double wf = w;
+                for (int f = 0; f < a.nf; ++f) {
+                    const double* cf = a.coeff + e * cst + own + f * ns;
+                    double fv = 0.0;
+                    for (int l = 0; l < ns; ++l) fv = fma(cf[l], sPhi[qq * ns + l], fv);
+                    wf *= fv;
+                }
                 if (FORM == MASS || FORM == HELMHOLTZ) {
-                    // w times prod_i f_i(X_q), f_i = sum_l f_il phi_l
-                    double wf = w;
-                    for (int f = 0; f < a.nf; ++f) {
-                        const double* cf = a.coeff + (e * a.nf + f) * ns;
-                        double fv = 0.0;
-                        for (int l = 0; l < ns; ++l) fv = fma(cf[l], sPhi[qq * ns + l], fv);
-                        wf *= fv;
-                    }
                     sw[0] = wf;
                 } else if (FORM == ELASTICITY) {
-                    const double* ce = a.coeff + e * 2 * NV;
+                    const double* ce = a.coeff + e * cst;
                     if (a.collapse) {
                         // sum_q W_q lambda(X_q), sum_q W_q mu(X_q)
                         double lam = 0.0, mu = 0.0;
@@ -235,12 +241,12 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
                             lam = fma(ce[l], ps[l], lam);
                             mu = fma(ce[NV + l], ps[l], mu);
                         }
-                        sw[0] = w * lam;
-                        sw[1] = w * mu;
+                        sw[0] = wf * lam;
+                        sw[1] = wf * mu;
                     }
                 } else {
                     // F = I + sum_k u_k (x) g_k at this point
-                    const double* ue = a.coeff + e * (D * ns);
+                    const double* ue = a.coeff + e * cst;
                     double F[3][3], Fi[3][3];
 #pragma unroll
                     for (int r = 0; r < 3; ++r)
@@ -263,9 +269,9 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
                         for (int c = 0; c < 3; ++c) fi[r * 3 + c] = (r < D && c < D) ? Fi[r][c] : 0.0;
                     if (!(jf > 0.0)) sEl[i * L::PER_ELEM + 10] = 1.0;
                     const double lnj = log(jf);
-                    sw[0] = w * a.lam;                    // lambda'
-                    sw[1] = w * (a.mu - a.lam * lnj);     // alpha'
-                    sw[2] = w * a.mu;                     // mu'
+                    sw[0] = wf * a.lam;                   // lambda'
+                    sw[1] = wf * (a.mu - a.lam * lnj);    // alpha'
+                    sw[2] = (a.skip & 2) ? 0.0 : wf * a.mu;   // mu' (the trace term)
                 }
             }
             __syncthreads();

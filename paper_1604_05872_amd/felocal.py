@@ -278,8 +278,9 @@ def fe_assemble_local(form: str, cell: str, degree: int, coords, coeff, out, qde
 
     shape: optional launch-shape override, keys of fe_shape_t (kernel: 1 tiled,
     2 streaming pre-evaluated, 3 VALU, 4 matrix-core quadrature, 5 hoisted
-    degree-1 vector kernel; block, epi, chunk, eb, qc, grid_per_cu).  nf: mass and
-    Helmholtz pre-multiplied by nf coefficient functions, coeff [E][nf][n_s].
+    degree-1 vector kernel; block, epi, chunk, eb, qc, grid_per_cu).  nf: the form
+    pre-multiplied by nf coefficient functions; an element's coeff record is the
+    form's own DOFs followed by the functions' [nf][n_s].
     pointgeo: prisms need not be affine (the vertex map at every point)."""
     _f64_dev(coords, "coords")
     _f64_dev(coeff, "coeff")
@@ -291,7 +292,7 @@ def fe_assemble_local(form: str, cell: str, degree: int, coords, coeff, out, qde
     if tuple(out.shape[-2:]) != (n, n) or out.numel() != E * n * n:
         raise ValueError(f"out must be [E][{n}][{n}]")
     if nf:
-        nc = int(nf) * NBASIS(cell, degree)
+        nc += int(nf) * NBASIS(cell, degree)
     if nc and (coeff is None or coeff.numel() != E * nc):
         raise ValueError(f"coeff must hold {nc} values per element")
     o = make_options(qdeg, precision, mode, stream, mu, lam, status, th_bytes, validate, shape=shape, nf=nf,

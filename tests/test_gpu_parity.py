@@ -494,6 +494,94 @@ def test_coefficient_mixed_plans(cell, p, nf, want):
         assert normwise(A, B).max() <= TOL["fp64"]
 
 
+# The vector forms pre-multiplied by nf functions (the Sec. 7.1 matrix for
+# Elasticity and Hyperelasticity): Algorithm 3's choice (the hyperelastic
+# trace term pre-evaluated by the coefficient kernel on top of the VALU
+# kernel where it pays), forced quadrature, and forced pre-evaluation
+# (elasticity, where its tile fits the LDS; illegal for the hyperelastic
+# terms in F).
+VEC_NF_CASES = [(f, c, p, nf) for f in ("elasticity", "hyperelastic")
+                for (c, p) in [("tetrahedron", 1), ("tetrahedron", 2), ("tetrahedron", 3), ("triangle", 2),
+                               ("triangle", 4), ("prism", 1)] for nf in (1, 2, 3)]
+
+
+def vec_nf_coeff(form, cell, p, E, V, cells, h, nf, seed):
+    own = coefficients(form, cell, p, E, V, cells, h, seed).reshape(E, -1)
+    f = np.random.default_rng(seed + 1).uniform(0.5, 1.5, size=(E, nf * oracle.nbasis(cell, p)))
+    return np.ascontiguousarray(np.concatenate([own, f], axis=1))
+
+
+def _elast_coef_lds_bytes(cell, p, nf):
+    from math import comb
+    ns, nc, d = oracle.nbasis(cell, p), oracle.NVERT[cell], oracle.TDIM[cell]
+    iota = comb(ns + nf - 1, nf)
+    ntp = (nc * iota * d * d + 7) // 8 * 8
+    return 8 * 16 * (ntp + 12 + 2 * nc + nf * ns + iota)
+
+
+@pytest.mark.parametrize("mode", ["auto", "quadrature", "preeval"])
+@pytest.mark.parametrize("form,cell,p,nf", VEC_NF_CASES)
+def test_vector_coefficient_functions(form, cell, p, nf, mode):
+    ns, d = oracle.nbasis(cell, p), oracle.TDIM[cell]
+    nq = oracle.rule(cell, oracle.default_qdeg(form, cell, p, nf))[1].size
+    E = int(max(7, min(400, 1.5e9 / (nq * (d * ns) ** 2 * 40))))
+    log(f"vector coefficient functions {form} {cell} P{p} nf={nf} {mode} E={E}")
+    coords, V, cells, h = mesh(cell, E, seed=90 + p)
+    cf = vec_nf_coeff(form, cell, p, E, V, cells, h, nf, seed=95 + nf)
+    if mode == "preeval" and form == "hyperelastic":
+        with pytest.raises(felocal.FeError) as ei:
+            gpu_assemble(form, cell, p, coords, cf, nf=nf, mode=mode)
+        assert ei.value.code == felocal.FE_ENOTSUP
+        return
+    lds = _elast_coef_lds_bytes(cell, p, nf)
+    if mode == "preeval" and lds > 160 * 1024:
+        with pytest.raises(felocal.FeError):
+            gpu_assemble(form, cell, p, coords, cf, nf=nf, mode=mode)
+        return
+    try:
+        A, st = gpu_assemble(form, cell, p, coords, cf, nf=nf, mode=mode)
+    except felocal.FeError:
+        assert mode == "preeval" and lds > 64 * 1024   # only where the device's limit decides
+        return
+    B, fl = oracle.assemble(form, cell, p, coords, cf, nf=nf)
+    bad = np.isnan(B[:, 0, 0])
+    assert st == fl == bad.sum() and fl <= E // 50
+    assert (np.isnan(A[:, 0, 0]) == bad).all() and np.isfinite(A[~bad]).all()
+    assert normwise(A[~bad], B[~bad]).max() <= TOL["fp64"]
+
+
+@pytest.mark.parametrize("cell,p,nf", [("tetrahedron", 1, 1), ("tetrahedron", 2, 2), ("triangle", 3, 1),
+                                       ("prism", 2, 1)])
+def test_hyperelastic_trace_preevaluated(cell, p, nf):
+    """A plan that pre-evaluates the hyperelastic trace term with nf
+    functions (Algorithm 3 with iota = C(n_s + nf - 1, nf)): the coefficient
+    kernel adds it to the diagonal blocks after the VALU kernel, and the
+    result equals forced quadrature and the oracle; flagged elements (a
+    degenerate map, an inverted point) stay NaN."""
+    plan = felocal.fe_plan("hyperelastic", cell, p, nf=nf)
+    assert plan["preevaluated"] == [False, True], plan
+    E = 300
+    log(f"hyperelastic trace pre-evaluated {cell} P{p} nf={nf}")
+    coords, V, cells, h = mesh(cell, E, seed=97)
+    coords = coords.copy()
+    coords[11, 1] = coords[11, 0]
+    cf = vec_nf_coeff("hyperelastic", cell, p, E, V, cells, h, nf, seed=98)
+    cf[[40, 200], :d_ns(cell, p)] *= 40.0
+    B, fl = oracle.assemble("hyperelastic", cell, p, coords, cf, nf=nf)
+    bad = np.isnan(B[:, 0, 0])
+    assert bad[11] and fl == bad.sum() >= 2
+    A, st = gpu_assemble("hyperelastic", cell, p, coords, cf, nf=nf)
+    Aq, stq = gpu_assemble("hyperelastic", cell, p, coords, cf, nf=nf, mode="quadrature")
+    assert st == stq == fl
+    for X in (A, Aq):
+        assert (np.isnan(X[:, 0, 0]) == bad).all() and np.isnan(X[bad]).all() and np.isfinite(X[~bad]).all()
+        assert normwise(X[~bad], B[~bad]).max() <= TOL["fp64"]
+
+
+def d_ns(cell, p):
+    return oracle.TDIM[cell] * oracle.nbasis(cell, p)
+
+
 # Indefinite point weights: a Lame field shifted below zero (lambda or mu),
 # and a negative hyperelastic lambda, through every precision.
 SIGNED_CASES = [("elasticity", "tetrahedron", 2, 0), ("elasticity", "triangle", 3, 0),

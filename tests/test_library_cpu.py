@@ -156,9 +156,18 @@ def test_planner_coefficient_functions():
     assert felocal.fe_plan("helmholtz", "tetrahedron", 4, nf=1, th_bytes=T)["preevaluated"] == [False, False]
     # with T_H relaxed the expansion still pays at P3 (theta < 0)
     assert felocal.fe_plan("helmholtz", "tetrahedron", 3, nf=1, th_bytes=1 << 30)["mode"] == "preeval"
-    # vector forms take no pre-multiplying functions
-    with pytest.raises(felocal.FeError):
-        felocal.fe_plan("elasticity", "tetrahedron", 2, nf=1)
+    # vector forms: elasticity expands its P1 Lame field and the functions
+    # (iota = n_c C(n_s + nf - 1, nf)), the hyperelastic trace term the
+    # functions only (iota = C(n_s + nf - 1, nf)); rho as without functions
+    pe = felocal.fe_plan("elasticity", "tetrahedron", 2, nf=1)
+    assert pe["iota"] == [40, 40] and pe["rho"] == [9, 18]
+    assert pe["table_bytes"][0] == 4 * 10 * 9 * 100 * 8
+    ph = felocal.fe_plan("hyperelastic", "tetrahedron", 2, nf=2)
+    assert ph["iota"] == [0, 55] and ph["rho"] == [0, 6]
+    nq = oracle.rule("tetrahedron", oracle.default_qdeg("hyperelastic", "tetrahedron", 2, 2))[1].size
+    # trace term: 2 rho iota + d operations per pair against 3 d per pair and point
+    assert ph["theta_pre"][1] == (2 * 6 * 55 + 3) * 100 and ph["theta_se"][1] == nq * 100 * 9
+    assert ph["preevaluated"] == [False, (2 * 6 * 55 + 3) < nq * 9]
 
 
 def test_argument_errors_are_synchronous():
@@ -184,7 +193,9 @@ def test_argument_errors_are_synchronous():
     o.nf = 4
     assert L.fe_assemble_local(0, 1, 2, 1, 8, 8, 8, ctypes.byref(o)) == felocal.FE_EINVAL     # nf in 0..3
     o.nf = 1
-    assert L.fe_assemble_local(2, 1, 2, 1, 8, 8, 8, ctypes.byref(o)) == felocal.FE_ENOTSUP    # not vector forms
+    o.precision = 2
+    assert L.fe_assemble_local(2, 1, 2, 1, 8, 8, 8, ctypes.byref(o)) == felocal.FE_ENOTSUP    # float64 only
+    o.precision = 0
     assert L.fe_assemble_local(1, 1, 2, 1, 8, None, 8, ctypes.byref(o)) == felocal.FE_EINVAL  # DOFs needed
     o.nf = 0
     for field, bad in (("kernel", 6), ("kernel", -1), ("block", -64), ("epi", -1), ("chunk", -2), ("eb", -1),
