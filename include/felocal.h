@@ -403,6 +403,27 @@ int fe_csr_destroy(fe_csr_t* csr);
 int fe_assemble_csr(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
                     fe_csr_t* csr, double* values, const fe_options_t* opt);
 
+/* fe_assemble_csr without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, result (bit for bit) and errors as
+ * fe_assemble_csr, and the same kernels; only the geometry workspace differs:
+ * instead of the handle's (allocated on first use), a file-scope device array
+ * of the library, 64 B per element, at most 1,048,576 elements (64 MiB that
+ * every GPU the library runs on holds until the process ends).  The call
+ * performs no hipMalloc, hipFree or other allocating call:
+ *   - n_elems above 1,048,576 returns FE_ENOMEM;
+ *   - the reference tables of (cell, degree, rule) are not built here: an
+ *     earlier call on this device must have built them (any fe_assemble_local
+ *     or fe_assemble_csr call with the same cell, degree and rule), else
+ *     FE_EINVAL.
+ * All calls on one GPU share that GPU's array, which keeps the last call's
+ * contents (every element's entry is rewritten before it is read, so nothing
+ * needs clearing): calls that overlap on one GPU (different streams or host
+ * threads) race and must be serialised by the caller.  Asynchronous on
+ * opt->stream. */
+int fe_assemble_csr_noalloc(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
+                            fe_csr_t* csr, double* values, const fe_options_t* opt);
+
 /* Automatic sharing elimination (Sec. 3.2, Algorithm 1) and code generation
  * for generic scalar bilinear forms.  A form is a sum of terms
  *     scale * c(x) * s_test(phi_j) * s_trial(phi_k),

@@ -15,6 +15,8 @@
 // for bit.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "csr.hpp"
 #include "felocal.h"
 #include "internal.hpp"
@@ -23,7 +25,7 @@
 namespace fe {
 
 int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
-                 const double* coeff_dofs, double* out_A, const fe_options_t* opt, Call* c);
+                 const double* coeff_dofs, double* out_A, const fe_options_t* opt, Call* c, int lookup_only);
 
 namespace {
 
@@ -166,7 +168,8 @@ __global__ __launch_bounds__(1024) void k_csr_preeval(int64_t N, int n, const in
 }
 
 template <int FORM, int CELL, int W, int KPL, int B>
-hipError_t launch_fused(const fe_csr* c, const double* tables, double* vals, int round_cap, hipStream_t s)
+hipError_t launch_fused(const fe_csr* c, const double* geo, const double* tables, double* vals, int round_cap,
+                        hipStream_t s)
 {
     constexpr int NT = n_tables(FORM, CELL);
     const size_t tab = sizeof(double) * (size_t)NT * c->n * c->n;
@@ -187,7 +190,7 @@ hipError_t launch_fused(const fe_csr* c, const double* tables, double* vals, int
     if (grid * waves > visits) grid = (visits + waves - 1) / waves;
     if (grid < 1) grid = 1;
     k_csr_preeval<FORM, CELL, W, KPL, B><<<(unsigned)grid, waves * CSR_WAVE, lds, s>>>(
-        c->N, c->n, c->row_ptr, c->pair_ptr, c->list, c->pos, c->geo, tables, vals, round_cap, vp);
+        c->N, c->n, c->row_ptr, c->pair_ptr, c->list, c->pos, geo, tables, vals, round_cap, vp);
     return hipGetLastError();
 }
 
@@ -195,23 +198,23 @@ hipError_t launch_fused(const fe_csr* c, const double* tables, double* vals, int
 // rows side by side in a wavefront, so that more rows have their loads in
 // flight at once (each row's chain of dependent loads is what bounds the pass).
 template <int FORM, int CELL>
-hipError_t fused_shape(const fe_csr* c, const double* tables, double* vals, hipStream_t s);
+hipError_t fused_shape(const fe_csr* c, const double* geo, const double* tables, double* vals, hipStream_t s);
 
 // The measured shape first; where its rounds do not fit in LDS beside the
 // tables (rows shared by very many elements), one row per round (the
 // smallest round).  hipErrorInvalidConfiguration when even that does not fit.
 template <int FORM, int CELL>
-hipError_t fused_for_n(const fe_csr* c, const double* tables, double* vals, hipStream_t s)
+hipError_t fused_for_n(const fe_csr* c, const double* geo, const double* tables, double* vals, hipStream_t s)
 {
-    const hipError_t e = fused_shape<FORM, CELL>(c, tables, vals, s);
+    const hipError_t e = fused_shape<FORM, CELL>(c, geo, tables, vals, s);
     if (e != hipErrorInvalidConfiguration) return e;
     const int cap0 = c->round_len[0] > 0 ? c->round_len[0] : 1;
-    if (c->n <= 64) return launch_fused<FORM, CELL, 64, 1, 2>(c, tables, vals, cap0, s);
-    return launch_fused<FORM, CELL, 64, 2, 2>(c, tables, vals, cap0, s);
+    if (c->n <= 64) return launch_fused<FORM, CELL, 64, 1, 2>(c, geo, tables, vals, cap0, s);
+    return launch_fused<FORM, CELL, 64, 2, 2>(c, geo, tables, vals, cap0, s);
 }
 
 template <int FORM, int CELL>
-hipError_t fused_shape(const fe_csr* c, const double* tables, double* vals, hipStream_t s)
+hipError_t fused_shape(const fe_csr* c, const double* geo, const double* tables, double* vals, hipStream_t s)
 {
     const int n = c->n;
     // lanes per row: 8 up to n = 32 (eight rows side by side; measured on
@@ -225,26 +228,68 @@ hipError_t fused_shape(const fe_csr* c, const double* tables, double* vals, hipS
     // for the seven-term Helmholtz tensors
     constexpr int BS = n_tables(FORM, CELL) > 1 ? 4 : 8;
     constexpr int B8 = BS / 2;
-    if (n <= 4) return launch_fused<FORM, CELL, 4, 1, BS>(c, tables, vals, cap, s);
-    if (n <= 8) return launch_fused<FORM, CELL, 8, 1, BS>(c, tables, vals, cap, s);
-    if (n <= 16) return launch_fused<FORM, CELL, 8, 2, B8>(c, tables, vals, cap, s);
-    if (n <= 24) return launch_fused<FORM, CELL, 8, 3, B8>(c, tables, vals, cap, s);
-    if (n <= 32) return launch_fused<FORM, CELL, 8, 4, B8>(c, tables, vals, cap, s);
-    if (n <= 48) return launch_fused<FORM, CELL, 16, 3, BS == 4 ? 3 : 4>(c, tables, vals, cap, s);
-    if (n <= 64) return launch_fused<FORM, CELL, 16, 4, BS == 4 ? 2 : 4>(c, tables, vals, cap, s);
-    if (n <= 96) return launch_fused<FORM, CELL, 32, 3, 2>(c, tables, vals, cap, s);
-    return launch_fused<FORM, CELL, 64, 2, 2>(c, tables, vals, cap, s);
+    if (n <= 4) return launch_fused<FORM, CELL, 4, 1, BS>(c, geo, tables, vals, cap, s);
+    if (n <= 8) return launch_fused<FORM, CELL, 8, 1, BS>(c, geo, tables, vals, cap, s);
+    if (n <= 16) return launch_fused<FORM, CELL, 8, 2, B8>(c, geo, tables, vals, cap, s);
+    if (n <= 24) return launch_fused<FORM, CELL, 8, 3, B8>(c, geo, tables, vals, cap, s);
+    if (n <= 32) return launch_fused<FORM, CELL, 8, 4, B8>(c, geo, tables, vals, cap, s);
+    if (n <= 48) return launch_fused<FORM, CELL, 16, 3, BS == 4 ? 3 : 4>(c, geo, tables, vals, cap, s);
+    if (n <= 64) return launch_fused<FORM, CELL, 16, 4, BS == 4 ? 2 : 4>(c, geo, tables, vals, cap, s);
+    if (n <= 96) return launch_fused<FORM, CELL, 32, 3, 2>(c, geo, tables, vals, cap, s);
+    return launch_fused<FORM, CELL, 64, 2, 2>(c, geo, tables, vals, cap, s);
 }
 
+// geo: the geometry workspace, [E][GEO_STRIDE] doubles
 template <int FORM, int CELL>
-hipError_t run_fused(const fe_csr* c, const double* coords, const double* tables, double* vals, int* status,
-                     hipStream_t s)
+hipError_t run_fused(const fe_csr* c, double* geo, const double* coords, const double* tables, double* vals,
+                     int* status, hipStream_t s)
 {
     const unsigned blocks = (unsigned)((c->E + 255) / 256);
-    k_csr_geometry<FORM, CELL><<<blocks, 256, 0, s>>>(c->E, coords, c->geo, status);
+    k_csr_geometry<FORM, CELL><<<blocks, 256, 0, s>>>(c->E, coords, geo, status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return fused_for_n<FORM, CELL>(c, tables, vals, s);
+    return fused_for_n<FORM, CELL>(c, geo, tables, vals, s);
+}
+
+hipError_t run_fused_form(int form, int cell, const fe_csr* c, double* geo, const double* coords,
+                          const double* R, double* values, int* status, hipStream_t s)
+{
+    if (form == FE_MASS)
+        return cell == FE_TRIANGLE      ? run_fused<MASS, TRI>(c, geo, coords, R, values, status, s)
+               : cell == FE_TETRAHEDRON ? run_fused<MASS, TET>(c, geo, coords, R, values, status, s)
+                                        : run_fused<MASS, PRISM>(c, geo, coords, R, values, status, s);
+    return cell == FE_TRIANGLE      ? run_fused<HELMHOLTZ, TRI>(c, geo, coords, R, values, status, s)
+           : cell == FE_TETRAHEDRON ? run_fused<HELMHOLTZ, TET>(c, geo, coords, R, values, status, s)
+                                    : run_fused<HELMHOLTZ, PRISM>(c, geo, coords, R, values, status, s);
+}
+
+// The geometry workspace of fe_assemble_csr_noalloc: file-scope device
+// memory (every GPU the library runs on holds its own copy until the process
+// ends), so the entry point allocates nothing.  In host code the array's
+// name is only a stand-in: kernels get the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+constexpr int64_t NOALLOC_MAX_ELEMS = (int64_t)1 << 20;   // 64 MiB of workspace
+__device__ __align__(256) double scratch[GEO_STRIDE * NOALLOC_MAX_ELEMS];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {nullptr};
+
+// the current device's address of `scratch`, or nullptr (error set)
+double* scratch_address()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol, "fe_assemble_csr_noalloc workspace address");
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    return g_scratch_ptr[dev];
 }
 
 }  // namespace
@@ -257,7 +302,7 @@ extern "C" int fe_assemble_csr(fe_form_t form, fe_cell_t cell, int degree, int64
     if (!csr) return FE_EINVAL;
     Call c;
     // out_A is not written here: pass values so that argument checks see a buffer
-    int rc = resolve_call(form, cell, degree, n_elems, coords, nullptr, values, opt, &c);
+    int rc = resolve_call(form, cell, degree, n_elems, coords, nullptr, values, opt, &c, 0);
     if (rc) return rc;
     if (csr->E != n_elems || csr->n != n_rows(form, cell, degree)) return FE_EINVAL;
     if ((form != FE_MASS && form != FE_HELMHOLTZ) || c.nf != 0 || c.prec != FE_FP64) return FE_ENOTSUP;
@@ -272,17 +317,30 @@ extern "C" int fe_assemble_csr(fe_form_t form, fe_cell_t cell, int degree, int64
             return FE_ENOMEM;
         }
     }
-    const double* R = c.tables->dR;
-    hipError_t e;
-    if (form == FE_MASS) {
-        e = cell == FE_TRIANGLE      ? run_fused<MASS, TRI>(csr, coords, R, values, c.status, c.stream)
-            : cell == FE_TETRAHEDRON ? run_fused<MASS, TET>(csr, coords, R, values, c.status, c.stream)
-                                     : run_fused<MASS, PRISM>(csr, coords, R, values, c.status, c.stream);
-    } else {
-        e = cell == FE_TRIANGLE      ? run_fused<HELMHOLTZ, TRI>(csr, coords, R, values, c.status, c.stream)
-            : cell == FE_TETRAHEDRON ? run_fused<HELMHOLTZ, TET>(csr, coords, R, values, c.status, c.stream)
-                                     : run_fused<HELMHOLTZ, PRISM>(csr, coords, R, values, c.status, c.stream);
-    }
+    const hipError_t e = run_fused_form(form, cell, csr, csr->geo, coords, c.tables->dR, values, c.status, c.stream);
     if (e == hipErrorInvalidConfiguration) return FE_ENOTSUP;   // one row and the tables exceed the LDS
     return e == hipSuccess ? FE_OK : set_hip_error(e, "fe_assemble_csr");
+}
+
+extern "C" int fe_assemble_csr_noalloc(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems,
+                                       const double* coords, fe_csr_t* csr, double* values, const fe_options_t* opt)
+{
+    using namespace fe;
+    if (!csr) return FE_EINVAL;
+    if (n_elems > NOALLOC_MAX_ELEMS) return FE_ENOMEM;
+    Call c;
+    // the reference tables must already be cached: look them up, never build
+    int rc = resolve_call(form, cell, degree, n_elems, coords, nullptr, values, opt, &c, /*lookup_only=*/1);
+    if (rc) return rc;
+    if (csr->E != n_elems || csr->n != n_rows(form, cell, degree)) return FE_EINVAL;
+    if ((form != FE_MASS && form != FE_HELMHOLTZ) || c.nf != 0 || c.prec != FE_FP64) return FE_ENOTSUP;
+    if (n_elems == 0 || csr->nnz == 0) return FE_OK;
+    if (c.mode != FE_MODE_PREEVAL) return FE_ENOTSUP;
+    const size_t tab = sizeof(double) * (size_t)n_tables(form, cell) * csr->n * csr->n;
+    if (tab > CSR_TABLE_LDS_MAX || tab > device_lds_per_block()) return FE_ENOTSUP;
+    double* geo = scratch_address();
+    if (!geo) return FE_EHIP;
+    const hipError_t e = run_fused_form(form, cell, csr, geo, coords, c.tables->dR, values, c.status, c.stream);
+    if (e == hipErrorInvalidConfiguration) return FE_ENOTSUP;
+    return e == hipSuccess ? FE_OK : set_hip_error(e, "fe_assemble_csr_noalloc");
 }

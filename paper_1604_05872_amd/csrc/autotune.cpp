@@ -202,7 +202,7 @@ void lookup_config(const Call& c, Config* cfg)
 }
 
 int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
-                 const double* coeff_dofs, double* out_A, const fe_options_t* opt, Call* c);
+                 const double* coeff_dofs, double* out_A, const fe_options_t* opt, Call* c, int lookup_only);
 
 }  // namespace fe
 
@@ -214,7 +214,7 @@ extern "C" int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n
 {
     if (n_elems < 1) return FE_EINVAL;
     Call c;
-    int rc = resolve_call(form, cell, degree, n_elems, coords, coeff_dofs, out_A, opt, &c);
+    int rc = resolve_call(form, cell, degree, n_elems, coords, coeff_dofs, out_A, opt, &c, 0);
     if (rc) return rc;
     if (c.pointgeo) return FE_ENOTSUP;   // per-point prism maps use the built-in shape
     std::vector<Config> cands;

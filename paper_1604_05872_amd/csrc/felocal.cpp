@@ -141,6 +141,17 @@ int get_tables(int cell, int p, int qdeg, hipStream_t s, const RefTables** out)
     return FE_OK;
 }
 
+// The cached reference tables of (cell, p, qdeg) on the current device,
+// without building them: FE_EINVAL when no earlier call built them.
+int find_tables(int cell, int p, int qdeg, const RefTables** out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tables.find(std::make_tuple(current_device(), cell, p, qdeg));
+    if (it == g_tables.end()) return FE_EINVAL;
+    *out = it->second;
+    return FE_OK;
+}
+
 // Builds (once) the multisets and the coefficient-expanded reference tensors
 // of (form, cell, p, qdeg, nf) on the current device.
 int get_coef_tables(int form, int cell, int p, int qdeg, int nf, hipStream_t s, const CoefTables** out)
@@ -793,7 +804,7 @@ int final_config(const Call& c, Config* cfg)
 
 // Validates the arguments of fe_assemble_local and resolves them into a Call.
 int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
-                 const double* coeff_dofs, double* out_A, const fe_options_t* opt, Call* c)
+                 const double* coeff_dofs, double* out_A, const fe_options_t* opt, Call* c, int lookup_only)
 {
     fe_options_t o;
     if (opt) o = *opt;
@@ -849,6 +860,7 @@ int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, co
         rc = validate_prisms(n_elems, coords, c->stream);
         if (rc) return rc;
     }
+    if (lookup_only) return find_tables(cell, degree, qdeg, &c->tables);
     return get_tables(cell, degree, qdeg, c->stream, &c->tables);
 }
 
@@ -860,7 +872,7 @@ int fe_assemble_local(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elem
                       const double* coeff_dofs, double* out_A, const fe_options_t* opt)
 {
     Call c;
-    int rc = resolve_call(form, cell, degree, n_elems, coords, coeff_dofs, out_A, opt, &c);
+    int rc = resolve_call(form, cell, degree, n_elems, coords, coeff_dofs, out_A, opt, &c, 0);
     if (rc || n_elems == 0) return rc;
     Config cfg;
     rc = final_config(c, &cfg);

@@ -186,6 +186,7 @@ struct CoefTables {
 
 // felocal.cpp
 int get_tables(int cell, int p, int qdeg, hipStream_t s, const RefTables** out);
+int find_tables(int cell, int p, int qdeg, const RefTables** out);
 int get_coef_tables(int form, int cell, int p, int qdeg, int nf, hipStream_t s, const CoefTables** out);
 int device_cus();
 size_t device_lds_per_cu();

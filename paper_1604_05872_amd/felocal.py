@@ -35,6 +35,7 @@ EXPORTS = (
     "fe_batch_create", "fe_batch_run", "fe_batch_destroy", "fe_batch_info", "fe_autotune", "fe_autotune_clear",
     "fe_strerror", "fe_release_caches", "fe_version",
     "fe_csr_create", "fe_csr_info", "fe_csr_pattern", "fe_csr_insert", "fe_csr_destroy", "fe_assemble_csr",
+    "fe_assemble_csr_noalloc",
     "fe_sharing_plan", "fe_form_source", "fe_assemble_form",
 )
 
@@ -183,6 +184,8 @@ def lib():
                                        vp, vp, vp, ctypes.POINTER(fe_options_t)]
         L.fe_assemble_csr.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, vp, vp, vp,
                                       ctypes.POINTER(fe_options_t)]
+        L.fe_assemble_csr_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, vp, vp, vp,
+                                              ctypes.POINTER(fe_options_t)]
         _lib = L
     return _lib
 
@@ -445,6 +448,20 @@ class CsrPattern:
         o = make_options(qdeg, "fp64", mode, stream, status=status, validate=validate)
         _check(lib().fe_assemble_csr(FORMS[form], CELLS[cell], int(degree), int(coords.shape[0]), _ptr(coords),
                                      self.handle, _ptr(values), ctypes.byref(o)), "fe_assemble_csr")
+        return values
+
+    def assemble_noalloc(self, form: str, cell: str, degree: int, coords, values, qdeg: int = -1,
+                         mode: str = "auto", stream=None, status=None):
+        """As assemble, through fe_assemble_csr_noalloc (no device allocation;
+        the reference tables must already be built on this device)."""
+        _f64_dev(coords, "coords")
+        _f64_dev(values, "values")
+        if values.numel() != self.info()["nnz"]:
+            raise ValueError("values must hold nnz entries")
+        o = make_options(qdeg, "fp64", mode, stream, status=status)
+        _check(lib().fe_assemble_csr_noalloc(FORMS[form], CELLS[cell], int(degree), int(coords.shape[0]),
+                                             _ptr(coords), self.handle, _ptr(values), ctypes.byref(o)),
+               "fe_assemble_csr_noalloc")
         return values
 
     def close(self):
