@@ -79,6 +79,9 @@ def lib():
         L.orc_assemble_pointgeo.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, dp, dp,
                                             ctypes.c_double, ctypes.c_double, dp, ctypes.c_int]
         L.orc_assemble_pointgeo.restype = ctypes.c_int64
+        L.orc_assemble_curved.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, dp,
+                                          dp, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int]
+        L.orc_assemble_curved.restype = ctypes.c_int64
         i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
         L.orc_csr_insert.argtypes = [ctypes.c_int64, ctypes.c_int, i32p, ctypes.c_int64, i64p, i32p, dp, dp]
         L.orc_csr_insert.restype = ctypes.c_int
@@ -239,6 +242,33 @@ def assemble_pointgeo(form: str, p: int, coords, coeff=None, qdeg=None, mu: floa
     if flagged < 0:
         raise ValueError("oracle rejected arguments")
     return out, int(flagged)
+
+
+def assemble_curved(form: str, cell: str, p: int, coords, coeff=None, qdeg=None, mu: float = 1.0,
+                    lam: float = 10.0, nthreads: int = 0):
+    """Element matrices of curved triangles and tetrahedra: the isoparametric
+    P2 map through the element's P2 nodes coords [E][n_2][d] (lattice order),
+    its J, det J and J^{-1} at every quadrature point.  The default rule adds
+    d degrees to the affine default (det J of a P2 map has degree d, so the
+    mass form stays exact).  Returns (out [E][n][n], flagged)."""
+    coords = _f64(coords)
+    E = coords.shape[0]
+    n = local_dim(form, cell, p)
+    if qdeg is None:
+        qdeg = default_qdeg_curved(form, cell, p)
+    out = np.empty((E, n, n))
+    cf = _f64(coeff) if coeff is not None else None
+    if form in ("elasticity", "hyperelastic") and cf is None:
+        raise ValueError("coefficients required")
+    flagged = lib().orc_assemble_curved(FORM[form], CELL[cell], p, qdeg, E, _p(coords), _p(cf), mu, lam, _p(out),
+                                        nthreads)
+    if flagged < 0:
+        raise ValueError("oracle rejected arguments")
+    return out, int(flagged)
+
+
+def default_qdeg_curved(form: str, cell: str, p: int) -> int:
+    return default_qdeg(form, cell, p) + TDIM[cell]
 
 
 def default_qdeg_pointgeo(form: str, p: int) -> int:

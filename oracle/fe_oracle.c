@@ -468,11 +468,27 @@ int64_t orc_assemble_coef(int form, int cell, int p, int qdeg, int nf, int64_t E
     return assemble_nest(form, cell, p, qdeg, nf, 0, E, coords, coeff, mu_c, lam_c, out, nthreads);
 }
 
+/* Curved triangles and tetrahedra: F_K is the isoparametric P2 map
+ * x(X) = sum_m psi2_m(X) x_m over the element's six (triangle) or ten
+ * (tetrahedron) P2 nodes, coords[E][n_2][d] in the lattice node order, so J,
+ * det J and J^{-1} vary over the element and are evaluated at every
+ * quadrature point (J(X_q) = sum_m x_m (x) grad psi2_m(X_q)).  The Lame
+ * fields stay P1 in the reference coordinates.  Flagged as the non-affine
+ * prisms above. */
+int64_t orc_assemble_curved(int form, int cell, int p, int qdeg, int64_t E, const double *coords,
+                            const double *coeff, double mu_c, double lam_c, double *out, int nthreads)
+{
+    if (cell != 0 && cell != 1) return -1;
+    return assemble_nest(form, cell, p, qdeg, 0, 2, E, coords, coeff, mu_c, lam_c, out, nthreads);
+}
+
 static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int pointgeo, int64_t E,
                              const double *coords, const double *coeff,
                              double mu_c, double lam_c, double *out, int nthreads)
 {
     int d = tdim_of(cell), nv = nvert_of(cell);
+    /* nodes of the element map: the vertices, or the P2 nodes of a curved simplex */
+    const int nmap = pointgeo == 2 ? orc_nbasis(cell, 2) : nv;
     int ns = orc_nbasis(cell, p);
     if (ns < 0 || form < 0 || form > 3) return -1;
     int vec = (form >= 2);
@@ -487,20 +503,28 @@ static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int po
     double *PHI = (double *)malloc(sizeof(double) * nq * ns);
     double *DPHI = (double *)malloc(sizeof(double) * nq * ns * 3);
     double *PSI = (double *)malloc(sizeof(double) * nq * 6);
-    double *DPSI = (double *)malloc(sizeof(double) * (nq + 1) * 18);
+    double *DPSI = (double *)malloc(sizeof(double) * (nq + 1) * 30);
     orc_rule(cell, qdeg, X, W);
     /* reference tabulation Phi_i(X_q), dPhi_i/dX_a(X_q): the tables of Eq. (7) */
     for (int q = 0; q < nq; ++q) {
         orc_basis(cell, p, X + q * d, PHI + q * ns, DPHI + q * ns * d);
         p1_basis(cell, X + q * d, PSI + q * 6);
-        if (pointgeo) {
+        if (pointgeo == 1) {
             double ps[6];
 #if ORC_MUTANT == 12
             /* planted mistake: the vertex map's gradient at the centroid for every point */
             const double Xc[3] = {1.0 / 3.0, 1.0 / 3.0, 0.5};
-            p1_basis_grad(cell, Xc, ps, DPSI + q * 18);
+            p1_basis_grad(cell, Xc, ps, DPSI + q * 30);
 #else
-            p1_basis_grad(cell, X + q * d, ps, DPSI + q * 18);
+            p1_basis_grad(cell, X + q * d, ps, DPSI + q * 30);
+#endif
+        } else if (pointgeo == 2) {
+            double ps[10];
+#if ORC_MUTANT == 14
+            /* planted mistake: the curved map's gradient taken at the first point for every point */
+            orc_basis(cell, 2, X, ps, DPSI + q * 30);
+#else
+            orc_basis(cell, 2, X + q * d, ps, DPSI + q * 30);
 #endif
         }
     }
@@ -511,7 +535,7 @@ static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int po
 #endif
     for (int64_t e = 0; e < E; ++e) {
         double *A = out + (size_t)e * n * n;
-        const double *v = coords + (size_t)e * nv * d;
+        const double *v = coords + (size_t)e * nmap * d;
         double J[9], K[9], detJ, det0 = 0.0;
         int bad = 0;
         if (!pointgeo) {
@@ -527,7 +551,7 @@ static int64_t assemble_nest(int form, int cell, int p, int qdeg, int nf, int po
                 for (int r = 0; r < d; ++r)
                     for (int a = 0; a < d; ++a) {
                         double s = 0.0;
-                        for (int l = 0; l < nv; ++l) s += v[l * d + r] * DPSI[q * 18 + l * d + a];
+                        for (int l = 0; l < nmap; ++l) s += v[l * d + r] * DPSI[q * 30 + l * d + a];
                         J[r * d + a] = s;
                     }
                 detJ = jac_inverse(d, J, K);

@@ -264,6 +264,41 @@ def displacement_dofs(E: int, gdim: int, n_s: int, h: float, seed: int,
     return np.ascontiguousarray(u * sig)
 
 
+def curved_mesh(cell: str, n: int, seed: int, bend: float = 0.04):
+    """Curved triangles or tetrahedra: the P2 nodes of the jittered structured
+    mesh (triangle_mesh(n, n) or tet_mesh(n)), laid out per element in the
+    library's lattice order, [E][n_s(2)][gdim].  Each node starts on the
+    straight element (v0 + (i (v1 - v0) + j (v2 - v0) [+ k (v3 - v0)]) / 2 for
+    lattice index (i, j[, k])); every edge-midpoint node strictly inside the
+    unit box then moves by U(+-bend h) per axis, drawn once per node, so the
+    elements sharing an edge share its curve and the mesh still fills the box
+    (boundary edges stay straight).  Returns (coords2, vertices, cells, h)."""
+    if cell == TRI:
+        V, cells = triangle_mesh(n, n, seed)
+    elif cell == TET:
+        V, cells = tet_mesh(n, seed)
+    else:
+        raise ValueError("curved meshes are triangles or tetrahedra")
+    d = GDIM[cell]
+    a = _node_multi_indices(cell, 2).astype(float) / 2.0               # [n2][d]
+    v = V[cells]                                                        # [E][nv][d]
+    x = v[:, None, 0, :] + sum(a[None, :, c, None] * (v[:, None, c + 1, :] - v[:, None, 0, :]) for c in range(d))
+    g, _ = global_dofs(cell, 2, cells, n, compact=False)                # refined-grid node ids
+    m = 2 * n + 1
+    if d == 2:
+        grid = np.stack([g // m, g % m], axis=-1)
+    else:
+        grid = np.stack([g // (m * m), (g // m) % m, g % m], axis=-1)
+    midpoint = (grid % 2 == 1).any(axis=-1)
+    inside = ((grid >= 1) & (grid <= m - 2)).all(axis=-1)
+    move = midpoint & inside
+    ids, inv = np.unique(g[move], return_inverse=True)
+    (rng,) = _streams(seed + 7919, 1)
+    disp = rng.uniform(-bend / n, bend / n, size=(ids.size, d))
+    x[move] += disp[inv]
+    return np.ascontiguousarray(x), V, cells, 1.0 / n
+
+
 # ---------------------------------------------------------------------------
 # Named workloads
 # ---------------------------------------------------------------------------

@@ -26,6 +26,7 @@ MUTANTS = {
     11: ("last local column dropped from the insertion", "global assembly"),
     12: ("non-affine prism geometry taken at the centroid for every point", "non-affine geometry"),
     13: ("test and trial basis indices swapped in a generic term", "generic forms"),
+    14: ("curved-simplex geometry taken at the first point for every point", "curved geometry"),
 }
 
 PINS = {
@@ -42,11 +43,12 @@ PINS = {
     11: "global_quadratic_forms_exact or pattern_and_insert_brute_force",
     12: "zjittered_box_quadratic_forms",
     13: "spec_constant_terms_exact",
+    14: "one_curved_edge_volume or curved_box_quadratic_forms",
 }
 
 # pins of the global assembly live in their own module
 PIN_FILE = {10: "test_global_pins.py", 11: "test_global_pins.py", 12: "test_nonaffine_pins.py",
-            13: "test_form_spec_pins.py"}
+            13: "test_form_spec_pins.py", 14: "test_curved_pins.py"}
 
 
 @pytest.mark.parametrize("k", sorted(MUTANTS))
