@@ -117,6 +117,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the built-in default launch shapes instead of the autotuned ones")
     ap.add_argument("--only-headline", action="store_true")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="time only the --workloads (for profiler runs); prints their rows as one JSON line")
     ap.add_argument("--workloads", default="mass,elasticity,hyperelastic,batch,sweep,global,nonaffine,forms",
                     help="comma list of the extra workloads to time")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -146,6 +148,12 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 1 GiB read + 1 GiB written")
         del src, dst
+
+    if args.no_headline:
+        rows = other_workloads(torch, felocal, inputs, stream, ev, max(3, args.steps // 2),
+                               set(args.workloads.split(",")))
+        print(json.dumps({"workloads": rows}), flush=True)
+        return
 
     # ------------------------------------------------------------------ headline
     log("headline: helmholtz P1-P4 on 750k tets")
@@ -476,7 +484,40 @@ def nonaffine_workload(torch, felocal, inputs, stream, ev, reps):
         del o
         torch.cuda.empty_cache()
     del ca, cj
+    out["curved_tet"] = curved_workload(torch, felocal, inputs, stream, ev, reps)
     return out
+
+
+def curved_workload(torch, felocal, inputs, stream, ev, reps):
+    """Curved tetrahedra (an isoparametric P2 coordinate field, interior edges
+    bent by U(+-0.04 h)): Helmholtz P1-P3 on 50^3 x 6 = 750,000 tetrahedra
+    with J at every point (fe_options_t.coord_degree = 2, quadrature only),
+    against the straight mesh's planner choice (pre-evaluated) and forced
+    quadrature."""
+    x2, V, cells, h = inputs.curved_mesh("tetrahedron", 50, 26)
+    cc = torch.from_numpy(x2).cuda()
+    ca = torch.from_numpy(inputs.gather(V, cells)).cuda()
+    E = int(cc.shape[0])
+    res = {"elements": E, "per_degree": {}}
+    for p in (1, 2, 3):
+        log(f"curved tetrahedra: helmholtz P{p}")
+        n, _ = felocal.fe_local_dims("helmholtz", "tetrahedron", p)
+        o = torch.empty((E, n, n), dtype=torch.float64, device="cuda")
+        ms_pre = time_launch(torch, lambda: felocal.fe_assemble_local("helmholtz", "tetrahedron", p, ca, None, o),
+                             stream, ev, reps)
+        ms_quad = time_launch(torch, lambda: felocal.fe_assemble_local("helmholtz", "tetrahedron", p, ca, None, o,
+                                                                       mode="quadrature"), stream, ev, reps)
+        ms_cv = time_launch(torch, lambda: felocal.fe_assemble_local("helmholtz", "tetrahedron", p, cc, None, o,
+                                                                     coord_degree=2), stream, ev, reps)
+        B = E * n * n * 8
+        res["per_degree"][f"P{p}"] = {"affine_planner_ms": round(ms_pre, 4), "affine_quadrature_ms": round(ms_quad, 4),
+                                      "curved_ms": round(ms_cv, 4), "curved_elem_per_s": round(E / (ms_cv * 1e-3), 1),
+                                      "curved_store_GBs": round(B / (ms_cv * 1e-3) / 1e9, 1)}
+        log(f"  P{p}: affine planner {ms_pre:.4f} ms, affine quadrature {ms_quad:.4f} ms, curved {ms_cv:.4f} ms")
+        del o
+        torch.cuda.empty_cache()
+    del cc, ca
+    return res
 
 
 def mass_workload(torch, felocal, inputs, stream, ev, record):
@@ -638,8 +679,54 @@ def sweep_workload(torch, felocal, inputs, stream, ev, reps):
             del out
             torch.cuda.empty_cache()
     hits = sum(r["planner_fastest"] for r in cases)
+    vec = vector_sweep(torch, felocal, inputs, stream, ev, reps)
+    vhits = sum(r["planner_fastest"] for r in vec["cases"])
     return {"workload": "nf_sweep_tet_83k", "elements": E, "cases": cases,
-            "planner_fastest_cases": f"{hits}/{len(cases)}"}
+            "planner_fastest_cases": f"{hits}/{len(cases)}", "vector": vec,
+            "vector_planner_fastest_cases": f"{vhits}/{len(vec['cases'])}"}
+
+
+def vector_sweep(torch, felocal, inputs, stream, ev, reps):
+    """The Sec. 7.1 matrix for Elasticity (P1 Lame fields) and the neo-Hookean
+    tangent: q = 1..4, nf = 0..3 functions of degree q, on the paper's mesh
+    size, 4,374 jittered tetrahedra (9^3 cubes x 6).  Per case: Algorithm 3's
+    choice and the time of the chosen mode, of forced quadrature and of forced
+    pre-evaluation (elasticity where a tile fits the LDS; illegal for the
+    hyperelastic terms in F)."""
+    log("sweep: elasticity / hyperelastic, q = 1..4, nf = 0..3 on 4,374 tets")
+    cn, V, cells = inputs.tet_workload(9, seed=8)
+    E = cn.shape[0]
+    c = torch.from_numpy(cn).cuda()
+    rng = np.random.default_rng(9)
+    cases = []
+    for form in ("elasticity", "hyperelastic"):
+        for q in (1, 2, 3, 4):
+            ns = n_scalar("tetrahedron", q)
+            out = torch.empty((E, 3 * ns, 3 * ns), dtype=torch.float64, device="cuda")
+            own = inputs.lame_p1(V.shape[0], cells, seed=10).reshape(E, -1) if form == "elasticity" else \
+                inputs.displacement_dofs(E, 3, ns, 1.0 / 9, seed=11, rel=0.05 / max(1, q - 1))
+            for nf in (0, 1, 2, 3):
+                cf = np.concatenate([own, rng.uniform(0.5, 1.5, size=(E, nf * ns))], axis=1)
+                cft = torch.from_numpy(np.ascontiguousarray(cf)).cuda()
+                plan = felocal.fe_plan(form, "tetrahedron", q, nf=nf)
+                row = {"form": form, "q": q, "nf": nf, "plan": plan["mode"],
+                       "preevaluated": plan["preevaluated"], "iota": plan["iota"]}
+                for mode in ("auto", "quadrature", "preeval"):
+                    try:
+                        ms = time_launch(torch, lambda: felocal.fe_assemble_local(
+                            form, "tetrahedron", q, c, cft, out, nf=nf, mode=mode), stream, ev, reps)
+                        row[f"ms_{mode}"] = round(ms, 4)
+                    except felocal.FeError:
+                        row[f"ms_{mode}"] = None
+                t = [v for k, v in row.items() if k.startswith("ms_") and k != "ms_auto" and v is not None]
+                row["planner_fastest"] = row["ms_auto"] is not None and row["ms_auto"] <= 1.05 * min(t) + 0.005
+                cases.append(row)
+                log(f"  {form} q={q} nf={nf}: plan {plan['preevaluated']} auto {row['ms_auto']} "
+                    f"quad {row['ms_quadrature']} pre {row['ms_preeval']} ms")
+                del cft
+            del out
+            torch.cuda.empty_cache()
+    return {"elements": E, "cases": cases}
 
 
 def batch_workload(torch, felocal, inputs, stream, ev, reps):

@@ -186,6 +186,28 @@ typedef struct {
                                   sign between points is flagged.  No effect
                                   on triangles and tetrahedra (their vertex
                                   map is affine).  Default 0 */
+    int            coord_degree; /* degree of the coordinate field: 0 or 1
+                                  (default) coords holds the vertices, the
+                                  map affine (Sec. 2.2); 2 (triangles and
+                                  tetrahedra) coords is [E][n_2][gdim], the
+                                  element's six or ten P2 nodes in the
+                                  lattice order, and the element map is the
+                                  isoparametric x(X) = sum_m psi2_m(X) x_m,
+                                  so the element is curved: J, det J and
+                                  J^{-1} are evaluated at every quadrature
+                                  point, pre-evaluation is illegal
+                                  (Sec. 3.3) and every monomial is
+                                  evaluated by a float64 quadrature kernel
+                                  (the VALU kernel, or for mass and
+                                  Helmholtz the matrix-core kernel), and the
+                                  default rule gains gdim degrees (det J of
+                                  a P2 map has degree gdim, so the mass form
+                                  stays exact).  FE_MODE_PREEVAL, nf > 0,
+                                  the split precisions, prisms, batches,
+                                  fe_autotune and fe_assemble_form are
+                                  FE_ENOTSUP.  Flagged as with pointgeo.
+                                  Lame fields stay P1 in the reference
+                                  coordinates. */
 } fe_options_t;
 
 /* Fills *opt with the defaults listed above. */

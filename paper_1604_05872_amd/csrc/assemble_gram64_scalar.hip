@@ -65,7 +65,7 @@ __device__ __forceinline__ void gs_operands(int R0, int nrows, int NC, int c_fir
     // column b of K (b = comp - 1), chosen by selects
     const int b = comp > 0 ? comp - 1 : 0;
     double kb0, kb1, kb2;
-    if (CELL == PRISM && pg) {
+    if (pg) {
         kb0 = sQ[qq * GS_PT + 1 + b];
         kb1 = sQ[qq * GS_PT + 4 + b];
         kb2 = sQ[qq * GS_PT + 7 + b];
@@ -98,6 +98,9 @@ __global__ __launch_bounds__(gs_waves(CELL) * 64) void k_gram64_scalar(GramScala
 {
     constexpr int GS_WAVES = gs_waves(CELL);
     constexpr int D = cell_dim(CELL), NV = cell_nv(CELL), NVD = NV * D;
+    // nodes of a per-point map: the prism's vertices, or the P2 nodes of a
+    // curved triangle or tetrahedron
+    constexpr int NM = CELL == PRISM ? NV : n_scalar(CELL, 2), NMD = NM * D;
     constexpr int NS = n_scalar(CELL, P);
     constexpr int T = (NS + 15) / 16;
     constexpr int NPAIR = T * (T + 1) / 2;
@@ -124,14 +127,15 @@ __global__ __launch_bounds__(gs_waves(CELL) * 64) void k_gram64_scalar(GramScala
         const int64_t e = base + wave;
         const bool live = e < a.E;
         const int64_t ec = live ? e : a.E - 1;
-        double v[NVD];
+        const int nvd = a.pointgeo ? NMD : NVD;
+        double v[NMD > NVD ? NMD : NVD];
 #pragma unroll
-        for (int k = 0; k < NVD; ++k) v[k] = a.coords[ec * NVD + k];
+        for (int k = 0; k < (NMD > NVD ? NMD : NVD); ++k) v[k] = k < nvd ? a.coords[ec * nvd + k] : 0.0;
         double K[3][3], adet = 0.0, det0 = 0.0;
         int bad = 0;
-        if (CELL == PRISM && a.pointgeo) {
+        if (a.pointgeo) {
             double J[3][3];
-            vertex_map_jacobian<NV, D>(v, a.dpsi_grad, J);
+            vertex_map_jacobian<NM, D>(v, a.dpsi_grad, J);
             det0 = inverse_small<D>(J, K);
             bad = !(det0 != 0.0 && isfinite(det0));
         } else {
@@ -153,9 +157,9 @@ __global__ __launch_bounds__(gs_waves(CELL) * 64) void k_gram64_scalar(GramScala
                 const int q = q0 + lane;
                 double* s = sQ + lane * GS_PT;
                 double w = a.W[q];
-                if (CELL == PRISM && a.pointgeo) {
+                if (a.pointgeo) {
                     double J[3][3], Kq[3][3];
-                    vertex_map_jacobian<NV, D>(v, a.dpsi_grad + (size_t)q * NVD, J);
+                    vertex_map_jacobian<NM, D>(v, a.dpsi_grad + (size_t)q * NMD, J);
                     const double det = inverse_small<D>(J, Kq);
                     if (!(det != 0.0 && isfinite(det)) || ((det > 0.0) != (det0 > 0.0))) bad = 1;
                     w *= fabs(det);
@@ -182,7 +186,7 @@ __global__ __launch_bounds__(gs_waves(CELL) * 64) void k_gram64_scalar(GramScala
             // the element's K as scalars (no array whose address escapes)
             const double k00 = K[0][0], k01 = K[0][1], k02 = K[0][2], k10 = K[1][0], k11 = K[1][1],
                          k12 = K[1][2], k20 = K[2][0], k21 = K[2][1], k22 = K[2][2];
-            const bool pg = CELL == PRISM && a.pointgeo;
+            const bool pg = a.pointgeo != 0;
             double za[T], zb[T];
             gs_operands<CELL, NS, T, D>(0, nrows, NC, c_first, rsub, m16, pg, sQ, sPhi, sDphi, k00, k01, k02, k10,
                                         k11, k12, k20, k21, k22, za, zb);

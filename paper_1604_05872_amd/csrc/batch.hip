@@ -184,7 +184,7 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
     fe_options_t o;
     if (opt) o = *opt;
     else fe_options_init(&o);
-    if (o.precision != FE_FP64 || o.nf != 0 || o.pointgeo != 0) return FE_ENOTSUP;
+    if (o.precision != FE_FP64 || o.nf != 0 || o.pointgeo != 0 || o.coord_degree > 1) return FE_ENOTSUP;
     hipStream_t s = (hipStream_t)o.stream;
     std::vector<std::vector<SubDesc>> by_vid(N_VARIANTS);
     std::vector<size_t> lds_vid(N_VARIANTS, 0);

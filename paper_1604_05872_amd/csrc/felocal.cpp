@@ -470,8 +470,8 @@ int store_mode()
 // the point loop and integrate the remaining scalar weights only.
 bool q_invariant(const Call& c)
 {
-    // (pre-multiplying functions vary over the element)
-    return is_vector_form(c.form) && c.degree == 1 && c.cell != PRISM && c.nf == 0;
+    // (pre-multiplying functions and a curved map vary over the element)
+    return is_vector_form(c.form) && c.degree == 1 && c.cell != PRISM && c.nf == 0 && !c.pointgeo;
 }
 
 // the hoisted degree-1 kernel: float64 quadrature mode, vector forms on
@@ -640,6 +640,7 @@ int launch_call(const Call& c, const Config& cfg)
         g.nf = c.nf;
         g.skip = c.nf > 0 ? c.mass_pre : 0;
         g.pointgeo = c.pointgeo;
+        if (c.pointgeo == 2) g.dpsi_grad = c.map_tables->ddphi;
         g.nt = store_mode();
         const int64_t blocks =
             (c.E + gram64_scalar_elems_per_block(c.cell) - 1) / gram64_scalar_elems_per_block(c.cell);
@@ -671,7 +672,7 @@ int launch_call(const Call& c, const Config& cfg)
     a.lam = c.lam;
     a.nf = c.nf;
     a.pointgeo = c.pointgeo;
-    a.dpsi_grad = t->ddpsi;
+    a.dpsi_grad = c.pointgeo == 2 ? c.map_tables->ddphi : t->ddpsi;
     const int64_t tiles = (c.E + a.eb - 1) / a.eb;
     const int grid = (int)std::min<int64_t>(tiles, (int64_t)cus * cfg.grid_per_cu);
     const size_t lds = quad_lds_bytes(c.form, c.cell, t->nb, a.eb, a.qc, c.pointgeo);
@@ -815,10 +816,14 @@ int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, co
     if ((int)o.precision < 0 || (int)o.precision > 2 || (int)o.mode < 0 || (int)o.mode > 2) return FE_EINVAL;
     if (o.nf < 0 || o.nf > 3) return FE_EINVAL;
     if (o.nf > 0 && o.precision != FE_FP64) return FE_ENOTSUP;
-    // the vertex map of a simplex is affine: per-point geometry only changes prisms
-    const int pg = (o.pointgeo && cell == PRISM) ? 1 : 0;
+    if (o.coord_degree < 0 || o.coord_degree > 2) return FE_EINVAL;
+    if (o.coord_degree == 2 && cell == PRISM) return FE_ENOTSUP;
+    // the vertex map of a simplex is affine: the vertex map at every point
+    // only changes prisms; a P2 coordinate field curves a simplex
+    const int pg = o.coord_degree == 2 ? 2 : (o.pointgeo && cell == PRISM) ? 1 : 0;
     if (pg && (o.nf > 0 || o.precision != FE_FP64 || o.mode == FE_MODE_PREEVAL)) return FE_ENOTSUP;
-    const int qdeg = o.qdeg < 0 ? default_qdeg(form, cell, degree, o.nf) + pg : o.qdeg;
+    // a per-point map adds the degree of det J: 1 (prism heights), d (P2 map)
+    const int qdeg = o.qdeg < 0 ? default_qdeg(form, cell, degree, o.nf) + (pg == 2 ? cell_dim(cell) : pg) : o.qdeg;
     if (qdeg > MAX_QDEG) return FE_EINVAL;
     c->nf = o.nf;
     c->pointgeo = pg;
@@ -861,6 +866,11 @@ int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, co
         if (rc) return rc;
     }
     if (lookup_only) return find_tables(cell, degree, qdeg, &c->tables);
+    if (pg == 2) {
+        // the P2 basis gradients at the same rule: the map's tables
+        rc = get_tables(cell, 2, qdeg, c->stream, &c->map_tables);
+        if (rc) return rc;
+    }
     return get_tables(cell, degree, qdeg, c->stream, &c->tables);
 }
 

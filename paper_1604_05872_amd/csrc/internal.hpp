@@ -221,7 +221,9 @@ struct Call {
     int form = 0, cell = 0, degree = 1, qdeg = 2;
     int mode = 0;       // FE_MODE_PREEVAL or FE_MODE_QUADRATURE
     int nf = 0;         // pre-multiplying coefficient functions
-    int pointgeo = 0;   // prisms: the vertex map evaluated at every point (non-affine)
+    int pointgeo = 0;   // J at every point: 1 the vertex map of a (non-affine)
+                        // prism, 2 the P2 coordinate field of a curved simplex
+    const RefTables* map_tables = nullptr;   // pointgeo 2: the P2 tables at the rule
     int shape[7] = {0, 0, 0, 0, 0, 0, 0};   // caller's launch-shape override (fe_shape_t order)
     int mass_pre = 0;   // Helmholtz quadrature: bit 0 mass monomial pre-evaluated,
                         // bit 1 gradient monomial pre-evaluated; hyperelastic

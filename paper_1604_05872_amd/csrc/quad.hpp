@@ -55,8 +55,10 @@ struct QuadArgs {
     int skip;             // Helmholtz: bit 0 leaves out the mass term, bit 1 the
                           // gradient term; hyperelastic: bit 1 leaves out the
                           // trace term (each added by another kernel afterwards)
-    int pointgeo = 0;     // prisms: J, det J, J^{-1} of the vertex map at every point
-    const double* dpsi_grad = nullptr;   // [nq][nv][d] gradients of the vertex basis (pointgeo)
+    int pointgeo = 0;     // J, det J, J^{-1} at every point: 1 the vertex map of a
+                          // prism, 2 the P2 coordinate field of a curved simplex
+                          // (coords then [E][n_s(2)][d])
+    const double* dpsi_grad = nullptr;   // [nq][nodes][d] gradients of the map's basis (pointgeo)
 };
 
 template <int FORM, int CELL>
@@ -88,8 +90,10 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
     const int ns = a.ns, nq = a.nq, qc_max = a.qc;
     const int64_t rem = a.E - e_begin;
     const int eb = rem < a.eb ? (int)rem : a.eb;
-    // per-point geometry applies to prisms only (a simplex's vertex map is affine)
-    const int pg = CELL == PRISM ? a.pointgeo : 0;
+    // per-point geometry: the vertex map of a prism, or the P2 coordinate
+    // field of a curved triangle or tetrahedron (NM nodes per element)
+    const int pg = a.pointgeo;
+    constexpr int NM = CELL == PRISM ? NV : n_scalar(CELL, 2);
     const int ppt = L::per_point(ns, pg);
     // an element's coefficient record: the form's own DOFs, then nf functions
     const int own = FORM == ELASTICITY ? 2 * NV : FORM == HYPERELASTIC ? D * ns : 0;
@@ -103,13 +107,13 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
     // first point, which every point must share)
     for (int i = tid; i < eb; i += B) {
         const int64_t e = e_begin + i;
-        double v[NV * D];
-#pragma unroll
-        for (int k = 0; k < NV * D; ++k) v[k] = a.coords[e * (NV * D) + k];
         double* s = sEl + i * L::PER_ELEM;
-        if (CELL == PRISM && pg) {
+        if (pg) {
+            double v[NM * D];
+#pragma unroll
+            for (int k = 0; k < NM * D; ++k) v[k] = a.coords[e * (NM * D) + k];
             double J[3][3], Kq[3][3];
-            vertex_map_jacobian<NV, D>(v, a.dpsi_grad, J);
+            vertex_map_jacobian<NM, D>(v, a.dpsi_grad, J);
             const double det = inverse_small<D>(J, Kq);
 #pragma unroll
             for (int r = 0; r < 10; ++r) s[r] = 0.0;
@@ -117,6 +121,9 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
             s[11] = det;
             continue;
         }
+        double v[NV * D];
+#pragma unroll
+        for (int k = 0; k < NV * D; ++k) v[k] = a.coords[e * (NV * D) + k];
         double K[3][3], adet;
         const int bad = affine_map<CELL>(v, K, adet);
 #pragma unroll
@@ -152,16 +159,16 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
             const int qc = min(qc_max, nq_loop - q0);
             // --- stage per-point data -------------------------------------
             for (int idx = tid; idx < qc * ns; idx += B) sPhi[idx] = a.phi[q0 * ns + idx];
-            if (CELL == PRISM && pg) {
-                // J(X_q) = sum_v v (x) grad psi_v(X_q), its inverse and |det J|
+            if (pg) {
+                // J(X_q) = sum_m x_m (x) grad psi_m(X_q), its inverse and |det J|
                 for (int idx = tid; idx < eb * qc; idx += B) {
                     const int i = idx / qc, qq = idx - i * qc;
                     const int64_t e = e_begin + i;
-                    double v[NV * D];
+                    double v[NM * D];
 #pragma unroll
-                    for (int k = 0; k < NV * D; ++k) v[k] = a.coords[e * (NV * D) + k];
+                    for (int k = 0; k < NM * D; ++k) v[k] = a.coords[e * (NM * D) + k];
                     double J[3][3], Kq[3][3];
-                    vertex_map_jacobian<NV, D>(v, a.dpsi_grad + (size_t)(q0 + qq) * NV * D, J);
+                    vertex_map_jacobian<NM, D>(v, a.dpsi_grad + (size_t)(q0 + qq) * NM * D, J);
                     const double det = inverse_small<D>(J, Kq);
                     double* gq = sPt + ((size_t)i * qc_max + qq) * ppt + ppt - 10;
 #pragma unroll
@@ -179,7 +186,7 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
                 const int i = idx / (qc * ns);
                 const int r = idx - i * qc * ns;
                 const int qq = r / ns, j = r - qq * ns;
-                const double* K = (CELL == PRISM && pg) ? sPt + ((size_t)i * qc_max + qq) * ppt + ppt - 10
+                const double* K = pg ? sPt + ((size_t)i * qc_max + qq) * ppt + ppt - 10
                                                         : sEl + i * L::PER_ELEM;
                 const double* gh = a.dphi + ((size_t)(q0 + qq) * ns + j) * D;
                 double* g = sPt + ((size_t)i * qc_max + qq) * ppt + j * D;
@@ -201,7 +208,7 @@ __device__ void quad_tile(const QuadArgs& a, int64_t e_begin, double* lds)
                     for (int q = 0; q < nq; ++q) wsum += a.W[q];
                 }
                 double* pt = sPt + ((size_t)i * qc_max + qq) * ppt;
-                const double w = wsum * ((CELL == PRISM && pg) ? pt[ppt - 1] : sEl[i * L::PER_ELEM + 9]);
+                const double w = wsum * (pg ? pt[ppt - 1] : sEl[i * L::PER_ELEM + 9]);
                 double* sw = pt + ns * D + (FORM == HYPERELASTIC ? ns * D + 9 : 0);
                 // w times prod_i f_i(X_q), f_i = sum_l f_il phi_l (collapse
                 // only without functions)

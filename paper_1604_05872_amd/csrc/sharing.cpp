@@ -529,6 +529,8 @@ extern "C" int fe_assemble_form(const fe_form_spec_t* spec, fe_cell_t cell, int 
     else fe_options_init(&o);
     if (n_elems < 0) return FE_EINVAL;
     if (o.shape.kernel != 0 && o.shape.kernel != 5) return FE_EINVAL;
+    if (o.coord_degree < 0 || o.coord_degree > 2) return FE_EINVAL;
+    if (o.coord_degree == 2) return FE_ENOTSUP;   // affine cells only
     Graph g;
     int x[MAXV] = {0}, owner[FE_MAX_TERMS] = {0};
     const int qdeg = o.qdeg < 0 ? -1 : o.qdeg;

@@ -64,6 +64,7 @@ class fe_options_t(ctypes.Structure):
         ("shape", fe_shape_t),
         ("nf", ctypes.c_int),
         ("pointgeo", ctypes.c_int),
+        ("coord_degree", ctypes.c_int),
     ]
 
 
@@ -227,7 +228,8 @@ def _f64_dev(t, name):
 
 
 def make_options(qdeg=-1, precision="fp64", mode="auto", stream=None, mu=1.0, lam=10.0, status=None,
-                 th_bytes=0, validate=False, need_stream=True, shape=None, nf=0, pointgeo=False) -> fe_options_t:
+                 th_bytes=0, validate=False, need_stream=True, shape=None, nf=0, pointgeo=False,
+                 coord_degree=1) -> fe_options_t:
     o = fe_options_t()
     lib().fe_options_init(ctypes.byref(o))
     o.qdeg = int(qdeg)
@@ -243,6 +245,7 @@ def make_options(qdeg=-1, precision="fp64", mode="auto", stream=None, mu=1.0, la
         setattr(o.shape, k, int(v))
     o.nf = int(nf)
     o.pointgeo = 1 if pointgeo else 0
+    o.coord_degree = int(coord_degree)
     return o
 
 
@@ -276,7 +279,7 @@ def fe_tabulate(cell: str, degree: int, qdeg: int, rule_only: bool = False):
 def fe_assemble_local(form: str, cell: str, degree: int, coords, coeff, out, qdeg: int = -1,
                       precision: str = "fp64", mode: str = "auto", stream=None, mu: float = 1.0,
                       lam: float = 10.0, status=None, th_bytes: int = 0, validate: bool = False,
-                      shape: dict | None = None, nf: int = 0, pointgeo: bool = False):
+                      shape: dict | None = None, nf: int = 0, pointgeo: bool = False, coord_degree: int = 1):
     """Element matrices of `form` into `out` [E][n][n] (asynchronous on the stream).
 
     shape: optional launch-shape override, keys of fe_shape_t (kernel: 1 tiled,
@@ -284,14 +287,17 @@ def fe_assemble_local(form: str, cell: str, degree: int, coords, coeff, out, qde
     degree-1 vector kernel; block, epi, chunk, eb, qc, grid_per_cu).  nf: the form
     pre-multiplied by nf coefficient functions; an element's coeff record is the
     form's own DOFs followed by the functions' [nf][n_s].
-    pointgeo: prisms need not be affine (the vertex map at every point)."""
+    pointgeo: prisms need not be affine (the vertex map at every point).
+    coord_degree 2: curved triangles and tetrahedra, coords [E][n_s(2)][gdim]
+    the P2 nodes of each element."""
     _f64_dev(coords, "coords")
     _f64_dev(coeff, "coeff")
     _f64_dev(out, "out")
     E = int(coords.shape[0])
     n, nc = fe_local_dims(form, cell, degree)
-    if tuple(coords.shape) != (E, NVERT[cell], GDIM[cell]):
-        raise ValueError(f"coords must be [E][{NVERT[cell]}][{GDIM[cell]}]")
+    nmap = NBASIS(cell, 2) if coord_degree == 2 else NVERT[cell]
+    if tuple(coords.shape) != (E, nmap, GDIM[cell]):
+        raise ValueError(f"coords must be [E][{nmap}][{GDIM[cell]}]")
     if tuple(out.shape[-2:]) != (n, n) or out.numel() != E * n * n:
         raise ValueError(f"out must be [E][{n}][{n}]")
     if nf:
@@ -299,7 +305,7 @@ def fe_assemble_local(form: str, cell: str, degree: int, coords, coeff, out, qde
     if nc and (coeff is None or coeff.numel() != E * nc):
         raise ValueError(f"coeff must hold {nc} values per element")
     o = make_options(qdeg, precision, mode, stream, mu, lam, status, th_bytes, validate, shape=shape, nf=nf,
-                     pointgeo=pointgeo)
+                     pointgeo=pointgeo, coord_degree=coord_degree)
     _check(lib().fe_assemble_local(FORMS[form], CELLS[cell], int(degree), E, _ptr(coords), _ptr(coeff),
                                    _ptr(out), ctypes.byref(o)), "fe_assemble_local")
     return out
