@@ -86,10 +86,14 @@ def alg_bytes(form, cell, p):
     return 8 * (NV[cell] * d + coeff + n * n)
 
 
-def alg_flops(form, cell, p, collapsed=True):
-    """Operation count of the flop-reduced evaluation (counting + and * once)."""
+def alg_flops(form, cell, p, collapsed=True, preeval=False):
+    """Operation count of the flop-reduced evaluation (counting + and * once);
+    preeval: elasticity in the pre-evaluated mode (one multiply-add per table
+    term and entry, rho iota = n_c d^2 terms per entry of the d^2 blocks)."""
     d, ns = GD[cell], n_scalar(cell, p)
     geo = 24 if d == 2 else 87
+    if form == "elasticity" and preeval:
+        return 2 * NV[cell] * d * d * ns * ns * d * d + geo
     if form == "mass":
         return ns * ns + geo
     if form == "helmholtz":
@@ -374,6 +378,48 @@ def summarize_traffic(fetch_dir, write_dir, out, title, command_fetch, command_w
     print("\n".join(lines))
 
 
+def roofline_row(B, F, ms, prec):
+    """t_roof = max(algorithmic bytes / 8 TB/s, algorithmic float64 flops /
+    78.6 TFLOP/s) for float64; the split precisions run the contraction on the
+    bf16/fp32 matrix cores (2.5 / 0.157 PFLOP/s), so their bound is the HBM
+    term (their float64 point work is a small part of F)."""
+    t_hbm = B / (HBM_PEAK_GBS * 1e9)
+    t_f64 = F / (FP64_PEAK_TFLOPS * 1e12)
+    if prec == "fp64" and t_f64 > t_hbm:
+        bound, t_roof = "fp64", t_f64
+    else:
+        bound, t_roof = "hbm", t_hbm
+    return {"bound": bound, "t_roof_ms": round(t_roof * 1e3, 4), "frac": round(t_roof / (ms * 1e-3), 4)}
+
+
+def summarize_counters(db_dir, out, title, command, only=""):
+    """Mean value per dispatch of every counter of a --pmc run, one row per
+    (kernel, block, grid, LDS); `only` (comma-separated) keeps kernels whose
+    name contains one of its parts."""
+    cur = _rocpd(db_dir).cursor()
+    q = ("select k.name, k.workgroup_x, k.grid_x, k.lds_size, p.counter_name, p.counter_value from pmc_events p "
+         "join kernels k on k.dispatch_id = p.dispatch_id")
+    parts = [x for x in only.split(",") if x]
+    agg, names = {}, []
+    for name, wg, grid, lds, cname, v in cur.execute(q).fetchall():
+        if parts and not any(f in name for f in parts):
+            continue
+        if cname not in names:
+            names.append(cname)
+        agg.setdefault((_short(name), wg, grid // max(1, wg), lds), {}).setdefault(cname, []).append(v)
+    lines = [f"# {title}", "", "Counter run (from the repository root on the GPU host):", "", "```", command, "```", "",
+             "Mean counter value per dispatch.", "",
+             "| kernel | block | grid | LDS B | dispatches | " + " | ".join(names) + " |",
+             "|---|---:|---:|---:|---:|" + "---:|" * len(names)]
+    for (name, wg, grid, lds), d in sorted(agg.items()):
+        nd = max(len(v) for v in d.values())
+        vals = " | ".join(f"{np.mean(d[c]):.4g}" if c in d else "" for c in names)
+        lines.append(f"| `{name}` | {wg} | {grid} | {lds} | {nd} | {vals} |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def time_launch(torch, fn, stream, ev, reps):
     fn()
     torch.cuda.synchronize()
@@ -397,6 +443,7 @@ def other_workloads(torch, felocal, inputs, stream, ev, reps, which):
                "alg_GBs": round(B / (ms * 1e-3) / 1e9, 1), "alg_GFLOPs": round(F / (ms * 1e-3) / 1e9, 1),
                "frac_hbm": round(B / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                "frac_fp64": round(F / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+        row["roofline"] = roofline_row(B, F, ms, prec)
         row.update(extra)
         res.append(row)
         log(f"  {name} {prec} {extra.get('kernel', '')}: {ms:.4f} ms, {row['elem_per_s']:.3e} elem/s, "
@@ -733,7 +780,7 @@ def batch_workload(torch, felocal, inputs, stream, ev, reps):
     log("mixed batch: 16 sub-batches, one graph launch of per-variant persistent kernels")
     rng = np.random.default_rng(5)
     subs, tot_e, tot_b, tot_f = [], 0, 0, 0
-    desc = []
+    desc, bounds = [], []
     for i in range(16):
         form = ["mass", "helmholtz", "elasticity"][rng.integers(3)]
         cell = ["triangle", "tetrahedron", "prism"][rng.integers(3)]
@@ -749,7 +796,18 @@ def batch_workload(torch, felocal, inputs, stream, ev, reps):
         desc.append(f"{form}/{cell}/P{p}/{E}")
         tot_e += E
         tot_b += alg_bytes(form, cell, p) * E
-        tot_f += alg_flops(form, cell, p) * E
+        pre = form == "elasticity" and felocal.fe_plan(form, cell, p)["mode"] == "preeval"
+        tot_f += alg_flops(form, cell, p, preeval=pre) * E
+        tb = alg_bytes(form, cell, p) * E / (HBM_PEAK_GBS * 1e9)
+        tf = alg_flops(form, cell, p, preeval=pre) * E / (FP64_PEAK_TFLOPS * 1e12)
+        bounds.append({"sub": desc[-1], "bound": "hbm" if tb >= tf else "fp64", "t_roof": max(tb, tf)})
+    # untimed: the autotuner picks each sub-batch's kernel shape (the batch and
+    # the separate launches both use it)
+    tuned = []
+    for sb in subs:
+        ms_t, shape = felocal.fe_autotune(sb["form"], sb["cell"], sb["degree"], sb["coords"], sb["coeff"], sb["out"],
+                                          return_shape=True)
+        tuned.append(dict({k: v for k, v in shape.items() if v}, ms=round(ms_t, 4)))
     b = felocal.Batch(subs)
     ntiles, grid = b.info()
     ms = time_launch(torch, b.run, stream, ev, reps)
@@ -757,10 +815,14 @@ def batch_workload(torch, felocal, inputs, stream, ev, reps):
                                                                  s["coeff"], s["out"]) for s in subs],
                       stream, ev, reps)
     b.close()
+    t_roof = sum(r["t_roof"] for r in bounds)
     row = {"workload": "mixed_batch_16", "elements": tot_e, "ms": round(ms, 4),
            "elem_per_s": round(tot_e / (ms * 1e-3), 1), "alg_GBs": round(tot_b / (ms * 1e-3) / 1e9, 1),
            "alg_GFLOPs": round(tot_f / (ms * 1e-3) / 1e9, 1), "tiles": ntiles, "grid": grid,
-           "separate_launches_ms": round(seq, 4), "sub_batches": desc}
+           "separate_launches_ms": round(seq, 4), "sub_batches": desc, "tuned_shapes": tuned,
+           "roofline": {"bound": "sum of the sub-batches' bounds", "t_roof_ms": round(t_roof * 1e3, 4),
+                        "frac": round(t_roof / (ms * 1e-3), 4),
+                        "per_sub_batch": [dict(r, t_roof=round(r["t_roof"] * 1e3, 4)) for r in bounds]}}
     log(f"  mixed batch: {ms:.3f} ms graph vs {seq:.3f} ms separate launches, {tot_e} elements")
     del subs
     torch.cuda.empty_cache()
@@ -836,6 +898,9 @@ if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-trace":
         # summarize-trace DB_DIR OUT.md TITLE COMMAND [NAME_FILTER]
         summarize_trace(*sys.argv[2:7])
+    elif len(sys.argv) > 1 and sys.argv[1] == "summarize-counters":
+        # summarize-counters DB_DIR OUT.md TITLE COMMAND [NAME_FILTER]
+        summarize_counters(*sys.argv[2:7])
     elif len(sys.argv) > 1 and sys.argv[1] == "summarize-traffic":
         # summarize-traffic FETCH_DIR WRITE_DIR OUT.md TITLE COMMAND_FETCH COMMAND_WRITE
         summarize_traffic(*sys.argv[2:8])

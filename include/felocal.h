@@ -301,20 +301,26 @@ int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int qdeg, size_t
             fe_plan_t* plan);
 
 /* Mixed batches: several (form, cell, degree) sub-batches in one HIP graph,
- * replayed by fe_batch_run with one graph launch.  Sub-batches are grouped by
- * kernel variant; each group runs as one persistent kernel, specialised for
- * the variant, whose workgroups take element tiles from the group's device
- * work queue, and the groups run on parallel branches of the graph.
+ * replayed by fe_batch_run with one graph launch.  Every sub-batch uses
+ * FE_FP64, the mode Algorithm 3 chooses for it, and the kernel and launch
+ * shape that a single fe_assemble_local call with the same options would use
+ * (the autotuner's, fe_autotune, when it has tuned the variant, else the
+ * built-in default), so the batch's output equals those single calls bit
+ * for bit.  Sub-batches whose kernel is the tiled pre-evaluated or the VALU
+ * quadrature tile are grouped by kernel variant; each group runs as one
+ * persistent kernel, specialised for the variant, whose workgroups take
+ * element tiles from the group's device work queue.  The groups run on
+ * parallel branches of the graph, the other sub-batches (streaming
+ * pre-evaluated, float64 matrix-core and hoisted degree-1 quadrature
+ * kernels) as single launches on up to four more branches, and elasticity
+ * sub-batches that Algorithm 3 pre-evaluates run the pre-evaluated
+ * elasticity kernel, one launch each, in sequence after the join.
  * All sub-batch pointers are DEVICE pointers owned by the caller and must
- * stay valid until fe_batch_destroy.  Every sub-batch uses FE_FP64 and the
- * mode Algorithm 3 chooses for it (tiled pre-evaluated or VALU quadrature
- * tiles; elasticity sub-batches that it pre-evaluates run the pre-evaluated
- * elasticity kernel, one launch each, in sequence after the groups);
- * tile sizes come from the autotune cache (fe_autotune) when
- * present, else from built-in defaults.  Sub-batches with no elements are
+ * stay valid until fe_batch_destroy.  Sub-batches with no elements are
  * allowed and do nothing.  Replays on one stream are ordered; replays of
  * one batch on different streams at once race on its work queues.
- * Coefficient functions (fe_options_t.nf) are not supported in batches.
+ * Coefficient functions (fe_options_t.nf), per-point geometry and curved
+ * elements are not supported in batches.
  * Errors: FE_EINVAL, FE_ENOTSUP (hyperelastic, nf > 0), FE_ENOMEM, FE_EHIP. */
 typedef struct fe_subbatch {
     fe_form_t     form;
@@ -333,8 +339,9 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
                     fe_batch_t** batch);
 int fe_batch_run(fe_batch_t* batch, void* stream);
 int fe_batch_destroy(fe_batch_t* batch);
-/* Number of work tiles and the total workgroups of the persistent kernels
- * of a batch. */
+/* Number of work tiles and the total workgroups of the persistent group
+ * kernels of a batch (sub-batches launched as single calls or as
+ * pre-evaluated elasticity are not counted). */
 int fe_batch_info(const fe_batch_t* batch, int64_t* n_tiles, int* grid);
 
 /* Autotuner: times the candidate launch shapes of the variant that serves

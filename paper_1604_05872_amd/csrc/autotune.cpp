@@ -64,7 +64,7 @@ Config default_for(const Call& c)
         // partial lines at once, the more of them the L2 merges (measured on
         // MI355X; the autotuner may find a better count for a given shape)
         Config x;
-        x.grid_per_cu = preeval_elast_grid_per_cu(c.tables->nb);
+        x.grid_per_cu = preeval_elast_grid_per_cu(c.cell, c.tables->nb);
         return x;
     }
     if (c.mode == FE_MODE_PREEVAL && c.nf > 0) return Config();

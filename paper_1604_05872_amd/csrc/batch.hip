@@ -125,6 +125,14 @@ struct fe_batch {
         int64_t E = 0;
     };
     std::vector<ElastSub> elast;
+    // sub-batches whose single-call kernel is not a group tile (the streaming
+    // pre-evaluated kernel, the float64 matrix-core and hoisted degree-1
+    // quadrature kernels): launched as single calls, with the same shape
+    struct Direct {
+        Call c;
+        Config cfg;
+    };
+    std::vector<Direct> direct;
     unsigned long long* d_counters = nullptr;
     int64_t total = 0;
     int grid = 0;
@@ -189,6 +197,7 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
     std::vector<std::vector<SubDesc>> by_vid(N_VARIANTS);
     std::vector<size_t> lds_vid(N_VARIANTS, 0);
     std::vector<fe_batch::ElastSub> elast;
+    std::vector<fe_batch::Direct> direct;
     for (int i = 0; i < n_subs; ++i) {
         const fe_subbatch_t& sb = subs[i];
         if ((int)sb.form < 0 || (int)sb.form > 2 || (int)sb.cell < 0 || (int)sb.cell > 2 || sb.degree < 1 ||
@@ -230,6 +239,19 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
         }
         Config cfg;
         lookup_config(c, &cfg);
+        // the sub-batch's single-call kernel and shape (the autotuner's when it
+        // has tuned the variant): launched as is where no group tile serves it
+        if ((c.mode == FE_MODE_PREEVAL && cfg.variant == 1) || (c.mode == FE_MODE_QUADRATURE && cfg.variant != 0)) {
+            c.coords = sb.coords;
+            c.coeff = sb.coeff_dofs;
+            c.out = sb.out_A;
+            c.status = o.d_status;
+            c.mu = o.mu;
+            c.lam = o.lambda;
+            if (check_config(c, cfg) != FE_OK) return FE_EINVAL;
+            direct.push_back({c, cfg});
+            continue;
+        }
         SubDesc d;
         std::memset(&d, 0, sizeof(d));
         int vid;
@@ -250,7 +272,6 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
             lds = preeval_lds_bytes(sb.form, sb.cell, cfg.chunk);
         } else {
             // the group kernels run the VALU quadrature tile
-            if (cfg.variant) cfg = default_quad_config(sb.form, sb.cell, sb.degree, t->nq);
             const int kb = quad_kb(sb.cell, sb.degree);
             vid = variant_id(1, sb.form, sb.cell, (kb == 5) ? 0 : 1);
             d.qa.coords = sb.coords;
@@ -280,6 +301,7 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
     }
     fe_batch* b = new fe_batch();
     b->elast = elast;
+    b->direct = direct;
     hipError_t e = hipSuccess;
     const int cus = device_cus();
     for (int v = 0; v < N_VARIANTS && e == hipSuccess; ++v) {
@@ -301,7 +323,11 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
         b->groups.push_back(g);
     }
     const int ng = (int)b->groups.size();
-    const int nbr = ng;   // parallel branches of the graph
+    // parallel branches of the graph: one per group, then the single-call
+    // sub-batches spread over at most four more (the device's hardware queues)
+    const int nd = (int)b->direct.size();
+    const int ndb = std::min(nd, 4);
+    const int nbr = ng + ndb;
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_counters, sizeof(unsigned long long) * std::max(1, ng));
     if (e != hipSuccess) {
         destroy(b);
@@ -336,6 +362,16 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
         if (e == hipSuccess) e = hipEventRecord(done[i], br[i]);
         if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[i], 0);
     }
+    for (int i = 0; i < ndb && e == hipSuccess; ++i) e = hipStreamWaitEvent(br[ng + i], start, 0);
+    for (int i = 0; i < nd && e == hipSuccess; ++i) {
+        fe_batch::Direct& dsub = b->direct[i];
+        dsub.c.stream = br[ng + i % ndb];
+        if (launch_call(dsub.c, dsub.cfg) != FE_OK) e = hipErrorLaunchFailure;
+    }
+    for (int i = 0; i < ndb && e == hipSuccess; ++i) {
+        e = hipEventRecord(done[ng + i], br[ng + i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[ng + i], 0);
+    }
     // pre-evaluated elasticity after the join, one sub-batch at a time: each
     // fills the GPU, and two running at once write partial lines over twice
     // the span, which the L2 merges less well (measured on MI355X: 4.2 ms
@@ -343,7 +379,7 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
     for (size_t i = 0; i < b->elast.size() && e == hipSuccess; ++i) {
         const fe_batch::ElastSub& es = b->elast[i];
         e = launch_preeval_elast(es.cell, es.coords, es.coeff, es.out, o.d_status, es.T, es.E, es.ns,
-                                 preeval_elast_grid_per_cu(es.ns), cus, cs);
+                                 preeval_elast_grid_per_cu(es.cell, es.ns), cus, cs);
     }
     if (capturing) {
         const hipError_t e2 = hipStreamEndCapture(cs, &b->graph);

@@ -64,7 +64,7 @@ hipError_t launch_elast_tables(int nq, int ns, int d, int nc, const double* W, c
 hipError_t launch_preeval_elast(int cell, const double* coords, const double* coeff, double* out, int* status,
                                 const double* T, int64_t E, int ns, int grid_per_cu, int cus, hipStream_t s);
 // default resident workgroups per CU of k_preeval_elast for n_s basis functions
-int preeval_elast_grid_per_cu(int ns);
+int preeval_elast_grid_per_cu(int cell, int ns);
 hipError_t launch_quad_mass(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_quad_helmholtz(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_quad_elasticity(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);

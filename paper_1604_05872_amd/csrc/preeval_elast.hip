@@ -17,6 +17,7 @@
 // L2; the planner admits the tables only when they fit T_H) feeding the
 // d^2 blocks as independent accumulator chains.
 #include <algorithm>
+#include <mutex>
 
 #include "device_common.hpp"
 #include "internal.hpp"
@@ -197,6 +198,176 @@ __global__ __launch_bounds__(64 * pe_waves(CELL)) __attribute__((amdgpu_waves_pe
     }
 }
 
+// Row-staged variant for triangles and tetrahedra with n_s >= 16 (a
+// 16-entry column group then touches at most two rows of a block).  A unit is (16-element tile, block row c): the
+// workgroup forms the coefficient rows of blocks (c, e2), e2 < d, and its
+// four wavefronts split the n_s rows j into contiguous bands.  A wavefront
+// walks its band's (j, k) entries 16 at a time (any 16 table columns serve as
+// one MFMA column group, so only a band's last group is partial), writes the
+// d blocks' results into its own LDS row buffer [16 elements][n], and as soon
+// as row (c, j) is complete stores it for the 16 elements: per element one
+// contiguous run of n doubles, and consecutive rows of the band follow each
+// other in memory, so the L2 receives whole lines from one wavefront instead
+// of 128-byte pieces from several.
+template <int CELL>
+__global__ __launch_bounds__(256) void k_preeval_elast_rows(ElastArgs a)
+{
+    constexpr int D = cell_dim(CELL), NC = cell_nv(CELL), NVD = NC * D;
+    constexpr int NT = NC * D * D, NTP = (NT + 7) / 8 * 8, NK = NTP / 4;
+    constexpr int LDA = NTP + 1;
+    extern __shared__ double lds_rows[];
+    const int ns = a.ns, nn = ns * ns, n = D * ns, ldr = n | 1;
+    double* sA = lds_rows;                       // [D][16][LDA] blocks (c, e2)
+    double* sG = sA + D * 16 * LDA;              // [16][12] K, |det J|, flag
+    double* sL = sG + 16 * 12;                   // [16][2 NC] Lame nodal values
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int i16 = lane & 15, kq = lane >> 4;
+    double* slot = sL + 16 * 2 * NC + (size_t)w * 16 * ldr;   // [16][ldr] this wavefront's row
+    const int64_t ntiles = (a.E + 15) / 16;
+    const int64_t units = ntiles * D;
+    const int jA = ns * w / 4, jB = ns * (w + 1) / 4;
+    const int f0 = jA * ns, f1 = jB * ns;        // the band's (j, k) entries
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t tile = u / D;
+        const int c = (int)(u - tile * D);
+        const int64_t e0 = tile * 16;
+        const int ne = a.E - e0 < 16 ? (int)(a.E - e0) : 16;
+        if (tid < 16) {
+            double K[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, adet = 0.0;
+            int bad = 0;
+            if (tid < ne) {
+                double v[NVD];
+#pragma unroll
+                for (int i = 0; i < NVD; ++i) v[i] = a.coords[(e0 + tid) * NVD + i];
+                bad = affine_map<CELL>(v, K, adet);
+                // the tile's first unit reports flagged elements
+                if (bad && c == 0 && a.status) atomicAdd(a.status, 1);
+            }
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) sG[tid * 12 + r * 3 + q] = K[r][q];
+            sG[tid * 12 + 9] = adet;
+            sG[tid * 12 + 10] = bad ? 1.0 : 0.0;
+        }
+        for (int i = tid; i < 16 * 2 * NC; i += blockDim.x) sL[i] = i < ne * 2 * NC ? a.coeff[e0 * 2 * NC + i] : 0.0;
+        __syncthreads();
+        // coefficient rows C^{c e2}[e][(l, a, b)] of the unit's blocks, zero-padded to NTP
+        for (int i = tid; i < D * 16 * NTP; i += blockDim.x) {
+            const int e2 = i / (16 * NTP), r = i - e2 * 16 * NTP, e = r / NTP, t = r - e * NTP;
+            double x = 0.0;
+            if (t < NT) {
+                const int l = t / (D * D), aa = (t / D) % D, b = t % D;
+                const double* K = sG + e * 12;
+                const double lam = sL[e * 2 * NC + l], mu = sL[e * 2 * NC + NC + l];
+                x = lam * (K[aa * 3 + c] * K[b * 3 + e2]) + mu * (K[aa * 3 + e2] * K[b * 3 + c]);
+                if (c == e2) {
+                    double g = 0.0;
+#pragma unroll
+                    for (int m = 0; m < D; ++m) g = fma(K[aa * 3 + m], K[b * 3 + m], g);
+                    x = fma(mu, g, x);
+                }
+                x *= K[9];
+            }
+            sA[(e2 * 16 + e) * LDA + t] = x;
+        }
+        __syncthreads();
+        // row (c, j) of the tile's elements, from the row buffer
+        auto flush = [&](int j) {
+            double* o = a.out + e0 * (int64_t)n * n + (int64_t)(c * ns + j) * n;
+            int e = 0, m = lane;
+            while (m >= n) {
+                m -= n;
+                ++e;
+            }
+            for (; e < ne;) {
+                const double v = sG[e * 12 + 10] != 0.0 ? __builtin_nan("") : slot[e * ldr + m];
+                store_out(o + (int64_t)e * n * n + m, v, 0);
+                m += 64;
+                while (m >= n) {
+                    m -= n;
+                    ++e;
+                }
+            }
+        };
+        double bv[NK];
+        auto load_b = [&](int f) {
+            const int col = f + i16;
+            const int colc = col < f1 ? col : f1 - 1;   // in-range table column for padding lanes
+#pragma unroll
+            for (int kk = 0; kk < NK; ++kk) {
+                const int k = 4 * kk + kq;
+                bv[kk] = k < NT ? a.T[(size_t)k * nn + colc] : 0.0;
+            }
+        };
+        if (f0 < f1) load_b(f0);
+        int jcur = jA;
+        for (int f = f0; f < f1; f += 16) {
+            double bc[NK];
+#pragma unroll
+            for (int kk = 0; kk < NK; ++kk) bc[kk] = bv[kk];
+            if (f + 16 < f1) load_b(f + 16);
+            v4d_e acc[D];
+#pragma unroll
+            for (int e2 = 0; e2 < D; ++e2) acc[e2] = (v4d_e){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < NK; ++kk)
+#pragma unroll
+                for (int e2 = 0; e2 < D; ++e2)
+                    acc[e2] = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[(e2 * 16 + i16) * LDA + 4 * kk + kq], bc[kk],
+                                                                   acc[e2], 0, 0, 0);
+            // lane holds elements kq + 4 r, entry col = (j, k) of blocks (c, e2)
+            const int col = f + i16;
+            const bool valid = col < f1;
+            const int j = valid ? col / ns : -1, k = valid ? col - (col / ns) * ns : 0;
+            if (j == jcur) {
+#pragma unroll
+                for (int e2 = 0; e2 < D; ++e2)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) slot[(kq + 4 * r) * ldr + e2 * ns + k] = acc[e2][r];
+            }
+            const int flast = (f + 16 < f1 ? f + 16 : f1) - 1;
+            if (flast >= (jcur + 1) * ns - 1) {
+                // row jcur is complete: store it, then the group's entries of the next row
+                wave_sync();
+                flush(jcur);
+                wave_sync();
+                ++jcur;
+                if (j == jcur) {
+#pragma unroll
+                    for (int e2 = 0; e2 < D; ++e2)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) slot[(kq + 4 * r) * ldr + e2 * ns + k] = acc[e2][r];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// raise the kernel's dynamic LDS limit to `bytes` once per (device, cell)
+// (a host-side attribute, so it is also safe while a stream is captured)
+hipError_t allow_dynamic_lds(const void* fn, int cell, size_t bytes)
+{
+    static std::mutex mu;
+    static size_t done[64][3] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= 64) return e != hipSuccess ? e : hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done[dev][cell] >= bytes) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) done[dev][cell] = bytes;
+    return e;
+}
+
+size_t preeval_elast_rows_lds_bytes(int cell, int ns)
+{
+    const int d = cell_dim(cell), nc = cell_nv(cell), nt = nc * d * d, ntp = (nt + 7) / 8 * 8;
+    const int n = d * ns, ldr = n | 1;
+    return sizeof(double) * ((size_t)d * 16 * (ntp + 1) + 16 * 12 + 16 * 2 * (size_t)nc + (size_t)4 * 16 * ldr);
+}
+
 }  // namespace
 
 hipError_t launch_elast_tables(int nq, int ns, int d, int nc, const double* W, const double* psi, const double* dphi,
@@ -219,6 +390,24 @@ hipError_t launch_preeval_elast(int cell, const double* coords, const double* co
     a.T = T;
     a.E = E;
     a.ns = ns;
+    if (ns >= 16 && cell != PRISM) {
+        // row-staged kernel: a workgroup per (tile, block row), as many
+        // resident per CU as the LDS holds, at most grid_per_cu
+        const size_t lds = preeval_elast_rows_lds_bytes(cell, ns);
+        const int by_lds = std::max(1, (int)(device_lds_per_cu() / lds));
+        const int64_t units = (E + 15) / 16 * cell_dim(cell);
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(units, (int64_t)cus * std::min(grid_per_cu, by_lds)));
+        a.parts = 1;
+        const void* fn = cell == TRI ? (const void*)k_preeval_elast_rows<TRI>
+                       : cell == TET ? (const void*)k_preeval_elast_rows<TET>
+                                     : (const void*)k_preeval_elast_rows<PRISM>;
+        hipError_t e = allow_dynamic_lds(fn, cell, lds);
+        if (e != hipSuccess) return e;
+        if (cell == TRI) hipLaunchKernelGGL((k_preeval_elast_rows<TRI>), dim3(grid), dim3(256), lds, s, a);
+        else if (cell == TET) hipLaunchKernelGGL((k_preeval_elast_rows<TET>), dim3(grid), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((k_preeval_elast_rows<PRISM>), dim3(grid), dim3(256), lds, s, a);
+        return hipGetLastError();
+    }
     // a workgroup per (tile, column-group range).  A tile's ranges are
     // consecutive units, so they run at the same time: splitting a large
     // tile into ranges of about 20 column groups narrows the span of output
@@ -240,10 +429,12 @@ hipError_t launch_preeval_elast(int cell, const double* coords, const double* co
     return hipGetLastError();
 }
 
-int preeval_elast_grid_per_cu(int ns)
+int preeval_elast_grid_per_cu(int cell, int ns)
 {
-    // wide element matrices (48 or more column groups) run best with one
-    // resident workgroup per CU, narrow ones with two (measured on MI355X)
+    // row-staged kernel (n_s >= 16): as many as the LDS holds.  Column-group
+    // kernel: wide element matrices (48 or more column groups) run best with
+    // one resident workgroup per CU, narrow ones with two (measured on MI355X)
+    if (ns >= 16 && cell != PRISM) return 8;
     return (ns * ns + 15) / 16 >= 48 ? 1 : 2;
 }
 
