@@ -155,7 +155,7 @@ def main():
 
     if args.no_headline:
         rows = other_workloads(torch, felocal, inputs, stream, ev, max(3, args.steps // 2),
-                               set(args.workloads.split(",")))
+                               set(args.workloads.split(",")), autotune=not args.no_autotune)
         print(json.dumps({"workloads": rows}), flush=True)
         return
 
@@ -253,7 +253,7 @@ def main():
     # ------------------------------------------------------------------ other workloads
     if not args.only_headline:
         result["workloads"] = other_workloads(torch, felocal, inputs, stream, ev, max(3, args.steps // 2),
-                                             set(args.workloads.split(",")))
+                                             set(args.workloads.split(",")), autotune=not args.no_autotune)
 
     # ------------------------------------------------------------------ CPU baseline (oracle)
     if not args.no_cpu_baseline:
@@ -432,7 +432,7 @@ def time_launch(torch, fn, stream, ev, reps):
     return a.elapsed_time(b) / reps
 
 
-def other_workloads(torch, felocal, inputs, stream, ev, reps, which):
+def other_workloads(torch, felocal, inputs, stream, ev, reps, which, autotune=True):
     res = []
 
     def record(name, form, cell, p, E, ms, prec="fp64", **extra):
@@ -457,7 +457,7 @@ def other_workloads(torch, felocal, inputs, stream, ev, reps, which):
     if "hyperelastic" in which:
         hyperelastic_workload(torch, felocal, inputs, stream, ev, record, reps)
     if "batch" in which:
-        res.append(batch_workload(torch, felocal, inputs, stream, ev, reps))
+        res.append(batch_workload(torch, felocal, inputs, stream, ev, reps, autotune))
     if "sweep" in which:
         res.append(sweep_workload(torch, felocal, inputs, stream, ev, max(2, reps // 3)))
     if "global" in which:
@@ -584,9 +584,10 @@ FP64_AND_SPLIT = [("fp64", {"kernel": 3}), ("fp64", {"kernel": 4}), ("fp32", Non
 FP64_P1 = [("fp64", {"kernel": 5})]
 
 
-def kernel_name(prec, shape):
+def kernel_name(prec, shape, degree=2):
     if prec != "fp64":
-        return f"k_split {prec} MFMA"
+        # degree 1 on simplices: the split precisions run the float64 hoisted kernel
+        return "k_vec_p1 (hoisted degree 1, float64)" if degree == 1 else f"k_split {prec} MFMA"
     return {3: "k_quad (VALU)", 4: "k_gram64 (f64 MFMA)", 5: "k_vec_p1 (hoisted degree 1)"}[shape["kernel"]]
 
 
@@ -621,7 +622,7 @@ def hyperelastic_workload(torch, felocal, inputs, stream, ev, record, reps):
                                                                       precision=prec, status=st, shape=kern),
                              stream, ev, reps)
             record(f"hyperelastic_tet_p{p}_1m", "hyperelastic", "tetrahedron", p, E4, ms, prec,
-                   kernel=kernel_name(prec, kern), flagged_per_launch=int(st.item()) // (reps + 1))
+                   kernel=kernel_name(prec, kern, p), flagged_per_launch=int(st.item()) // (reps + 1))
         del o4, u
         torch.cuda.empty_cache()
     del c4
@@ -694,6 +695,8 @@ def sweep_workload(torch, felocal, inputs, stream, ev, reps):
     time of the chosen mode, of forced quadrature and of forced
     pre-evaluation (where a tile of the expanded tensor fits in LDS)."""
     log("sweep: mass / helmholtz, q = 1..4, nf = 0..3 on 82,944 tets")
+    # Algorithm 3's own choices: forget the modes the autotuner measured
+    felocal.lib().fe_autotune_clear()
     cn, V, cells = inputs.tet_workload(24, seed=6)
     E = cn.shape[0]
     c = torch.from_numpy(cn).cuda()
@@ -776,7 +779,7 @@ def vector_sweep(torch, felocal, inputs, stream, ev, reps):
     return {"elements": E, "cases": cases}
 
 
-def batch_workload(torch, felocal, inputs, stream, ev, reps):
+def batch_workload(torch, felocal, inputs, stream, ev, reps, autotune=True):
     log("mixed batch: 16 sub-batches, one graph launch of per-variant persistent kernels")
     rng = np.random.default_rng(5)
     subs, tot_e, tot_b, tot_f = [], 0, 0, 0
@@ -803,8 +806,9 @@ def batch_workload(torch, felocal, inputs, stream, ev, reps):
         bounds.append({"sub": desc[-1], "bound": "hbm" if tb >= tf else "fp64", "t_roof": max(tb, tf)})
     # untimed: the autotuner picks each sub-batch's kernel shape (the batch and
     # the separate launches both use it)
+    # (--no-autotune: the shapes already in the cache, e.g. from FE_AUTOTUNE_CACHE)
     tuned = []
-    for sb in subs:
+    for sb in subs if autotune else []:
         ms_t, shape = felocal.fe_autotune(sb["form"], sb["cell"], sb["degree"], sb["coords"], sb["coeff"], sb["out"],
                                           return_shape=True)
         tuned.append(dict({k: v for k, v in shape.items() if v}, ms=round(ms_t, 4)))

@@ -72,7 +72,10 @@ typedef enum { FE_MASS = 0, FE_HELMHOLTZ = 1, FE_ELASTICITY = 2, FE_HYPERELASTIC
  *                    three-term combination, stored as float64
  * The split precisions apply to FE_ELASTICITY and FE_HYPERELASTIC when the
  * element matrix fits one 32x32 tile (gdim*n_s <= 32) and the rule has at most
- * 32 points; otherwise FE_ENOTSUP.  Stated error bounds (normwise per element,
+ * 32 points; otherwise FE_ENOTSUP.  At degree 1 on triangles and tetrahedra
+ * (every gradient constant, the point loop hoisted) a split precision without
+ * a shape override runs the float64 hoisted kernel (shape kernel 5), which is
+ * faster there and meets the float64 bound.  Stated error bounds (normwise per element,
  * max|A - A_exact| / max|A_exact|): FE_SPLIT_BF16X3 <= 1e-4,
  * FE_SPLIT_FP32 <= 2e-6; FE_FP64 agrees with the float64 oracle to 1e-12. */
 typedef enum { FE_FP64 = 0, FE_SPLIT_FP32 = 1, FE_SPLIT_BF16X3 = 2 } fe_precision_t;
@@ -310,11 +313,11 @@ int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int qdeg, size_t
  * quadrature tile are grouped by kernel variant; each group runs as one
  * persistent kernel, specialised for the variant, whose workgroups take
  * element tiles from the group's device work queue.  The groups run on
- * parallel branches of the graph, the other sub-batches (streaming
- * pre-evaluated, float64 matrix-core and hoisted degree-1 quadrature
- * kernels) as single launches on up to four more branches, and elasticity
- * sub-batches that Algorithm 3 pre-evaluates run the pre-evaluated
- * elasticity kernel, one launch each, in sequence after the join.
+ * parallel branches of the graph; after their join the other sub-batches
+ * (streaming pre-evaluated, float64 matrix-core and hoisted degree-1
+ * quadrature kernels) run as single launches one after another, and then
+ * the elasticity sub-batches that Algorithm 3 pre-evaluates, one launch
+ * each.
  * All sub-batch pointers are DEVICE pointers owned by the caller and must
  * stay valid until fe_batch_destroy.  Sub-batches with no elements are
  * allowed and do nothing.  Replays on one stream are ordered; replays of
@@ -352,13 +355,20 @@ int fe_batch_info(const fe_batch_t* batch, int64_t* n_tiles, int* grid);
  * best time per launch and its shape (kernel 1 or 2 for the pre-evaluated
  * mode, 0 otherwise; chunk 0 = automatic visit length), which the caller can
  * also pass back through fe_options_t.shape.  opt->shape is ignored.
+ * With opt->mode = FE_MODE_AUTO and a form that has two legal modes (mass,
+ * Helmholtz, elasticity in FE_FP64), the other mode is tuned and timed as
+ * well, and later FE_MODE_AUTO calls of the variant (fe_assemble_local,
+ * batches) run the measured faster mode, the whole form in it; fe_plan keeps
+ * reporting Algorithm 3's choice, and fe_autotune_clear forgets the choice.
+ * The returned time and shape are those of the faster mode.
  * Errors: FE_EINVAL, FE_ENOTSUP, FE_EHIP. */
 int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems,
                 const double* coords, const double* coeff_dofs, double* out_A,
                 const fe_options_t* opt, double* best_ms, fe_shape_t* best_shape);
 
-/* Empties the in-memory autotune cache (the JSON file is left as it is; it
- * is not read again in this process).  Host-only, thread-safe. */
+/* Empties the in-memory autotune cache, measured modes included (the JSON
+ * file is left as it is; it is not read again in this process).  Host-only,
+ * thread-safe. */
 void fe_autotune_clear(void);
 
 /* Global assembly (Sec. 2): the element matrices are coupled by adding them

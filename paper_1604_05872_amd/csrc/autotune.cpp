@@ -27,8 +27,10 @@ namespace fe {
 namespace {
 
 using Key = std::tuple<int, int, int, int, int, int, int>;
+using ModeKey = std::tuple<int, int, int, int, int, int>;   // form, cell, degree, qdeg, precision, nf
 std::mutex g_tmu;
 std::map<Key, Config> g_tuned;
+std::map<ModeKey, int> g_mode;   // the measured faster mode of an AUTO request
 bool g_loaded = false;
 
 Key key_of(const Call& c) { return Key(c.form, c.cell, c.degree, c.qdeg, c.mode, c.prec, c.nf); }
@@ -52,6 +54,11 @@ void load_file_locked()
                         &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &c.block, &c.epi, &c.chunk, &c.eb, &c.qc,
                         &c.grid_per_cu, &c.variant, &v[6]) == 14)
             g_tuned[Key(v[0], v[1], v[2], v[3], v[4], v[5], v[6])] = c;
+        else if (std::sscanf(line,
+                             "{\"form\": %d, \"cell\": %d, \"degree\": %d, \"qdeg\": %d, \"precision\": %d, "
+                             "\"nf\": %d, \"tuned_mode\": %d",
+                             &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6]) == 7)
+            g_mode[ModeKey(v[0], v[1], v[2], v[3], v[4], v[5])] = v[6];
     }
     std::fclose(f);
 }
@@ -201,22 +208,25 @@ void lookup_config(const Call& c, Config* cfg)
     *cfg = default_for(c);
 }
 
+bool tuned_mode(int form, int cell, int degree, int qdeg, int prec, int nf, int* mode)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    load_file_locked();
+    auto it = g_mode.find(ModeKey(form, cell, degree, qdeg, prec, nf));
+    if (it == g_mode.end()) return false;
+    *mode = it->second;
+    return true;
+}
+
 int resolve_call(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
                  const double* coeff_dofs, double* out_A, const fe_options_t* opt, Call* c, int lookup_only);
 
-}  // namespace fe
+namespace {
 
-using namespace fe;
-
-extern "C" int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
-                           const double* coeff_dofs, double* out_A, const fe_options_t* opt, double* best_ms,
-                           fe_shape_t* best_shape)
+// Times every valid candidate shape of the call\"s kernel (a warm-up launch,
+// then three timed ones) and stores the fastest in the cache.
+int tune_call(const Call& c, double* best_out, Config* best_cfg_out)
 {
-    if (n_elems < 1) return FE_EINVAL;
-    Call c;
-    int rc = resolve_call(form, cell, degree, n_elems, coords, coeff_dofs, out_A, opt, &c, 0);
-    if (rc) return rc;
-    if (c.pointgeo) return FE_ENOTSUP;   // per-point prism maps use the built-in shape
     std::vector<Config> cands;
     for (const Config& x : candidates(c))
         if (check_config(c, x) == FE_OK) cands.push_back(x);
@@ -226,6 +236,7 @@ extern "C" int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n
         return set_hip_error(hipErrorUnknown, "autotune events");
     double best = 1e30;
     Config best_cfg = cands[0];
+    int rc = FE_OK;
     for (const Config& x : cands) {
         rc = launch_call(c, x);   // warm-up
         if (rc) break;
@@ -248,23 +259,89 @@ extern "C" int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    {
-        std::lock_guard<std::mutex> lk(g_tmu);
-        load_file_locked();
-        g_tuned[key_of(c)] = best_cfg;
-        const char* path = std::getenv("FE_AUTOTUNE_CACHE");
-        if (path) {
-            FILE* f = std::fopen(path, "a");
-            if (f) {
-                std::fprintf(f,
-                             "{\"form\": %d, \"cell\": %d, \"degree\": %d, \"qdeg\": %d, \"mode\": %d, "
-                             "\"precision\": %d, \"block\": %d, \"epi\": %d, \"chunk\": %d, \"eb\": %d, \"qc\": %d, "
-                             "\"grid_per_cu\": %d, \"variant\": %d, \"nf\": %d, \"ms\": %.6f}\n",
-                             c.form, c.cell, c.degree, c.qdeg, c.mode, c.prec, best_cfg.block, best_cfg.epi,
-                             best_cfg.chunk, best_cfg.eb, best_cfg.qc, best_cfg.grid_per_cu, best_cfg.variant, c.nf, best);
-                std::fclose(f);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    load_file_locked();
+    g_tuned[key_of(c)] = best_cfg;
+    const char* path = std::getenv("FE_AUTOTUNE_CACHE");
+    if (path) {
+        FILE* f = std::fopen(path, "a");
+        if (f) {
+            std::fprintf(f,
+                         "{\"form\": %d, \"cell\": %d, \"degree\": %d, \"qdeg\": %d, \"mode\": %d, "
+                         "\"precision\": %d, \"block\": %d, \"epi\": %d, \"chunk\": %d, \"eb\": %d, \"qc\": %d, "
+                         "\"grid_per_cu\": %d, \"variant\": %d, \"nf\": %d, \"ms\": %.6f}\n",
+                         c.form, c.cell, c.degree, c.qdeg, c.mode, c.prec, best_cfg.block, best_cfg.epi,
+                         best_cfg.chunk, best_cfg.eb, best_cfg.qc, best_cfg.grid_per_cu, best_cfg.variant, c.nf, best);
+            std::fclose(f);
+        }
+    }
+    *best_out = best;
+    *best_cfg_out = best_cfg;
+    return FE_OK;
+}
+
+void record_mode(const Call& c, int mode)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_mode[ModeKey(c.form, c.cell, c.degree, c.qdeg, c.prec, c.nf)] = mode;
+    const char* path = std::getenv("FE_AUTOTUNE_CACHE");
+    if (path) {
+        FILE* f = std::fopen(path, "a");
+        if (f) {
+            std::fprintf(f,
+                         "{\"form\": %d, \"cell\": %d, \"degree\": %d, \"qdeg\": %d, \"precision\": %d, "
+                         "\"nf\": %d, \"tuned_mode\": %d}\n",
+                         c.form, c.cell, c.degree, c.qdeg, c.prec, c.nf, mode);
+            std::fclose(f);
+        }
+    }
+}
+
+}  // namespace
+
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" int fe_autotune(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elems, const double* coords,
+                           const double* coeff_dofs, double* out_A, const fe_options_t* opt, double* best_ms,
+                           fe_shape_t* best_shape)
+{
+    if (n_elems < 1) return FE_EINVAL;
+    Call c;
+    int rc = resolve_call(form, cell, degree, n_elems, coords, coeff_dofs, out_A, opt, &c, 0);
+    if (rc) return rc;
+    if (c.pointgeo) return FE_ENOTSUP;   // per-point maps use the built-in shape
+    // the kernel fe_assemble_local runs: split precisions at degree 1 on a
+    // simplex take the float64 hoisted kernel
+    if (c.prec != FE_FP64 && q_invariant(c)) c.prec = FE_FP64;
+    double best = 0.0;
+    Config best_cfg;
+    rc = tune_call(c, &best, &best_cfg);
+    if (rc) return rc;
+    // an AUTO request of a form with two legal modes: time the other mode as
+    // well (with its own best shape), and let later AUTO calls of the variant
+    // run the faster one -- operation counts and run times need not agree
+    // (Sec. 7.2); fe_plan keeps reporting Algorithm 3's choice
+    fe_options_t o;
+    if (opt) o = *opt;
+    else fe_options_init(&o);
+    if (o.mode == FE_MODE_AUTO && c.prec == FE_FP64 && c.form != HYPERELASTIC) {
+        Call c2 = c;
+        c2.mode = c.mode == FE_MODE_PREEVAL ? FE_MODE_QUADRATURE : FE_MODE_PREEVAL;
+        c2.mass_pre = 0;
+        double best2 = 0.0;
+        Config cfg2;
+        if (tune_call(c2, &best2, &cfg2) == FE_OK) {
+            const bool other = best2 < best;
+            record_mode(c, other ? c2.mode : c.mode);
+            if (other) {
+                c = c2;
+                best = best2;
+                best_cfg = cfg2;
             }
         }
+        (void)hipGetLastError();
     }
     if (best_ms) *best_ms = best;
     if (best_shape) {
@@ -286,4 +363,5 @@ extern "C" void fe_autotune_clear(void)
 {
     std::lock_guard<std::mutex> lk(g_tmu);
     g_tuned.clear();
+    g_mode.clear();
 }

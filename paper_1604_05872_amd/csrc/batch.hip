@@ -323,11 +323,11 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
         b->groups.push_back(g);
     }
     const int ng = (int)b->groups.size();
-    // parallel branches of the graph: one per group, then the single-call
-    // sub-batches spread over at most four more (the device's hardware queues)
+    // parallel branches of the graph: one per group; the single-call
+    // sub-batches follow the join one after another (each fills the GPU; on
+    // parallel branches they contend for the L2 and ran slower on MI355X)
     const int nd = (int)b->direct.size();
-    const int ndb = std::min(nd, 4);
-    const int nbr = ng + ndb;
+    const int nbr = ng;
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_counters, sizeof(unsigned long long) * std::max(1, ng));
     if (e != hipSuccess) {
         destroy(b);
@@ -362,15 +362,10 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
         if (e == hipSuccess) e = hipEventRecord(done[i], br[i]);
         if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[i], 0);
     }
-    for (int i = 0; i < ndb && e == hipSuccess; ++i) e = hipStreamWaitEvent(br[ng + i], start, 0);
     for (int i = 0; i < nd && e == hipSuccess; ++i) {
         fe_batch::Direct& dsub = b->direct[i];
-        dsub.c.stream = br[ng + i % ndb];
+        dsub.c.stream = cs;
         if (launch_call(dsub.c, dsub.cfg) != FE_OK) e = hipErrorLaunchFailure;
-    }
-    for (int i = 0; i < ndb && e == hipSuccess; ++i) {
-        e = hipEventRecord(done[ng + i], br[ng + i]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(cs, done[ng + i], 0);
     }
     // pre-evaluated elasticity after the join, one sub-batch at a time: each
     // fills the GPU, and two running at once write partial lines over twice

@@ -437,6 +437,13 @@ int fe_resolve_variant(int form, int cell, int degree, int qdeg, const fe_option
     int rc = fe_plan((fe_form_t)form, (fe_cell_t)cell, degree, o->nf, qdeg, o->th_bytes, &plan);
     if (rc) return rc;
     *mode_out = plan.mode;
+    // fe_autotune measured the other mode faster for this variant: run it
+    // (the whole form in one mode)
+    int tm = 0;
+    if (tuned_mode(form, cell, degree, qdeg, FE_FP64, o->nf, &tm) && tm != plan.mode) {
+        *mode_out = tm;
+        return FE_OK;
+    }
     // a mixed Helmholtz plan: with nf = 0 the quadrature kernel adds the
     // pre-evaluated monomial's tables; with coefficient functions the
     // coefficient pre-evaluation kernel adds that monomial afterwards
@@ -884,6 +891,10 @@ int fe_assemble_local(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elem
     Call c;
     int rc = resolve_call(form, cell, degree, n_elems, coords, coeff_dofs, out_A, opt, &c, 0);
     if (rc || n_elems == 0) return rc;
+    // at degree 1 on a simplex the point loop is hoisted and the contraction is
+    // one record per element: the split precisions take the float64 hoisted
+    // kernel there (faster than the matrix-core split kernel, and exact)
+    if (c.prec != FE_FP64 && q_invariant(c) && c.shape[0] == 0) c.prec = FE_FP64;
     Config cfg;
     rc = final_config(c, &cfg);
     if (rc) return rc;

@@ -244,6 +244,8 @@ int add_coef_monomial(const Call& c, const Config& cfg);
 int store_mode();
 // configuration from the autotune cache, else the built-in default
 void lookup_config(const Call& c, Config* cfg);
+// the mode fe_autotune measured faster for an AUTO request of this variant
+bool tuned_mode(int form, int cell, int degree, int qdeg, int prec, int nf, int* mode);
 // the float64 matrix-core kernel serves this call (vector form, n <= 32,
 // at most 32 contraction points)
 bool gram64_eligible(const Call& c);
