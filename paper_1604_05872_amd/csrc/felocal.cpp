@@ -172,7 +172,7 @@ int get_coef_tables(int form, int cell, int p, int qdeg, int nf, hipStream_t s, 
         CoefTables* t = new CoefTables();
         t->iota = rt->nv;
         t->nt = rt->nv * rt->d * rt->d;
-        hipError_t e = hipMalloc((void**)&t->dR, (size_t)t->nt * nb * nb * sizeof(double));
+        hipError_t e = hipMalloc((void**)&t->dR, elast_table_doubles(cell, nb) * sizeof(double));
         if (e == hipSuccess) e = launch_elast_tables(rt->nq, nb, rt->d, rt->nv, rt->dW, rt->dpsi, rt->ddphi, t->dR, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {

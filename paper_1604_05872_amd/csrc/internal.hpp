@@ -61,9 +61,11 @@ size_t preeval_elast_coef_lds_bytes(int cell, int nt, int nf, int nb);
 // preeval_elast.hip: pre-evaluated linear elasticity with P1 Lame fields
 hipError_t launch_elast_tables(int nq, int ns, int d, int nc, const double* W, const double* psi, const double* dphi,
                                double* T, hipStream_t s);
+// doubles in the blocked elasticity tables of a cell with n_s basis functions
+size_t elast_table_doubles(int cell, int ns);
 hipError_t launch_preeval_elast(int cell, const double* coords, const double* coeff, double* out, int* status,
                                 const double* T, int64_t E, int ns, int grid_per_cu, int cus, hipStream_t s);
-// default resident workgroups per CU of k_preeval_elast for n_s basis functions
+// default resident workgroups (four wavefronts each) per CU of k_preeval_elast
 int preeval_elast_grid_per_cu(int cell, int ns);
 hipError_t launch_quad_mass(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_quad_helmholtz(int cell, int kb, const QuadArgs& a, int grid, size_t lds, hipStream_t s);

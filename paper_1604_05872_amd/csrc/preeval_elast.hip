@@ -9,13 +9,23 @@
 //     A[(c,j),(e,k)] = sum_{l,a,b} C^{ce}_{l,a,b} T_{l,a,b}[j][k],
 //     C^{ce}_{l,a,b} = |det J| (lambda_l K_ac K_be + mu_l K_ae K_bc
 //                               + delta_ce mu_l (K K^T)_ab):
-// one dense product of a (16 elements) x (n_c d^2) coefficient matrix with
-// the table matrix per block, on the FP64 matrix cores
-// (v_mfma_f64_16x16x4_f64).  A workgroup takes a 16-element tile: it forms
-// the coefficient rows of all d^2 blocks in LDS, then its wavefronts split
-// the 16-entry column groups, each group's table values (read through the
-// L2; the planner admits the tables only when they fit T_H) feeding the
-// d^2 blocks as independent accumulator chains.
+// dense products of a coefficient matrix with the table matrix on the FP64
+// matrix cores (v_mfma_f64_16x16x4_f64).
+//
+// The kernel is shaped by the order of its stores more than by its
+// arithmetic: the output (88 KB per element at tet P4) is written far
+// faster when each wavefront walks a few element matrices front to back
+// than when many wavefronts write interleaved pieces of the same matrices
+// (a store-only kernel with the 4.3 GB of tet P4 takes 0.85 ms in the
+// first order and 1.1-1.3 ms in the second on MI355X).  So a unit of work
+// is (floor(16 / d) elements, block row c) and belongs to one wavefront:
+// the 16 rows of each MFMA tile are the (element, e) pairs of the unit
+// (15 of 16 used in 3D, all 16 in 2D), its columns 16 consecutive (j, k)
+// entries.  As the wavefront walks the table columns in order it fills
+// block row c of its elements row after row.  The coefficient operand is
+// formed in registers once per unit; the table operand is the same for
+// every unit and is read through the L2 several column groups ahead, in a
+// layout that gives each lane its values as consecutive 16-byte words.
 #include <algorithm>
 #include <mutex>
 
@@ -25,6 +35,7 @@
 namespace fe {
 
 typedef double v4d_e __attribute__((ext_vector_type(4)));
+typedef double v2d_e __attribute__((ext_vector_type(2)));
 typedef unsigned u2_e __attribute__((ext_vector_type(2)));
 // buffer resource word 3 on gfx950: a raw (stride 0) byte buffer whose
 // accesses are range-checked against num_records; stores beyond it are
@@ -33,43 +44,246 @@ constexpr int BUFFER_WORD3 = 0x00020000;
 
 namespace {
 
-// wavefronts per workgroup: eight on prisms, whose coefficient rows are the
-// largest to form and whose units hold the most column groups (prism P4
-// 1.79 -> 1.65 ms on MI355X), four elsewhere (eight are slower there)
-__host__ __device__ constexpr int pe_waves(int cell) { return cell == PRISM ? 8 : 4; }
+constexpr int elast_nt(int cell) { return cell_nv(cell) * cell_dim(cell) * cell_dim(cell); }
+// the contraction length padded to whole MFMA steps of 4, and to an even
+// number of steps so that the lane's table values are whole 16-byte words
+constexpr int elast_nk(int cell) { return (elast_nt(cell) + 7) / 8 * 2; }
+__host__ __device__ constexpr unsigned elast_table_doubles_dev(int cell, int ns)
+{
+    return (unsigned)((ns * ns + 15) / 16) * 64u * (unsigned)elast_nk(cell);
+}
 
-// T[((l * d + a) * d + b)][j * ns + k]
-__global__ void k_elast_tables(int nq, int ns, int d, int nc, const double* __restrict__ W,
+// Table layout: Tb[g][kq][i][kk] = T_{t = 4 kk + kq}[column 16 g + i] (zero
+// for t >= n_c d^2 or a column past n_s^2), so that lane (kq, i) of a
+// column group reads its NK operand values as consecutive words.
+__global__ void k_elast_tables(int nq, int ns, int d, int nc, int nk, const double* __restrict__ W,
                                const double* __restrict__ psi, const double* __restrict__ dphi, double* __restrict__ T)
 {
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int nn = ns * ns, nt = nc * d * d;
-    if (tid >= (int64_t)nt * nn) return;
-    const int t = (int)(tid / nn), jk = (int)(tid % nn), j = jk / ns, k = jk % ns;
-    const int l = t / (d * d), a = (t / d) % d, b = t % d;
+    const int nn = ns * ns, nt = nc * d * d, ng = (nn + 15) / 16;
+    if (tid >= (int64_t)ng * 64 * nk) return;
+    const int kk = (int)(tid % nk), i = (int)((tid / nk) % 16), kq = (int)((tid / (16 * nk)) % 4);
+    const int g = (int)(tid / (64 * nk));
+    const int t = 4 * kk + kq, col = 16 * g + i;
     double x = 0.0;
-    for (int q = 0; q < nq; ++q)
-        x = fma(W[q] * psi[q * nc + l], dphi[(q * ns + j) * d + a] * dphi[(q * ns + k) * d + b], x);
+    if (t < nt && col < nn) {
+        const int j = col / ns, k = col % ns;
+        const int l = t / (d * d), a = (t / d) % d, b = t % d;
+        for (int q = 0; q < nq; ++q)
+            x = fma(W[q] * psi[q * nc + l], dphi[(q * ns + j) * d + a] * dphi[(q * ns + k) * d + b], x);
+    }
     T[tid] = x;
 }
 
 struct ElastArgs {
     const double* coords;
     const double* coeff;   // [E][2][nc]: lambda, then mu, at the vertices
-    double* out;           // [E][n][n]
+    double* out;
     int* status;
-    const double* T;       // [nt][ns * ns]
+    const double* T;       // blocked tables (k_elast_tables)
     int64_t E;
     int ns;
-    int parts;             // column-group ranges per tile (units = tiles x parts)
+    int parts;             // column-group kernel: column-group ranges per tile
 };
 
+// groups per step (independent accumulator chains) and steps of table
+// operands in flight; a unit's groups are padded to whole loop iterations
+constexpr int GP = 2, PFS = 2, GSTEP = GP * PFS;
+// a byte offset past every unit's records: an invalid row plus an invalid
+// column stays below 2^32 and above the buffer's range
+constexpr unsigned OFF_NONE = 0x40000000u;
+
+// One wavefront per unit of work, four per workgroup, no workgroup barrier
+// after the set-up.  Per step the wavefront multiplies two column groups
+// (two accumulator chains), issues the table reads of the groups PFS steps
+// ahead (into the registers just read; past the unit's last group they are
+// the next unit's first groups, the tables being the same for every unit)
+// and stores the two tiles: each lane its rows kq + 4 r at its column.
+// On gfx950 an FP64 MFMA and a VALU instruction of any wavefront on the same
+// SIMD do not overlap (a 16x16x4 product takes about 64 cycles, an integer
+// VALU instruction about 4 more), so the loop keeps its VALU work small:
+// table reads are buffer loads with scalar offsets, the column part of every
+// store offset comes from an LDS table built once, and units without flagged
+// elements store their values unselected.
 template <int CELL>
-__global__ __launch_bounds__(64 * pe_waves(CELL)) __attribute__((amdgpu_waves_per_eu(2))) void k_preeval_elast(ElastArgs a)
+__global__ __launch_bounds__(256) void k_preeval_elast(ElastArgs a)
+{
+    constexpr int D = cell_dim(CELL), NC = cell_nv(CELL), NVD = NC * D;
+    constexpr int NT = elast_nt(CELL), NK = elast_nk(CELL);
+    constexpr int EPU = 16 / D;               // elements per unit
+    extern __shared__ unsigned coff[];        // [ngp][16] column byte offsets
+    const int lane = threadIdx.x & 63;
+    // the wavefront index as a scalar: the unit, and with it the output
+    // buffer descriptor, is uniform across the wavefront
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int ns = a.ns, nn = ns * ns, n = D * ns, ng = (nn + 15) / 16;
+    const int ngp = (ng + GSTEP - 1) / GSTEP * GSTEP;
+    const unsigned nn_e = (unsigned)n * (unsigned)n;
+    const int64_t units = (a.E + EPU - 1) / EPU * D;
+
+    // byte offset of column 16 g + i of a block row within a block (j n + k),
+    // OFF_NONE past n_s^2
+    for (int i = threadIdx.x; i < ngp * 16; i += blockDim.x) {
+        const int j = i / ns, k = i - j * ns;
+        coff[i] = i < nn ? (unsigned)(j * n + k) * 8u : OFF_NONE;
+    }
+    __syncthreads();
+
+    // table reads: lane (kq, i16) of group g reads NK consecutive doubles
+    const __amdgpu_buffer_rsrc_t trsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double*>(a.T), 0, (int)(elast_table_doubles_dev(CELL, ns) * 8u), BUFFER_WORD3);
+    const unsigned tvoff = (unsigned)lane * NK * 8u;
+    const int er = i16 / D, e2r = i16 - er * D;   // the operand row this lane forms
+    v2d_e B[PFS][GP][NK / 2];
+    // table operands of step s of a unit (past the last group, the last again)
+    auto load_step = [&](v2d_e (&Bs)[GP][NK / 2], int st) {
+#pragma unroll
+        for (int q = 0; q < GP; ++q) {
+            const int g = GP * st + q < ng ? GP * st + q : ng - 1;
+            const int soff = g * 64 * NK * 8;
+#pragma unroll
+            for (int h = 0; h < NK / 2; ++h)
+                Bs[q][h] = __builtin_bit_cast(v2d_e, __builtin_amdgcn_raw_buffer_load_b128(trsrc, tvoff + 16u * h, soff, 0));
+        }
+    };
+#pragma unroll
+    for (int b = 0; b < PFS; ++b) {
+        load_step(B[b], b);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    const int nst = ngp / GP;                 // steps per unit
+
+    for (int64_t u = (int64_t)blockIdx.x * 4 + w; u < units; u += (int64_t)gridDim.x * 4) {
+        const int64_t e0 = u / D * EPU;
+        const int c = (int)(u - u / D * D);
+        const int ne = a.E - e0 < EPU ? (int)(a.E - e0) : EPU;
+        // coefficient operand A[i16][4 kk + kq] = C^{c e2r}_{t}(element er)
+        double A[NK];
+        int bad = 0;
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) A[kk] = 0.0;
+        if (er < ne) {
+            const int64_t e = e0 + er;
+            double v[NVD], lm[2 * NC];
+#pragma unroll
+            for (int i = 0; i < NVD; ++i) v[i] = a.coords[e * NVD + i];
+#pragma unroll
+            for (int i = 0; i < 2 * NC; ++i) lm[i] = a.coeff[e * 2 * NC + i];
+            double K[3][3], adet;
+            bad = affine_map<CELL>(v, K, adet);
+            // columns c (uniform) and e2r (per lane) of K, selected rather
+            // than indexed so that K stays in registers
+            double Kc[D], Ke[D];
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                Kc[m] = K[m][0];
+                Ke[m] = K[m][0];
+#pragma unroll
+                for (int x = 1; x < D; ++x) {
+                    Kc[m] = c == x ? K[m][x] : Kc[m];
+                    Ke[m] = e2r == x ? K[m][x] : Ke[m];
+                }
+            }
+            const bool diag = c == e2r;
+            // every t = (l, aa, b) with compile-time indices; lane kq keeps
+            // t = 4 kk + kq
+#pragma unroll
+            for (int kk = 0; kk < NK; ++kk) {
+                double xs[4];
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    const int t = 4 * kk + q4;
+                    xs[q4] = 0.0;
+                    if (t < NT) {
+                        const int l = t / (D * D), aa = (t / D) % D, b = t % D;
+                        const double lam = lm[l], mu = lm[NC + l];
+                        double x = lam * (Kc[aa] * Ke[b]) + mu * (Ke[aa] * Kc[b]);
+                        double g = 0.0;
+#pragma unroll
+                        for (int m = 0; m < D; ++m) g = fma(K[aa][m], K[b][m], g);
+                        x = diag ? fma(mu, g, x) : x;
+                        xs[q4] = x * adet;
+                    }
+                }
+                A[kk] = kq == 0 ? xs[0] : kq == 1 ? xs[1] : kq == 2 ? xs[2] : xs[3];
+            }
+            // each flagged element is reported once, by its block row 0
+            if (bad && c == 0 && e2r == 0 && kq == 0 && a.status) atomicAdd(a.status, 1);
+        }
+        // flagged elements' rows are stored as NaN (a rare, separate path)
+        const bool anybad = __builtin_amdgcn_readfirstlane(__ballot(bad) != 0 ? 1 : 0) != 0;
+        bool nanr[4];
+        // the lane's rows kq + 4 r (element, block column) as byte offsets
+        // within the unit's records
+        unsigned ro[4];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int i = kq + 4 * rr, ei = i / D, ci = i - ei * D;
+            nanr[rr] = __shfl(bad, i) != 0;
+            ro[rr] = ei < ne ? ((unsigned)ei * nn_e + (unsigned)((c * ns) * n + ci * ns)) * 8u : OFF_NONE;
+        }
+        const __amdgpu_buffer_rsrc_t out_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            a.out + e0 * (int64_t)nn_e, 0, (int)((unsigned)ne * nn_e * 8u), BUFFER_WORD3);
+
+        for (int s0 = 0; s0 < nst; s0 += PFS) {
+#pragma unroll
+            for (int ps = 0; ps < PFS; ++ps) {
+                const int st = s0 + ps;
+                v4d_e acc[GP];
+#pragma unroll
+                for (int q = 0; q < GP; ++q) acc[q] = (v4d_e){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int h = 0; h < NK / 2; ++h)
+#pragma unroll
+                    for (int q = 0; q < GP; ++q) {
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[2 * h], B[ps][q][h].x, acc[q], 0, 0, 0);
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[2 * h + 1], B[ps][q][h].y, acc[q], 0, 0, 0);
+                    }
+                // the operands PFS steps ahead, into the registers just read
+                __builtin_amdgcn_sched_barrier(0);
+                load_step(B[ps], st + PFS < nst ? st + PFS : st + PFS - nst);
+#pragma unroll
+                for (int q = 0; q < GP; ++q) {
+                    const unsigned co = coff[(GP * st + q) * 16 + i16];
+                    if (anybad) {
+#pragma unroll
+                        for (int rr = 0; rr < 4; ++rr) {
+                            const double v = nanr[rr] ? __builtin_nan("") : acc[q][rr];
+                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_e, v), out_rsrc, ro[rr] + co, 0, 0);
+                        }
+                    } else {
+#pragma unroll
+                        for (int rr = 0; rr < 4; ++rr) {
+                            // through a scalar: a bit cast of the vector element
+                            // itself is compiled as a cast of element 0 here
+                            const double v = acc[q][rr];
+                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_e, v), out_rsrc, ro[rr] + co, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Column-group kernel (prisms).  At n_s = 75 the tables (2.5 MB) do not
+// stay in the L2 while the output streams through it, so each table value
+// read must feed as many products as possible: a workgroup takes a 16-element
+// tile, forms the coefficient rows of all d^2 blocks (c, e) in LDS (rows
+// padded to an odd number of doubles), and its eight wavefronts split the
+// 16-entry column groups, each group's table operand feeding the d^2 blocks
+// as independent accumulator chains.  A tile's column groups are split into
+// ranges run by consecutive workgroups.
+__host__ __device__ constexpr int pe_waves(int cell) { return cell == PRISM ? 8 : 4; }
+
+template <int CELL>
+__global__ __launch_bounds__(64 * pe_waves(CELL)) __attribute__((amdgpu_waves_per_eu(2))) void k_preeval_elast_cols(ElastArgs a)
 {
     constexpr int PE_WAVES = pe_waves(CELL);
     constexpr int D = cell_dim(CELL), NC = cell_nv(CELL), NVD = NC * D;
     constexpr int NT = NC * D * D, NTP = (NT + 7) / 8 * 8, NB = D * D, NK = NTP / 4;
+    static_assert(NK == elast_nk(CELL), "table padding");
     // coefficient rows [block][element][(l, a, b)], rows NTP + 1 doubles apart
     // so that the 16 rows of an operand read fall in distinct LDS banks
     constexpr int LDA = NTP + 1;
@@ -149,13 +363,10 @@ __global__ __launch_bounds__(64 * pe_waves(CELL)) __attribute__((amdgpu_waves_pe
         const int cb_lo = (int)((int64_t)ncb * part / parts), cb_hi = (int)((int64_t)ncb * (part + 1) / parts);
         double bv[NK];
         auto load_b = [&](int cb) {
-            const int col = 16 * cb + i16;
-            const int colc = col < nn ? col : nn - 1;   // in-range table column for padding lanes
+            // the blocked tables: this lane's NK operand values of group cb
+            const double* tp = a.T + ((size_t)cb * 64 + lane) * NK;
 #pragma unroll
-            for (int kk = 0; kk < NK; ++kk) {
-                const int k = 4 * kk + kq;
-                bv[kk] = k < NT ? a.T[(size_t)k * nn + colc] : 0.0;
-            }
+            for (int kk = 0; kk < NK; ++kk) bv[kk] = tp[kk];
         };
         if (cb_lo + w < cb_hi) load_b(cb_lo + w);
         for (int cb = cb_lo + w; cb < cb_hi; cb += PE_WAVES) {
@@ -198,153 +409,6 @@ __global__ __launch_bounds__(64 * pe_waves(CELL)) __attribute__((amdgpu_waves_pe
     }
 }
 
-// Row-staged variant for triangles and tetrahedra with n_s >= 16 (a
-// 16-entry column group then touches at most two rows of a block).  A unit is (16-element tile, block row c): the
-// workgroup forms the coefficient rows of blocks (c, e2), e2 < d, and its
-// four wavefronts split the n_s rows j into contiguous bands.  A wavefront
-// walks its band's (j, k) entries 16 at a time (any 16 table columns serve as
-// one MFMA column group, so only a band's last group is partial), writes the
-// d blocks' results into its own LDS row buffer [16 elements][n], and as soon
-// as row (c, j) is complete stores it for the 16 elements: per element one
-// contiguous run of n doubles, and consecutive rows of the band follow each
-// other in memory, so the L2 receives whole lines from one wavefront instead
-// of 128-byte pieces from several.
-template <int CELL>
-__global__ __launch_bounds__(256) void k_preeval_elast_rows(ElastArgs a)
-{
-    constexpr int D = cell_dim(CELL), NC = cell_nv(CELL), NVD = NC * D;
-    constexpr int NT = NC * D * D, NTP = (NT + 7) / 8 * 8, NK = NTP / 4;
-    constexpr int LDA = NTP + 1;
-    extern __shared__ double lds_rows[];
-    const int ns = a.ns, nn = ns * ns, n = D * ns, ldr = n | 1;
-    double* sA = lds_rows;                       // [D][16][LDA] blocks (c, e2)
-    double* sG = sA + D * 16 * LDA;              // [16][12] K, |det J|, flag
-    double* sL = sG + 16 * 12;                   // [16][2 NC] Lame nodal values
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int i16 = lane & 15, kq = lane >> 4;
-    double* slot = sL + 16 * 2 * NC + (size_t)w * 16 * ldr;   // [16][ldr] this wavefront's row
-    const int64_t ntiles = (a.E + 15) / 16;
-    const int64_t units = ntiles * D;
-    const int jA = ns * w / 4, jB = ns * (w + 1) / 4;
-    const int f0 = jA * ns, f1 = jB * ns;        // the band's (j, k) entries
-    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-        const int64_t tile = u / D;
-        const int c = (int)(u - tile * D);
-        const int64_t e0 = tile * 16;
-        const int ne = a.E - e0 < 16 ? (int)(a.E - e0) : 16;
-        if (tid < 16) {
-            double K[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, adet = 0.0;
-            int bad = 0;
-            if (tid < ne) {
-                double v[NVD];
-#pragma unroll
-                for (int i = 0; i < NVD; ++i) v[i] = a.coords[(e0 + tid) * NVD + i];
-                bad = affine_map<CELL>(v, K, adet);
-                // the tile's first unit reports flagged elements
-                if (bad && c == 0 && a.status) atomicAdd(a.status, 1);
-            }
-#pragma unroll
-            for (int r = 0; r < 3; ++r)
-#pragma unroll
-                for (int q = 0; q < 3; ++q) sG[tid * 12 + r * 3 + q] = K[r][q];
-            sG[tid * 12 + 9] = adet;
-            sG[tid * 12 + 10] = bad ? 1.0 : 0.0;
-        }
-        for (int i = tid; i < 16 * 2 * NC; i += blockDim.x) sL[i] = i < ne * 2 * NC ? a.coeff[e0 * 2 * NC + i] : 0.0;
-        __syncthreads();
-        // coefficient rows C^{c e2}[e][(l, a, b)] of the unit's blocks, zero-padded to NTP
-        for (int i = tid; i < D * 16 * NTP; i += blockDim.x) {
-            const int e2 = i / (16 * NTP), r = i - e2 * 16 * NTP, e = r / NTP, t = r - e * NTP;
-            double x = 0.0;
-            if (t < NT) {
-                const int l = t / (D * D), aa = (t / D) % D, b = t % D;
-                const double* K = sG + e * 12;
-                const double lam = sL[e * 2 * NC + l], mu = sL[e * 2 * NC + NC + l];
-                x = lam * (K[aa * 3 + c] * K[b * 3 + e2]) + mu * (K[aa * 3 + e2] * K[b * 3 + c]);
-                if (c == e2) {
-                    double g = 0.0;
-#pragma unroll
-                    for (int m = 0; m < D; ++m) g = fma(K[aa * 3 + m], K[b * 3 + m], g);
-                    x = fma(mu, g, x);
-                }
-                x *= K[9];
-            }
-            sA[(e2 * 16 + e) * LDA + t] = x;
-        }
-        __syncthreads();
-        // row (c, j) of the tile's elements, from the row buffer
-        auto flush = [&](int j) {
-            double* o = a.out + e0 * (int64_t)n * n + (int64_t)(c * ns + j) * n;
-            int e = 0, m = lane;
-            while (m >= n) {
-                m -= n;
-                ++e;
-            }
-            for (; e < ne;) {
-                const double v = sG[e * 12 + 10] != 0.0 ? __builtin_nan("") : slot[e * ldr + m];
-                store_out(o + (int64_t)e * n * n + m, v, 0);
-                m += 64;
-                while (m >= n) {
-                    m -= n;
-                    ++e;
-                }
-            }
-        };
-        double bv[NK];
-        auto load_b = [&](int f) {
-            const int col = f + i16;
-            const int colc = col < f1 ? col : f1 - 1;   // in-range table column for padding lanes
-#pragma unroll
-            for (int kk = 0; kk < NK; ++kk) {
-                const int k = 4 * kk + kq;
-                bv[kk] = k < NT ? a.T[(size_t)k * nn + colc] : 0.0;
-            }
-        };
-        if (f0 < f1) load_b(f0);
-        int jcur = jA;
-        for (int f = f0; f < f1; f += 16) {
-            double bc[NK];
-#pragma unroll
-            for (int kk = 0; kk < NK; ++kk) bc[kk] = bv[kk];
-            if (f + 16 < f1) load_b(f + 16);
-            v4d_e acc[D];
-#pragma unroll
-            for (int e2 = 0; e2 < D; ++e2) acc[e2] = (v4d_e){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int kk = 0; kk < NK; ++kk)
-#pragma unroll
-                for (int e2 = 0; e2 < D; ++e2)
-                    acc[e2] = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[(e2 * 16 + i16) * LDA + 4 * kk + kq], bc[kk],
-                                                                   acc[e2], 0, 0, 0);
-            // lane holds elements kq + 4 r, entry col = (j, k) of blocks (c, e2)
-            const int col = f + i16;
-            const bool valid = col < f1;
-            const int j = valid ? col / ns : -1, k = valid ? col - (col / ns) * ns : 0;
-            if (j == jcur) {
-#pragma unroll
-                for (int e2 = 0; e2 < D; ++e2)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) slot[(kq + 4 * r) * ldr + e2 * ns + k] = acc[e2][r];
-            }
-            const int flast = (f + 16 < f1 ? f + 16 : f1) - 1;
-            if (flast >= (jcur + 1) * ns - 1) {
-                // row jcur is complete: store it, then the group's entries of the next row
-                wave_sync();
-                flush(jcur);
-                wave_sync();
-                ++jcur;
-                if (j == jcur) {
-#pragma unroll
-                    for (int e2 = 0; e2 < D; ++e2)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) slot[(kq + 4 * r) * ldr + e2 * ns + k] = acc[e2][r];
-                }
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // raise the kernel's dynamic LDS limit to `bytes` once per (device, cell)
 // (a host-side attribute, so it is also safe while a stream is captured)
 hipError_t allow_dynamic_lds(const void* fn, int cell, size_t bytes)
@@ -361,21 +425,20 @@ hipError_t allow_dynamic_lds(const void* fn, int cell, size_t bytes)
     return e;
 }
 
-size_t preeval_elast_rows_lds_bytes(int cell, int ns)
-{
-    const int d = cell_dim(cell), nc = cell_nv(cell), nt = nc * d * d, ntp = (nt + 7) / 8 * 8;
-    const int n = d * ns, ldr = n | 1;
-    return sizeof(double) * ((size_t)d * 16 * (ntp + 1) + 16 * 12 + 16 * 2 * (size_t)nc + (size_t)4 * 16 * ldr);
-}
-
 }  // namespace
+
+size_t elast_table_doubles(int cell, int ns)
+{
+    return elast_table_doubles_dev(cell, ns);
+}
 
 hipError_t launch_elast_tables(int nq, int ns, int d, int nc, const double* W, const double* psi, const double* dphi,
                                double* T, hipStream_t s)
 {
-    const int64_t n = (int64_t)nc * d * d * ns * ns;
-    hipLaunchKernelGGL(k_elast_tables, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, nq, ns, d, nc, W, psi, dphi,
-                       T);
+    const int cell = d == 2 ? TRI : nc == 4 ? TET : PRISM;
+    const int64_t n = (int64_t)elast_table_doubles(cell, ns);
+    hipLaunchKernelGGL(k_elast_tables, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, nq, ns, d, nc,
+                       elast_nk(cell), W, psi, dphi, T);
     return hipGetLastError();
 }
 
@@ -390,51 +453,48 @@ hipError_t launch_preeval_elast(int cell, const double* coords, const double* co
     a.T = T;
     a.E = E;
     a.ns = ns;
-    if (ns >= 16 && cell != PRISM) {
-        // row-staged kernel: a workgroup per (tile, block row), as many
-        // resident per CU as the LDS holds, at most grid_per_cu
-        const size_t lds = preeval_elast_rows_lds_bytes(cell, ns);
-        const int by_lds = std::max(1, (int)(device_lds_per_cu() / lds));
-        const int64_t units = (E + 15) / 16 * cell_dim(cell);
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(units, (int64_t)cus * std::min(grid_per_cu, by_lds)));
-        a.parts = 1;
-        const void* fn = cell == TRI ? (const void*)k_preeval_elast_rows<TRI>
-                       : cell == TET ? (const void*)k_preeval_elast_rows<TET>
-                                     : (const void*)k_preeval_elast_rows<PRISM>;
-        hipError_t e = allow_dynamic_lds(fn, cell, lds);
-        if (e != hipSuccess) return e;
-        if (cell == TRI) hipLaunchKernelGGL((k_preeval_elast_rows<TRI>), dim3(grid), dim3(256), lds, s, a);
-        else if (cell == TET) hipLaunchKernelGGL((k_preeval_elast_rows<TET>), dim3(grid), dim3(256), lds, s, a);
-        else hipLaunchKernelGGL((k_preeval_elast_rows<PRISM>), dim3(grid), dim3(256), lds, s, a);
+    if (cell == PRISM) {
+        // a workgroup per (tile, column-group range).  A tile's ranges are
+        // consecutive units, so they run at the same time: splitting a large
+        // tile into ranges of about 20 column groups narrows the span of
+        // output that the grid writes at once, and the L2 merges more of its
+        // partial lines before they are evicted.  Small problems split their
+        // tiles so that every CU gets two units.
+        const int64_t tiles = (E + 15) / 16;
+        const int64_t want = (int64_t)cus * 2;
+        const int ncb = (ns * ns + 15) / 16;
+        const int by_width = std::min(16, (ncb + 19) / 20);
+        const int by_count = (int)std::max<int64_t>(1, std::min<int64_t>(4, (want + tiles - 1) / tiles));
+        a.parts = std::max(1, std::min(ncb, std::max(by_width, by_count)));
+        const int64_t units = tiles * a.parts;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(units, (int64_t)cus * grid_per_cu));
+        hipLaunchKernelGGL((k_preeval_elast_cols<PRISM>), dim3(grid), dim3(64 * pe_waves(PRISM)), 0, s, a);
         return hipGetLastError();
     }
-    // a workgroup per (tile, column-group range).  A tile's ranges are
-    // consecutive units, so they run at the same time: splitting a large
-    // tile into ranges of about 20 column groups narrows the span of output
-    // that the grid writes at once, and the L2 merges more of its partial
-    // lines before they are evicted (tet P4 1.89 -> 1.60 ms, prism P4
-    // 2.20 -> 1.75 ms on MI355X).  Small problems split their tiles so that
-    // every CU gets two units.
-    const int64_t tiles = (E + 15) / 16;
-    const int64_t want = (int64_t)cus * 2;
-    const int ncb = (ns * ns + 15) / 16;
-    const int by_width = std::min(16, (ncb + 19) / 20);
-    const int by_count = (int)std::max<int64_t>(1, std::min<int64_t>(4, (want + tiles - 1) / tiles));
-    a.parts = std::max(1, std::min(ncb, std::max(by_width, by_count)));
-    const int64_t units = tiles * a.parts;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(units, (int64_t)cus * grid_per_cu));
-    if (cell == TRI) hipLaunchKernelGGL((k_preeval_elast<TRI>), dim3(grid), dim3(64 * pe_waves(TRI)), 0, s, a);
-    else if (cell == TET) hipLaunchKernelGGL((k_preeval_elast<TET>), dim3(grid), dim3(64 * pe_waves(TET)), 0, s, a);
-    else hipLaunchKernelGGL((k_preeval_elast<PRISM>), dim3(grid), dim3(64 * pe_waves(PRISM)), 0, s, a);
+    a.parts = 1;
+    // a wavefront per unit, four per workgroup
+    const int epu = 16 / cell_dim(cell);
+    const int64_t units = (E + epu - 1) / epu * cell_dim(cell);
+    const int64_t blocks = (units + 3) / 4;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, (int64_t)cus * grid_per_cu));
+    // LDS: the column offsets of every group
+    const int ngp = ((ns * ns + 15) / 16 + GSTEP - 1) / GSTEP * GSTEP;
+    const size_t lds = sizeof(unsigned) * (size_t)ngp * 16;
+    const void* fn = cell == TRI ? (const void*)k_preeval_elast<TRI> : (const void*)k_preeval_elast<TET>;
+    hipError_t e = allow_dynamic_lds(fn, cell, lds);
+    if (e != hipSuccess) return e;
+    if (cell == TRI) hipLaunchKernelGGL((k_preeval_elast<TRI>), dim3(grid), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_preeval_elast<TET>), dim3(grid), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
 int preeval_elast_grid_per_cu(int cell, int ns)
 {
-    // row-staged kernel (n_s >= 16): as many as the LDS holds.  Column-group
-    // kernel: wide element matrices (48 or more column groups) run best with
-    // one resident workgroup per CU, narrow ones with two (measured on MI355X)
-    if (ns >= 16 && cell != PRISM) return 8;
+    // unit kernel: one wavefront per SIMD (more resident wavefronts write more
+    // element matrices at once, which the HBM absorbs less well).
+    // Column-group kernel: wide element matrices (48 or more column groups)
+    // one resident workgroup per CU, narrow ones two
+    if (cell != PRISM) return 1;
     return (ns * ns + 15) / 16 >= 48 ? 1 : 2;
 }
 

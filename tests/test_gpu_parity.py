@@ -312,11 +312,12 @@ def test_elasticity_preevaluated(cell, p):
         assert np.array_equal(A2[~bad], A[~bad])
 
 
-@pytest.mark.parametrize("cell,p,E", [("tetrahedron", 4, 2100), ("prism", 4, 1210)])
+@pytest.mark.parametrize("cell,p,E", [("tetrahedron", 4, 2103), ("prism", 4, 1213), ("triangle", 4, 3005)])
 def test_elasticity_preevaluated_many_units(cell, p, E):
-    """More (tile, column-range) units than workgroups, so every workgroup
-    takes several, and a ragged last tile: sampled elements (every 17th and
-    the last 20) against the oracle, at one and two workgroups per CU."""
+    """More units (a few elements and one block row each) than wavefronts,
+    so every wavefront takes several, and a ragged last unit: sampled
+    elements (every 17th and the last 20) against the oracle, at one and two
+    workgroups per CU."""
     log(f"elasticity pre-evaluated, many units: {cell} P{p} E={E}")
     coords, V, cells, h = mesh(cell, E, seed=540)
     cf = coefficients("elasticity", cell, p, E, V, cells, h, seed=541)
