@@ -12,20 +12,19 @@
 // dense products of a coefficient matrix with the table matrix on the FP64
 // matrix cores (v_mfma_f64_16x16x4_f64).
 //
-// The kernel is shaped by the order of its stores more than by its
-// arithmetic: the output (88 KB per element at tet P4) is written far
-// faster when each wavefront walks a few element matrices front to back
-// than when many wavefronts write interleaved pieces of the same matrices
-// (a store-only kernel with the 4.3 GB of tet P4 takes 0.85 ms in the
-// first order and 1.1-1.3 ms in the second on MI355X).  So a unit of work
-// is (floor(16 / d) elements, block row c) and belongs to one wavefront:
-// the 16 rows of each MFMA tile are the (element, e) pairs of the unit
-// (15 of 16 used in 3D, all 16 in 2D), its columns 16 consecutive (j, k)
-// entries.  As the wavefront walks the table columns in order it fills
-// block row c of its elements row after row.  The coefficient operand is
-// formed in registers once per unit; the table operand is the same for
-// every unit and is read through the L2 several column groups ahead, in a
-// layout that gives each lane its values as consecutive 16-byte words.
+// On triangles and tetrahedra the kernel is shaped by the order of its
+// stores more than by its arithmetic: the output (88 KB per element at tet
+// P4) is written far faster when each wavefront walks a few element matrices
+// front to back than when many wavefronts write interleaved pieces of the
+// same matrices (a store-only kernel with the 4.3 GB of tet P4 takes 0.85 ms
+// in the first order and 1.1-1.3 ms in the second on MI355X).  So a unit of
+// work is (floor(16 / d) elements, block row c) and belongs to one
+// wavefront: the 16 rows of each MFMA tile are the (element, e) pairs of the
+// unit (15 of 16 used in 3D, all 16 in 2D), its columns 16 consecutive (j, k)
+// entries, and as the wavefront walks the table columns in order it fills
+// block row c of its elements row after row.  Prisms, whose tables do not
+// stay in the L2, use a column-group kernel that reads each table value once
+// per 16 elements and d^2 blocks.
 #include <algorithm>
 #include <mutex>
 
@@ -45,25 +44,24 @@ constexpr int BUFFER_WORD3 = 0x00020000;
 namespace {
 
 constexpr int elast_nt(int cell) { return cell_nv(cell) * cell_dim(cell) * cell_dim(cell); }
-// the contraction length padded to whole MFMA steps of 4, and to an even
-// number of steps so that the lane's table values are whole 16-byte words
-constexpr int elast_nk(int cell) { return (elast_nt(cell) + 7) / 8 * 2; }
+// the contraction length in MFMA steps of 4 (tet 9, triangle 3, prism 14)
+constexpr int elast_nk(int cell) { return (elast_nt(cell) + 3) / 4; }
 __host__ __device__ constexpr unsigned elast_table_doubles_dev(int cell, int ns)
 {
     return (unsigned)((ns * ns + 15) / 16) * 64u * (unsigned)elast_nk(cell);
 }
 
-// Table layout: Tb[g][kq][i][kk] = T_{t = 4 kk + kq}[column 16 g + i] (zero
-// for t >= n_c d^2 or a column past n_s^2), so that lane (kq, i) of a
-// column group reads its NK operand values as consecutive words.
+// Table layout: Tb[g][kk][kq][i] = T_{t = 4 kk + kq}[column 16 g + i] (zero
+// for t >= n_c d^2 or a column past n_s^2): the operand values of one
+// contraction step of a column group are 64 consecutive doubles, one per lane.
 __global__ void k_elast_tables(int nq, int ns, int d, int nc, int nk, const double* __restrict__ W,
                                const double* __restrict__ psi, const double* __restrict__ dphi, double* __restrict__ T)
 {
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int nn = ns * ns, nt = nc * d * d, ng = (nn + 15) / 16;
     if (tid >= (int64_t)ng * 64 * nk) return;
-    const int kk = (int)(tid % nk), i = (int)((tid / nk) % 16), kq = (int)((tid / (16 * nk)) % 4);
-    const int g = (int)(tid / (64 * nk));
+    const int lane = (int)(tid % 64), i = lane % 16, kq = lane / 16;
+    const int kk = (int)((tid / 64) % nk), g = (int)(tid / (64 * nk));
     const int t = 4 * kk + kq, col = 16 * g + i;
     double x = 0.0;
     if (t < nt && col < nn) {
@@ -86,182 +84,313 @@ struct ElastArgs {
     int parts;             // column-group kernel: column-group ranges per tile
 };
 
-// groups per step (independent accumulator chains) and steps of table
-// operands in flight; a unit's groups are padded to whole loop iterations
-constexpr int GP = 2, PFS = 2, GSTEP = GP * PFS;
 // a byte offset past every unit's records: an invalid row plus an invalid
 // column stays below 2^32 and above the buffer's range
 constexpr unsigned OFF_NONE = 0x40000000u;
+constexpr int GP = 2;       // column groups per step (independent accumulator chains)
+constexpr int NSLOT = 4;    // steps of table operands in LDS
 
-// One wavefront per unit of work, four per workgroup, no workgroup barrier
-// after the set-up.  Per step the wavefront multiplies two column groups
-// (two accumulator chains), issues the table reads of the groups PFS steps
-// ahead (into the registers just read; past the unit's last group they are
-// the next unit's first groups, the tables being the same for every unit)
-// and stores the two tiles: each lane its rows kq + 4 r at its column.
-// On gfx950 an FP64 MFMA and a VALU instruction of any wavefront on the same
-// SIMD do not overlap (a 16x16x4 product takes about 64 cycles, an integer
-// VALU instruction about 4 more), so the loop keeps its VALU work small:
-// table reads are buffer loads with scalar offsets, the column part of every
-// store offset comes from an LDS table built once, and units without flagged
-// elements store their values unselected.
+__device__ __forceinline__ void lds_barrier()
+{
+    // orders LDS only: nothing here waits for the global stores
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Unit kernel (triangles, tetrahedra): four compute wavefronts, each taking
+// units (EPU elements, block row c), and one loader wavefront.
+//  * On gfx950 a global store is counted with the loads it precedes, so a
+//    wavefront that both loads and stores waits for its stores whenever it
+//    needs a load.  Here only the loader reads global memory: the table
+//    operands of each step (the same for every unit, so read once per
+//    workgroup and step) and the element data of the next unit round, into
+//    LDS.  The compute wavefronts read LDS and write the output; they never
+//    wait for memory, and their stores stay in flight.
+//  * An FP64 MFMA and a VALU instruction of any wavefront on the same SIMD
+//    do not overlap (a 16x16x4 product takes about 64 cycles, a VALU
+//    instruction 4 to 8 more), so the step loop keeps its VALU work small:
+//    the column part of every store offset comes from an LDS table built
+//    once, and units without flagged elements store their values unselected.
+//  * All five wavefronts take one workgroup barrier per step.  In step s the
+//    loader writes the operands of step s + NSLOT - 1 to LDS (read during
+//    step s - 1) and reads those of step s + NSLOT; a compute wavefront
+//    multiplies step s (two column groups, two accumulator chains), reads
+//    the operands of step s + 1 from LDS into registers and stores the tiles
+//    of step s - 1, each lane its rows kq + 4 r at its column.
 template <int CELL>
-__global__ __launch_bounds__(256) void k_preeval_elast(ElastArgs a)
+__global__ __launch_bounds__(320) void k_preeval_elast(ElastArgs a)
 {
     constexpr int D = cell_dim(CELL), NC = cell_nv(CELL), NVD = NC * D;
     constexpr int NT = elast_nt(CELL), NK = elast_nk(CELL);
     constexpr int EPU = 16 / D;               // elements per unit
-    extern __shared__ unsigned coff[];        // [ngp][16] column byte offsets
+    constexpr int ED = NVD + 2 * NC;          // element record: vertices, then lambda and mu at the vertices
     const int lane = threadIdx.x & 63;
-    // the wavefront index as a scalar: the unit, and with it the output
-    // buffer descriptor, is uniform across the wavefront
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i16 = lane & 15, kq = lane >> 4;
     const int ns = a.ns, nn = ns * ns, n = D * ns, ng = (nn + 15) / 16;
-    const int ngp = (ng + GSTEP - 1) / GSTEP * GSTEP;
+    const int nst = (ng + GP - 1) / GP;       // steps per unit
     const unsigned nn_e = (unsigned)n * (unsigned)n;
-    const int64_t units = (a.E + EPU - 1) / EPU * D;
+    const int units = (int)((a.E + EPU - 1) / EPU * D);
+    const int stride = gridDim.x * 4, first = blockIdx.x * 4;
+    // unit rounds of this workgroup (its compute wavefront 0 has the most)
+    const int rounds = first < units ? (units - first + stride - 1) / stride : 0;
+    const int total = rounds * nst;           // steps with work
+    extern __shared__ double lds_elast[];
+    double* bring = lds_elast;                               // [NSLOT][GP][NK][64]
+    double* ering = bring + NSLOT * GP * NK * 64;            // [2][4][EPU][ED]
+    unsigned* coff = reinterpret_cast<unsigned*>(ering + 2 * 4 * EPU * ED);   // [nst GP][16]
 
     // byte offset of column 16 g + i of a block row within a block (j n + k),
     // OFF_NONE past n_s^2
-    for (int i = threadIdx.x; i < ngp * 16; i += blockDim.x) {
+    for (int i = threadIdx.x; i < nst * GP * 16; i += blockDim.x) {
         const int j = i / ns, k = i - j * ns;
         coff[i] = i < nn ? (unsigned)(j * n + k) * 8u : OFF_NONE;
     }
-    __syncthreads();
 
-    // table reads: lane (kq, i16) of group g reads NK consecutive doubles
-    const __amdgpu_buffer_rsrc_t trsrc = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<double*>(a.T), 0, (int)(elast_table_doubles_dev(CELL, ns) * 8u), BUFFER_WORD3);
-    const unsigned tvoff = (unsigned)lane * NK * 8u;
-    const int er = i16 / D, e2r = i16 - er * D;   // the operand row this lane forms
-    v2d_e B[PFS][GP][NK / 2];
-    // table operands of step s of a unit (past the last group, the last again)
-    auto load_step = [&](v2d_e (&Bs)[GP][NK / 2], int st) {
+    if (w == 4) {
+        // ---------------------------------------------------------------- loader
+        // Every read is issued one step before its values go to LDS, so the
+        // loader waits for reads that had a whole step to arrive.
+        double x[GP][NK];                     // table operands of one step, in flight
+        auto fetch = [&](int st) {
 #pragma unroll
-        for (int q = 0; q < GP; ++q) {
-            const int g = GP * st + q < ng ? GP * st + q : ng - 1;
-            const int soff = g * 64 * NK * 8;
+            for (int q = 0; q < GP; ++q) {
+                const int g = GP * st + q < ng ? GP * st + q : ng - 1;
 #pragma unroll
-            for (int h = 0; h < NK / 2; ++h)
-                Bs[q][h] = __builtin_bit_cast(v2d_e, __builtin_amdgcn_raw_buffer_load_b128(trsrc, tvoff + 16u * h, soff, 0));
+                for (int kk = 0; kk < NK; ++kk) x[q][kk] = a.T[((size_t)g * NK + kk) * 64 + lane];
+            }
+        };
+        auto put = [&](int sl) {
+#pragma unroll
+            for (int q = 0; q < GP; ++q)
+#pragma unroll
+                for (int kk = 0; kk < NK; ++kk) bring[((sl * GP + q) * NK + kk) * 64 + lane] = x[q][kk];
+        };
+        // element records of a unit round: [4 wavefronts][EPU][ED], NE per lane
+        constexpr int NE = (4 * EPU * ED + 63) / 64;
+        double ex[NE];
+        auto fetch_elems = [&](int r) {
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+                const int idx = lane + 64 * i;
+                const int wv = idx / (EPU * ED), m = (idx / ED) % EPU, f = idx % ED;
+                const int u = first + wv + r * stride;
+                const int64_t e = (int64_t)(u / D) * EPU + m;
+                double v = 0.0;
+                if (idx < 4 * EPU * ED && u < units && e < a.E)
+                    v = f < NVD ? a.coords[e * NVD + f] : a.coeff[e * 2 * NC + (f - NVD)];
+                ex[i] = v;
+            }
+        };
+        auto put_elems = [&](int r) {
+            double* dst = ering + (r & 1) * 4 * EPU * ED;
+#pragma unroll
+            for (int i = 0; i < NE; ++i)
+                if (lane + 64 * i < 4 * EPU * ED) dst[lane + 64 * i] = ex[i];
+        };
+        // steps 0, 1 and 2 in place, step 3 in flight, round 0's records in place
+#pragma unroll
+        for (int g = 0; g < NSLOT - 1; ++g) {
+            fetch(g % nst);
+            put(g);
         }
-    };
-#pragma unroll
-    for (int b = 0; b < PFS; ++b) {
-        load_step(B[b], b);
-        __builtin_amdgcn_sched_barrier(0);
+        fetch((NSLOT - 1) % nst);
+        fetch_elems(0);
+        put_elems(0);
+        lds_barrier();
+        int stn = NSLOT % nst, r = 0, st = 0;  // unit step of global step gs + NSLOT; round and step of gs
+        bool epend = false;                    // round r + 1's records in flight
+        for (int gs = 0; gs < total; ++gs) {
+            put((gs + NSLOT - 1) % NSLOT);     // step gs + NSLOT - 1
+            fetch(stn);
+            if (epend) {
+                put_elems(r + 1);
+                epend = false;
+            }
+            if (st == 0 && r + 1 < rounds) {
+                // the next round's records: in place before it begins
+                fetch_elems(r + 1);
+                if (nst == 1) put_elems(r + 1);
+                else epend = true;
+            }
+            if (++stn == nst) stn = 0;
+            if (++st == nst) {
+                st = 0;
+                ++r;
+            }
+            lds_barrier();
+        }
+        return;
     }
-    const int nst = ngp / GP;                 // steps per unit
 
-    for (int64_t u = (int64_t)blockIdx.x * 4 + w; u < units; u += (int64_t)gridDim.x * 4) {
-        const int64_t e0 = u / D * EPU;
-        const int c = (int)(u - u / D * D);
-        const int ne = a.E - e0 < EPU ? (int)(a.E - e0) : EPU;
-        // coefficient operand A[i16][4 kk + kq] = C^{c e2r}_{t}(element er)
-        double A[NK];
-        int bad = 0;
+    // -------------------------------------------------------------------- compute
+    const int er = i16 / D, e2r = i16 - er * D;   // the operand row this lane forms
+    double A[NK];
+    // store state: the unit whose tiles are being stored
+    unsigned ro[4] = {OFF_NONE, OFF_NONE, OFF_NONE, OFF_NONE};
+    bool nanr[4] = {false, false, false, false};
+    bool anybad = false;
+    __amdgpu_buffer_rsrc_t out_rsrc = __builtin_amdgcn_make_buffer_rsrc(a.out, 0, 0, BUFFER_WORD3);
+    double B[2][GP][NK];
+    v4d_e acc[2][GP];
 #pragma unroll
-        for (int kk = 0; kk < NK; ++kk) A[kk] = 0.0;
-        if (er < ne) {
-            const int64_t e = e0 + er;
-            double v[NVD], lm[2 * NC];
+    for (int p2 = 0; p2 < 2; ++p2)
 #pragma unroll
-            for (int i = 0; i < NVD; ++i) v[i] = a.coords[e * NVD + i];
+        for (int q = 0; q < GP; ++q) acc[p2][q] = (v4d_e){0.0, 0.0, 0.0, 0.0};
+    auto read_ops = [&](double (&Bs)[GP][NK], int sl) {
 #pragma unroll
-            for (int i = 0; i < 2 * NC; ++i) lm[i] = a.coeff[e * 2 * NC + i];
-            double K[3][3], adet;
-            bad = affine_map<CELL>(v, K, adet);
-            // columns c (uniform) and e2r (per lane) of K, selected rather
-            // than indexed so that K stays in registers
-            double Kc[D], Ke[D];
+        for (int q = 0; q < GP; ++q)
 #pragma unroll
-            for (int m = 0; m < D; ++m) {
-                Kc[m] = K[m][0];
-                Ke[m] = K[m][0];
+            for (int kk = 0; kk < NK; ++kk) Bs[q][kk] = bring[((sl * GP + q) * NK + kk) * 64 + lane];
+    };
+    lds_barrier();
+    read_ops(B[0], 0);
+    int r = 0, st = 0, stp = 0;               // round and unit step of gs; unit step of gs - 1
+    // new store state, taking effect after the previous unit's last tiles
+    unsigned nro[4];
+    bool nnanr[4], nanybad = false;
+    __amdgpu_buffer_rsrc_t nrsrc = out_rsrc;
+    // global steps in pairs: the register slot (ps) is a constant
+    for (int g0 = 0; g0 < total + 1; g0 += 2) {
 #pragma unroll
-                for (int x = 1; x < D; ++x) {
-                    Kc[m] = c == x ? K[m][x] : Kc[m];
-                    Ke[m] = e2r == x ? K[m][x] : Ke[m];
-                }
-            }
-            const bool diag = c == e2r;
-            // every t = (l, aa, b) with compile-time indices; lane kq keeps
-            // t = 4 kk + kq
+        for (int ps = 0; ps < 2; ++ps) {
+            const int gs = g0 + ps;
+            if (gs <= total) {
+                const bool work = gs < total;
+                if (work && st == 0) {
+                    // a new unit: its coefficient operand from the element
+                    // records, A[i16][4 kk + kq] = C^{c e2r}_{t}(element er)
+                    const int u = first + w + r * stride;
+                    const int64_t e0 = (int64_t)(u / D) * EPU;
+                    const int c = u - u / D * D;
+                    const int ne = u < units ? (a.E - e0 < EPU ? (int)(a.E - e0) : EPU) : 0;
+                    int bad = 0;
 #pragma unroll
-            for (int kk = 0; kk < NK; ++kk) {
-                double xs[4];
+                    for (int kk = 0; kk < NK; ++kk) A[kk] = 0.0;
+                    if (er < ne) {
+                        const double* rec = ering + (((r & 1) * 4 + w) * EPU + er) * ED;
+                        double v[NVD], lm[2 * NC];
 #pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4) {
-                    const int t = 4 * kk + q4;
-                    xs[q4] = 0.0;
-                    if (t < NT) {
-                        const int l = t / (D * D), aa = (t / D) % D, b = t % D;
-                        const double lam = lm[l], mu = lm[NC + l];
-                        double x = lam * (Kc[aa] * Ke[b]) + mu * (Ke[aa] * Kc[b]);
-                        double g = 0.0;
+                        for (int i = 0; i < NVD; ++i) v[i] = rec[i];
 #pragma unroll
-                        for (int m = 0; m < D; ++m) g = fma(K[aa][m], K[b][m], g);
-                        x = diag ? fma(mu, g, x) : x;
-                        xs[q4] = x * adet;
+                        for (int i = 0; i < 2 * NC; ++i) lm[i] = rec[NVD + i];
+                        double K[3][3], adet;
+                        bad = affine_map<CELL>(v, K, adet);
+                        // columns c (uniform) and e2r (per lane) of K, selected
+                        // rather than indexed so that K stays in registers
+                        double Kc[D], Ke[D];
+#pragma unroll
+                        for (int m = 0; m < D; ++m) {
+                            Kc[m] = K[m][0];
+                            Ke[m] = K[m][0];
+#pragma unroll
+                            for (int x = 1; x < D; ++x) {
+                                Kc[m] = c == x ? K[m][x] : Kc[m];
+                                Ke[m] = e2r == x ? K[m][x] : Ke[m];
+                            }
+                        }
+                        const bool diag = c == e2r;
+                        // every t = (l, aa, b) with compile-time indices; lane
+                        // kq keeps t = 4 kk + kq
+#pragma unroll
+                        for (int kk = 0; kk < NK; ++kk) {
+                            double xs[4];
+#pragma unroll
+                            for (int q4 = 0; q4 < 4; ++q4) {
+                                const int t = 4 * kk + q4;
+                                xs[q4] = 0.0;
+                                if (t < NT) {
+                                    const int l = t / (D * D), aa = (t / D) % D, b = t % D;
+                                    const double lam = lm[l], mu = lm[NC + l];
+                                    double x = lam * (Kc[aa] * Ke[b]) + mu * (Ke[aa] * Kc[b]);
+                                    double g = 0.0;
+#pragma unroll
+                                    for (int m = 0; m < D; ++m) g = fma(K[aa][m], K[b][m], g);
+                                    x = diag ? fma(mu, g, x) : x;
+                                    xs[q4] = x * adet;
+                                }
+                            }
+                            A[kk] = kq == 0 ? xs[0] : kq == 1 ? xs[1] : kq == 2 ? xs[2] : xs[3];
+                        }
+                        // each flagged element is reported once, by its block row 0
+                        if (bad && c == 0 && e2r == 0 && kq == 0 && a.status) atomicAdd(a.status, 1);
                     }
-                }
-                A[kk] = kq == 0 ? xs[0] : kq == 1 ? xs[1] : kq == 2 ? xs[2] : xs[3];
-            }
-            // each flagged element is reported once, by its block row 0
-            if (bad && c == 0 && e2r == 0 && kq == 0 && a.status) atomicAdd(a.status, 1);
-        }
-        // flagged elements' rows are stored as NaN (a rare, separate path)
-        const bool anybad = __builtin_amdgcn_readfirstlane(__ballot(bad) != 0 ? 1 : 0) != 0;
-        bool nanr[4];
-        // the lane's rows kq + 4 r (element, block column) as byte offsets
-        // within the unit's records
-        unsigned ro[4];
+                    // flagged elements' rows are stored as NaN (a rare, separate path)
+                    nanybad = __builtin_amdgcn_readfirstlane(__ballot(bad) != 0 ? 1 : 0) != 0;
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int i = kq + 4 * rr, ei = i / D, ci = i - ei * D;
-            nanr[rr] = __shfl(bad, i) != 0;
-            ro[rr] = ei < ne ? ((unsigned)ei * nn_e + (unsigned)((c * ns) * n + ci * ns)) * 8u : OFF_NONE;
-        }
-        const __amdgpu_buffer_rsrc_t out_rsrc = __builtin_amdgcn_make_buffer_rsrc(
-            a.out + e0 * (int64_t)nn_e, 0, (int)((unsigned)ne * nn_e * 8u), BUFFER_WORD3);
-
-        for (int s0 = 0; s0 < nst; s0 += PFS) {
-#pragma unroll
-            for (int ps = 0; ps < PFS; ++ps) {
-                const int st = s0 + ps;
-                v4d_e acc[GP];
-#pragma unroll
-                for (int q = 0; q < GP; ++q) acc[q] = (v4d_e){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int h = 0; h < NK / 2; ++h)
-#pragma unroll
-                    for (int q = 0; q < GP; ++q) {
-                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[2 * h], B[ps][q][h].x, acc[q], 0, 0, 0);
-                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[2 * h + 1], B[ps][q][h].y, acc[q], 0, 0, 0);
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const int i = kq + 4 * rr, ei = i / D, ci = i - ei * D;
+                        nnanr[rr] = __shfl(bad, i) != 0;
+                        nro[rr] = ei < ne ? ((unsigned)ei * nn_e + (unsigned)((c * ns) * n + ci * ns)) * 8u : OFF_NONE;
                     }
-                // the operands PFS steps ahead, into the registers just read
-                __builtin_amdgcn_sched_barrier(0);
-                load_step(B[ps], st + PFS < nst ? st + PFS : st + PFS - nst);
+                    nrsrc = __builtin_amdgcn_make_buffer_rsrc(a.out + (u < units ? e0 * (int64_t)nn_e : 0), 0,
+                                                              (int)((unsigned)ne * nn_e * 8u), BUFFER_WORD3);
+                }
+                // the tiles of step gs - 1, with the state of its unit: values
+                // and byte offsets (in step 0 they go to an empty buffer)
+                double sv[GP * 4];
+                unsigned so[GP * 4];
 #pragma unroll
                 for (int q = 0; q < GP; ++q) {
-                    const unsigned co = coff[(GP * st + q) * 16 + i16];
-                    if (anybad) {
+                    const unsigned co = coff[(GP * stp + q) * 16 + i16];
 #pragma unroll
-                        for (int rr = 0; rr < 4; ++rr) {
-                            const double v = nanr[rr] ? __builtin_nan("") : acc[q][rr];
-                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_e, v), out_rsrc, ro[rr] + co, 0, 0);
-                        }
-                    } else {
-#pragma unroll
-                        for (int rr = 0; rr < 4; ++rr) {
-                            // through a scalar: a bit cast of the vector element
-                            // itself is compiled as a cast of element 0 here
-                            const double v = acc[q][rr];
-                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_e, v), out_rsrc, ro[rr] + co, 0, 0);
-                        }
+                    for (int rr = 0; rr < 4; ++rr) {
+                        // through a scalar: a bit cast of the vector element
+                        // itself is compiled as a cast of element 0 here
+                        const double v = acc[1 - ps][q][rr];
+                        sv[q * 4 + rr] = v;
+                        so[q * 4 + rr] = ro[rr] + co;
                     }
                 }
+                if (anybad) {
+                    // flagged elements' rows are stored as NaN (a rare path)
+#pragma unroll
+                    for (int i = 0; i < GP * 4; ++i) sv[i] = nanr[i % 4] ? __builtin_nan("") : sv[i];
+                }
+                auto store1 = [&](int i) {
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_e, sv[i]), out_rsrc, so[i], 0, 0);
+                };
+                if (work) {
+                    // step gs: its operands are in B[ps]; those of gs + 1 into B[1 - ps]
+                    read_ops(B[1 - ps], (gs + 1) % NSLOT);
+#pragma unroll
+                    for (int q = 0; q < GP; ++q) acc[ps][q] = (v4d_e){0.0, 0.0, 0.0, 0.0};
+                    // the stores of step gs - 1 between the products of step gs,
+                    // so that the matrix core keeps working while they issue
+#pragma unroll
+                    for (int kk = 0; kk < NK; ++kk) {
+#pragma unroll
+                        for (int q = 0; q < GP; ++q)
+                            acc[ps][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[kk], B[ps][q][kk], acc[ps][q], 0, 0, 0);
+                        if (kk < GP * 4) store1(kk);
+                    }
+#pragma unroll
+                    for (int i = NK; i < GP * 4; ++i) store1(i);
+#pragma unroll
+                    for (int kk = 0; kk < NK; ++kk) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, GP, 0);   // MFMA
+                        if (kk < GP * 4) __builtin_amdgcn_sched_group_barrier(0x040, 1, 0);   // VMEM write
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < GP * 4; ++i) store1(i);
+                }
+                if (work && st == 0) {
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        ro[rr] = nro[rr];
+                        nanr[rr] = nnanr[rr];
+                    }
+                    anybad = nanybad;
+                    out_rsrc = nrsrc;
+                }
+                stp = st;
+                if (++st == nst) {
+                    st = 0;
+                    ++r;
+                }
+                if (work) lds_barrier();
             }
         }
     }
@@ -364,9 +493,9 @@ __global__ __launch_bounds__(64 * pe_waves(CELL)) __attribute__((amdgpu_waves_pe
         double bv[NK];
         auto load_b = [&](int cb) {
             // the blocked tables: this lane's NK operand values of group cb
-            const double* tp = a.T + ((size_t)cb * 64 + lane) * NK;
+            const double* tp = a.T + (size_t)cb * 64 * NK + lane;
 #pragma unroll
-            for (int kk = 0; kk < NK; ++kk) bv[kk] = tp[kk];
+            for (int kk = 0; kk < NK; ++kk) bv[kk] = tp[64 * kk];
         };
         if (cb_lo + w < cb_hi) load_b(cb_lo + w);
         for (int cb = cb_lo + w; cb < cb_hi; cb += PE_WAVES) {
@@ -472,19 +601,22 @@ hipError_t launch_preeval_elast(int cell, const double* coords, const double* co
         return hipGetLastError();
     }
     a.parts = 1;
-    // a wavefront per unit, four per workgroup
-    const int epu = 16 / cell_dim(cell);
-    const int64_t units = (E + epu - 1) / epu * cell_dim(cell);
+    // four compute wavefronts (a unit each) and a loader per workgroup
+    const int d = cell_dim(cell), epu = 16 / d;
+    const int64_t units = (E + epu - 1) / epu * d;
+    if (units >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     const int64_t blocks = (units + 3) / 4;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, (int64_t)cus * grid_per_cu));
-    // LDS: the column offsets of every group
-    const int ngp = ((ns * ns + 15) / 16 + GSTEP - 1) / GSTEP * GSTEP;
-    const size_t lds = sizeof(unsigned) * (size_t)ngp * 16;
+    // LDS: the operand ring, the element records and the column offsets
+    const int nk = elast_nk(cell), nvd = cell_nv(cell) * d, ed = nvd + 2 * cell_nv(cell);
+    const int nst = ((ns * ns + 15) / 16 + GP - 1) / GP;
+    const size_t lds = sizeof(double) * ((size_t)NSLOT * GP * nk * 64 + 2 * 4 * (size_t)epu * ed) +
+                       sizeof(unsigned) * (size_t)nst * GP * 16;
     const void* fn = cell == TRI ? (const void*)k_preeval_elast<TRI> : (const void*)k_preeval_elast<TET>;
     hipError_t e = allow_dynamic_lds(fn, cell, lds);
     if (e != hipSuccess) return e;
-    if (cell == TRI) hipLaunchKernelGGL((k_preeval_elast<TRI>), dim3(grid), dim3(256), lds, s, a);
-    else hipLaunchKernelGGL((k_preeval_elast<TET>), dim3(grid), dim3(256), lds, s, a);
+    if (cell == TRI) hipLaunchKernelGGL((k_preeval_elast<TRI>), dim3(grid), dim3(320), lds, s, a);
+    else hipLaunchKernelGGL((k_preeval_elast<TET>), dim3(grid), dim3(320), lds, s, a);
     return hipGetLastError();
 }
 
