@@ -419,7 +419,10 @@ __global__ __launch_bounds__(64 * pe_waves(CELL)) __attribute__((amdgpu_waves_pe
     __shared__ double sA[NB * 16 * LDA];
     __shared__ double sG[16 * 12];           // K [9], |det J|, flag
     __shared__ double sL[16 * 2 * NC];       // Lame nodal values
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const __amdgpu_buffer_rsrc_t trsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double*>(a.T), 0, (int)(elast_table_doubles_dev(CELL, a.ns) * 8u), BUFFER_WORD3);
+    const unsigned tvo = (unsigned)(tid & 63) * 8u;
     const int i16 = lane & 15, kq = lane >> 4;
     const int ns = a.ns, nn = ns * ns, n = D * ns;
     const int64_t ntiles = (a.E + 15) / 16;
@@ -485,28 +488,39 @@ __global__ __launch_bounds__(64 * pe_waves(CELL)) __attribute__((amdgpu_waves_pe
         const __amdgpu_buffer_rsrc_t out_rsrc = __builtin_amdgcn_make_buffer_rsrc(
             a.out + e0 * (int64_t)nn_e, 0, (int)((unsigned)ne * (unsigned)nn_e * 8u), BUFFER_WORD3);
         bool bad_row[4];
+        // the lane's rows (elements kq + 4 r) as byte offsets in the tile's
+        // records, past them for elements beyond the tile
+        unsigned rowo[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) bad_row[r] = sG[(kq + 4 * r) * 12 + 10] != 0.0;
+        for (int r = 0; r < 4; ++r) {
+            bad_row[r] = sG[(kq + 4 * r) * 12 + 10] != 0.0;
+            rowo[r] = kq + 4 * r < ne ? (unsigned)(kq + 4 * r) * (unsigned)nn_e * 8u : OFF_NONE;
+        }
+        // flagged elements' rows are stored as NaN (a rare, separate path)
+        const bool anybad = __builtin_amdgcn_readfirstlane(__ballot(bad_row[0] || bad_row[1] || bad_row[2] || bad_row[3]) != 0 ? 1 : 0) != 0;
         // this unit's column groups, wavefront w taking every PE_WAVES-th; a
         // group's table values feed all NB blocks, loaded one group ahead
+        // into the other of two register sets
         const int cb_lo = (int)((int64_t)ncb * part / parts), cb_hi = (int)((int64_t)ncb * (part + 1) / parts);
-        double bv[NK];
-        auto load_b = [&](int cb) {
+        double B[2][NK];
+        auto load_b = [&](double (&Bs)[NK], int cb) {
             // the blocked tables: this lane's NK operand values of group cb
-            const double* tp = a.T + (size_t)cb * 64 * NK + lane;
+            // (buffer loads: a scalar group offset and constant lane offsets)
+            const int soff = cb * 64 * NK * 8;
 #pragma unroll
-            for (int kk = 0; kk < NK; ++kk) bv[kk] = tp[64 * kk];
+            for (int kk = 0; kk < NK; ++kk)
+                Bs[kk] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(trsrc, tvo + 512u * kk, soff, 0));
         };
-        if (cb_lo + w < cb_hi) load_b(cb_lo + w);
-        for (int cb = cb_lo + w; cb < cb_hi; cb += PE_WAVES) {
-            double bc[NK];
+        auto group = [&](const double (&Bc)[NK], int cb) {
+            // the lane's column (j, k) of every block: a per-lane byte offset
+            // (past the records beyond n_s^2); block (c, e2) adds a scalar one
+            const int col = 16 * cb + i16;
+            const unsigned cog = col < nn ? (unsigned)((col / ns) * n + col % ns) * 8u : OFF_NONE;
+            unsigned vo[4];
 #pragma unroll
-            for (int kk = 0; kk < NK; ++kk) bc[kk] = bv[kk];
-            if (cb + PE_WAVES < cb_hi) load_b(cb + PE_WAVES);
+            for (int r = 0; r < 4; ++r) vo[r] = rowo[r] + cog;
             // blocks in groups of D (D independent accumulator chains per
             // group, few registers live), each group stored before the next
-            const int col = 16 * cb + i16;
-            const int j = col < nn ? col / ns : 0, k = col < nn ? col - (col / ns) * ns : 0;
 #pragma unroll 1
             for (int c = 0; c < D; ++c) {
                 v4d_e acc[D];
@@ -517,22 +531,43 @@ __global__ __launch_bounds__(64 * pe_waves(CELL)) __attribute__((amdgpu_waves_pe
 #pragma unroll
                     for (int e2 = 0; e2 < D; ++e2)
                         acc[e2] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                            sA[((c * D + e2) * 16 + i16) * LDA + 4 * kk + kq], bc[kk], acc[e2], 0, 0, 0);
-                // lane holds elements kq + 4 r, entry col = (j, k) of blocks
-                // (c, e2).  Every store is issued: a lane past the block or an
-                // element past the tile addresses beyond the tile's records,
-                // and the buffer unit drops it
+                            sA[((c * D + e2) * 16 + i16) * LDA + 4 * kk + kq], Bc[kk], acc[e2], 0, 0, 0);
+                // lane holds elements kq + 4 r at column (j, k) of blocks
+                // (c, e2).  Every store is issued; the buffer unit drops those
+                // past the tile's records
+                if (anybad) {
 #pragma unroll
-                for (int e2 = 0; e2 < D; ++e2) {
-                    const unsigned off = (unsigned)((c * ns + j) * n + e2 * ns + k);
+                    for (int e2 = 0; e2 < D; ++e2) {
+                        const int soff = ((c * ns) * n + e2 * ns) * 8;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const unsigned byte = col < nn ? (unsigned)((kq + 4 * r) * nn_e + off) * 8u : 0x80000000u;
-                        const double v = bad_row[r] ? __builtin_nan("") : acc[e2][r];
-                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_e, v), out_rsrc, byte, 0, 0);
+                        for (int r = 0; r < 4; ++r) {
+                            const double v = bad_row[r] ? __builtin_nan("") : acc[e2][r];
+                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_e, v), out_rsrc, vo[r], soff, 0);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int e2 = 0; e2 < D; ++e2) {
+                        const int soff = ((c * ns) * n + e2 * ns) * 8;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            // through a scalar: a bit cast of the vector element
+                            // itself is compiled as a cast of element 0 here
+                            const double v = acc[e2][r];
+                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_e, v), out_rsrc, vo[r], soff, 0);
+                        }
                     }
                 }
             }
+        };
+        int cb = cb_lo + w;
+        if (cb < cb_hi) load_b(B[0], cb);
+        for (; cb < cb_hi; cb += 2 * PE_WAVES) {
+            if (cb + PE_WAVES < cb_hi) load_b(B[1], cb + PE_WAVES);
+            group(B[0], cb);
+            if (cb + PE_WAVES >= cb_hi) break;
+            if (cb + 2 * PE_WAVES < cb_hi) load_b(B[0], cb + 2 * PE_WAVES);
+            group(B[1], cb + PE_WAVES);
         }
         __syncthreads();
     }
