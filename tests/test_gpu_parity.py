@@ -331,6 +331,22 @@ def test_elasticity_preevaluated_many_units(cell, p, E):
         assert normwise(A[idx], B).max() <= TOL["fp64"]
 
 
+@pytest.mark.parametrize("cell,p", [(c, p) for c in CELLS for p in (1, 4)])
+@pytest.mark.parametrize("E", [1, 2, 7])
+def test_elasticity_preevaluated_few_elements(cell, p, E):
+    """Fewer elements than one unit (triangles take 8 per unit, tetrahedra 5)
+    or a single partial unit: most wavefronts of the grid idle, and the
+    padding rows of the unit's tiles must not be stored."""
+    log(f"elasticity pre-evaluated, few elements: {cell} P{p} E={E}")
+    coords, V, cells, h = mesh(cell, E, seed=570 + E)
+    cf = coefficients("elasticity", cell, p, E, V, cells, h, seed=571 + E)
+    B, fl = oracle.assemble("elasticity", cell, p, coords, cf)
+    assert fl == 0
+    A, st = gpu_assemble("elasticity", cell, p, coords, cf, mode="preeval")
+    assert st == 0 and np.isfinite(A).all()
+    assert normwise(A, B).max() <= TOL["fp64"]
+
+
 # Forced quadrature for elasticity where Algorithm 3 pre-evaluates (P4) or
 # where only the VALU kernel serves (n > 32): the float64 VALU kernel.
 @pytest.mark.parametrize("cell,p", [("tetrahedron", 4), ("prism", 4), ("triangle", 4), ("prism", 3),
