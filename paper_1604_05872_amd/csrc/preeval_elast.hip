@@ -34,7 +34,6 @@
 namespace fe {
 
 typedef double v4d_e __attribute__((ext_vector_type(4)));
-typedef double v2d_e __attribute__((ext_vector_type(2)));
 typedef unsigned u2_e __attribute__((ext_vector_type(2)));
 // buffer resource word 3 on gfx950: a raw (stride 0) byte buffer whose
 // accesses are range-checked against num_records; stores beyond it are
