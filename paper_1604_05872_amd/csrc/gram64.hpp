@@ -283,9 +283,9 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
                 }
             }
             // --- epilogue -----------------------------------------------------
-            // P_2 (both triangles) and D to LDS; each lane then combines and
-            // stores the entries its P_lam tiles hold (rows of 16 consecutive
-            // columns; the mirrored 10 tile scatters, merged in L2)
+            // P_2 (both triangles) and D to LDS; each lane then combines the
+            // entries its P_lam tiles hold, and the element matrix leaves
+            // through LDS
 #pragma unroll
             for (int t = 0; t < (NTILE == 2 ? 3 : 1); ++t) {
                 const int I = t == 2 ? 1 : 0, J = t == 0 ? 0 : 1;
@@ -313,9 +313,10 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
             wave_sync();
             const bool bad = sFlag[ib] != 0;
             const double nanv = __builtin_nan("");
-            double* o = a.out + e * (int64_t)(n * n);
-            auto emit = [&](int row, int col, double pl) {
-                if (row >= n || col >= n) return;
+            // the combined entry (row, col) of the element matrix from a
+            // P_lam value of the lane's tiles, P_2 (and D) in LDS
+            auto value = [&](int row, int col, double pl) -> double {
+                if (row >= n || col >= n) return 0.0;
                 const int c = row / ns, j = row - c * ns;
                 const int e2 = col / ns, k = col - e2 * ns;
                 double v = pl + sT[(e2 * ns + j) * G64_TLD + c * ns + k];
@@ -325,17 +326,52 @@ __device__ void gram64_kernel_body(const SplitArgs& a, char* lds)
 #pragma unroll
                         for (int b = 0; b < D; ++b) v += sT[(b * ns + j) * G64_TLD + b * ns + k];
                 }
-                store_out(o + row * n + col, bad ? nanv : v, a.nt);
+                return v;
             };
+            // every entry the lane's P_lam tiles hold (the 01 tile also gives
+            // the mirrored 10 entries), kept in registers until all reads of
+            // sT are done; then the element matrix is packed into sT and
+            // stored as contiguous 512-byte pieces (scattered 8-byte stores
+            // of single entries would leave partial lines to merge)
+            constexpr int NVAL = NTILE == 2 ? 16 : 4;
+            double vals[NVAL];
+            {
+                int kv = 0;
 #pragma unroll
-            for (int t = 0; t < (NTILE == 2 ? 3 : 1); ++t) {
-                const int I = t == 2 ? 1 : 0, J = t == 0 ? 0 : 1;
+                for (int t = 0; t < (NTILE == 2 ? 3 : 1); ++t) {
+                    const int I = t == 2 ? 1 : 0, J = t == 0 ? 0 : 1;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * I + kq + 4 * r, col = 16 * J + i16;
-                    emit(row, col, aL[t][r]);
-                    if (I != J) emit(col, row, aL[t][r]);
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 16 * I + kq + 4 * r, col = 16 * J + i16;
+                        vals[kv++] = value(row, col, aL[t][r]);
+                        if (I != J) vals[kv++] = value(col, row, aL[t][r]);
+                    }
                 }
+            }
+            wave_sync();
+            {
+                int kv = 0;
+#pragma unroll
+                for (int t = 0; t < (NTILE == 2 ? 3 : 1); ++t) {
+                    const int I = t == 2 ? 1 : 0, J = t == 0 ? 0 : 1;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 16 * I + kq + 4 * r, col = 16 * J + i16;
+                        if (row < n && col < n) sT[row * n + col] = vals[kv];
+                        ++kv;
+                        if (I != J) {
+                            if (row < n && col < n) sT[col * n + row] = vals[kv];
+                            ++kv;
+                        }
+                    }
+                }
+            }
+            wave_sync();
+            double* o = a.out + e * (int64_t)(n * n);
+            if (bad) {   // uniform over the wavefront
+                for (int i = lane; i < n * n; i += 64) store_out(o + i, nanv, a.nt);
+            } else {
+                for (int i = lane; i < n * n; i += 64) store_out(o + i, sT[i], a.nt);
             }
             if (bad && lane == 0 && a.status) atomicAdd(a.status, 1);
             wave_sync();
