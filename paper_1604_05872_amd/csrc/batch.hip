@@ -123,6 +123,7 @@ struct fe_batch {
         double* out = nullptr;
         const double* T = nullptr;
         int64_t E = 0;
+        int grid_per_cu = 1;   // the single call's (autotuned or default) launch width
     };
     std::vector<ElastSub> elast;
     // sub-batches whose single-call kernel is not a group tile (the streaming
@@ -234,6 +235,9 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
             es.out = sb.out_A;
             es.T = ct->dR;
             es.E = sb.n_elems;
+            Config ecfg;
+            lookup_config(c, &ecfg);
+            es.grid_per_cu = ecfg.grid_per_cu > 0 ? ecfg.grid_per_cu : preeval_elast_grid_per_cu(sb.cell, t->nb);
             elast.push_back(es);
             continue;
         }
@@ -374,7 +378,7 @@ int fe_batch_create(const fe_subbatch_t* subs, int n_subs, const fe_options_t* o
     for (size_t i = 0; i < b->elast.size() && e == hipSuccess; ++i) {
         const fe_batch::ElastSub& es = b->elast[i];
         e = launch_preeval_elast(es.cell, es.coords, es.coeff, es.out, o.d_status, es.T, es.E, es.ns,
-                                 preeval_elast_grid_per_cu(es.cell, es.ns), cus, cs);
+                                 es.grid_per_cu, cus, cs);
     }
     if (capturing) {
         const hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
