@@ -76,6 +76,10 @@ def lib():
         L.orc_assemble_spec.argtypes = [ctypes.c_int, ip, ip, ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_int64, dp, dp, dp, ctypes.c_int]
         L.orc_assemble_spec.restype = ctypes.c_int64
+        L.orc_assemble_vspec.argtypes = [ctypes.c_int, ip, ip, ip, ip, ip, dp, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, dp, dp, dp,
+                                         ctypes.c_int]
+        L.orc_assemble_vspec.restype = ctypes.c_int64
         L.orc_assemble_pointgeo.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, dp, dp,
                                             ctypes.c_double, ctypes.c_double, dp, ctypes.c_int]
         L.orc_assemble_pointgeo.restype = ctypes.c_int64
@@ -218,6 +222,35 @@ def assemble_spec(terms, cell: str, p: int, coords, fields=None, qdeg=None, nthr
     out = np.empty((E, ns, ns))
     flagged = lib().orc_assemble_spec(len(terms), te, tr, fl, _p(sc), nfld, CELL[cell], p, qdeg, E, _p(coords),
                                       _p(fd), _p(out), nthreads)
+    if flagged < 0:
+        raise ValueError("oracle rejected the form")
+    return out, int(flagged)
+
+
+def assemble_vspec(terms, cell: str, p: int, coords, fields=None, qdeg=None, n_comp=None, nthreads: int = 0):
+    """Element matrices of a generic bilinear form on the vector-valued space
+    of n_comp components (default: the cell dimension), component-blocked.
+    terms: list of (test_symbol, trial_symbol, field, scale, test_comp,
+    trial_comp); the rest as for assemble_spec."""
+    coords = _f64(coords)
+    E = coords.shape[0]
+    ns = nbasis(cell, p)
+    nc = TDIM[cell] if n_comp is None else int(n_comp)
+    code = lambda s: SYMBOLS[s] if isinstance(s, str) else int(s)  # noqa: E731
+    arr = lambda xs: (ctypes.c_int * max(1, len(xs)))(*xs)  # noqa: E731
+    te = arr([code(t[0]) for t in terms])
+    tr = arr([code(t[1]) for t in terms])
+    fl = arr([int(t[2]) for t in terms])
+    tc = arr([int(t[4]) for t in terms])
+    rc = arr([int(t[5]) for t in terms])
+    sc = np.array([float(t[3]) for t in terms] or [0.0])
+    nfld = 0 if fields is None else np.asarray(fields).shape[1]
+    if qdeg is None:
+        qdeg = 2 * p + (1 if any(int(t[2]) >= 0 for t in terms) else 0)
+    fd = _f64(fields) if fields is not None else None
+    out = np.empty((E, nc * ns, nc * ns))
+    flagged = lib().orc_assemble_vspec(len(terms), te, tr, tc, rc, fl, _p(sc), nfld, nc, CELL[cell], p, qdeg, E,
+                                       _p(coords), _p(fd), _p(out), nthreads)
     if flagged < 0:
         raise ValueError("oracle rejected the form")
     return out, int(flagged)

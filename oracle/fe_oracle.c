@@ -768,7 +768,7 @@ int64_t orc_assemble_spec(int n_terms, const int *test, const int *trial, const 
     int d = tdim_of(cell), nv = nvert_of(cell);
     int ns = orc_nbasis(cell, p);
     int nq = orc_rule_size(cell, qdeg);
-    if (ns < 0 || nq < 0 || n_terms < 0) return -1;
+    if (ns < 0 || nq < 0 || n_terms < 0 || n_terms > 32) return -1;
     for (int t = 0; t < n_terms; ++t)
         if (test[t] < 0 || test[t] > d || trial[t] < 0 || trial[t] > d || field[t] >= n_fields ||
             (field[t] >= 0 && !fields))
@@ -828,6 +828,97 @@ int64_t orc_assemble_spec(int n_terms, const int *test, const int *trial, const 
                         s += c[t] * sym[j * 4 + test[t]] * sym[k * 4 + trial[t]];
 #endif
                     A[j * ns + k] += dx * s;
+                }
+        }
+    }
+    free(X); free(W); free(PHI); free(DPHI); free(PSI);
+    return flagged;
+}
+
+/* ------------------------------------------------------------------------
+ * Generic bilinear forms on a vector-valued Lagrange space of n_comp
+ * components: basis functions phi_j e_c, numbered component-blocked
+ * (c * n_s + j).  A term couples component test_comp of the test function
+ * with component trial_comp of the trial function,
+ *     scale_t * c_t(x) * s_test_t(phi_j) * s_trial_t(phi_k)
+ * added at (test_comp * n_s + j, trial_comp * n_s + k); symbols and fields as
+ * for the scalar forms above.  The same naive nest of Fig. 1 for Eq. (7),
+ * over every (row, column) pair of the n_comp * n_s square matrix and every
+ * term (zero unless the term's components are the row's and the column's).
+ * ------------------------------------------------------------------------ */
+int64_t orc_assemble_vspec(int n_terms, const int *test, const int *trial, const int *test_comp,
+                           const int *trial_comp, const int *field, const double *scale, int n_fields, int n_comp,
+                           int cell, int p, int qdeg, int64_t E, const double *coords, const double *fields,
+                           double *out, int nthreads)
+{
+    int d = tdim_of(cell), nv = nvert_of(cell);
+    int ns = orc_nbasis(cell, p);
+    int nq = orc_rule_size(cell, qdeg);
+    if (ns < 0 || nq < 0 || n_terms < 0 || n_terms > 64 || n_comp < 1 || n_comp > 3) return -1;
+    for (int t = 0; t < n_terms; ++t)
+        if (test[t] < 0 || test[t] > d || trial[t] < 0 || trial[t] > d || field[t] >= n_fields ||
+            (field[t] >= 0 && !fields) || test_comp[t] < 0 || test_comp[t] >= n_comp || trial_comp[t] < 0 ||
+            trial_comp[t] >= n_comp)
+            return -1;
+    int n = n_comp * ns;
+    double *X = (double *)malloc(sizeof(double) * nq * 3);
+    double *W = (double *)malloc(sizeof(double) * nq);
+    double *PHI = (double *)malloc(sizeof(double) * nq * ns);
+    double *DPHI = (double *)malloc(sizeof(double) * nq * ns * 3);
+    double *PSI = (double *)malloc(sizeof(double) * nq * 6);
+    orc_rule(cell, qdeg, X, W);
+    for (int q = 0; q < nq; ++q) {
+        orc_basis(cell, p, X + q * d, PHI + q * ns, DPHI + q * ns * d);
+        p1_basis(cell, X + q * d, PSI + q * 6);
+    }
+    int64_t flagged = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static) reduction(+ : flagged)
+#endif
+    for (int64_t e = 0; e < E; ++e) {
+        double *A = out + (size_t)e * n * n;
+        const double *v = coords + (size_t)e * nv * d;
+        double J[9], K[9], detJ;
+        int bad = orc_geometry(cell, v, J, &detJ, K);
+        if (!(detJ != 0.0) || !isfinite(detJ)) bad = 1;
+        for (int k = 0; k < n * n; ++k) A[k] = bad ? NAN : 0.0;
+        if (bad) { flagged += 1; continue; }
+        double sym[ORC_MAXNB * 4];
+        double c[64];
+        for (int q = 0; q < nq; ++q) {
+            const double *phi = PHI + q * ns, *dphi = DPHI + q * ns * d;
+            double dx = W[q] * fabs(detJ);
+            for (int i = 0; i < ns; ++i) {
+                sym[i * 4] = phi[i];
+                for (int b = 0; b < d; ++b) {
+                    double s = 0.0;
+                    for (int a = 0; a < d; ++a) s += K[a * d + b] * dphi[i * d + a];
+                    sym[i * 4 + 1 + b] = s;
+                }
+            }
+            for (int t = 0; t < n_terms; ++t) {
+                double ct = scale[t];
+                if (field[t] >= 0) {
+                    double f = 0.0;
+                    for (int l = 0; l < nv; ++l) f += fields[((size_t)e * n_fields + field[t]) * nv + l] * PSI[q * 6 + l];
+                    ct *= f;
+                }
+                c[t] = ct;
+            }
+            for (int r = 0; r < n; ++r)
+                for (int s = 0; s < n; ++s) {
+                    int cr = r / ns, j = r % ns, cs = s / ns, k = s % ns;
+                    double acc = 0.0;
+                    for (int t = 0; t < n_terms; ++t) {
+#if ORC_MUTANT == 15
+                        if (trial_comp[t] != cr || test_comp[t] != cs) continue;
+#else
+                        if (test_comp[t] != cr || trial_comp[t] != cs) continue;
+#endif
+                        acc += c[t] * sym[j * 4 + test[t]] * sym[k * 4 + trial[t]];
+                    }
+                    A[r * n + s] += dx * acc;
                 }
         }
     }

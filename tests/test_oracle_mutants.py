@@ -27,6 +27,7 @@ MUTANTS = {
     12: ("non-affine prism geometry taken at the centroid for every point", "non-affine geometry"),
     13: ("test and trial basis indices swapped in a generic term", "generic forms"),
     14: ("curved-simplex geometry taken at the first point for every point", "curved geometry"),
+    15: ("component blocks of a vector-valued form transposed", "generic vector forms"),
 }
 
 PINS = {
@@ -44,11 +45,12 @@ PINS = {
     12: "zjittered_box_quadratic_forms",
     13: "spec_constant_terms_exact",
     14: "one_curved_edge_volume or curved_box_quadratic_forms",
+    15: "vspec_blocks_exact",
 }
 
 # pins of the global assembly live in their own module
 PIN_FILE = {10: "test_global_pins.py", 11: "test_global_pins.py", 12: "test_nonaffine_pins.py",
-            13: "test_form_spec_pins.py", 14: "test_curved_pins.py"}
+            13: "test_form_spec_pins.py", 14: "test_curved_pins.py", 15: "test_form_spec_pins.py"}
 
 
 @pytest.mark.parametrize("k", sorted(MUTANTS))
