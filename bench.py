@@ -493,7 +493,43 @@ def forms_workload(torch, felocal, inputs, stream, ev, reps):
                                       "factorised_symbols": int(sum(pl["factorized"]))}
         log(f"  sharing elimination P{p}: factorised {ms[False]:.4f} ms, expanded {ms[True]:.4f} ms")
         del o
-    del c
+    # a vector-valued form (component-blocked, one loop nest per block):
+    # nu grad u : grad v + (w . grad) u . v with a P1 velocity w, whose
+    # diagonal blocks factorise to the 3 trial derivatives (6 products each);
+    # and the elasticity form as component terms (every block a matching, so
+    # expanded) against the library's own elasticity kernel
+    D3 = ("dx", "dy", "dz")
+    vterms = [t for a in range(3) for b in range(3)
+              for t in ((D3[b], D3[b], -1, 0.1, a, a), ("value", D3[b], b, 1.0, a, a))]
+    eterms = [t for a in range(3) for b in range(3)
+              for t in ((D3[b], D3[b], 1, 1.0, a, a), (D3[b], D3[a], 1, 1.0, a, b), (D3[a], D3[b], 0, 1.0, a, b))]
+    g = torch.from_numpy(np.random.default_rng(47).uniform(0.5, 2.0, size=(int(c.shape[0]), 3, 4))).cuda()
+    vec = {"form": "vector advection-diffusion, P1 velocity", "per_degree": {}}
+    for p in (2, 3, 4):
+        n = 3 * felocal.NBASIS("tetrahedron", p)
+        o = torch.empty((int(c.shape[0]), n, n), dtype=torch.float64, device="cuda")
+        pl = felocal.fe_sharing_plan(vterms, "tetrahedron", p, n_fields=3, n_comp=3)
+        ms = {}
+        for ex in (False, True):
+            ms[ex] = time_launch(torch, lambda: felocal.fe_assemble_form(vterms, "tetrahedron", p, c, g, o, n_fields=3,
+                                                                         expanded=ex, n_comp=3), stream, ev, reps)
+        row = {"factorised_ms": round(ms[False], 4), "expanded_ms": round(ms[True], 4), "theta_se": pl["theta_se"],
+               "theta_expanded": pl["theta_expanded"], "factorised_symbols": int(sum(pl["factorized"]))}
+        if p == 2:
+            lm = g[:, :2].contiguous()
+            row["elasticity_generated_ms"] = round(time_launch(
+                torch, lambda: felocal.fe_assemble_form(eterms, "tetrahedron", p, c, lm, o, n_fields=2, n_comp=3),
+                stream, ev, reps), 4)
+            row["elasticity_library_ms"] = round(time_launch(
+                torch, lambda: felocal.fe_assemble_local("elasticity", "tetrahedron", p, c, lm.reshape(len(lm), -1), o,
+                                                         stream=stream), stream, ev, reps), 4)
+        vec["per_degree"][f"P{p}"] = row
+        log(f"  vector form P{p}: factorised {ms[False]:.4f} ms, expanded {ms[True]:.4f} ms"
+            + (f"; elasticity generated {row['elasticity_generated_ms']} ms, library "
+               f"{row['elasticity_library_ms']} ms" if p == 2 else ""))
+        del o
+    out["vector"] = vec
+    del c, g
     torch.cuda.empty_cache()
     return out
 

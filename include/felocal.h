@@ -464,46 +464,60 @@ int fe_assemble_csr_noalloc(fe_form_t form, fe_cell_t cell, int degree, int64_t 
                             fe_csr_t* csr, double* values, const fe_options_t* opt);
 
 /* Automatic sharing elimination (Sec. 3.2, Algorithm 1) and code generation
- * for generic scalar bilinear forms.  A form is a sum of terms
+ * for generic bilinear forms, scalar or on a vector-valued space.  A form is a
+ * sum of terms
  *     scale * c(x) * s_test(phi_j) * s_trial(phi_k),
  * s_test and s_trial being the basis function (FE_SYM_VALUE) or one of its
  * physical derivatives d/dx_1..3 (FE_SYM_DX, _DY, _DZ), and c = 1 (field =
  * -1) or the P1 field `field` interpolated from its vertex values.  Rows are
- * test functions, columns trial functions, as for fe_assemble_local. */
+ * test functions, columns trial functions, as for fe_assemble_local.
+ * Vector-valued spaces (n_comp = the cell dimension): the basis functions are
+ * phi_j e_c, numbered component-blocked (row c * n_s + j) as for the
+ * elasticity form, and a term adds to block (test_comp, trial_comp) only;
+ * e.g. linear elasticity is mu d_b v_a d_b u_a on the diagonal blocks plus
+ * mu d_b v_a d_a u_b and lambda d_a v_a d_b u_b on every block (a, b). */
 typedef enum { FE_SYM_VALUE = 0, FE_SYM_DX = 1, FE_SYM_DY = 2, FE_SYM_DZ = 3 } fe_symbol_t;
-#define FE_MAX_TERMS 16
+#define FE_MAX_TERMS 64
 #define FE_MAX_FIELDS 4
+#define FE_MAX_VERTICES 72   /* 9 component blocks of at most 8 symbols */
 typedef struct {
     int    test, trial;   /* fe_symbol_t; derivatives up to the cell dimension */
     int    field;         /* -1 (constant) or the index of a P1 field         */
     double scale;
+    int    test_comp, trial_comp;   /* components coupled; 0 for a scalar form */
 } fe_term_t;
 typedef struct {
     int       n_terms;    /* 1 .. FE_MAX_TERMS */
     fe_term_t terms[FE_MAX_TERMS];
     int       n_fields;   /* 0 .. FE_MAX_FIELDS */
+    int       n_comp;     /* 0 or 1: scalar form; the cell dimension: vector-valued space */
 } fe_form_spec_t;
 
-/* Result of Algorithm 1 for one form.  Terms with the same pair of symbols
- * are merged into one product (step 1); the sharing graph (step 3) has one
- * vertex per distinct symbol of each side (test vertices first) and one edge
- * per product; the ILP of step 5 (minimise the factorised symbols so that
- * every product is grouped under exactly one factorised endpoint, i.e. a
- * minimum vertex cover with an orientation) is solved exactly.  The
- * factorisation is kept only if it lowers the operation count (steps 2 and
- * 4); otherwise no symbol is factorised, every edge_owner is -1 and the
- * expanded nest is used.  Operation counts are per element for the rule of
- * degree qdeg. */
+/* Result of Algorithm 1 for one form.  Each component block (test_comp,
+ * trial_comp) of the element matrix is its own (j, k) loop nest; a scalar
+ * form has one block.  Per block: terms with the same pair of symbols are
+ * merged into one product (step 1); the sharing graph (step 3) has one vertex
+ * per distinct symbol of each side (test vertices first) and one edge per
+ * product; the ILP of step 5 (minimise the factorised symbols so that every
+ * product is grouped under exactly one factorised endpoint, i.e. a minimum
+ * vertex cover with an orientation) is solved exactly.  A block's
+ * factorisation is kept only if it lowers the block's operation count (steps
+ * 2 and 4); otherwise none of its symbols is factorised, its edge_owner
+ * entries are -1 and its expanded nest is used.  Vertices are listed block
+ * by block (block index test_comp * n_comp + trial_comp).  Operation counts
+ * are per element for the rule of degree qdeg, summed over the blocks. */
 typedef struct {
     int    n_vertices;
-    int    vertex_side[8];      /* 0 test, 1 trial */
-    int    vertex_symbol[8];    /* fe_symbol_t */
-    int    factorized[8];       /* x_i: the symbol is factorised (Strategy 2) */
+    int    vertex_side[FE_MAX_VERTICES];      /* 0 test, 1 trial */
+    int    vertex_symbol[FE_MAX_VERTICES];    /* fe_symbol_t */
+    int    factorized[FE_MAX_VERTICES];       /* x_i: the symbol is factorised (Strategy 2) */
     int    n_edges;
     int    edge_test[FE_MAX_TERMS], edge_trial[FE_MAX_TERMS];   /* vertex indices */
     int    edge_owner[FE_MAX_TERMS];   /* y: the factorised vertex a product is grouped under */
     double theta_expanded;      /* every product in the innermost (j, k) body */
     double theta_se;            /* after sharing elimination */
+    int    n_comp;              /* 1 for a scalar form */
+    int    vertex_block[FE_MAX_VERTICES];     /* test_comp * n_comp + trial_comp */
 } fe_sharing_t;
 
 /* qdeg = -1: 2 * degree, plus one when a term carries a field.  Host only.
@@ -519,8 +533,10 @@ int fe_form_source(const fe_form_spec_t* spec, fe_cell_t cell, int degree, int e
 /* Element matrices of a generic form (affine cells) by a quadrature kernel
  * generated from Algorithm 1's result, compiled at run time with hipRTC for
  * the current device on first use and cached (the compilation is
- * synchronous).  coords and out_A as in fe_assemble_local; fields DEVICE
- * [n_elems][n_fields][nv] (may be NULL without fields).  Options used: qdeg,
+ * synchronous).  coords as in fe_assemble_local; out_A DEVICE
+ * [n_elems][n][n] with n = n_comp * n_s (n_s for a scalar form), fully
+ * overwritten; fields DEVICE [n_elems][n_fields][nv] (may be NULL without
+ * fields).  Options used: qdeg,
  * stream, d_status, and shape.kernel (0 = sharing-eliminated nest, 5 = the
  * expanded nest, for comparison).  Degenerate and non-affine elements are
  * flagged (NaN block, d_status).  n_s <= 64.

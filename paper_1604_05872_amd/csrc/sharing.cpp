@@ -1,20 +1,26 @@
-// Automatic sharing elimination (Sec. 3.2, Algorithm 1) for generic scalar
-// bilinear forms, and a quadrature kernel generated from its result.
+// Automatic sharing elimination (Sec. 3.2, Algorithm 1) for generic
+// bilinear forms, scalar or on a vector-valued space, and a quadrature kernel
+// generated from its result.
 //
 // A form is a sum of terms scale * c(x) * s_test(phi_j) * s_trial(phi_k),
 // s being the basis function or one of its physical derivatives (the
 // multilinear symbols) and c a constant or a P1 field (a coefficient, hoisted
-// out of the (j, k) loops by generalised code motion, Strategy 1).
+// out of the (j, k) loops by generalised code motion, Strategy 1).  On a
+// vector-valued space (basis functions phi_j e_c, component-blocked) a term
+// couples one test and one trial component, so each component block of the
+// element matrix is a (j, k) loop nest of its own, with its own products;
+// the steps below run per block, and the symbols of phi_j are the same in
+// every block.
 //   * Terms with the same pair of symbols are merged into one product whose
 //     coefficient is their sum (the partition of step 1).
 //   * The sharing graph (step 3) has one vertex per distinct symbol of each
 //     side and one edge per product.
 //   * The ILP of step 5 -- minimise the number of factorised symbols such
 //     that every product is grouped under exactly one factorised endpoint --
-//     asks for a minimum vertex cover with an orientation of the edges; the
-//     graphs have at most 8 vertices, so it is solved exactly by enumerating
-//     the vertex subsets (ties: the lower operation count, then the first
-//     subset in enumeration order).
+//     asks for a minimum vertex cover with an orientation of the edges; a
+//     block's graph has at most 8 vertices, so it is solved exactly by
+//     enumerating the vertex subsets (ties: the lower operation count, then
+//     the first subset in enumeration order).
 //   * Step 6 emits the loop nest: per point, each factorised test symbol u
 //     gets a hoisted temporary h_u(k) = sum over its products of c s_trial(k)
 //     (Strategy 2), each factorised trial symbol v a temporary h_v(j); the
@@ -43,48 +49,63 @@
 namespace fe {
 namespace {
 
-constexpr int MAXV = 8;
+constexpr int MAXV = FE_MAX_VERTICES;
+constexpr int MAXBV = 8;   // vertices of one block: 4 symbols per side
 
 struct Graph {
+    int nc = 1;   // components of the space (1: scalar form)
     int nv = 0, ne = 0;
-    int side[MAXV], sym[MAXV];
+    int blk[MAXV], side[MAXV], sym[MAXV];
     int et[FE_MAX_TERMS], er[FE_MAX_TERMS];      // vertex indices of each product
     std::vector<int> terms_of[FE_MAX_TERMS];      // terms merged into product e
+    int nblocks() const { return nc * nc; }
 };
 
-int vertex_of(Graph& g, int side, int sym)
+int term_block(const fe_form_spec_t* s, int nc, int t) { return s->terms[t].test_comp * nc + s->terms[t].trial_comp; }
+
+int vertex_of(Graph& g, int blk, int side, int sym)
 {
     for (int i = 0; i < g.nv; ++i)
-        if (g.side[i] == side && g.sym[i] == sym) return i;
+        if (g.blk[i] == blk && g.side[i] == side && g.sym[i] == sym) return i;
+    g.blk[g.nv] = blk;
     g.side[g.nv] = side;
     g.sym[g.nv] = sym;
     return g.nv++;
 }
 
+int spec_components(const fe_form_spec_t* s) { return s->n_comp > 1 ? s->n_comp : 1; }
+
 int validate_spec(const fe_form_spec_t* s, int d)
 {
     if (!s || s->n_terms < 1 || s->n_terms > FE_MAX_TERMS || s->n_fields < 0 || s->n_fields > FE_MAX_FIELDS)
         return FE_EINVAL;
+    if (s->n_comp < 0 || (s->n_comp > 1 && s->n_comp != d)) return FE_EINVAL;
+    const int nc = spec_components(s);
     for (int t = 0; t < s->n_terms; ++t) {
         const fe_term_t& x = s->terms[t];
         if (x.test < 0 || x.test > d || x.trial < 0 || x.trial > d) return FE_EINVAL;
         if (x.field < -1 || x.field >= s->n_fields || !std::isfinite(x.scale)) return FE_EINVAL;
+        if (x.test_comp < 0 || x.test_comp >= nc || x.trial_comp < 0 || x.trial_comp >= nc) return FE_EINVAL;
     }
     return FE_OK;
 }
 
 void build_graph(const fe_form_spec_t* s, Graph& g)
 {
-    // test vertices first, then trial vertices (symbol order within a side)
-    for (int side = 0; side < 2; ++side)
-        for (int sym = 0; sym < 4; ++sym)
-            for (int t = 0; t < s->n_terms; ++t)
-                if ((side == 0 ? s->terms[t].test : s->terms[t].trial) == sym) {
-                    vertex_of(g, side, sym);
-                    break;
-                }
+    g.nc = spec_components(s);
+    // block by block; within a block test vertices first, then trial
+    // vertices (symbol order within a side)
+    for (int b = 0; b < g.nblocks(); ++b)
+        for (int side = 0; side < 2; ++side)
+            for (int sym = 0; sym < 4; ++sym)
+                for (int t = 0; t < s->n_terms; ++t)
+                    if (term_block(s, g.nc, t) == b && (side == 0 ? s->terms[t].test : s->terms[t].trial) == sym) {
+                        vertex_of(g, b, side, sym);
+                        break;
+                    }
     for (int t = 0; t < s->n_terms; ++t) {
-        const int u = vertex_of(g, 0, s->terms[t].test), v = vertex_of(g, 1, s->terms[t].trial);
+        const int b = term_block(s, g.nc, t);
+        const int u = vertex_of(g, b, 0, s->terms[t].test), v = vertex_of(g, b, 1, s->terms[t].trial);
         int e = 0;
         while (e < g.ne && !(g.et[e] == u && g.er[e] == v)) ++e;
         if (e == g.ne) {
@@ -97,18 +118,20 @@ void build_graph(const fe_form_spec_t* s, Graph& g)
     }
 }
 
-// Operation counts per element (multiply and add each count one).
+// Operation counts per element and block (multiply and add each count one;
+// n is the block's width, the number of scalar basis functions).
 //   expanded: per point w c_e s_test(j) for every product and j, then one
 //             multiply-add per product and (j, k);
 //   factorised: per point the temporaries (a multiply-add per grouped
 //             product and index), w s(j) per factorised symbol and j, then one
 //             multiply-add per factorised symbol and (j, k).
-double theta_expanded(const Graph& g, double n, double nq) { return nq * (2.0 * g.ne * n * n + 2.0 * g.ne * n); }
+double theta_expanded(int ne, double n, double nq) { return nq * (2.0 * ne * n * n + 2.0 * ne * n); }
 
-double theta_factorised(const Graph& g, const int* x, const int* owner, double n, double nq)
+double theta_factorised(const Graph& g, const std::vector<int>& vs, const int* x, const int* owner, double n,
+                        double nq)
 {
     double inner = 0.0, hoist = 0.0;
-    for (int i = 0; i < g.nv; ++i)
+    for (int i : vs)
         if (x[i]) {
             int deg = 0;
             for (int e = 0; e < g.ne; ++e) deg += owner[e] == i;
@@ -118,29 +141,37 @@ double theta_factorised(const Graph& g, const int* x, const int* owner, double n
     return nq * (inner + hoist);
 }
 
-// Exact solution of the ILP of Algorithm 1, step 5.
-void solve_ilp(const Graph& g, double n, double nq, int* best_x, int* best_owner, double* best_theta)
+// Exact solution of the ILP of Algorithm 1, step 5, for one block (its
+// vertices vs and products es); writes x and owner for them.
+void solve_ilp(const Graph& g, const std::vector<int>& vs, const std::vector<int>& es, double n, double nq, int* x,
+               int* owner, double* best_theta)
 {
-    int best_count = MAXV + 1;
+    const int m = (int)vs.size();
+    int best_count = MAXBV + 1;
     *best_theta = 0.0;
-    for (unsigned m = 1; m < (1u << g.nv); ++m) {
-        int x[MAXV], owner[FE_MAX_TERMS], count = 0;
-        for (int i = 0; i < g.nv; ++i) count += x[i] = (m >> i) & 1;
+    int tx[MAXV], town[FE_MAX_TERMS];
+    for (int e = 0; e < g.ne; ++e) town[e] = -2;   // other blocks' products stay unowned here
+    for (unsigned sel = 1; sel < (1u << m); ++sel) {
+        int count = 0;
+        for (int a = 0; a < m; ++a) count += tx[vs[a]] = (sel >> a) & 1;
         bool cover = true;
-        for (int e = 0; e < g.ne && cover; ++e) {
+        for (int e : es) {
             // y: a product goes to its factorised test symbol when both ends are
             // factorised (either choice gives the same count)
-            if (x[g.et[e]]) owner[e] = g.et[e];
-            else if (x[g.er[e]]) owner[e] = g.er[e];
-            else cover = false;
+            if (tx[g.et[e]]) town[e] = g.et[e];
+            else if (tx[g.er[e]]) town[e] = g.er[e];
+            else {
+                cover = false;
+                break;
+            }
         }
         if (!cover || count > best_count) continue;
-        const double th = theta_factorised(g, x, owner, n, nq);
+        const double th = theta_factorised(g, vs, tx, town, n, nq);
         if (count < best_count || th < *best_theta) {
             best_count = count;
             *best_theta = th;
-            for (int i = 0; i < g.nv; ++i) best_x[i] = x[i];
-            for (int e = 0; e < g.ne; ++e) best_owner[e] = owner[e];
+            for (int i : vs) x[i] = tx[i];
+            for (int e : es) owner[e] = town[e];
         }
     }
 }
@@ -191,61 +222,74 @@ void pick_layout(int ns, int* epw, int* tr, int* tc)
 }
 
 // HIP source of the quadrature kernel of one form: EPW elements per
-// wavefront.  Per point, lane i of an element computes the symbols of basis function i and
-// from them the row factor X_f(i) and the column factor Y_f(i) of every K
-// step f; the element matrix is the sum over points and K steps of
-// X_f Y_f^T, accumulated in register tiles.  Sharing-eliminated: one K step
-// per factorised symbol (test symbol u: X = w s_u, Y = h_u, the hoisted sum
-// of c_e s_trial over its products; trial symbol v: X = w h_v, Y = s_v).
-// Expanded: one K step per product (X = w c_e s_test, Y = s_trial).
+// wavefront.  Per element, the component blocks with products are taken one
+// after the other (a scalar form has one block); an empty block is stored as
+// zeros.  Per block and point, lane i of an element computes the symbols of
+// basis function i and from them the row factor X_f(i) and the column factor
+// Y_f(i) of every K step f of the block; the block is the sum over points and
+// K steps of X_f Y_f^T, accumulated in register tiles.  Sharing-eliminated:
+// one K step per factorised symbol (test symbol u: X = w s_u, Y = h_u, the
+// hoisted sum of c_e s_trial over its products; trial symbol v: X = w h_v,
+// Y = s_v).  Expanded: one K step per product (X = w c_e s_test, Y =
+// s_trial).
 std::string generate(const fe_form_spec_t* s, const Graph& g, const int* x, const int* owner, int cell, int p,
                      bool expanded)
 {
-    bool any = false;
-    for (int i = 0; i < g.nv; ++i) any |= x[i] != 0;
-    expanded = expanded || !any;
-    const int d = cell_dim(cell), nv = cell_nv(cell), ns = n_scalar(cell, p);
-    // the K steps: (row factor, column factor) expressions in the symbols of
-    // the lane's own basis function
-    std::vector<std::string> xs, ys;
+    const int d = cell_dim(cell), nv = cell_nv(cell), ns = n_scalar(cell, p), nc = g.nc;
+    struct Block {
+        int a = 0, b = 0;
+        std::vector<int> edges;
+        std::vector<std::string> xs, ys;
+    };
+    std::vector<Block> blocks(g.nblocks());
     auto coef_sum = [&](int i, bool test_side) {
         std::string t = "(0.0";
         for (int e = 0; e < g.ne; ++e)
             if (owner[e] == i) t += std::string(" + c") + std::to_string(e) + " * " + SYMNAME[g.sym[test_side ? g.et[e] : g.er[e]]];
         return t + ")";
     };
-    if (expanded) {
-        for (int e = 0; e < g.ne; ++e) {
-            xs.push_back(std::string("wq * c") + std::to_string(e) + " * " + SYMNAME[g.sym[g.et[e]]]);
-            ys.push_back(SYMNAME[g.sym[g.er[e]]]);
-        }
-    } else {
-        for (int i = 0; i < g.nv; ++i) {
-            if (!x[i]) continue;
-            if (g.side[i] == 0) {
-                xs.push_back(std::string("wq * ") + SYMNAME[g.sym[i]]);
-                ys.push_back(coef_sum(i, false));
-            } else {
-                xs.push_back("wq * " + coef_sum(i, true));
-                ys.push_back(SYMNAME[g.sym[i]]);
+    int nkmax = 1;
+    for (int bi = 0; bi < g.nblocks(); ++bi) {
+        Block& B = blocks[bi];
+        B.a = bi / nc;
+        B.b = bi % nc;
+        bool any = false;
+        for (int e = 0; e < g.ne; ++e)
+            if (g.blk[g.et[e]] == bi) B.edges.push_back(e);
+        for (int i = 0; i < g.nv; ++i) any |= g.blk[i] == bi && x[i] != 0;
+        if (expanded || !any) {
+            for (int e : B.edges) {
+                B.xs.push_back(std::string("wq * c") + std::to_string(e) + " * " + SYMNAME[g.sym[g.et[e]]]);
+                B.ys.push_back(SYMNAME[g.sym[g.er[e]]]);
+            }
+        } else {
+            for (int i = 0; i < g.nv; ++i) {
+                if (g.blk[i] != bi || !x[i]) continue;
+                if (g.side[i] == 0) {
+                    B.xs.push_back(std::string("wq * ") + SYMNAME[g.sym[i]]);
+                    B.ys.push_back(coef_sum(i, false));
+                } else {
+                    B.xs.push_back("wq * " + coef_sum(i, true));
+                    B.ys.push_back(SYMNAME[g.sym[i]]);
+                }
             }
         }
+        nkmax = std::max(nkmax, (int)B.xs.size());
     }
-    const int nk = (int)xs.size();
     int epw = 1, tr = 1, tc = 1;
     pick_layout(ns, &epw, &tr, &tc);
     const int rt = (ns + tr - 1) / tr, ct = (ns + tc - 1) / tc;
     // two buffers of factors per wavefront (one wave_sync per point) when
     // they fit in 48 KiB per block
-    const int nbuf = 2 * 4 * epw * nk * (rt * tr + ct * tc) * 8 <= 48 * 1024 ? 2 : 1;
+    const int nbuf = 2 * 4 * epw * nkmax * (rt * tr + ct * tc) * 8 <= 48 * 1024 ? 2 : 1;
     std::ostringstream o;
     o.precision(17);
-    o << "// generated: scalar bilinear form, cell " << cell << ", degree " << p
-      << (expanded ? ", expanded products\n" : ", sharing-eliminated\n");
-    o << "#define NS " << ns << "\n#define D " << d << "\n#define NV " << nv << "\n#define NF " << s->n_fields
-      << "\n#define NK " << nk << "\n#define TR " << tr << "\n#define TC " << tc << "\n#define RT " << rt
-      << "\n#define CT " << ct << "\n#define NXP " << rt * tr << "\n#define NYP " << ct * tc << "\n#define NBUF "
-      << nbuf << "\n#define EPW " << epw << "\n#define LPE " << 64 / epw << "\n";
+    o << "// generated: " << (nc > 1 ? "vector-valued" : "scalar") << " bilinear form, cell " << cell << ", degree "
+      << p << (expanded ? ", expanded products\n" : ", sharing-eliminated\n");
+    o << "#define NS " << ns << "\n#define NN " << nc * ns << "\n#define D " << d << "\n#define NV " << nv
+      << "\n#define NF " << s->n_fields << "\n#define NK " << nkmax << "\n#define TR " << tr << "\n#define TC " << tc
+      << "\n#define RT " << rt << "\n#define CT " << ct << "\n#define NXP " << rt * tr << "\n#define NYP " << ct * tc
+      << "\n#define NBUF " << nbuf << "\n#define EPW " << epw << "\n#define LPE " << 64 / epw << "\n";
     o << R"(
 __device__ static inline void wave_sync()
 {
@@ -306,7 +350,33 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
                     if (__builtin_fabs((v[(t + 3) * 3 + r] - v[t * 3 + r]) - (v[9 + r] - v[r])) > 1e-12 * (vmax > 0 ? vmax : 1.0))
                         bad = 1;
         }
-        double acc[TR][TC];
+)";
+    for (const Block& B : blocks) {
+        const int nk = (int)B.xs.size();
+        o << "        // block (" << B.a << ", " << B.b << "): " << B.edges.size() << " products, " << nk
+          << " K steps\n        {\n";
+        if (nk == 0) {
+            o << "        const int ro = " << B.a * ns << ", co = " << B.b * ns << ";\n";
+            o << R"(        if (act && valid) {
+#pragma unroll
+            for (int r = 0; r < TR; ++r) {
+                const int j = rt * TR + r;
+                if (j < NS) {
+                    double* row = out + (e * NN + ro + j) * NN + co;
+#pragma unroll
+                    for (int c = 0; c < TC; ++c) {
+                        const int k = ct * TC + c;
+                        if (k < NS) row[k] = bad ? __builtin_nan("") : 0.0;
+                    }
+                }
+            }
+        }
+        }
+)";
+            continue;
+        }
+        o << "        const int ro = " << B.a * ns << ", co = " << B.b * ns << ";\n";
+        o << R"(        double acc[TR][TC];
 #pragma unroll
         for (int r = 0; r < TR; ++r)
 #pragma unroll
@@ -334,7 +404,7 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
             const double s2 = K[0][1] * h0 + K[1][1] * h1 + (D == 3 ? K[2][1] * h2 : 0.0);
             const double s3 = D == 3 ? K[0][2] * h0 + K[1][2] * h1 + K[2][2] * h2 : 0.0;
             (void)s0; (void)s1; (void)s2; (void)s3;
-            // the coefficient of every product at the point
+            // the coefficient of every product of the block at the point
             double f[NF > 0 ? NF : 1];
             for (int i = 0; i < NF; ++i) {
                 double t = 0.0;
@@ -343,25 +413,23 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
             }
             (void)f;
 )";
-    for (int e = 0; e < g.ne; ++e) {
-        o << "            const double c" << e << " = 0.0";
-        for (int t : g.terms_of[e]) {
-            o << " + " << s->terms[t].scale;
-            if (s->terms[t].field >= 0) o << " * f[" << s->terms[t].field << "]";
+        for (int e : B.edges) {
+            o << "            const double c" << e << " = 0.0";
+            for (int t : g.terms_of[e]) {
+                o << " + " << s->terms[t].scale;
+                if (s->terms[t].field >= 0) o << " * f[" << s->terms[t].field << "]";
+            }
+            o << ";\n";
         }
-        o << ";\n";
-    }
-    o << "            const double wq = W[q] * adet;\n";
-    o << "            const int b = NBUF == 2 ? (q & 1) : 0;\n";
-    for (int k = 0; k < nk; ++k) {
-        o << "            if (li < NXP) sX[wv][b][sub][" << k << "][li] = " << xs[k] << ";\n";
-        o << "            if (li < NYP) sY[wv][b][sub][" << k << "][li] = " << ys[k] << ";\n";
-    }
-    o << R"(            wave_sync();
-            if (act) {
-#pragma unroll
-                for (int f = 0; f < NK; ++f) {
-                    double xr[TR], yc[TC];
+        o << "            const double wq = W[q] * adet;\n";
+        o << "            const int b = NBUF == 2 ? (q & 1) : 0;\n";
+        for (int k = 0; k < nk; ++k) {
+            o << "            if (li < NXP) sX[wv][b][sub][" << k << "][li] = " << B.xs[k] << ";\n";
+            o << "            if (li < NYP) sY[wv][b][sub][" << k << "][li] = " << B.ys[k] << ";\n";
+        }
+        o << "            wave_sync();\n            if (act) {\n#pragma unroll\n                for (int f = 0; f < "
+          << nk << "; ++f) {\n";
+        o << R"(                    double xr[TR], yc[TC];
 #pragma unroll
                     for (int r = 0; r < TR; ++r) xr[r] = sX[wv][b][sub][f][rt * TR + r];
 #pragma unroll
@@ -379,7 +447,7 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
             for (int r = 0; r < TR; ++r) {
                 const int j = rt * TR + r;
                 if (j < NS) {
-                    double* row = out + (e * NS + j) * NS;
+                    double* row = out + (e * NN + ro + j) * NN + co;
 #pragma unroll
                     for (int c = 0; c < TC; ++c) {
                         const int k = ct * TC + c;
@@ -388,8 +456,12 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
                 }
             }
         }
-        if (bad && valid && li == 0 && status) atomicAdd(status, 1);
+        // the next block's first point may reuse this block's last buffer
         wave_sync();
+        }
+)";
+    }
+    o << R"(        if (bad && valid && li == 0 && status) atomicAdd(status, 1);
     }
 }
 )";
@@ -459,21 +531,36 @@ int plan_form(const fe_form_spec_t* spec, int cell, int degree, int qdeg, Graph&
     if (qdeg > MAX_QDEG) return FE_EINVAL;
     build_graph(spec, g);
     const double n = n_scalar(cell, degree), nq = rule_size(cell, qdeg);
-    double th = 0.0;
-    solve_ilp(g, n, nq, x, owner, &th);
-    // steps 2 and 4 keep only flop-decreasing factorisations: when grouping
-    // does not pay for its temporaries (e.g. a perfect matching, as for the
-    // Laplacian) the expanded nest (Strategy 1 alone) is kept
-    const double th_exp = theta_expanded(g, n, nq);
-    if (!(th < th_exp)) {
-        for (int i = 0; i < g.nv; ++i) x[i] = 0;
-        for (int e = 0; e < g.ne; ++e) owner[e] = -1;
-        th = th_exp;
+    double th = 0.0, th_exp = 0.0;
+    for (int e = 0; e < g.ne; ++e) owner[e] = -1;
+    for (int i = 0; i < g.nv; ++i) x[i] = 0;
+    for (int b = 0; b < g.nblocks(); ++b) {
+        std::vector<int> vs, es;
+        for (int i = 0; i < g.nv; ++i)
+            if (g.blk[i] == b) vs.push_back(i);
+        for (int e = 0; e < g.ne; ++e)
+            if (g.blk[g.et[e]] == b) es.push_back(e);
+        if (es.empty()) continue;
+        double thb = 0.0;
+        solve_ilp(g, vs, es, n, nq, x, owner, &thb);
+        // steps 2 and 4 keep only flop-decreasing factorisations: when grouping
+        // does not pay for its temporaries (e.g. a perfect matching, as for the
+        // Laplacian) the block's expanded nest (Strategy 1 alone) is kept
+        const double thb_exp = theta_expanded((int)es.size(), n, nq);
+        if (!(thb < thb_exp)) {
+            for (int i : vs) x[i] = 0;
+            for (int e : es) owner[e] = -1;
+            thb = thb_exp;
+        }
+        th += thb;
+        th_exp += thb_exp;
     }
     if (out) {
         std::memset(out, 0, sizeof(*out));
         out->n_vertices = g.nv;
+        out->n_comp = g.nc;
         for (int i = 0; i < g.nv; ++i) {
+            out->vertex_block[i] = g.blk[i];
             out->vertex_side[i] = g.side[i];
             out->vertex_symbol[i] = g.sym[i];
             out->factorized[i] = x[i];

@@ -84,41 +84,53 @@ class fe_plan_t(ctypes.Structure):
 
 
 SYMBOLS = {"value": 0, "dx": 1, "dy": 2, "dz": 3}
-MAX_TERMS, MAX_FIELDS = 16, 4
+MAX_TERMS, MAX_FIELDS, MAX_VERTICES = 64, 4, 72
 
 
 class fe_term_t(ctypes.Structure):
-    _fields_ = [("test", ctypes.c_int), ("trial", ctypes.c_int), ("field", ctypes.c_int), ("scale", ctypes.c_double)]
+    _fields_ = [("test", ctypes.c_int), ("trial", ctypes.c_int), ("field", ctypes.c_int), ("scale", ctypes.c_double),
+                ("test_comp", ctypes.c_int), ("trial_comp", ctypes.c_int)]
 
 
 class fe_form_spec_t(ctypes.Structure):
-    _fields_ = [("n_terms", ctypes.c_int), ("terms", fe_term_t * MAX_TERMS), ("n_fields", ctypes.c_int)]
+    _fields_ = [("n_terms", ctypes.c_int), ("terms", fe_term_t * MAX_TERMS), ("n_fields", ctypes.c_int),
+                ("n_comp", ctypes.c_int)]
 
 
 class fe_sharing_t(ctypes.Structure):
     _fields_ = [
         ("n_vertices", ctypes.c_int),
-        ("vertex_side", ctypes.c_int * 8),
-        ("vertex_symbol", ctypes.c_int * 8),
-        ("factorized", ctypes.c_int * 8),
+        ("vertex_side", ctypes.c_int * MAX_VERTICES),
+        ("vertex_symbol", ctypes.c_int * MAX_VERTICES),
+        ("factorized", ctypes.c_int * MAX_VERTICES),
         ("n_edges", ctypes.c_int),
         ("edge_test", ctypes.c_int * MAX_TERMS),
         ("edge_trial", ctypes.c_int * MAX_TERMS),
         ("edge_owner", ctypes.c_int * MAX_TERMS),
         ("theta_expanded", ctypes.c_double),
         ("theta_se", ctypes.c_double),
+        ("n_comp", ctypes.c_int),
+        ("vertex_block", ctypes.c_int * MAX_VERTICES),
     ]
 
 
-def form_spec(terms, n_fields: int = 0) -> fe_form_spec_t:
-    """terms: list of (test_symbol, trial_symbol, field, scale); symbols are
-    names from SYMBOLS or their codes, field -1 for a constant term."""
+def form_spec(terms, n_fields: int = 0, n_comp: int = 0) -> fe_form_spec_t:
+    """terms: list of (test_symbol, trial_symbol, field, scale) or, on a
+    vector-valued space (n_comp = the cell dimension), (test_symbol,
+    trial_symbol, field, scale, test_comp, trial_comp); symbols are names
+    from SYMBOLS or their codes, field -1 for a constant term."""
+    if len(terms) > MAX_TERMS:
+        raise ValueError(f"at most {MAX_TERMS} terms")
     sp = fe_form_spec_t()
     sp.n_terms = len(terms)
     sp.n_fields = int(n_fields)
+    sp.n_comp = int(n_comp)
     code = lambda x: SYMBOLS[x] if isinstance(x, str) else int(x)  # noqa: E731
-    for i, (te, tr, f, sc) in enumerate(terms):
+    for i, t in enumerate(terms):
+        te, tr, f, sc = t[:4]
         sp.terms[i].test, sp.terms[i].trial, sp.terms[i].field, sp.terms[i].scale = code(te), code(tr), int(f), float(sc)
+        if len(t) > 4:
+            sp.terms[i].test_comp, sp.terms[i].trial_comp = int(t[4]), int(t[5])
     return sp
 
 
@@ -482,16 +494,18 @@ class CsrPattern:
             pass
 
 
-def fe_sharing_plan(terms, cell: str, degree: int, qdeg: int = -1, n_fields: int = 0) -> dict:
-    """Algorithm 1 (Sec. 3.2) for a generic scalar form: the factorised
-    symbols and operation counts (host only)."""
-    sp = form_spec(terms, n_fields)
+def fe_sharing_plan(terms, cell: str, degree: int, qdeg: int = -1, n_fields: int = 0, n_comp: int = 0) -> dict:
+    """Algorithm 1 (Sec. 3.2) for a generic form, per component block: the
+    factorised symbols and operation counts (host only)."""
+    sp = form_spec(terms, n_fields, n_comp)
     pl = fe_sharing_t()
     _check(lib().fe_sharing_plan(ctypes.byref(sp), CELLS[cell], int(degree), int(qdeg), ctypes.byref(pl)),
            "fe_sharing_plan")
     nv, ne = pl.n_vertices, pl.n_edges
     return {
+        "n_comp": pl.n_comp,
         "vertices": [(pl.vertex_side[i], pl.vertex_symbol[i]) for i in range(nv)],
+        "blocks": [pl.vertex_block[i] for i in range(nv)],
         "factorized": [bool(pl.factorized[i]) for i in range(nv)],
         "edges": [(pl.edge_test[e], pl.edge_trial[e]) for e in range(ne)],
         "owner": [pl.edge_owner[e] for e in range(ne)],
@@ -500,8 +514,9 @@ def fe_sharing_plan(terms, cell: str, degree: int, qdeg: int = -1, n_fields: int
     }
 
 
-def fe_form_source(terms, cell: str, degree: int, expanded: bool = False, n_fields: int = 0) -> str:
-    sp = form_spec(terms, n_fields)
+def fe_form_source(terms, cell: str, degree: int, expanded: bool = False, n_fields: int = 0,
+                   n_comp: int = 0) -> str:
+    sp = form_spec(terms, n_fields, n_comp)
     n = ctypes.c_size_t(0)
     _check(lib().fe_form_source(ctypes.byref(sp), CELLS[cell], int(degree), int(expanded), None, ctypes.byref(n)),
            "fe_form_source")
@@ -512,12 +527,17 @@ def fe_form_source(terms, cell: str, degree: int, expanded: bool = False, n_fiel
 
 
 def fe_assemble_form(terms, cell: str, degree: int, coords, fields, out, n_fields: int = 0, qdeg: int = -1,
-                     expanded: bool = False, stream=None, status=None):
-    """Element matrices of a generic scalar form by the generated kernel."""
+                     expanded: bool = False, stream=None, status=None, n_comp: int = 0):
+    """Element matrices of a generic form by the generated kernel; out is
+    [E][n][n], n = n_comp * n_s on a vector-valued space."""
     _f64_dev(coords, "coords")
     _f64_dev(fields, "fields")
     _f64_dev(out, "out")
-    sp = form_spec(terms, n_fields)
+    ns = fe_local_dims("mass", cell, degree)[0]
+    n = max(1, int(n_comp)) * ns
+    if out is not None and coords is not None and out.numel() < int(coords.shape[0]) * n * n:
+        raise ValueError(f"out holds fewer than {int(coords.shape[0])} x {n} x {n} values")
+    sp = form_spec(terms, n_fields, n_comp)
     o = make_options(qdeg, stream=stream, status=status, shape={"kernel": 5} if expanded else None)
     _check(lib().fe_assemble_form(ctypes.byref(sp), CELLS[cell], int(degree), int(coords.shape[0]), _ptr(coords),
                                   _ptr(fields), _ptr(out), ctypes.byref(o)), "fe_assemble_form")

@@ -1,7 +1,7 @@
-"""Generic scalar forms assembled by kernels generated from Algorithm 1's
-result (fe_assemble_form, compiled at run time with hipRTC) against the
-oracle's naive nest, per element max |A - A_oracle| / max |A_oracle| <=
-1e-12; both the sharing-eliminated and the expanded nests."""
+"""Generic forms, scalar and on vector-valued spaces, assembled by kernels
+generated from Algorithm 1's result (fe_assemble_form, compiled at run time
+with hipRTC) against the oracle's naive nest, per element max |A - A_oracle| /
+max |A_oracle| <= 1e-12; both the sharing-eliminated and the expanded nests."""
 import itertools
 import sys
 
@@ -125,3 +125,107 @@ def test_sharing_elimination_timing():
         pl = felocal.fe_sharing_plan(terms, "tetrahedron", p)
         log(f"full tensor P{p}: factorised {ms[False]:.3f} ms, expanded {ms[True]:.3f} ms, "
             f"theta {pl['theta_se']:.0f} vs {pl['theta_expanded']:.0f}")
+
+
+# --------------------------------------------------------------------------
+# Vector-valued spaces (component-blocked, one loop nest per block)
+
+def elasticity_terms(d):
+    t = []
+    for a in range(d):
+        for b in range(d):
+            t.append((D3[b], D3[b], 1, 1.0, a, a))
+            t.append((D3[b], D3[a], 1, 1.0, a, b))
+            t.append((D3[a], D3[b], 0, 1.0, a, b))
+    return t
+
+
+def advection_diffusion_terms(d):
+    """nu grad u : grad v + (w . grad) u . v, velocity w the P1 fields 0..d-1,
+    plus a coupling v_1 d_x u_0 (factorised diagonal blocks, one off-diagonal
+    block, the others empty)."""
+    t = []
+    for a in range(d):
+        for b in range(d):
+            t.append((D3[b], D3[b], -1, 0.1, a, a))
+            t.append(("value", D3[b], b, 1.0, a, a))
+    return t + [("value", "dx", -1, 0.5, 1, 0)]
+
+
+def random_vector_terms(d, seed):
+    rng = np.random.default_rng(seed)
+    syms = ["value"] + D3[:d]
+    return [(syms[int(rng.integers(0, d + 1))], syms[int(rng.integers(0, d + 1))], int(rng.integers(-1, 3)),
+             float(rng.uniform(-2, 2)), int(rng.integers(0, d)), int(rng.integers(0, d))) for _ in range(14)]
+
+
+VFORMS = {"elasticity": elasticity_terms, "advection_diffusion": advection_diffusion_terms,
+          "random": lambda d: random_vector_terms(d, 7 + d)}
+VCASES = [(f, c, p) for f in sorted(VFORMS) for c in ("triangle", "tetrahedron", "prism")
+          for p in ((1, 2, 3) if c == "prism" else (1, 2, 3, 4))]
+
+
+def run_vector(terms, cell, p, coords, fields, nf, expanded=False):
+    d = 2 if cell == "triangle" else 3
+    n = d * inputs.n_scalar_dofs(cell, p)
+    out = torch.full((len(coords), n, n), float("nan"), dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    felocal.fe_assemble_form(terms, cell, p, dev(coords), dev(fields) if fields is not None else None, out,
+                             n_fields=nf, expanded=expanded, status=st, n_comp=d)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), int(st.item())
+
+
+@pytest.mark.parametrize("name,cell,p", VCASES)
+def test_generated_vector_form_matches_oracle(name, cell, p):
+    log(f"generated vector form: {name} {cell} P{p}")
+    d = 2 if cell == "triangle" else 3
+    terms = VFORMS[name](d)
+    coords, V, cells, h = inputs.first_elements(cell, 97, 51)
+    nv = inputs.NVERT[cell]
+    nf = 3
+    fields = np.random.default_rng(52).uniform(0.5, 2.0, size=(len(coords), nf, nv))
+    B, fl = oracle.assemble_vspec(terms, cell, p, coords, fields)
+    for expanded in ((False, True) if name == "advection_diffusion" else (False,)):
+        A, st = run_vector(terms, cell, p, coords, fields, nf, expanded)
+        assert st == fl == 0
+        assert normwise(A, B).max() <= TOL, expanded
+
+
+@pytest.mark.parametrize("cell,p", [("triangle", 2), ("tetrahedron", 3), ("prism", 2)])
+def test_generated_elasticity_equals_library_form(cell, p):
+    """The elasticity form written as component terms, through the generated
+    kernel, equals the library's own elasticity kernel (its default plan)."""
+    d = 2 if cell == "triangle" else 3
+    coords, V, cells, h = inputs.first_elements(cell, 200, 53)
+    nv = inputs.NVERT[cell]
+    lm = np.random.default_rng(54).uniform(0.5, 2.0, size=(len(coords), 2, nv))
+    A, st = run_vector(elasticity_terms(d), cell, p, coords, lm, 2)
+    n = A.shape[1]
+    ref = torch.empty((len(coords), n, n), dtype=torch.float64, device="cuda")
+    felocal.fe_assemble_local("elasticity", cell, p, dev(coords), dev(lm.reshape(len(coords), -1)), ref)
+    torch.cuda.synchronize()
+    assert st == 0 and normwise(A, ref.cpu().numpy()).max() <= TOL
+
+
+def test_generated_vector_flags_and_ragged_grid():
+    """A degenerate element gets a NaN block over all component blocks, and
+    element counts that leave a wavefront partly filled store nothing past
+    the end (the output's tail keeps its canary)."""
+    coords, V, cells, h = inputs.first_elements("tetrahedron", 37, 55)
+    coords = coords.copy()
+    coords[5, 2] = coords[5, 0]
+    terms = advection_diffusion_terms(3)
+    fields = np.random.default_rng(56).uniform(0.5, 2.0, size=(37, 3, 4))
+    n = 3 * 10
+    out = torch.full((38, n, n), 7.0, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    felocal.fe_assemble_form(terms, "tetrahedron", 2, dev(coords), dev(fields), out[:37], n_fields=3, status=st,
+                             n_comp=3)
+    torch.cuda.synchronize()
+    A = out.cpu().numpy()
+    B, fl = oracle.assemble_vspec(terms, "tetrahedron", 2, coords, fields)
+    assert int(st.item()) == fl == 1
+    assert np.isnan(A[5]).all() and (A[37] == 7.0).all()
+    keep = [i for i in range(37) if i != 5]
+    assert normwise(A[keep], B[keep]).max() <= TOL

@@ -104,3 +104,100 @@ def test_generated_kernels_compile_for_gfx950(cell, p, expanded):
     rtc.hiprtcGetCodeSize(prog, ctypes.byref(n))
     rtc.hiprtcDestroyProgram(ctypes.byref(prog))
     assert rc == 0 and n.value > 1000
+
+
+# --------------------------------------------------------------------------
+# Vector-valued spaces: one sharing graph per component block
+
+D3 = ["dx", "dy", "dz"]
+
+
+def elasticity_terms(d):
+    """2 mu eps(u):eps(v) + lambda div u div v with P1 Lame fields (lambda
+    field 0, mu field 1) as component terms."""
+    t = []
+    for a in range(d):
+        for b in range(d):
+            t.append((D3[b], D3[b], 1, 1.0, a, a))
+            t.append((D3[b], D3[a], 1, 1.0, a, b))
+            t.append((D3[a], D3[b], 0, 1.0, a, b))
+    return t
+
+
+def test_elasticity_blocks_are_matchings():
+    """Every block of the elasticity form is a perfect matching (diagonal
+    blocks: d_b v d_b u; off-diagonal: mu d_b v d_a u and lambda d_a v d_b u),
+    so nothing is factorised and the expanded nests are kept."""
+    pl = F.fe_sharing_plan(elasticity_terms(3), "tetrahedron", 2, n_fields=2, n_comp=3)
+    assert pl["n_comp"] == 3 and len(pl["edges"]) == 3 * 3 + 6 * 2
+    assert not any(pl["factorized"]) and pl["theta_se"] == pl["theta_expanded"]
+    assert sorted(set(pl["blocks"])) == list(range(9))
+
+
+def test_vector_advection_diffusion_factorises_each_diagonal_block():
+    """nu grad u : grad v + (w . grad) u . v with a P1 velocity w: each
+    diagonal block has the products d_b v d_b u and v w_b d_b u (a matching
+    plus a star on the test value), covered by the three trial derivatives."""
+    terms = []
+    for a in range(3):
+        for b in range(3):
+            terms.append((D3[b], D3[b], -1, 0.1, a, a))
+            terms.append(("value", D3[b], b, 1.0, a, a))
+    pl = F.fe_sharing_plan(terms, "tetrahedron", 3, n_fields=3, n_comp=3)
+    x, blocks = pl["factorized"], pl["blocks"]
+    for blk in (0, 4, 8):
+        assert sum(f for f, b in zip(x, blocks) if b == blk) == 3
+    assert all(not f for f, b in zip(x, blocks) if b not in (0, 4, 8))
+    assert pl["theta_se"] < 0.6 * pl["theta_expanded"]
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_vector_ilp_is_a_minimum_cover_per_block(seed):
+    rng = np.random.default_rng(100 + seed)
+    d = 3
+    terms = []
+    for _ in range(int(rng.integers(2, 25))):
+        terms.append((SYMS[int(rng.integers(0, 4))], SYMS[int(rng.integers(0, 4))], -1,
+                      float(rng.uniform(0.5, 2)), int(rng.integers(0, d)), int(rng.integers(0, d))))
+    pl = F.fe_sharing_plan(terms, "tetrahedron", int(rng.integers(1, 5)), n_comp=d)
+    x, blocks, edges, owner = pl["factorized"], pl["blocks"], pl["edges"], pl["owner"]
+    assert len(edges) == len({(t[0], t[1], t[4], t[5]) for t in terms})
+    assert pl["theta_se"] <= pl["theta_expanded"]
+    for blk in set(blocks):
+        vs = [i for i, b in enumerate(blocks) if b == blk]
+        es = [(a, b) for a, b in edges if blocks[a] == blk]
+        assert all(blocks[b] == blk for a, b in es)
+        if any(x[i] for i in vs):
+            idx = {v: k for k, v in enumerate(vs)}
+            assert all(x[a] or x[b] for a, b in es)
+            assert sum(x[i] for i in vs) == _min_cover(len(vs), [(idx[a], idx[b]) for a, b in es])
+    for o, (a, b) in zip(owner, edges):
+        assert o == -1 or (o in (a, b) and x[o])
+
+
+def test_bad_vector_specs_rejected():
+    for terms, cell, nc in (([("dx", "dx", -1, 1.0, 0, 3)], "tetrahedron", 3),   # component out of range
+                            ([("dx", "dx", -1, 1.0, 0, 1)], "tetrahedron", 0),   # components of a scalar form
+                            ([("dx", "dx", -1, 1.0, 0, 0)], "tetrahedron", 2),   # not the cell dimension
+                            ([("dx", "dx", -1, 1.0, 2, 0)], "triangle", 2)):
+        with pytest.raises(F.FeError) as ei:
+            F.fe_sharing_plan(terms, cell, 2, n_comp=nc)
+        assert ei.value.code == F.FE_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(RTC), reason="hipRTC not installed")
+@pytest.mark.parametrize("cell,p,expanded", [("tetrahedron", 2, False), ("triangle", 3, True), ("prism", 2, False)])
+def test_generated_vector_kernels_compile_for_gfx950(cell, p, expanded):
+    rtc = ctypes.CDLL(RTC)
+    d = 2 if cell == "triangle" else 3
+    terms = elasticity_terms(d) + [("value", "dx", -1, 0.5, 1, 0), ("value", "dy", -1, 0.5, 1, 0)]
+    src = F.fe_form_source(terms, cell, p, expanded, n_fields=2, n_comp=d)
+    assert "vector-valued" in src and src.count("// block (") == d * d
+    prog = ctypes.c_void_p()
+    assert rtc.hiprtcCreateProgram(ctypes.byref(prog), src.encode(), b"form.hip", 0, None, None) == 0
+    opts = [b"--offload-arch=gfx950", b"-O3", b"-Xclang", b"-target-feature", b"-Xclang", b"-packed-fp32-ops"]
+    rc = rtc.hiprtcCompileProgram(prog, len(opts), (ctypes.c_char_p * len(opts))(*opts))
+    n = ctypes.c_size_t()
+    rtc.hiprtcGetCodeSize(prog, ctypes.byref(n))
+    rtc.hiprtcDestroyProgram(ctypes.byref(prog))
+    assert rc == 0 and n.value > 1000
