@@ -460,26 +460,42 @@ __global__ __launch_bounds__(64 * pe_waves(CELL)) __attribute__((amdgpu_waves_pe
         }
         for (int i = tid; i < 16 * 2 * NC; i += blockDim.x) sL[i] = i < ne * 2 * NC ? a.coeff[e0 * 2 * NC + i] : 0.0;
         __syncthreads();
-        // coefficient rows C^{c e2}[e][(l, a, b)] of every block, zero-padded to NTP
-        for (int i = tid; i < NB * 16 * NTP; i += blockDim.x) {
-            const int blk = i / (16 * NTP), r = i - blk * 16 * NTP, e = r / NTP, t = r - e * NTP;
-            const int at = (blk * 16 + e) * LDA + t;
+        // coefficient rows C^{c e2}[e][(l, a, b)] of every block, zero-padded to
+        // NTP: one work item per (block, element, l) forms its D^2 entries with
+        // compile-time (a, b), so the setup of a unit stays short against its
+        // products (it is repeated by each of the tile's column-group ranges)
+        for (int it = tid; it < NB * 16 * NC; it += blockDim.x) {
+            const int blk = it / (16 * NC), r = it - blk * 16 * NC, e = r / NC, l = r - e * NC;
             const int c = blk / D, e2 = blk - c * D;
-            double x = 0.0;
-            if (t < NT) {
-                const int l = t / (D * D), aa = (t / D) % D, b = t % D;
-                const double* K = sG + e * 12;
-                const double lam = sL[e * 2 * NC + l], mu = sL[e * 2 * NC + NC + l];
-                x = lam * (K[aa * 3 + c] * K[b * 3 + e2]) + mu * (K[aa * 3 + e2] * K[b * 3 + c]);
-                if (c == e2) {
-                    double g = 0.0;
+            const double* K = sG + e * 12;
+            const double lam = sL[e * 2 * NC + l] * K[9], mu = sL[e * 2 * NC + NC + l] * K[9];
+            double Kc[D], Ke[D];
 #pragma unroll
-                    for (int m = 0; m < D; ++m) g = fma(K[aa * 3 + m], K[b * 3 + m], g);
-                    x = fma(mu, g, x);
-                }
-                x *= K[9];
+            for (int m = 0; m < D; ++m) {
+                Kc[m] = K[m * 3 + c];
+                Ke[m] = K[m * 3 + e2];
             }
-            sA[at] = x;
+            double* dst = sA + (blk * 16 + e) * LDA + l * D * D;
+            if (c == e2) {
+#pragma unroll
+                for (int aa = 0; aa < D; ++aa)
+#pragma unroll
+                    for (int b = 0; b < D; ++b) {
+                        double g = 0.0;
+#pragma unroll
+                        for (int m = 0; m < D; ++m) g = fma(K[aa * 3 + m], K[b * 3 + m], g);
+                        dst[aa * D + b] = fma(mu, g, lam * (Kc[aa] * Kc[b]) + mu * (Kc[aa] * Kc[b]));
+                    }
+            } else {
+#pragma unroll
+                for (int aa = 0; aa < D; ++aa)
+#pragma unroll
+                    for (int b = 0; b < D; ++b) dst[aa * D + b] = lam * (Kc[aa] * Ke[b]) + mu * (Ke[aa] * Kc[b]);
+            }
+        }
+        for (int i = tid; i < NB * 16 * (NTP - NT); i += blockDim.x) {
+            const int row = i / (NTP - NT);
+            sA[row * LDA + NT + (i - row * (NTP - NT))] = 0.0;
         }
         __syncthreads();
         // the tile's output as a buffer of ne element matrices (byte records)
