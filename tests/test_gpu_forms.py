@@ -229,3 +229,30 @@ def test_generated_vector_flags_and_ragged_grid():
     assert np.isnan(A[5]).all() and (A[37] == 7.0).all()
     keep = [i for i in range(37) if i != 5]
     assert normwise(A[keep], B[keep]).max() <= TOL
+
+
+@pytest.mark.parametrize("name,vector,p", [("full_tensor_diffusion", False, 3), ("advection_diffusion", True, 2)])
+def test_generated_forms_full_size_windows(name, vector, p):
+    """82,944 tetrahedra: every wavefront runs the kernel's element loop
+    several times (2,048 workgroups of 4 wavefronts).  Three 384-element
+    windows (the first, one in the middle, the last, which ends ragged) are
+    compared with the oracle element by element."""
+    log(f"generated form full size: {name} vector={vector} P{p}")
+    E = 82944
+    coords, V, cells, h = inputs.first_elements("tetrahedron", E, 57)
+    nf = 3
+    fields = np.random.default_rng(58).uniform(0.5, 2.0, size=(E, nf, 4))
+    if vector:
+        terms = advection_diffusion_terms(3)
+        A, st = run_vector(terms, "tetrahedron", p, coords, fields, nf)
+        ref = lambda sl: oracle.assemble_vspec(terms, "tetrahedron", p, coords[sl], fields[sl])  # noqa: E731
+    else:
+        terms = FORMS[name](3)
+        A, st = run(terms, "tetrahedron", p, coords, fields, nf)
+        ref = lambda sl: oracle.assemble_spec(terms, "tetrahedron", p, coords[sl], fields[sl])  # noqa: E731
+    assert st == 0 and np.isfinite(A).all()
+    for lo in (0, E // 2 - 192, E - 384):
+        sl = slice(lo, lo + 384)
+        B, fl = ref(sl)
+        assert fl == 0
+        assert normwise(A[sl], B).max() <= TOL, lo
