@@ -466,15 +466,26 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
                         if (half ? row0 + 4 < n : row0 < n) store_out(o + row0 * n, nanv, a.nt);
                     }
                 } else {
+                    // every LDS read first, unpredicated (rows past the matrix
+                    // read row 0's entries), so that their latencies overlap;
+                    // then the sums and the stores
+                    float tv[16], dvv[16];
+                    bool diag[16];
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const int row0 = 8 * (r >> 2) + (r & 3), row1 = row0 + 4;
-                        const int c0 = row0 / ns, j0 = row0 - c0 * ns, c1 = row1 / ns, j1 = row1 - c1 * ns;
+                        const int c0 = row0 < n ? row0 / ns : 0, j0 = row0 < n ? row0 - c0 * ns : 0;
+                        const int c1 = row1 < n ? row1 / ns : 0, j1 = row1 < n ? row1 - c1 * ns : 0;
+                        const int c = half ? c1 : c0, j = half ? j1 : j0;
+                        tv[r] = tb[j * SPLIT_TILE_LD + c * ns];
+                        dvv[r] = db[j * 16];
+                        diag[r] = c == cc;
+                    }
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int row0 = 8 * (r >> 2) + (r & 3), row1 = row0 + 4;
                         if (half ? row1 < n : row0 < n) {
-                            const int c = half ? c1 : c0, j = half ? j1 : j0;
-                            float v = accL[r] + tb[j * SPLIT_TILE_LD + c * ns];
-                            const float dv = db[j * 16];
-                            v += c == cc ? dv : 0.f;
+                            const float v = accL[r] + tv[r] + (diag[r] ? dvv[r] : 0.f);
                             store_out(o + row0 * n, (double)v, a.nt);
                         }
                     }
