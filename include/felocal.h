@@ -525,9 +525,13 @@ typedef struct {
 int fe_sharing_plan(const fe_form_spec_t* spec, fe_cell_t cell, int degree, int qdeg, fe_sharing_t* plan);
 
 /* HIP source of the kernel fe_assemble_form generates (expanded != 0: the
- * loop nest without sharing elimination).  buf may be NULL; *len receives the
- * size including the terminating zero and, on input, is the capacity of buf.
- * Host only.  Errors: FE_EINVAL. */
+ * loop nest without sharing elimination).  For a vector-valued form whose
+ * blocks' register tiles fit together, this is the fused nest (one point
+ * loop, every block accumulated from it); fe_assemble_form replaces it by the
+ * per-block nest where the fused kernel would hold less than two wavefronts
+ * per SIMD on the device.  buf may be NULL; *len receives the size including
+ * the terminating zero and, on input, is the capacity of buf.  Host only.
+ * Errors: FE_EINVAL. */
 int fe_form_source(const fe_form_spec_t* spec, fe_cell_t cell, int degree, int expanded, char* buf, size_t* len);
 
 /* Element matrices of a generic form (affine cells) by a quadrature kernel

@@ -233,7 +233,7 @@ void pick_layout(int ns, int* epw, int* tr, int* tc)
 // Y = s_v).  Expanded: one K step per product (X = w c_e s_test, Y =
 // s_trial).
 std::string generate(const fe_form_spec_t* s, const Graph& g, const int* x, const int* owner, int cell, int p,
-                     bool expanded)
+                     bool expanded, bool allow_fused = true)
 {
     const int d = cell_dim(cell), nv = cell_nv(cell), ns = n_scalar(cell, p), nc = g.nc;
     struct Block {
@@ -351,6 +351,117 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
                         bad = 1;
         }
 )";
+    // Vector forms whose non-empty blocks' register tiles fit together (at most
+    // 64 doubles per lane): one point loop per element; the symbols and the
+    // coefficient fields of a point are formed once and every non-empty block
+    // accumulates from them (its factors through the same LDS buffer, two
+    // wave_syncs per block and point).  Otherwise, for scalar forms, and when
+    // the caller asks for it (the fused kernel would hold less than two
+    // wavefronts per SIMD), the blocks take the point loop one after the other.
+    int nbne = 0;
+    for (const Block& B : blocks) nbne += B.xs.empty() ? 0 : 1;
+    const bool fused = allow_fused && nc > 1 && nbne > 1 && nbne * tr * tc <= 64;
+    if (fused) {
+        o << "        // fused blocks: " << nbne << " non-empty of " << blocks.size() << "\n";
+        o << "        double acc[" << nbne << "][TR][TC];\n";
+        o << R"(#pragma unroll
+        for (int bb = 0; bb < )" << nbne << R"(; ++bb)
+#pragma unroll
+            for (int r = 0; r < TR; ++r)
+#pragma unroll
+                for (int c = 0; c < TC; ++c) acc[bb][r][c] = 0.0;
+        double np = 0.0, ng0 = 0.0, ng1 = 0.0, ng2 = 0.0;
+        if (li < NS) {
+            np = phi[li];
+            ng0 = dphi[li * D];
+            ng1 = dphi[li * D + 1];
+            if (D == 3) ng2 = dphi[li * D + D - 1];
+        }
+        for (int q = 0; q < nq; ++q) {
+            const double h0 = ng0, h1 = ng1, h2 = ng2;
+            const double s0 = np;
+            if (li < NS && q + 1 < nq) {
+                np = phi[(q + 1) * NS + li];
+                ng0 = dphi[((q + 1) * NS + li) * D];
+                ng1 = dphi[((q + 1) * NS + li) * D + 1];
+                if (D == 3) ng2 = dphi[((q + 1) * NS + li) * D + D - 1];
+            }
+            const double s1 = K[0][0] * h0 + K[1][0] * h1 + (D == 3 ? K[2][0] * h2 : 0.0);
+            const double s2 = K[0][1] * h0 + K[1][1] * h1 + (D == 3 ? K[2][1] * h2 : 0.0);
+            const double s3 = D == 3 ? K[0][2] * h0 + K[1][2] * h1 + K[2][2] * h2 : 0.0;
+            (void)s0; (void)s1; (void)s2; (void)s3;
+            double f[NF > 0 ? NF : 1];
+            for (int i = 0; i < NF; ++i) {
+                double t = 0.0;
+                for (int l = 0; l < NV; ++l) t += fields[(e * NF + i) * NV + l] * psi[q * NV + l];
+                f[i] = t;
+            }
+            (void)f;
+            const double wq = W[q] * adet;
+)";
+        int bb = 0;
+        for (const Block& B : blocks) {
+            const int nk = (int)B.xs.size();
+            if (nk == 0) continue;
+            o << "            {   // block (" << B.a << ", " << B.b << "): " << B.edges.size() << " products, " << nk
+              << " K steps\n";
+            for (int e : B.edges) {
+                o << "            const double c" << e << " = 0.0";
+                for (int t : g.terms_of[e]) {
+                    o << " + " << s->terms[t].scale;
+                    if (s->terms[t].field >= 0) o << " * f[" << s->terms[t].field << "]";
+                }
+                o << ";\n";
+            }
+            for (int k = 0; k < nk; ++k) {
+                o << "            if (li < NXP) sX[wv][0][sub][" << k << "][li] = " << B.xs[k] << ";\n";
+                o << "            if (li < NYP) sY[wv][0][sub][" << k << "][li] = " << B.ys[k] << ";\n";
+            }
+            o << "            wave_sync();\n            if (act) {\n#pragma unroll\n                for (int f = 0; f < "
+              << nk << "; ++f) {\n";
+            o << R"(                    double xr[TR], yc[TC];
+#pragma unroll
+                    for (int r = 0; r < TR; ++r) xr[r] = sX[wv][0][sub][f][rt * TR + r];
+#pragma unroll
+                    for (int c = 0; c < TC; ++c) yc[c] = sY[wv][0][sub][f][ct * TC + c];
+#pragma unroll
+                    for (int r = 0; r < TR; ++r)
+#pragma unroll
+                        for (int c = 0; c < TC; ++c) acc[)" << bb << R"(][r][c] = __builtin_fma(xr[r], yc[c], acc[)" << bb << R"(][r][c]);
+                }
+            }
+            wave_sync();
+            }
+)";
+            ++bb;
+        }
+        o << "        }\n";
+        // stores: non-empty blocks from their tiles, empty blocks as zeros
+        bb = 0;
+        for (const Block& B : blocks) {
+            const bool empty = B.xs.empty();
+            o << "        {   // store block (" << B.a << ", " << B.b << ")\n";
+            o << "        const int ro = " << B.a * ns << ", co = " << B.b * ns << ";\n";
+            o << R"(        if (act && valid) {
+#pragma unroll
+            for (int r = 0; r < TR; ++r) {
+                const int j = rt * TR + r;
+                if (j < NS) {
+                    double* row = out + (e * NN + ro + j) * NN + co;
+#pragma unroll
+                    for (int c = 0; c < TC; ++c) {
+                        const int k = ct * TC + c;
+                        if (k < NS) row[k] = bad ? __builtin_nan("") : )"
+              << (empty ? std::string("0.0") : "acc[" + std::to_string(bb) + "][r][c]") << R"(;
+                    }
+                }
+            }
+        }
+        }
+)";
+            if (!empty) ++bb;
+        }
+    } else {
     for (const Block& B : blocks) {
         const int nk = (int)B.xs.size();
         o << "        // block (" << B.a << ", " << B.b << "): " << B.edges.size() << " products, " << nk
@@ -460,6 +571,7 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
         wave_sync();
         }
 )";
+    }
     }
     o << R"(        if (bad && valid && li == 0 && status) atomicAdd(status, 1);
     }
@@ -632,6 +744,18 @@ extern "C" int fe_assemble_form(const fe_form_spec_t* spec, fe_cell_t cell, int 
     hipFunction_t fn = nullptr;
     rc = compile(generate(spec, g, x, owner, cell, degree, o.shape.kernel == 5), &fn);
     if (rc) return rc;
+    if (spec->n_comp > 1) {
+        // the fused vector nest keeps every block's tile in registers; where
+        // that leaves less than two wavefronts per SIMD (measured on MI355X:
+        // slower than the per-block nest) the per-block nest is used
+        int per_cu = 0;
+        const hipError_t oe = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
+        if (oe != hipSuccess) return set_hip_error(oe, "generated kernel occupancy");
+        if (per_cu < 2) {
+            rc = compile(generate(spec, g, x, owner, cell, degree, o.shape.kernel == 5, false), &fn);
+            if (rc) return rc;
+        }
+    }
     const double* W = t->dW;
     const double* phi = t->dphi;
     const double* dphi = t->ddphi;
