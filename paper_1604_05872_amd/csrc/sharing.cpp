@@ -370,6 +370,10 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
                     if (__builtin_fabs((v[(t + 3) * 3 + r] - v[t * 3 + r]) - (v[9 + r] - v[r])) > 1e-12 * (vmax > 0 ? vmax : 1.0))
                         bad = 1;
         }
+        // the element's coefficient-field values at its vertices, read once
+        double fv[NF > 0 ? NF * NV : 1];
+        for (int i = 0; i < NF * NV; ++i) fv[i] = fields[e * NF * NV + i];
+        (void)fv;
 )";
     // Vector forms whose non-empty blocks' register tiles fit together (at most
     // 64 doubles per lane): one point loop per element; the symbols and the
@@ -411,7 +415,7 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
             double f[NF > 0 ? NF : 1];
             for (int i = 0; i < NF; ++i) {
                 double t = 0.0;
-                for (int l = 0; l < NV; ++l) t += fields[(e * NF + i) * NV + l] * psi[q * NV + l];
+                for (int l = 0; l < NV; ++l) t += fv[i * NV + l] * psi[q * NV + l];
                 f[i] = t;
             }
             (void)f;
@@ -537,7 +541,7 @@ extern "C" __global__ __launch_bounds__(256) void fe_form_kernel(
             double f[NF > 0 ? NF : 1];
             for (int i = 0; i < NF; ++i) {
                 double t = 0.0;
-                for (int l = 0; l < NV; ++l) t += fields[(e * NF + i) * NV + l] * psi[q * NV + l];
+                for (int l = 0; l < NV; ++l) t += fv[i * NV + l] * psi[q * NV + l];
                 f[i] = t;
             }
             (void)f;
