@@ -30,6 +30,16 @@
  *   out_A       [E][n][n]         n = n_s (scalar forms) or gdim*n_s (vector
  *                                 forms); fully overwritten
  *
+ * Environment
+ *   FE_TH_BYTES        T_H in bytes where fe_options_t.th_bytes is 0 (read
+ *                      at every plan)
+ *   FE_AUTOTUNE_CACHE  JSON file of autotuned launch shapes (fe_autotune)
+ *   FE_LOG=1           one line on stderr per fe_assemble_local call: the
+ *                      mode, precision and launch configuration used (read
+ *                      at every call)
+ *   FE_NT_STORES=1     non-temporal output stores in the kernels that offer
+ *                      them (ordinary stores otherwise; read once)
+ *
  * Forms (integrands summed with weight W_q |det J|; g = J^{-T} grad_X phi):
  *   FE_MASS          phi_i phi_j
  *   FE_HELMHOLTZ     g_i . g_j + phi_i phi_j
@@ -144,9 +154,10 @@ typedef struct {
                                   (degenerate map, non-affine prism, or
                                   det F <= 0 at a point); the element's block
                                   is filled with NaN.  NULL = not counted.    */
-    size_t         th_bytes;   /* T_H (Constraint 2); 0 = the device's L2
-                                  capacity (one XCD's 4 MiB on MI355X), the
-                                  cache the pre-evaluated kernels stream
+    size_t         th_bytes;   /* T_H (Constraint 2); 0 = FE_TH_BYTES from
+                                  the environment if set, else the device's
+                                  L2 capacity (one XCD's 4 MiB on MI355X),
+                                  the cache the pre-evaluated kernels stream
                                   their tables through                      */
     int            validate;   /* nonzero: synchronously copy coords to the
                                   host and reject non-affine prisms with
@@ -281,8 +292,9 @@ typedef struct {
                                   pre-evaluated, else FE_MODE_QUADRATURE     */
 } fe_plan_t;
 
-/* qdeg = -1 for the form default; th_bytes = 0 for the device's L2 capacity
- * (4 MiB when no device is present); nf as in fe_options_t
+/* qdeg = -1 for the form default; th_bytes = 0 for FE_TH_BYTES from the
+ * environment if set, else the device's L2 capacity (4 MiB when no device is
+ * present); nf as in fe_options_t
  * (iota = C(n_s + nf - 1, nf), Sec. 4.2; times n_c for elasticity, whose
  * P1 Lame fields are expanded as well).  A plan may
  * pre-evaluate only some monomials (Fig. 5): mode is then

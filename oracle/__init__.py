@@ -28,13 +28,14 @@ NVERT = {"triangle": 3, "tetrahedron": 4, "prism": 6}
 REF_VOLUME = {"triangle": 0.5, "tetrahedron": 1.0 / 6.0, "prism": 0.5}
 
 
-def build(force: bool = False, out: str | None = None, defines=()) -> str:
-    """Compile the oracle with gcc (portable flags: it runs on other hosts)."""
+def build(force: bool = False, out: str | None = None, defines=(), flags=()) -> str:
+    """Compile the oracle with gcc (portable flags: it runs on other hosts);
+    `flags` adds compiler options (e.g. sanitizers for a test build)."""
     target = out or _LIB
     if force or not os.path.exists(target) or os.path.getmtime(target) < os.path.getmtime(_SRC):
         tmp = target + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", *[f"-D{d}" for d in defines],
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", *flags, *[f"-D{d}" for d in defines],
              _SRC, "-o", tmp, "-lm"]
         )
         os.replace(tmp, target)

@@ -461,6 +461,28 @@ int fe_resolve_variant(int form, int cell, int degree, int qdeg, const fe_option
 
 namespace fe {
 
+// FE_LOG=1 in the environment (read at every call): one line on stderr per
+// dispatched call (the plan's mode, the precision and the launch
+// configuration).
+bool log_enabled()
+{
+    const char* v = std::getenv("FE_LOG");
+    return v && v[0] == '1';
+}
+
+void log_call(const Call& c, const Config& cfg)
+{
+    static const char* forms[] = {"mass", "helmholtz", "elasticity", "hyperelastic"};
+    static const char* cells[] = {"triangle", "tetrahedron", "prism"};
+    static const char* precs[] = {"fp64", "fp32", "bf16x3"};
+    std::fprintf(stderr,
+                 "felocal: %s %s P%d E=%lld qdeg=%d nf=%d mode=%s precision=%s pointgeo=%d variant=%d block=%d "
+                 "epi=%d chunk=%d eb=%d qc=%d grid_per_cu=%d\n",
+                 forms[c.form & 3], cells[c.cell % 3], c.degree, (long long)c.E, c.qdeg, c.nf,
+                 c.mode == FE_MODE_PREEVAL ? "preevaluated" : "quadrature", precs[c.prec % 3], c.pointgeo,
+                 cfg.variant, cfg.block, cfg.epi, cfg.chunk, cfg.eb, cfg.qc, cfg.grid_per_cu);
+}
+
 // Output store mode: ordinary stores unless FE_NT_STORES=1 in the environment.
 int store_mode()
 {
@@ -898,6 +920,7 @@ int fe_assemble_local(fe_form_t form, fe_cell_t cell, int degree, int64_t n_elem
     Config cfg;
     rc = final_config(c, &cfg);
     if (rc) return rc;
+    if (log_enabled()) log_call(c, cfg);
     return launch_call(c, cfg);
 }
 

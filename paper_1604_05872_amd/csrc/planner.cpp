@@ -18,6 +18,7 @@
 // Argmin ties go to a plan with all monomials in one mode (one kernel),
 // then to fewer pre-evaluated monomials (less memory).
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 
@@ -47,8 +48,13 @@ extern "C" int fe_plan(fe_form_t form, fe_cell_t cell, int degree, int nf, int q
     if (qdeg < 0) qdeg = default_qdeg(form, cell, degree, nf);
     if (qdeg > MAX_QDEG) return FE_EINVAL;
     if (th_bytes == 0) {
+        // FE_TH_BYTES in the environment (a positive byte count) overrides the
+        // device's L2 capacity
+        const char* env = std::getenv("FE_TH_BYTES");
+        const unsigned long long v = env ? std::strtoull(env, nullptr, 10) : 0ull;
         int ndev = 0;
-        th_bytes = (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) ? device_l2_bytes() : (size_t)4 << 20;
+        th_bytes = v > 0 ? (size_t)v
+                         : (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) ? device_l2_bytes() : (size_t)4 << 20;
     }
     const double inf = std::numeric_limits<double>::infinity();
     const int d = cell_dim(cell), ns = n_scalar(cell, degree), nq = rule_size(cell, qdeg), nc = cell_nv(cell);

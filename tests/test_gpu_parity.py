@@ -874,3 +874,23 @@ def test_full_hyperelastic_tets_1m(p):
     for st in _full_check("hyperelastic", "tetrahedron", p, coords, u, ["fp64", "fp32", "bf16x3"],
                           extra_idx=flagged):
         assert st == len(flagged)
+
+
+def test_fe_log_reports_each_dispatch(monkeypatch, capfd):
+    """FE_LOG=1: one line on stderr per fe_assemble_local call with the mode,
+    precision and launch configuration."""
+    c, V, cells, h = inputs.first_elements("tetrahedron", 1000, 61)
+    dc = torch.from_numpy(c).cuda()
+    out = torch.empty((1000, 10, 10), dtype=torch.float64, device="cuda")
+    capfd.readouterr()
+    monkeypatch.setenv("FE_LOG", "1")
+    felocal.fe_assemble_local("helmholtz", "tetrahedron", 2, dc, None, out)
+    felocal.fe_assemble_local("mass", "tetrahedron", 2, dc, None, out, mode="quadrature")
+    torch.cuda.synchronize()
+    monkeypatch.delenv("FE_LOG")
+    felocal.fe_assemble_local("mass", "tetrahedron", 2, dc, None, out)
+    torch.cuda.synchronize()
+    lines = [l for l in capfd.readouterr().err.splitlines() if l.startswith("felocal: ")]
+    assert len(lines) == 2, lines
+    assert "helmholtz tetrahedron P2 E=1000" in lines[0] and "mode=preevaluated" in lines[0]
+    assert "mass tetrahedron P2 E=1000" in lines[1] and "mode=quadrature" in lines[1] and "precision=fp64" in lines[1]

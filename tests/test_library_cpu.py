@@ -211,3 +211,17 @@ def test_argument_errors_are_synchronous():
     assert "invalid" in felocal.strerror(felocal.FE_EINVAL)
     info = (ctypes.c_int * 3)()
     assert L.fe_tabulate(1, 4, 8, None, None, None, None, info) == 0 and list(info) == [125, 35, 3]
+
+
+def test_th_bytes_from_the_environment(monkeypatch):
+    """FE_TH_BYTES replaces the device's L2 capacity as T_H where the caller
+    passes th_bytes = 0 (Sec. 3.4, Constraint 2): a tiny T_H keeps every
+    table-bearing monomial of Helmholtz P4 in quadrature; an explicit
+    th_bytes still wins."""
+    monkeypatch.setenv("FE_TH_BYTES", "1000")
+    p = felocal.fe_plan("helmholtz", "tetrahedron", 4)
+    assert p["th_bytes"] == 1000 and not any(p["preevaluated"])
+    big = felocal.fe_plan("helmholtz", "tetrahedron", 4, th_bytes=64 << 20)
+    assert big["th_bytes"] == 64 << 20 and any(big["preevaluated"])
+    monkeypatch.delenv("FE_TH_BYTES")
+    assert felocal.fe_plan("helmholtz", "tetrahedron", 4)["th_bytes"] != 1000
