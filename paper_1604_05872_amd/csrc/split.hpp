@@ -223,8 +223,10 @@ __device__ void split_kernel_body(const SplitArgs& a, char* lds)
     };
     int64_t b0 = ((int64_t)blockIdx.x * SPLIT_WAVES + wave) * EB;
     // inputs of a batch go to LDS right after the previous batch's point
-    // phase (the only reader of sBuf), so the wait for their loads never
-    // also waits for the output stores of the batch before
+    // phase (the only reader of sBuf).  The compiler's wait for their loads
+    // is a full one (it cannot count the element loop's stores), so it also
+    // waits for the stores of the batch before; a variant whose stores were
+    // counted exactly (the wait then left them in flight) ran no faster
     auto stage = [&]() {
 #pragma unroll
         for (int k = 0; k < NPRE; ++k) {
