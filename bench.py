@@ -474,7 +474,11 @@ def forms_workload(torch, felocal, inputs, stream, ev, reps):
     hand-written kernel covers: full-tensor diffusion sum_ab K_ab d_a u d_b v
     (9 products between 3 test and 3 trial symbols; the ILP factorises the 3
     test gradients) on 82,944 tetrahedra, P2-P4, with the generated
-    sharing-eliminated nest against the generated expanded nest."""
+    sharing-eliminated nest against the generated expanded nest; then a
+    vector-valued form (advection-diffusion with a P1 velocity, component
+    blocks) the same way, and elasticity written as component terms against
+    the library's own elasticity kernel.  Each row carries the algorithmic
+    float64 rate (theta_se x elements / time) against the FP64 peak."""
     import itertools
     terms = [(a, b, -1, 1.0 + 0.25 * i) for i, (a, b) in enumerate(itertools.product(("dx", "dy", "dz"), repeat=2))]
     coords, V, cells, h = inputs.first_elements("tetrahedron", 82944, 46)
@@ -488,9 +492,12 @@ def forms_workload(torch, felocal, inputs, stream, ev, reps):
         for ex in (False, True):
             ms[ex] = time_launch(torch, lambda: felocal.fe_assemble_form(terms, "tetrahedron", p, c, None, o,
                                                                          expanded=ex), stream, ev, reps)
+        tf = pl["theta_se"] * int(c.shape[0]) / (ms[False] * 1e-3) / 1e12
         out["per_degree"][f"P{p}"] = {"factorised_ms": round(ms[False], 4), "expanded_ms": round(ms[True], 4),
                                       "theta_se": pl["theta_se"], "theta_expanded": pl["theta_expanded"],
-                                      "factorised_symbols": int(sum(pl["factorized"]))}
+                                      "factorised_symbols": int(sum(pl["factorized"])),
+                                      "roofline": {"bound": "fp64", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
+                                                   "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4)}}
         log(f"  sharing elimination P{p}: factorised {ms[False]:.4f} ms, expanded {ms[True]:.4f} ms")
         del o
     # a vector-valued form (component-blocked, one loop nest per block):
@@ -523,6 +530,9 @@ def forms_workload(torch, felocal, inputs, stream, ev, reps):
             row["elasticity_library_ms"] = round(time_launch(
                 torch, lambda: felocal.fe_assemble_local("elasticity", "tetrahedron", p, c, lm.reshape(len(lm), -1), o,
                                                          stream=stream), stream, ev, reps), 4)
+        tf = pl["theta_se"] * int(c.shape[0]) / (ms[False] * 1e-3) / 1e12
+        row["roofline"] = {"bound": "fp64", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(tf / FP64_PEAK_TFLOPS, 4)}
         vec["per_degree"][f"P{p}"] = row
         log(f"  vector form P{p}: factorised {ms[False]:.4f} ms, expanded {ms[True]:.4f} ms"
             + (f"; elasticity generated {row['elasticity_generated_ms']} ms, library "
