@@ -608,7 +608,22 @@ struct Compiled {
 };
 std::mutex g_gen_mu;
 std::map<std::pair<int, std::string>, Compiled> g_gen;   // (device, source) -> kernel
+std::map<std::string, hipFunction_t> g_chosen;           // call_key -> the kernel fe_assemble_form uses
 std::string g_gen_log;
+
+// The meaningful content of a call (the spec's used terms, not its padding).
+std::string call_key(const fe_form_spec_t* s, int dev, int cell, int degree, int qdeg, int nest)
+{
+    std::ostringstream k;
+    k.precision(17);
+    k << dev << ' ' << cell << ' ' << degree << ' ' << qdeg << ' ' << nest << ' ' << s->n_fields << ' ' << s->n_comp;
+    for (int t = 0; t < s->n_terms; ++t) {
+        const fe_term_t& x = s->terms[t];
+        k << ' ' << x.test << ' ' << x.trial << ' ' << x.field << ' ' << x.scale << ' ' << x.test_comp << ' '
+          << x.trial_comp;
+    }
+    return k.str();
+}
 
 int compile(const std::string& src, hipFunction_t* fn)
 {
@@ -763,20 +778,34 @@ extern "C" int fe_assemble_form(const fe_form_spec_t* spec, fe_cell_t cell, int 
     const RefTables* t = nullptr;
     rc = get_tables(cell, degree, qdeg < 0 ? default_form_qdeg(spec, degree) : qdeg, (hipStream_t)o.stream, &t);
     if (rc) return rc;
+    // the kernel chosen for this (device, form, cell, degree, rule, nest) is
+    // kept, so a repeated call neither regenerates nor looks up its source
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const std::string key = call_key(spec, dev, cell, degree, qdeg, o.shape.kernel);
     hipFunction_t fn = nullptr;
-    rc = compile(generate(spec, g, x, owner, cell, degree, o.shape.kernel == 5), &fn);
-    if (rc) return rc;
-    if (spec->n_comp > 1) {
-        // the fused vector nest keeps every block's tile in registers; where
-        // that leaves less than two wavefronts per SIMD (measured on MI355X:
-        // slower than the per-block nest) the per-block nest is used
-        int per_cu = 0;
-        const hipError_t oe = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
-        if (oe != hipSuccess) return set_hip_error(oe, "generated kernel occupancy");
-        if (per_cu < 2) {
-            rc = compile(generate(spec, g, x, owner, cell, degree, o.shape.kernel == 5, false), &fn);
-            if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_gen_mu);
+        auto it = g_chosen.find(key);
+        if (it != g_chosen.end()) fn = it->second;
+    }
+    if (!fn) {
+        rc = compile(generate(spec, g, x, owner, cell, degree, o.shape.kernel == 5), &fn);
+        if (rc) return rc;
+        if (spec->n_comp > 1) {
+            // the fused vector nest keeps every block's tile in registers; where
+            // that leaves less than two wavefronts per SIMD (measured on MI355X:
+            // slower than the per-block nest) the per-block nest is used
+            int per_cu = 0;
+            const hipError_t oe = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
+            if (oe != hipSuccess) return set_hip_error(oe, "generated kernel occupancy");
+            if (per_cu < 2) {
+                rc = compile(generate(spec, g, x, owner, cell, degree, o.shape.kernel == 5, false), &fn);
+                if (rc) return rc;
+            }
         }
+        std::lock_guard<std::mutex> lk(g_gen_mu);
+        g_chosen[key] = fn;
     }
     const double* W = t->dW;
     const double* phi = t->dphi;
