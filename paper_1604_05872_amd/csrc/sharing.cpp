@@ -616,8 +616,11 @@ std::string call_key(const fe_form_spec_t* s, int dev, int cell, int degree, int
 {
     std::ostringstream k;
     k.precision(17);
-    k << dev << ' ' << cell << ' ' << degree << ' ' << qdeg << ' ' << nest << ' ' << s->n_fields << ' ' << s->n_comp;
-    for (int t = 0; t < s->n_terms; ++t) {
+    k << dev << ' ' << cell << ' ' << degree << ' ' << qdeg << ' ' << nest << ' ' << s->n_fields << ' ' << s->n_comp
+      << ' ' << s->n_terms;
+    // (an out-of-range term count keys nothing that was ever planned)
+    const int nt = s->n_terms < 0 ? 0 : s->n_terms > FE_MAX_TERMS ? FE_MAX_TERMS : s->n_terms;
+    for (int t = 0; t < nt; ++t) {
         const fe_term_t& x = s->terms[t];
         k << ' ' << x.test << ' ' << x.trial << ' ' << x.field << ' ' << x.scale << ' ' << x.test_comp << ' '
           << x.trial_comp;
@@ -770,16 +773,10 @@ extern "C" int fe_assemble_form(const fe_form_spec_t* spec, fe_cell_t cell, int 
     Graph g;
     int x[MAXV] = {0}, owner[FE_MAX_TERMS] = {0};
     const int qdeg = o.qdeg < 0 ? -1 : o.qdeg;
-    int rc = plan_form(spec, cell, degree, qdeg, g, x, owner, nullptr);
-    if (rc) return rc;
-    if (n_scalar(cell, degree) > 64) return FE_ENOTSUP;
-    if (n_elems == 0) return FE_OK;
-    if (!coords || !out_A || (spec->n_fields > 0 && !fields)) return FE_EINVAL;
-    const RefTables* t = nullptr;
-    rc = get_tables(cell, degree, qdeg < 0 ? default_form_qdeg(spec, degree) : qdeg, (hipStream_t)o.stream, &t);
-    if (rc) return rc;
+    if (!spec) return FE_EINVAL;
     // the kernel chosen for this (device, form, cell, degree, rule, nest) is
-    // kept, so a repeated call neither regenerates nor looks up its source
+    // kept (only after the form was planned and validated), so a repeated
+    // call skips the planning, the generation and the source lookup
     int dev = 0;
     (void)hipGetDevice(&dev);
     const std::string key = call_key(spec, dev, cell, degree, qdeg, o.shape.kernel);
@@ -789,6 +786,17 @@ extern "C" int fe_assemble_form(const fe_form_spec_t* spec, fe_cell_t cell, int 
         auto it = g_chosen.find(key);
         if (it != g_chosen.end()) fn = it->second;
     }
+    int rc = FE_OK;
+    if (!fn) {
+        rc = plan_form(spec, cell, degree, qdeg, g, x, owner, nullptr);
+        if (rc) return rc;
+        if (n_scalar(cell, degree) > 64) return FE_ENOTSUP;
+    }
+    if (n_elems == 0) return FE_OK;
+    if (!coords || !out_A || (spec->n_fields > 0 && !fields)) return FE_EINVAL;
+    const RefTables* t = nullptr;
+    rc = get_tables(cell, degree, qdeg < 0 ? default_form_qdeg(spec, degree) : qdeg, (hipStream_t)o.stream, &t);
+    if (rc) return rc;
     if (!fn) {
         rc = compile(generate(spec, g, x, owner, cell, degree, o.shape.kernel == 5), &fn);
         if (rc) return rc;
