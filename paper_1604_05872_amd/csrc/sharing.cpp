@@ -224,8 +224,10 @@ bool pick_layout(int ns, int* epw, int* tr, int* tc, int max_area = 64)
 
 // HIP source of the quadrature kernel of one form: EPW elements per
 // wavefront.  Per element, the component blocks with products are taken one
-// after the other (a scalar form has one block); an empty block is stored as
-// zeros.  Per block and point, lane i of an element computes the symbols of
+// after the other (a scalar form has one block), or, for a vector form whose
+// blocks' tiles fit together (allow_fused), all in one point loop (the fused
+// nest below); an empty block is stored as zeros.  Per block and point, lane
+// i of an element computes the symbols of
 // basis function i and from them the row factor X_f(i) and the column factor
 // Y_f(i) of every K step f of the block; the block is the sum over points and
 // K steps of X_f Y_f^T, accumulated in register tiles.  Sharing-eliminated:
