@@ -231,7 +231,8 @@ def test_generated_vector_flags_and_ragged_grid():
     assert normwise(A[keep], B[keep]).max() <= TOL
 
 
-@pytest.mark.parametrize("name,vector,p", [("full_tensor_diffusion", False, 3), ("advection_diffusion", True, 2)])
+@pytest.mark.parametrize("name,vector,p", [("full_tensor_diffusion", False, 3), ("advection_diffusion", True, 2),
+                                           ("elasticity", True, 2)])
 def test_generated_forms_full_size_windows(name, vector, p):
     """82,944 tetrahedra: every wavefront runs the kernel's element loop
     several times (2,048 workgroups of 4 wavefronts).  Three 384-element
@@ -243,7 +244,7 @@ def test_generated_forms_full_size_windows(name, vector, p):
     nf = 3
     fields = np.random.default_rng(58).uniform(0.5, 2.0, size=(E, nf, 4))
     if vector:
-        terms = advection_diffusion_terms(3)
+        terms = VFORMS[name](3)
         A, st = run_vector(terms, "tetrahedron", p, coords, fields, nf)
         ref = lambda sl: oracle.assemble_vspec(terms, "tetrahedron", p, coords[sl], fields[sl])  # noqa: E731
     else:
@@ -256,3 +257,31 @@ def test_generated_forms_full_size_windows(name, vector, p):
         B, fl = ref(sl)
         assert fl == 0
         assert normwise(A[sl], B).max() <= TOL, lo
+
+
+def test_kernel_cache_keeps_calls_apart():
+    """The kernel kept per call signature: alternating forms, degrees, the
+    expanded nest, scalar and vector calls and an explicit rule, each result
+    still equals the oracle's."""
+    coords, V, cells, h = inputs.first_elements("tetrahedron", 61, 62)
+    fields = np.random.default_rng(63).uniform(0.5, 2.0, size=(61, 3, 4))
+    adv, el = advection_diffusion_terms(3), elasticity_terms(3)
+    diff = FORMS["full_tensor_diffusion"](3)
+    seq = [("v", adv, 2, False), ("v", el, 2, False), ("s", diff, 2, False), ("v", adv, 3, False),
+           ("v", adv, 2, True), ("s", diff, 2, True), ("v", el, 2, False), ("s", diff, 3, False), ("v", adv, 2, False)]
+    for kind, terms, p, ex in seq:
+        if kind == "v":
+            A, st = run_vector(terms, "tetrahedron", p, coords, fields, 3, ex)
+            B, fl = oracle.assemble_vspec(terms, "tetrahedron", p, coords, fields)
+        else:
+            A, st = run(terms, "tetrahedron", p, coords, fields, 3, ex)
+            B, fl = oracle.assemble_spec(terms, "tetrahedron", p, coords, fields)
+        assert st == fl == 0
+        assert normwise(A, B).max() <= TOL, (kind, p, ex)
+    # an explicit rule of higher degree is a different call (and still exact)
+    n = 3 * 10
+    out = torch.full((61, n, n), float("nan"), dtype=torch.float64, device="cuda")
+    felocal.fe_assemble_form(adv, "tetrahedron", 2, dev(coords), dev(fields), out, n_fields=3, qdeg=7, n_comp=3)
+    torch.cuda.synchronize()
+    B, _ = oracle.assemble_vspec(adv, "tetrahedron", 2, coords, fields, qdeg=7)
+    assert normwise(out.cpu().numpy(), B).max() <= TOL
