@@ -223,6 +223,26 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None, "bytes_per_launch": dom_bytes, "ms_per_launch": round(kern_ms[dom], 4)}
     roofline.update(profiled_traffic(kname, dom_shape))
+    # context, after the timed region: a plain fill (torch's fill_) of as many
+    # bytes as the dominant launch writes, the practical write ceiling
+    nfill = int(E * n_scalar("tetrahedron", dom) ** 2)
+    fbuf = torch.empty(nfill, dtype=torch.float64, device="cuda")
+    fbuf.fill_(0.0)
+    torch.cuda.synchronize()
+    fts = []
+    for i in range(5):
+        fa, fb = ev(), ev()
+        fa.record(stream)
+        fbuf.fill_(float(i))
+        fb.record(stream)
+        fts.append((fa, fb))
+    torch.cuda.synchronize()
+    fill_ms = sorted(fa.elapsed_time(fb) for fa, fb in fts)[2]
+    del fbuf
+    torch.cuda.empty_cache()
+    fill_gbs = nfill * 8 / (fill_ms * 1e-3) / 1e9
+    roofline["fill_ceiling"] = {"what": "torch fill_ of the dominant launch's output bytes", "ms": round(fill_ms, 4),
+                                "GB/s": round(fill_gbs, 1), "frac_of_fill": round(achieved / fill_gbs, 4)}
     step_bytes = sum(alg_bytes("helmholtz", "tetrahedron", p) for p in (1, 2, 3, 4)) * E
     step_flops = sum(alg_flops("helmholtz", "tetrahedron", p) for p in (1, 2, 3, 4)) * E
     # the last timed step's matrices, kept for the element-by-element check of
