@@ -285,3 +285,26 @@ def test_kernel_cache_keeps_calls_apart():
     torch.cuda.synchronize()
     B, _ = oracle.assemble_vspec(adv, "tetrahedron", 2, coords, fields, qdeg=7)
     assert normwise(out.cpu().numpy(), B).max() <= TOL
+
+
+def test_generated_vector_form_empty_and_refusals():
+    """No elements: nothing launched, no error.  A component count other than
+    the cell dimension, a component out of range and a vector matrix too small
+    for its output are refused before any launch."""
+    coords = np.zeros((0, 4, 3))
+    out = torch.empty((0, 30, 30), dtype=torch.float64, device="cuda")
+    felocal.fe_assemble_form(advection_diffusion_terms(3), "tetrahedron", 2, dev(coords),
+                             dev(np.zeros((0, 3, 4))), out, n_fields=3, n_comp=3)
+    c, V, cells, h = inputs.first_elements("tetrahedron", 8, 64)
+    f = dev(np.ones((8, 3, 4)))
+    o = torch.empty((8, 30, 30), dtype=torch.float64, device="cuda")
+    with pytest.raises(felocal.FeError) as ei:
+        felocal.fe_assemble_form([("dx", "dx", -1, 1.0, 0, 0)], "tetrahedron", 2, dev(c), f, o, n_fields=3, n_comp=2)
+    assert ei.value.code == felocal.FE_EINVAL
+    with pytest.raises(felocal.FeError) as ei:
+        felocal.fe_assemble_form([("dx", "dx", -1, 1.0, 0, 3)], "tetrahedron", 2, dev(c), f, o, n_fields=3, n_comp=3)
+    assert ei.value.code == felocal.FE_EINVAL
+    small = torch.empty((8, 10, 10), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        felocal.fe_assemble_form([("dx", "dx", -1, 1.0, 0, 0)], "tetrahedron", 2, dev(c), f, small, n_fields=3,
+                                 n_comp=3)
