@@ -225,3 +225,31 @@ def test_th_bytes_from_the_environment(monkeypatch):
     assert big["th_bytes"] == 64 << 20 and any(big["preevaluated"])
     monkeypatch.delenv("FE_TH_BYTES")
     assert felocal.fe_plan("helmholtz", "tetrahedron", 4)["th_bytes"] != 1000
+
+
+def test_generated_form_argument_errors_are_synchronous():
+    """fe_assemble_form refuses bad arguments on the host before any launch:
+    a negative element count, a launch-shape kernel other than the generated
+    nests, curved coordinates, a missing spec, more than 64 scalar basis
+    functions (prism P4), a component count other than the cell dimension,
+    and missing pointers; no elements is a no-op."""
+    L = felocal.lib()
+    o = felocal.fe_options_t()
+    L.fe_options_init(ctypes.byref(o))
+    sp = felocal.form_spec([("dx", "dx", -1, 1.0)])
+    tet, prism = felocal.CELLS["tetrahedron"], felocal.CELLS["prism"]
+    call = lambda spec, cell, p, E, ptr=8: L.fe_assemble_form(spec, cell, p, E, ptr, None, ptr, ctypes.byref(o))  # noqa
+    assert call(ctypes.byref(sp), tet, 2, -1) == felocal.FE_EINVAL
+    assert call(None, tet, 2, 1) == felocal.FE_EINVAL
+    assert call(ctypes.byref(sp), prism, 4, 1) == felocal.FE_ENOTSUP
+    assert call(ctypes.byref(sp), tet, 2, 0, None) == felocal.FE_OK
+    assert call(ctypes.byref(sp), tet, 2, 1, None) == felocal.FE_EINVAL
+    assert call(ctypes.byref(felocal.form_spec([("dx", "dx", -1, 1.0, 0, 0)], n_comp=2)), tet, 2, 0) == \
+        felocal.FE_EINVAL
+    assert call(ctypes.byref(felocal.form_spec([("value", "value", 0, 1.0)], n_fields=1)), tet, 2, 1) == \
+        felocal.FE_EINVAL   # a field term without fields
+    o.shape.kernel = 3
+    assert call(ctypes.byref(sp), tet, 2, 1) == felocal.FE_EINVAL
+    o.shape.kernel = 0
+    o.coord_degree = 2
+    assert call(ctypes.byref(sp), tet, 2, 1) == felocal.FE_ENOTSUP
