@@ -564,7 +564,8 @@ int fe_assemble_form(const fe_form_spec_t* spec, fe_cell_t cell, int degree, int
 const char* fe_strerror(int code);
 
 /* Frees the reference-table, coefficient-table and autotune caches (device
- * memory included).  No call may be in flight. */
+ * memory included) and unloads the kernels fe_assemble_form compiled (a later
+ * call compiles its kernel again).  No call may be in flight. */
 void fe_release_caches(void);
 
 /* Library version string. */

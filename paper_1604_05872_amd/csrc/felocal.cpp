@@ -929,6 +929,7 @@ void fe_autotune_clear(void);
 void fe_release_caches(void)
 {
     fe_autotune_clear();
+    release_generated();
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& kv : g_tables) {
         RefTables* t = kv.second;

@@ -265,5 +265,8 @@ int check_config(const Call& c, const Config& cfg);
 // automatic shape with the caller's override applied and checked
 int final_config(const Call& c, Config* cfg);
 size_t device_lds_per_block();
+// unloads every kernel module fe_assemble_form compiled and forgets the
+// kernels chosen per call (no generated kernel may be in flight)
+void release_generated();
 
 }  // namespace fe

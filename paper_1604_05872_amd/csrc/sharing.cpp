@@ -732,6 +732,22 @@ int plan_form(const fe_form_spec_t* spec, int cell, int degree, int qdeg, Graph&
 }
 
 }  // namespace
+
+void release_generated()
+{
+    std::lock_guard<std::mutex> lk(g_gen_mu);
+    g_chosen.clear();
+    int cur = 0;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    for (auto& kv : g_gen) {
+        if (!kv.second.mod) continue;
+        // a module belongs to the device it was loaded on
+        if (hipSetDevice(kv.first.first) == hipSuccess) (void)hipModuleUnload(kv.second.mod);
+    }
+    if (have_cur) (void)hipSetDevice(cur);
+    g_gen.clear();
+}
+
 }  // namespace fe
 
 using namespace fe;

@@ -308,3 +308,26 @@ def test_generated_vector_form_empty_and_refusals():
     with pytest.raises(ValueError):
         felocal.fe_assemble_form([("dx", "dx", -1, 1.0, 0, 0)], "tetrahedron", 2, dev(c), f, small, n_fields=3,
                                  n_comp=3)
+
+
+def test_release_caches_unloads_and_recompiles_generated_kernels():
+    """After fe_release_caches the generated kernels are compiled again on
+    the next call, with the same results bit for bit."""
+    coords, V, cells, h = inputs.first_elements("tetrahedron", 45, 66)
+    fields = np.random.default_rng(67).uniform(0.5, 2.0, size=(45, 3, 4))
+    cases = [([("dx", "dy", -1, 0.5), ("value", "value", 0, 1.0)], 3, False, 1),
+             (advection_diffusion_terms(3), 2, True, 3), (elasticity_terms(3), 2, True, 2)]
+    def go():
+        outs = []
+        for terms, p, vec, nf in cases:
+            if vec:
+                outs.append(run_vector(terms, "tetrahedron", p, coords, fields[:, :nf], nf)[0])
+            else:
+                outs.append(run(terms, "tetrahedron", p, coords, fields[:, :nf], nf)[0])
+        return outs
+    first = go()
+    torch.cuda.synchronize()
+    felocal.lib().fe_release_caches()
+    second = go()
+    for a, b in zip(first, second):
+        assert not np.isnan(a).any() and np.array_equal(a, b)
