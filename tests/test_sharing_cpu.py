@@ -201,3 +201,23 @@ def test_generated_vector_kernels_compile_for_gfx950(cell, p, expanded):
     rtc.hiprtcGetCodeSize(prog, ctypes.byref(n))
     rtc.hiprtcDestroyProgram(ctypes.byref(prog))
     assert rc == 0 and n.value > 1000
+
+
+@pytest.mark.parametrize("cell,p,fused", [("tetrahedron", 2, "9 non-empty of 9"), ("prism", 2, "9 non-empty of 9"),
+                                          ("triangle", 4, "4 non-empty of 4"), ("tetrahedron", 3, None),
+                                          ("tetrahedron", 4, None), ("prism", 3, None)])
+def test_fused_vector_nest_choice(cell, p, fused):
+    """The vector nest takes every non-empty block in one point loop when
+    their register tiles fit together at a K-step cost within 1.5 times the
+    per-block layout's; elasticity on tetrahedra from P3 (20 basis functions
+    per block) and on prisms from P3 keeps one point loop per block.  Empty
+    blocks are left out of the fused loop, and scalar forms have one block."""
+    d = 2 if cell == "triangle" else 3
+    src = F.fe_form_source(elasticity_terms(d), cell, p, False, n_fields=2, n_comp=d)
+    lines = [ln.strip() for ln in src.splitlines() if "fused blocks:" in ln]
+    assert lines == ([f"// fused blocks: {fused}"] if fused else [])
+    adv = [(D3[b], D3[b], -1, 0.1, a, a) for a in range(3) for b in range(3)] + [("value", "dx", -1, 0.5, 1, 0)]
+    src = F.fe_form_source(adv, "tetrahedron", 2, False, n_comp=3)
+    assert "// fused blocks: 4 non-empty of 9" in src
+    scalar = F.fe_form_source([("dx", "dx", -1, 1.0)], "tetrahedron", 2, False)
+    assert "fused blocks" not in scalar
