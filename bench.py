@@ -20,7 +20,7 @@ Inputs are seeded
 synthetic meshes resident in HBM before timing.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-       python bench.py summarize-trace DB_DIR OUT.md TITLE COMMAND [NAME_FILTER]
+       python bench.py summarize-trace DB_DIR OUT.md TITLE COMMAND [NAME_FILTER [LABELS]]
        python bench.py summarize-traffic FETCH_DIR WRITE_DIR OUT.md TITLE CMD_FETCH CMD_WRITE
 (the last two turn rocprofv3 output into the text summaries under profiles/).
 """
@@ -329,25 +329,50 @@ def _short(name):
     return name.split("(")[0] if name.startswith("k_") else name[:60]
 
 
-def summarize_trace(db_dir, out, title, command, only=""):
+def summarize_trace(db_dir, out, title, command, only="", labels=""):
     """Per-kernel duration statistics of a --kernel-trace run, one row per
     (kernel, block, grid, LDS); `only` (comma-separated) keeps kernels whose
-    name contains one of its parts."""
+    name contains one of its parts.  With `labels` (';'-separated) the kept
+    dispatches, in launch order, are cut into runs of consecutive dispatches
+    of one (kernel, block, grid, LDS), and run i is reported as labels[i]
+    (for kernels that share a name, such as run-time generated ones)."""
     cur = _rocpd(db_dir).cursor()
     parts = only.split(",")
-    rows = [r for r in cur.execute("select name, workgroup_x, grid_x, lds_size, duration from kernels").fetchall()
-            if any(f in r[0] for f in parts)]
-    agg = {}
-    for name, wg, grid, lds, dur in rows:
-        agg.setdefault((_short(name), wg, grid // max(1, wg), lds), []).append(dur)
+    rows = [r for r in cur.execute("select name, workgroup_x, grid_x, lds_size, duration, vgpr_count from kernels "
+                                   "order by start").fetchall() if any(f in r[0] for f in parts)]
+    agg, regs = {}, {}
+    if labels:
+        names = labels.split(";")
+        runs = []
+        for name, wg, grid, lds, dur, vg in rows:
+            sig = (_short(name), wg, grid // max(1, wg), lds)
+            if not runs or runs[-1][0] != sig:
+                runs.append((sig, []))
+            runs[-1][1].append(dur)
+            regs[sig] = vg
+        if len(runs) != len(names):
+            raise SystemExit(f"{len(runs)} runs of dispatches but {len(names)} labels")
+        for lab, (sig, d) in zip(names, runs):
+            agg[(lab,) + sig] = d
+    else:
+        for name, wg, grid, lds, dur, vg in rows:
+            agg.setdefault((_short(name), wg, grid // max(1, wg), lds), []).append(dur)
     total = sum(sum(v) for v in agg.values())
     lines = [f"# {title}", "", "Command (from the repository root on the GPU host):", "", "```", command, "```", "",
-             f"{len(rows)} dispatches.  Durations from the kernel trace (ns -> us).", "",
-             "| kernel | block | grid | LDS B | calls | avg us | min us | max us | share |",
-             "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
-    for (name, wg, grid, lds), d in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
-        lines.append(f"| `{name}` | {wg} | {grid} | {lds} | {len(d)} | {np.mean(d) / 1e3:.2f} | "
-                     f"{min(d) / 1e3:.2f} | {max(d) / 1e3:.2f} | {100 * sum(d) / total:.1f}% |")
+             f"{len(rows)} dispatches.  Durations from the kernel trace (ns -> us).", ""]
+    if labels:
+        lines += ["| case | kernel | block | grid | LDS B | VGPRs | calls | avg us | min us | max us | share |",
+                  "|---|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+        for (lab, name, wg, grid, lds), d in agg.items():
+            lines.append(f"| {lab} | `{name}` | {wg} | {grid} | {lds} | {regs[(name, wg, grid, lds)]} | {len(d)} | "
+                         f"{np.mean(d) / 1e3:.2f} | {min(d) / 1e3:.2f} | {max(d) / 1e3:.2f} | "
+                         f"{100 * sum(d) / total:.1f}% |")
+    else:
+        lines += ["| kernel | block | grid | LDS B | calls | avg us | min us | max us | share |",
+                  "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+        for (name, wg, grid, lds), d in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+            lines.append(f"| `{name}` | {wg} | {grid} | {lds} | {len(d)} | {np.mean(d) / 1e3:.2f} | "
+                         f"{min(d) / 1e3:.2f} | {max(d) / 1e3:.2f} | {100 * sum(d) / total:.1f}% |")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -966,8 +991,8 @@ def cpu_baseline(coords_np, gpu_out=None):
 
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-trace":
-        # summarize-trace DB_DIR OUT.md TITLE COMMAND [NAME_FILTER]
-        summarize_trace(*sys.argv[2:7])
+        # summarize-trace DB_DIR OUT.md TITLE COMMAND [NAME_FILTER [LABELS]]
+        summarize_trace(*sys.argv[2:8])
     elif len(sys.argv) > 1 and sys.argv[1] == "summarize-counters":
         # summarize-counters DB_DIR OUT.md TITLE COMMAND [NAME_FILTER]
         summarize_counters(*sys.argv[2:7])
